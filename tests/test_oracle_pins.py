@@ -1,0 +1,423 @@
+"""Pins for the CPU oracle, against things other than the oracle itself.
+
+Each test ties an oracle function to a fact fixed by the paper or by the
+mathematics: printed worked examples (tests/golden), closed forms, brute
+force, scipy's periodic k-d tree, invariances and statistical expectations
+for uniform points.  None of these tests needs a GPU.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+BOXES = {
+    "cube3": np.diag([20.0, 20.0, 20.0]),
+    "ortho3": np.diag([18.0, 23.0, 21.0]),
+    "tric3": W.triclinic_h((20.0, 22.0, 21.0), (80.0, 95.0, 100.0)),
+    "skew3": W.triclinic_h((20.0, 20.0, 22.0), (70.0, 110.0, 75.0)),
+    "sq2": np.diag([25.0, 25.0]),
+    "tric2": np.array([[24.0, -7.0], [0.0, 22.0]]),
+}
+
+
+def exhaustive_d2(xi, xj, H, kmax=3):
+    """Minimum over every image K in [-kmax, kmax]^dim of |x_j - x_i + H K|^2 (numpy)."""
+    dim = H.shape[0]
+    rng = np.arange(-kmax, kmax + 1)
+    Ks = np.stack(np.meshgrid(*([rng] * dim), indexing="ij"), axis=-1).reshape(-1, dim)
+    D = (xj - xi)[None, :] + Ks @ H.T
+    d2 = (D * D).sum(1)
+    return d2.min()
+
+
+# ---------------------------------------------------------------- box setup
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_inverse_is_inverse(name):
+    H = BOXES[name]
+    Hi = oracle.box_inverse(H)
+    assert np.abs(H @ Hi - np.eye(H.shape[0])).max() < 1e-14
+    assert np.abs(Hi @ H - np.eye(H.shape[0])).max() < 1e-14
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_widths_match_face_normals(name):
+    # the perpendicular width along axis d is 1/|row d of H^-1| (independent formula)
+    H = BOXES[name]
+    w, V = oracle.box_widths(H)
+    w_ref = 1.0 / np.linalg.norm(np.linalg.inv(H), axis=1)
+    assert np.allclose(w, w_ref, rtol=1e-13)
+    assert math.isclose(V, abs(np.linalg.det(H)), rel_tol=1e-13)
+
+
+def test_lengths_angles_roundtrip():
+    L = np.array([215.4, 215.4, 215.4])
+    A = np.array([80.0, 95.0, 100.0])
+    H = oracle.box_from_lengths_angles(L, A)
+    a, b, c = H[:, 0], H[:, 1], H[:, 2]
+    assert np.allclose([np.linalg.norm(a), np.linalg.norm(b), np.linalg.norm(c)], L, rtol=1e-14)
+    ang = lambda u, v: math.degrees(math.acos(u @ v / np.linalg.norm(u) / np.linalg.norm(v)))
+    assert np.allclose([ang(b, c), ang(a, c), ang(a, b)], A, atol=1e-10)
+    assert np.allclose(H, W.triclinic_h(L, A), rtol=1e-14, atol=1e-12)
+
+
+def test_code3_grid_and_column_convention(golden_dir):
+    """Paper Code 3: lattice vectors are the columns of the input matrix."""
+    g = json.load(open(os.path.join(golden_dir, "code3_box_grids.json")))
+    for case in g["cases"]:
+        H = np.array(case["input_rows"], dtype=float)
+        printed = np.array(case["printed_unit_cell"]).reshape(3, 3)  # one lattice vector per row
+        assert np.array_equal(printed, H.T), "printed unit cell = columns of H"
+        n, sizes = oracle.paper_ghost_grid(H, case["cutoff"], 1)
+        assert list(n) == case["cells_per_dim"]
+        assert np.allclose(sizes, case["cell_sizes"], rtol=1e-12)
+        assert int(np.prod(n)) == case["total_cells"]
+        # rows-as-vectors would put the z extent (30) on y: the grid would differ
+        n_rows, _ = oracle.paper_ghost_grid(H.T.copy(), case["cutoff"], 1)
+        if not case["orthorhombic"]:
+            assert list(n_rows) != case["cells_per_dim"]
+
+
+# ---------------------------------------------------------------- wrapping
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_wrap_properties(name):
+    H = BOXES[name]
+    dim = H.shape[0]
+    g = W.rng(11)
+    x = (g.random((500, dim)) * 6.0 - 2.5) @ H.T  # spans several cells in every direction
+    xw, fr, w = oracle.wrap(x, H)
+    assert (fr >= 0).all() and (fr < 1).all()
+    # wrapped = raw - H w, up to rounding
+    assert np.abs(xw - (x - w @ H.T)).max() < 1e-11
+    # shifting by a lattice vector changes only the wrap integers
+    K = np.array([3, -2, 5][:dim])
+    xw2, fr2, w2 = oracle.wrap(x + H @ K, H)
+    assert (w2 - w == K).all()
+    assert np.abs(xw2 - xw).max() < 1e-10
+
+
+# ---------------------------------------------------------------- minimum image
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_min_image_vs_exhaustive(name):
+    H = BOXES[name]
+    dim = H.shape[0]
+    g = W.rng(12)
+    w, _ = oracle.box_widths(H)
+    for _ in range(300):
+        xi = g.random(dim) @ H.T + g.normal(0, 30, dim)
+        xj = g.random(dim) @ H.T + g.normal(0, 30, dim)
+        d2, K = oracle.pair_d2(xi, xj, H, reach=10 * w.max())
+        ref = exhaustive_d2(xi, xj, H, kmax=8)
+        assert math.isclose(d2, ref, rel_tol=1e-9, abs_tol=1e-9)
+        D = xj - xi + H @ K
+        assert math.isclose(D @ D, d2, rel_tol=1e-9, abs_tol=1e-9)
+
+
+# ---------------------------------------------------------------- pair sets
+
+@pytest.mark.parametrize("name", list(BOXES))
+@pytest.mark.parametrize("rc_frac", [0.12, 0.3])
+def test_brute_force_equals_cell_list(name, rc_frac):
+    H = BOXES[name]
+    dim = H.shape[0]
+    w, _ = oracle.box_widths(H)
+    rc = rc_frac * w.min()
+    n = 900 if dim == 3 else 700
+    x = W.uniform_in_box(n, H, 21)
+    v = W.rng(22).normal(size=(n, dim))
+    kw = dict(sum_d=True, sum_inv_d=True, lj=(1.1, 0.3), lj_grad=True, hist=(24, rc),
+              rel_hist=(16, 4.0), vel_x=v, nl=True)
+    b = oracle.compute(x, H, rc, method=oracle.METHOD_BRUTE, **kw)
+    c = oracle.compute(x, H, rc, method=oracle.METHOD_AUTO, **kw)
+    if rc_frac <= 0.3:
+        assert c["method"] == oracle.METHOD_CELLS
+    assert b["count"] == c["count"] > 0
+    assert np.array_equal(b["nl_i"], c["nl_i"]) and np.array_equal(b["nl_j"], c["nl_j"])
+    assert np.array_equal(b["nl_d"], c["nl_d"])
+    assert np.array_equal(b["hist"], c["hist"])
+    assert np.array_equal(b["rel_hist"], c["rel_hist"])
+    for k in ("sum_d", "sum_inv_d", "lj_energy"):
+        assert math.isclose(b[k], c[k], rel_tol=1e-13), k
+    assert np.allclose(b["virial"], c["virial"], rtol=1e-12, atol=1e-12 * abs(b["virial"]).max())
+    assert np.allclose(b["lj_grad"], c["lj_grad"], rtol=1e-12, atol=1e-12 * abs(b["lj_grad"]).max())
+    assert np.allclose(b["rel_sum"], c["rel_sum"], rtol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["cube3", "ortho3", "sq2"])
+def test_pair_set_vs_scipy_periodic_kdtree(name):
+    from scipy.spatial import cKDTree
+    H = BOXES[name]
+    L = np.diag(H)
+    rc = 0.27 * L.min()
+    x = W.uniform_in_box(1200, H, 31)
+    r = oracle.compute(x, H, rc, nl=True)
+    ours = set(zip(r["nl_i"].tolist(), r["nl_j"].tolist()))
+    theirs = set(cKDTree(np.mod(x, L), boxsize=L).query_pairs(rc))
+    diff = ours ^ theirs
+    for i, j in diff:  # only pairs at the cutoff up to rounding may differ
+        d2, _ = oracle.pair_d2(x[i], x[j], H, rc * 2)
+        assert abs(d2 - rc * rc) < 1e-12 * rc * rc
+    assert len(ours) > 1000
+
+
+@pytest.mark.parametrize("name", ["cube3", "tric3", "sq2"])
+def test_nl_distance_is_min_image_norm(name):
+    H = BOXES[name]
+    w, _ = oracle.box_widths(H)
+    rc = 0.25 * w.min()
+    x = W.uniform_in_box(400, H, 41)
+    r = oracle.compute(x, H, rc, nl=True)
+    for i, j, d in list(zip(r["nl_i"], r["nl_j"], r["nl_d"]))[::7]:
+        ref = math.sqrt(exhaustive_d2(x[i], x[j], H))
+        assert math.isclose(d, ref, rel_tol=1e-12)
+
+
+def test_small_box_min_image_one_image_per_pair():
+    # rc above half the box: each pair counted once, with its nearest image
+    H = W.triclinic_h((10.0, 11.0, 10.5), (85.0, 95.0, 100.0))
+    x = W.uniform_in_box(150, H, 51)
+    rc = 7.0
+    r = oracle.compute(x, H, rc, nl=True, sum_d=True)
+    assert r["method"] == oracle.METHOD_BRUTE
+    ref = []
+    for i in range(len(x)):
+        for j in range(i + 1, len(x)):
+            d2 = exhaustive_d2(x[i], x[j], H, kmax=3)
+            if d2 <= rc * rc:
+                ref.append((i, j, math.sqrt(d2)))
+    assert r["count"] == len(ref)
+    assert list(zip(r["nl_i"].tolist(), r["nl_j"].tolist())) == [(i, j) for i, j, _ in ref]
+    assert math.isclose(r["sum_d"], sum(d for _, _, d in ref), rel_tol=1e-12)
+
+
+def test_cross_set_is_union_minus_parts():
+    H = BOXES["tric3"]
+    x = W.uniform_in_box(300, H, 61)
+    y = W.uniform_in_box(700, H, 62)
+    rc = 5.0
+    cxy = oracle.compute(x, H, rc, y)["count"]
+    both = oracle.compute(np.concatenate([x, y]), H, rc)["count"]
+    cx = oracle.compute(x, H, rc)["count"]
+    cy = oracle.compute(y, H, rc)["count"]
+    assert cxy == both - cx - cy
+    nl = oracle.compute(x, H, rc, y, nl=True)
+    assert nl["nl_count"] == cxy and (nl["nl_i"] < 300).all() and (nl["nl_j"] < 700).all()
+
+
+# ---------------------------------------------------------------- closed forms / statistics
+
+def _ideal_gas(n, V, rc, dim):
+    M = n * (n - 1) / 2
+    p = (4.0 / 3.0) * math.pi * rc ** 3 / V if dim == 3 else math.pi * rc ** 2 / V
+    return M * p, math.sqrt(M * p * (1 - p))
+
+
+@pytest.mark.parametrize("seed", [101, 102, 103])
+def test_ideal_gas_pair_count_3sigma(seed):
+    H = BOXES["tric3"]
+    _, V = oracle.box_widths(H)
+    n, rc = 3000, 6.0
+    x = W.uniform_in_box(n, H, seed)
+    mu, sd = _ideal_gas(n, V, rc, 3)
+    assert abs(oracle.compute(x, H, rc)["count"] - mu) < 3 * sd
+
+
+def test_ideal_gas_config1_scale():
+    c = W.config1()
+    mu, sd = _ideal_gas(10_000, 46.42 ** 3, 8.0, 3)
+    r = oracle.compute(c["x"], c["H"], c["cutoff"], sum_d=True, sum_inv_d=True)
+    assert abs(r["count"] - mu) < 3 * sd
+    M = 10_000 * 9_999 / 2
+    V = 46.42 ** 3
+    # E[sum 1/d] = M 2 pi rc^2 / V, E[sum d] = M pi rc^4 / V (uniform periodic points)
+    assert abs(r["sum_inv_d"] / (M * 2 * math.pi * 8.0 ** 2 / V) - 1) < 0.01
+    assert abs(r["sum_d"] / (M * math.pi * 8.0 ** 4 / V) - 1) < 0.01
+
+
+def test_code9_sum_of_distances_statistical(golden_dir):
+    """Paper Code 9 prints sum d = 10.446 for 1000 points, unit box, rc 0.05."""
+    g = json.load(open(os.path.join(golden_dir, "code9_sum_d.json")))
+    n, rc = g["n"], g["cutoff"]
+    H = np.eye(3) * g["side"]
+    vals = [oracle.compute(W.uniform_in_box(n, H, 1000 + s), H, rc, sum_d=True)["sum_d"]
+            for s in range(120)]
+    mean, sd = float(np.mean(vals)), float(np.std(vals))
+    M = n * (n - 1) / 2
+    expected = M * math.pi * rc ** 4  # closed form E[sum d]
+    assert abs(mean - expected) < 4 * sd / math.sqrt(len(vals))
+    assert abs(g["printed_value"] - mean) < 3 * sd
+
+
+def test_distance_histogram_uniform_chi2():
+    H = BOXES["cube3"]
+    n, rc, nb = 4000, 6.0, 12
+    x = W.uniform_in_box(n, H, 71)
+    r = oracle.compute(x, H, rc, hist=(nb, rc))
+    h = r["hist"]
+    assert h[nb] == 0 and int(h.sum()) == r["count"]
+    M = n * (n - 1) / 2
+    e = np.arange(nb + 1) * rc / nb
+    expct = M * (4.0 / 3.0) * math.pi * np.diff(e ** 3) / 8000.0
+    chi2 = (((h[:nb] - expct) ** 2) / expct).sum()
+    assert chi2 < 35.0  # 12 dof, p ~ 5e-4
+
+
+def test_code10_binning_rule(golden_dir):
+    """Right-closed bins of width binstep: paper Code 10 rounding-up rule."""
+    g = json.load(open(os.path.join(golden_dir, "code10_binning.json")))
+    step, nb = g["binstep"], g["nbins"]
+    rc = step * nb
+    H = np.eye(3) * 100.0
+    for d, b1 in g["cases_d_and_bin_1based"] + [(d, None) for d in g["beyond_last_bin_d"]]:
+        x = np.array([[10.0, 10.0, 10.0], [10.0 + d, 10.0, 10.0]])
+        r = oracle.compute(x, H, 6.0, hist=(nb, rc))
+        got = int(np.nonzero(r["hist"])[0][0])
+        assert got == (nb if b1 is None else b1 - 1), (d, got)
+
+
+def test_two_particle_lj_closed_forms():
+    s, e = 3.4, 0.238
+    H = np.eye(3) * 50.0
+    for d, u_ref, g_ref in [(s, 0.0, 24 * e / s), (2 ** (1 / 6) * s, -e, 0.0)]:
+        x = np.array([[5.0, 5.0, 5.0], [5.0 + d, 5.0, 5.0]])
+        r = oracle.compute(x, H, 12.0, lj=(s, e), lj_grad=True)
+        assert abs(r["lj_energy"] - u_ref) < 1e-13
+        # dE/dx_0: moving particle 0 towards 1 on the repulsive wall raises E
+        assert abs(r["lj_grad"][0, 0] - g_ref) < 1e-12 and abs(r["lj_grad"][1, 0] + g_ref) < 1e-12
+        assert math.isclose(r["virial"][0, 0], g_ref * d, rel_tol=1e-12, abs_tol=1e-12)
+
+
+# ---------------------------------------------------------------- derivatives (no formula retyped)
+
+def _lattice(H, m, seed, jitter=0.15):
+    g = W.rng(seed)
+    dim = H.shape[0]
+    grid = np.stack(np.meshgrid(*([np.arange(m)] * dim), indexing="ij"), -1).reshape(-1, dim)
+    s = (grid + 0.5 + jitter * (g.random(grid.shape) - 0.5)) / m
+    return s @ H.T
+
+
+def test_forces_sum_to_zero():
+    H = BOXES["tric3"]
+    x = W.uniform_in_box(2000, H, 81)
+    r = oracle.compute(x, H, 6.0, lj=(3.4, 0.238), lj_grad=True)
+    G = r["lj_grad"]
+    assert np.linalg.norm(G.sum(0)) <= 1e-10 * np.linalg.norm(G, axis=1).sum()
+
+
+@pytest.mark.parametrize("name", ["tric3", "tric2"])
+def test_gradient_vs_finite_differences(name):
+    H = BOXES[name]
+    dim = H.shape[0]
+    x = _lattice(H, 8 if dim == 3 else 20, 91)
+    s, e, rc = 3.0, 0.238, 6.5
+    r = oracle.compute(x, H, rc, lj=(s, e), lj_grad=True)
+    h = 1e-6
+    for i in (0, 17, 101):
+        for a in range(dim):
+            xp = x.copy(); xp[i, a] += h
+            xm = x.copy(); xm[i, a] -= h
+            fd = (oracle.compute(xp, H, rc, lj=(s, e))["lj_energy"]
+                  - oracle.compute(xm, H, rc, lj=(s, e))["lj_energy"]) / (2 * h)
+            assert abs(fd - r["lj_grad"][i, a]) < 1e-6 * max(1.0, abs(r["lj_grad"][i]).max())
+
+
+@pytest.mark.parametrize("name", ["tric3", "skew3", "tric2"])
+def test_virial_trace_is_minus_scaling_derivative(name):
+    # scaling positions, box and cutoff by lam keeps the pair set; dE/dlam = -tr W
+    H = BOXES[name]
+    dim = H.shape[0]
+    x = _lattice(H, 7 if dim == 3 else 18, 92)
+    s, e, rc = 3.0, 0.238, 6.0
+    r = oracle.compute(x, H, rc, lj=(s, e))
+    h = 1e-7
+    Ep = oracle.compute(x * (1 + h), H * (1 + h), rc * (1 + h), lj=(s, e))["lj_energy"]
+    Em = oracle.compute(x * (1 - h), H * (1 - h), rc * (1 - h), lj=(s, e))["lj_energy"]
+    fd = (Ep - Em) / (2 * h)
+    assert abs(fd + np.trace(r["virial"])) < 1e-6 * abs(np.trace(r["virial"]))
+
+
+@pytest.mark.parametrize("name", ["tric3", "tric2"])
+def test_box_gradient_vs_finite_differences(name):
+    H = BOXES[name]
+    dim = H.shape[0]
+    x = _lattice(H, 7 if dim == 3 else 18, 93) + (H @ np.array([2, -1, 3][:dim]))
+    s, e, rc = 3.0, 0.238, 6.0
+    r = oracle.compute(x, H, rc, lj=(s, e))
+    h = 1e-7
+    for a in range(dim):
+        for b in range(dim):
+            Hp = H.copy(); Hp[a, b] += h
+            Hm = H.copy(); Hm[a, b] -= h
+            fd = (oracle.compute(x, Hp, rc, lj=(s, e))["lj_energy"]
+                  - oracle.compute(x, Hm, rc, lj=(s, e))["lj_energy"]) / (2 * h)
+            assert abs(fd - r["dEdH"][a, b]) < 2e-6 * max(1.0, abs(r["dEdH"]).max())
+
+
+# ---------------------------------------------------------------- invariances
+
+def test_translation_by_lattice_vectors():
+    c = W.config2(n=20_000)
+    H, rc = c["H"], c["cutoff"]
+    x = c["x"]
+    far = x + H @ np.array([1000.0, -700.0, 300.0])
+    a = oracle.compute(x, H, rc, lj=(3.4, 0.238), lj_grad=True, nl=True)
+    b = oracle.compute(far, H, rc, lj=(3.4, 0.238), lj_grad=True, nl=True)
+    assert a["count"] == b["count"]
+    assert np.array_equal(a["nl_i"], b["nl_i"]) and np.array_equal(a["nl_j"], b["nl_j"])
+    assert math.isclose(a["lj_energy"], b["lj_energy"], rel_tol=1e-9)
+    scale = np.abs(a["lj_grad"]).max()
+    assert np.abs(a["lj_grad"] - b["lj_grad"]).max() < 1e-8 * scale
+
+
+def test_permutation_invariance():
+    H = BOXES["skew3"]
+    x = W.uniform_in_box(800, H, 94)
+    perm = W.rng(95).permutation(len(x))
+    a = oracle.compute(x, H, 5.0, lj=(3.0, 0.2), lj_grad=True, nl=True)
+    b = oracle.compute(x[perm], H, 5.0, lj=(3.0, 0.2), lj_grad=True, nl=True)
+    assert a["count"] == b["count"]
+    pa = set(zip(a["nl_i"].tolist(), a["nl_j"].tolist()))
+    pb = {tuple(sorted((int(perm[i]), int(perm[j])))) for i, j in zip(b["nl_i"], b["nl_j"])}
+    assert pa == pb
+    assert math.isclose(a["lj_energy"], b["lj_energy"], rel_tol=1e-12)
+    assert np.allclose(a["lj_grad"][perm], b["lj_grad"], rtol=1e-11, atol=1e-11 * abs(a["lj_grad"]).max())
+
+
+def test_relative_speed_histogram_two_velocity_groups():
+    # group A moves with u, group B rests: A-B pairs have |dv| = |u|, others 0
+    H = BOXES["tric3"]
+    n = 1000
+    x = W.uniform_in_box(n, H, 96)
+    A = W.rng(97).random(n) < 0.4
+    u = np.array([1.3, -0.4, 0.9])
+    v = np.where(A[:, None], u[None, :], 0.0)
+    rc, nb, hi = 5.0, 20, 4.0
+    r = oracle.compute(x, H, rc, rel_hist=(nb, hi), vel_x=v)
+    n_ab = r["count"] - oracle.compute(x[A], H, rc)["count"] - oracle.compute(x[~A], H, rc)["count"]
+    k = int(math.ceil(np.linalg.norm(u) / (hi / nb))) - 1
+    exp = np.zeros(nb + 1, dtype=np.uint64)
+    exp[0] = r["count"] - n_ab
+    exp[k] += n_ab
+    assert np.array_equal(r["rel_hist"], exp)
+    assert math.isclose(r["rel_sum"][k], n_ab * np.linalg.norm(u), rel_tol=1e-12)
+    assert r["rel_sum"][0] == 0.0
+
+
+def test_thread_count_does_not_change_results():
+    H = BOXES["tric3"]
+    x = W.uniform_in_box(3000, H, 98)
+    kw = dict(lj=(3.4, 0.238), lj_grad=True, sum_inv_d=True)
+    a = oracle.compute(x, H, 6.0, nthreads=1, **kw)
+    b = oracle.compute(x, H, 6.0, nthreads=7, **kw)
+    assert a["lj_energy"] == b["lj_energy"] and a["sum_inv_d"] == b["sum_inv_d"]
+    assert np.array_equal(a["lj_grad"], b["lj_grad"])
