@@ -1,0 +1,192 @@
+/*
+ * clmap.h -- C-ABI of libclmap.so: cell-list pair mapping on AMD MI355X
+ * (gfx950), after "CellListMap.jl" (Martinez, arXiv 2202.06427).
+ *
+ * The calls follow the paper's statement of the problem (section 2.1):
+ *   1. the pair function  -> a map kind chosen from a fixed set (clm_map_kind),
+ *                            because a C ABI cannot take a closure
+ *                            (the paper's user function, sections 2.3 and 2.7);
+ *   2. geometry and cutoff -> clm_box_create (the paper's Box, section 2.5);
+ *   3. the cell lists      -> clm_celllist_create + clm_celllist_build
+ *                            (the paper's CellList, section 2.6);
+ *   4. the mapping         -> clm_map, which always returns the reduced
+ *                            result (map_pairwise, sections 2.3 and 2.7).
+ *
+ * Conventions
+ *  - Every function returns clm_status (0 = CLM_OK).  None throws, exits or
+ *    prints.  On an error the outputs are untouched and clm_last_error()
+ *    returns a thread-local message.
+ *  - Pointers named *_dev are device pointers on the context's device.  The
+ *    caller owns every device buffer, including the workspace; the library
+ *    never allocates device memory.  The library owns only the small host
+ *    handles (context, box, cell list).
+ *  - Device work is enqueued on the context's stream and the calls return
+ *    before it completes (clm_celllist_build, clm_map); results are valid
+ *    after clm_synchronize or any later stream-ordered event.
+ *  - Box matrices are row-major dim x dim: H[a*dim+b] is Cartesian component
+ *    a of lattice vector b, i.e. the lattice vectors are the COLUMNS of H
+ *    (the paper prints the unit cell this way, Code 3).  An orthorhombic box
+ *    is a diagonal H.
+ *  - Coordinates are row-major n x dim FP64 (the paper's (N,M) coordinate
+ *    matrices, section 2.4, stored particle by particle).  Indices in all
+ *    outputs are 0-based (the paper's listings are 1-based).
+ *  - The pair set is defined exactly (section 2.8 and the "minimum-image
+ *    convention" of section 2.3): particle positions are first wrapped into
+ *    the primary cell, s = Hinv r, w = floor(s), f = s - w (f = 0, w += 1 if
+ *    the subtraction rounds to 1), r' = H f; a pair's displacement for an
+ *    integer image K is D = (r'_j - r'_i) + H K, its squared distance
+ *    d2 = (D0*D0 + D1*D1) + D2*D2, every operation rounded on its own in
+ *    FP64 (no fused multiply-add; sums and products in the order written,
+ *    Hinv = adjugate / determinant).  A pair is in the set when the minimum
+ *    over K of d2 is <= rc2 = rc*rc.  Single set: unordered pairs i<j once;
+ *    cross set: every (i in x, j in y).  Both precisions return exactly this
+ *    set and these integer results.
+ */
+#ifndef CLMAP_H
+#define CLMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CLMAP_VERSION_MAJOR 0
+#define CLMAP_VERSION_MINOR 1
+
+typedef enum clm_status {
+  CLM_OK = 0,
+  CLM_E_INVALID_ARG = 1,  /* null pointer, bad size, bad enum value, ... */
+  CLM_E_BAD_BOX = 2,      /* dim not 2/3, non-finite H, det H <= 0, cell flatter than 1:64 */
+  CLM_E_BAD_CUTOFF = 3,   /* rc <= 0 or non-finite, lcell < 1 */
+  CLM_E_CAPACITY = 4,     /* (reserved: overflow is reported on the device, see clm_map_out) */
+  CLM_E_WORKSPACE = 5,    /* workspace missing, too small or misaligned */
+  CLM_E_DEVICE = 6,       /* a HIP call failed (message from the runtime) */
+  CLM_E_UNSUPPORTED = 7   /* valid request this library does not serve */
+} clm_status;
+
+typedef enum clm_precision {
+  CLM_FP64 = 0,       /* plain method: every distance in FP64, canonical */
+  CLM_FP32_GUARD = 1  /* FP32 coordinates and distances, FP64 accumulation;
+                         pairs whose FP32 squared distance lies within a
+                         rigorous error band of the cutoff (or of a histogram
+                         edge) are re-tested in canonical FP64, so the pair
+                         set and every integer output equal the FP64 ones. */
+} clm_precision;
+
+typedef enum clm_map_kind {
+  CLM_MAP_COUNT = 0,          /* number of pairs (paper section 2.8) */
+  CLM_MAP_SUM_D = 1,          /* sum of d (Code 1) */
+  CLM_MAP_SUM_INV_D = 2,      /* sum of 1/d (Code 5) */
+  CLM_MAP_LJ_E = 3,           /* Lennard-Jones energy u = 4 eps ((s/d)^12 - (s/d)^6) (Code 6) */
+  CLM_MAP_LJ_EF = 4,          /* LJ energy + forces (= -dE/dr, Code 7) + dE/dH [+ virial] */
+  CLM_MAP_LJ_ADJOINT = 5,     /* g * dE/dr and g * dE/dH for an upstream g (differentiation, section 3.3) */
+  CLM_MAP_HIST_DIST = 6,      /* histogram of d on (0, hi], right-closed bins (Code 10's rule) */
+  CLM_MAP_HIST_RELSPEED = 7,  /* histogram of |v_j - v_i| on (0, hi] + per-bin sums (Code 10) */
+  CLM_MAP_NEIGHBOR_LIST = 8   /* compacted list of pairs (i, j[, d]) (section 4.1) */
+} clm_map_kind;
+
+typedef struct clm_context clm_context;
+typedef struct clm_box clm_box;
+typedef struct clm_celllist clm_celllist;
+
+typedef struct clm_box_info {
+  int dim;
+  int lcell_requested;
+  int lcell;            /* effective: largest l <= requested with >= 2l+1 cells per axis */
+  int small_box;        /* 1: fewer than 3 cells on some axis -> brute-force minimum image */
+  int grid[3];          /* cells per fractional axis (1 on unused axes) */
+  int64_t ncells;
+  double H[9];          /* row-major dim x dim (stride dim) */
+  double Hinv[9];
+  double widths[3];     /* perpendicular widths of the cell (distance between opposite faces) */
+  double volume;
+  double cutoff;
+  double rc2;           /* fl(cutoff * cutoff), the membership threshold */
+  double guard_band;    /* absolute band on FP32 squared distances, see clm_precision */
+} clm_box_info;
+
+typedef struct clm_celllist_info {
+  int64_t n_x, n_y;
+  int64_t ncells;
+  int64_t ntiles;          /* work units of <= 64 particles */
+  int64_t nonempty_cells;  /* cells holding particles of x */
+  int64_t max_occupancy;   /* most particles in one cell (x or y) */
+  int64_t candidate_pairs; /* pairs the sweep tests (half shell; full shell for
+                              LJ_EF/LJ_ADJOINT and cross sets counts both) */
+} clm_celllist_info;
+
+typedef struct clm_map_params {
+  double sigma, epsilon;        /* LJ_* */
+  double near_factor;           /* FP32_GUARD LJ: pairs with d < near_factor*sigma are evaluated
+                                   in FP64 (0 -> 1.0; the repulsive wall loses FP32 accuracy) */
+  int want_virial;              /* LJ_EF: also the virial sum f_s D (x) D (costs ~6 FMAs/pair) */
+  const double* upstream_dev;   /* LJ_ADJOINT: device pointer to the upstream gradient g (1 double) */
+  int nbins;                    /* HIST_*: number of bins (1..1000) */
+  double hist_hi;               /* HIST_*: upper edge of the last bin */
+  const double* vel_x_dev;      /* HIST_RELSPEED: velocities of x, n_x*dim FP64 */
+  const double* vel_y_dev;      /* HIST_RELSPEED, cross set: velocities of y */
+  int want_sums;                /* HIST_RELSPEED: per-bin FP64 sum of |v_j - v_i| */
+  int64_t capacity;             /* NEIGHBOR_LIST: pair slots available in pairs_dev */
+  int with_distances;           /* NEIGHBOR_LIST: also write d (FP64) */
+} clm_map_params;
+
+typedef struct clm_map_out {
+  double* energy_dev;      /* [1] LJ energy; SUM_D / SUM_INV_D: the sum (FP64) */
+  double* forces_dev;      /* LJ_EF: -dE/dr, LJ_ADJOINT: g*dE/dr; n_x*dim FP64, original order */
+  double* virial_dev;      /* LJ_EF with want_virial: dim*dim FP64 */
+  double* grad_box_dev;    /* LJ_EF: dE/dH, LJ_ADJOINT: g*dE/dH (fixed Cartesian r); dim*dim */
+  uint64_t* hist_dev;      /* HIST_*: nbins+1 counts, the last slot counts values above hist_hi */
+  double* hist_sums_dev;   /* HIST_RELSPEED with want_sums: nbins FP64 */
+  int32_t* pairs_dev;      /* NEIGHBOR_LIST: capacity x 2 (i, j); single set i < j;
+                              cross set i indexes x and j indexes y; order unspecified */
+  double* dist_dev;        /* NEIGHBOR_LIST with with_distances: capacity FP64 */
+  uint64_t* count_dev;     /* [1] REQUIRED for every kind: number of pairs in the set.
+                              NEIGHBOR_LIST: if *count_dev > capacity only the first
+                              capacity pairs were written; re-call with a larger buffer. */
+} clm_map_out;
+
+/* Context: a device and the caller's stream (hipStream_t; NULL = default). */
+clm_status clm_context_create(int hip_device, void* hip_stream, clm_context** out);
+clm_status clm_context_set_stream(clm_context* ctx, void* hip_stream);
+clm_status clm_context_destroy(clm_context* ctx);
+
+/* Box (host only, no device work): H as above, cutoff rc > 0, lcell >= 1
+ * (cell side ~ rc/lcell, the paper's lcell, section 2.8). */
+clm_status clm_box_create(int dim, const double* H, double cutoff, int lcell, clm_box** out);
+/* Triclinic box from lengths (a, b, c) and angles in degrees (alpha =
+ * angle(b,c), beta = angle(a,c), gamma = angle(a,b)); a along x, b in xy. */
+clm_status clm_box_from_lengths_angles(const double* lengths, const double* angles_deg,
+                                       double cutoff, int lcell, clm_box** out);
+clm_status clm_box_info_get(const clm_box* box, clm_box_info* out);
+clm_status clm_box_destroy(clm_box* box);
+
+/* Cell list over n_x particles (and, for a cross set, n_y more; n_y = 0 for
+ * a single set).  The workspace (device memory, 256-byte aligned) holds the
+ * cell-sorted coordinates, the cell offsets, the work tiles and the map
+ * partials; query its size first. */
+clm_status clm_celllist_workspace_bytes(const clm_box* box, int64_t n_x, int64_t n_y,
+                                        clm_precision precision, size_t* bytes);
+clm_status clm_celllist_create(clm_context* ctx, const clm_box* box, int64_t n_x, int64_t n_y,
+                               clm_precision precision, void* workspace_dev,
+                               size_t workspace_bytes, clm_celllist** out);
+/* Bin the particles (async).  x_dev: n_x*dim FP64; y_dev: n_y*dim FP64 or
+ * NULL for a single set.  The inputs may be freed after the build. */
+clm_status clm_celllist_build(clm_celllist* cl, const double* x_dev, const double* y_dev);
+/* Map one kind over the pair set and reduce it (async). */
+clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* params,
+                   const clm_map_out* out);
+/* Host-side counters of the last build (synchronizes the stream). */
+clm_status clm_celllist_info_get(clm_celllist* cl, clm_celllist_info* out);
+clm_status clm_celllist_destroy(clm_celllist* cl);
+
+clm_status clm_synchronize(clm_context* ctx);
+const char* clm_last_error(void);
+const char* clm_status_string(clm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLMAP_H */

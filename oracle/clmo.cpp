@@ -450,6 +450,16 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
   std::vector<std::vector<Neumaier>> relsum_part;
 
   if (method == CLMO_METHOD_BRUTE) {
+    /* The nearest image of any displacement lies within half the sum of the
+     * lattice-vector lengths (round the fractional displacement), so no
+     * image beyond that reach can be the minimum. */
+    double sum_len = 0.0;
+    for (int b = 0; b < dim; ++b) {
+      double s2 = 0.0;
+      for (int a = 0; a < dim; ++a) s2 += B.h(a, b) * B.h(a, b);
+      sum_len += std::sqrt(s2);
+    }
+    const double reach = std::min(B.rc, 0.5 * sum_len * (1.0 + 1e-6));
     partial.assign(nx, Partial());
     relsum_part.assign(nx, std::vector<Neumaier>(nrel));
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
@@ -461,7 +471,7 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
       for (int64_t j = 0; j < nyy; ++j) {
         if (!cross && j == i) continue;
         double d2 = min_image(B, &C.xw[i * dim], &C.fx[i * dim], &yw[j * dim], &fy[j * dim],
-                              B.rc, D, K);
+                              reach, D, K);
         if (!(d2 <= B.rc2)) continue;
         if (grad) lj_grad_add(*req, dim, d2, D, g);
         if (cross || i < j) accumulate(C, partial[i], relsum_part[i], tid, i, j, d2, D, K);

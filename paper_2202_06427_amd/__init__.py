@@ -1,0 +1,298 @@
+"""Cell-list pair mapping on AMD MI355X (after CellListMap.jl, arXiv 2202.06427).
+
+Python binding over ``libclmap.so`` (include/clmap.h).  This module only
+marshals arguments: PyTorch provides device memory and the current stream;
+binning, the cell-pair sweep and every reduction run in the library's HIP
+kernels.  The user-facing steps mirror the paper (section 2.1): a ``Box``
+(geometry and cutoff, section 2.5), a ``CellList`` (section 2.6) and a map
+over the pairs within the cutoff that returns the reduced result (sections
+2.3 and 2.7), with the user's closure replaced by a fixed map kind.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import ClmError
+
+__all__ = ["Box", "CellList", "LJEnergy", "lj_energy", "ClmError"]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- contexts
+_contexts = {}
+
+
+def _context(device):
+    """The library context of a device, following torch's current stream."""
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    h = _contexts.get(idx)
+    if h is None:
+        h = ctypes.c_void_p()
+        L.check(L.lib().clm_context_create(idx, None, ctypes.byref(h)))
+        _contexts[idx] = h
+    L.check(L.lib().clm_context_set_stream(h, ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream)))
+    return h
+
+
+# ---------------------------------------------------------------- box
+class Box:
+    """Periodic box: H with the lattice vectors as columns (paper Code 3), a
+    cutoff, and lcell (cell side about cutoff/lcell, paper section 2.8)."""
+
+    def __init__(self, H, cutoff, lcell=2):
+        H = np.ascontiguousarray(np.asarray(H, dtype=np.float64))
+        if H.ndim != 2 or H.shape[0] != H.shape[1]:
+            raise ValueError("H must be a square matrix")
+        self.dim = H.shape[0]
+        self.H = H
+        self.cutoff = float(cutoff)
+        self.lcell_requested = int(lcell)
+        h = ctypes.c_void_p()
+        L.check(L.lib().clm_box_create(self.dim, H.ctypes.data_as(_dp), self.cutoff, int(lcell),
+                                       ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_lengths_angles(cls, lengths, angles_deg, cutoff, lcell=2):
+        la = np.ascontiguousarray(lengths, dtype=np.float64)
+        an = np.ascontiguousarray(angles_deg, dtype=np.float64)
+        h = ctypes.c_void_p()
+        L.check(L.lib().clm_box_from_lengths_angles(la.ctypes.data_as(_dp), an.ctypes.data_as(_dp),
+                                                    float(cutoff), int(lcell), ctypes.byref(h)))
+        b = cls.__new__(cls)
+        b._h = h
+        info = b.info()
+        b.dim = 3
+        b.H = np.array(info["H"])
+        b.cutoff = float(cutoff)
+        b.lcell_requested = int(lcell)
+        return b
+
+    def info(self):
+        bi = L.BoxInfo()
+        L.check(L.lib().clm_box_info_get(self._h, ctypes.byref(bi)))
+        d = bi.dim
+        return {
+            "dim": d, "lcell_requested": bi.lcell_requested, "lcell": bi.lcell,
+            "small_box": bool(bi.small_box), "grid": list(bi.grid[:d]), "ncells": bi.ncells,
+            "H": np.array(bi.H[: d * d]).reshape(d, d), "Hinv": np.array(bi.Hinv[: d * d]).reshape(d, d),
+            "widths": list(bi.widths[:d]), "volume": bi.volume, "cutoff": bi.cutoff, "rc2": bi.rc2,
+            "guard_band": bi.guard_band,
+        }
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and L._lib is not None:
+            L.lib().clm_box_destroy(h)
+            self._h = None
+
+
+def _as_coords(x, dim, name):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on a GPU")
+    if not x.is_cuda:
+        raise ValueError(f"{name} must live on a GPU")
+    if x.ndim != 2 or x.shape[1] != dim:
+        raise ValueError(f"{name} must have shape (n, {dim})")
+    return x.detach().to(torch.float64).contiguous()
+
+
+# ---------------------------------------------------------------- cell list
+class CellList:
+    """Cell list of one set (or of two sets x and y, paper section 3.2).
+
+    precision: "fp32" (FP32 coordinates and distances with FP64 guard bands
+    and FP64 accumulation) or "fp64" (plain method).  Results of every map
+    are torch tensors on the device, valid in stream order.
+    """
+
+    def __init__(self, x, box, y=None, precision="fp32"):
+        self.box = box
+        self.dim = box.dim
+        x = _as_coords(x, self.dim, "x")
+        self.device = x.device
+        self.nx = x.shape[0]
+        self.ny = 0 if y is None else int(y.shape[0])
+        self.cross = y is not None
+        if precision not in ("fp32", "fp64"):
+            raise ValueError("precision must be 'fp32' or 'fp64'")
+        self.precision = precision
+        p = L.CLM_FP32_GUARD if precision == "fp32" else L.CLM_FP64
+        nbytes = ctypes.c_size_t(0)
+        L.check(L.lib().clm_celllist_workspace_bytes(box._h, self.nx, self.ny, p, ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        raw = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        pad = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self._ws = raw[pad: pad + self.workspace_bytes]
+        ctx = _context(self.device)
+        h = ctypes.c_void_p()
+        L.check(L.lib().clm_celllist_create(ctx, box._h, self.nx, self.ny, p, _ptr(self._ws),
+                                            self.workspace_bytes, ctypes.byref(h)))
+        self._h = h
+        self.build(x, y)
+
+    def build(self, x, y=None):
+        """(Re)bin positions of the same sizes (paper section 2.6)."""
+        x = _as_coords(x, self.dim, "x")
+        if x.shape[0] != self.nx:
+            raise ValueError("x has a different particle count than this cell list")
+        yy = None
+        if self.cross:
+            if y is None:
+                raise ValueError("cross-set cell list needs y")
+            yy = _as_coords(y, self.dim, "y")
+            if yy.shape[0] != self.ny:
+                raise ValueError("y has a different particle count than this cell list")
+        _context(self.device)
+        L.check(L.lib().clm_celllist_build(self._h, _ptr(x), _ptr(yy)))
+        self._keep = (x, yy)  # inputs stay alive until the build has run
+        return self
+
+    def info(self):
+        ci = L.CellListInfo()
+        _context(self.device)
+        L.check(L.lib().clm_celllist_info_get(self._h, ctypes.byref(ci)))
+        return {k: getattr(ci, k) for k, _ in L.CellListInfo._fields_}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and L._lib is not None:
+            L.lib().clm_celllist_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------ maps
+    def _map(self, kind, params, out):
+        _context(self.device)
+        L.check(L.lib().clm_map(self._h, L.MAP_KINDS[kind], ctypes.byref(params), ctypes.byref(out)))
+
+    def _scalars(self):
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
+        c = torch.empty(1, dtype=torch.int64, device=self.device)
+        return e, c
+
+    def count(self):
+        """Number of pairs within the cutoff (device tensor, int64[1])."""
+        _, c = self._scalars()
+        o = L.MapOut(count_dev=_ptr(c))
+        self._map("count", L.MapParams(), o)
+        return c
+
+    def sum_d(self):
+        """Sum of d over the pairs (paper Code 1)."""
+        e, c = self._scalars()
+        self._map("sum_d", L.MapParams(), L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
+        return e, c
+
+    def sum_inv_d(self):
+        """Sum of 1/d over the pairs (paper Code 5)."""
+        e, c = self._scalars()
+        self._map("sum_inv_d", L.MapParams(), L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
+        return e, c
+
+    def lj_energy(self, sigma, epsilon, near_factor=1.0):
+        """Lennard-Jones energy 4 eps ((s/d)^12 - (s/d)^6) (paper Code 6)."""
+        e, c = self._scalars()
+        P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor)
+        self._map("lj_e", P, L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
+        return e, c
+
+    def lj_forces(self, sigma, epsilon, near_factor=1.0, virial=False):
+        """Energy, forces (-dE/dr, paper Code 7), dE/dH and optionally the virial."""
+        e, c = self._scalars()
+        f = torch.empty((self.nx, self.dim), dtype=torch.float64, device=self.device)
+        gb = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device)
+        w = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device) if virial else None
+        P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, want_virial=int(virial))
+        o = L.MapOut(energy_dev=_ptr(e), forces_dev=_ptr(f), grad_box_dev=_ptr(gb),
+                     virial_dev=_ptr(w), count_dev=_ptr(c))
+        self._map("lj_ef", P, o)
+        return {"energy": e, "forces": f, "grad_box": gb, "virial": w, "count": c}
+
+    def lj_adjoint(self, sigma, epsilon, upstream, near_factor=1.0):
+        """g dE/dr and g dE/dH for an upstream gradient g (device float64[1])."""
+        e, c = self._scalars()
+        up = upstream.detach().to(device=self.device, dtype=torch.float64).reshape(1).contiguous()
+        gx = torch.empty((self.nx, self.dim), dtype=torch.float64, device=self.device)
+        gb = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device)
+        P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, upstream_dev=_ptr(up))
+        o = L.MapOut(energy_dev=_ptr(e), forces_dev=_ptr(gx), grad_box_dev=_ptr(gb), count_dev=_ptr(c))
+        self._map("lj_adjoint", P, o)
+        self._keep_up = up
+        return gx, gb, e
+
+    def histogram(self, nbins, hi=None):
+        """Histogram of d on (0, hi] (right-closed bins, paper Code 10); the
+        last slot counts pairs beyond hi."""
+        hi = self.box.cutoff if hi is None else float(hi)
+        h = torch.empty(nbins + 1, dtype=torch.int64, device=self.device)
+        _, c = self._scalars()
+        P = L.MapParams(nbins=nbins, hist_hi=hi)
+        self._map("hist_dist", P, L.MapOut(hist_dev=_ptr(h), count_dev=_ptr(c)))
+        return h, c
+
+    def relspeed_histogram(self, v, nbins, hi, vy=None, sums=True):
+        """Histogram of |v_j - v_i| over the pairs and per-bin sums (paper Code 10)."""
+        vx = _as_coords(v, self.dim, "v")
+        vyy = _as_coords(vy, self.dim, "vy") if self.cross else None
+        h = torch.empty(nbins + 1, dtype=torch.int64, device=self.device)
+        s = torch.empty(nbins, dtype=torch.float64, device=self.device) if sums else None
+        _, c = self._scalars()
+        P = L.MapParams(nbins=nbins, hist_hi=float(hi), vel_x_dev=_ptr(vx), vel_y_dev=_ptr(vyy),
+                        want_sums=int(sums))
+        self._map("hist_relspeed", P, L.MapOut(hist_dev=_ptr(h), hist_sums_dev=_ptr(s), count_dev=_ptr(c)))
+        self._keep_v = (vx, vyy)
+        return h, s, c
+
+    def neighbor_list(self, capacity=None, distances=True):
+        """Pairs (i, j) within the cutoff (single set: i < j) and their d.
+
+        Synchronizes to read the pair count; grows the buffers and re-runs
+        when the capacity was too small."""
+        cap = int(capacity) if capacity is not None else max(1024, 64 * self.nx)
+        while True:
+            pairs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.device)
+            dist = torch.empty(max(cap, 1), dtype=torch.float64, device=self.device) if distances else None
+            _, c = self._scalars()
+            P = L.MapParams(capacity=cap, with_distances=int(distances))
+            self._map("neighbor_list", P, L.MapOut(pairs_dev=_ptr(pairs), dist_dev=_ptr(dist), count_dev=_ptr(c)))
+            n = int(c.item())
+            if n <= cap:
+                return pairs[:n], (dist[:n] if distances else None)
+            cap = n
+
+
+# ---------------------------------------------------------------- autograd
+class LJEnergy(torch.autograd.Function):
+    """E(x, H) = sum over pairs of 4 eps ((s/d)^12 - (s/d)^6); backward runs the
+    library's adjoint sweep (g dE/dx and g dE/dH at fixed Cartesian x)."""
+
+    @staticmethod
+    def forward(ctx, x, H, sigma, epsilon, cutoff, lcell=2, precision="fp32"):
+        Hn = H.detach().cpu().numpy() if isinstance(H, torch.Tensor) else np.asarray(H)
+        box = Box(Hn, cutoff, lcell)
+        cl = CellList(x.detach(), box, precision=precision)
+        e, _ = cl.lj_energy(sigma, epsilon)
+        ctx.cl = cl
+        ctx.params = (sigma, epsilon)
+        ctx.h_is_tensor = isinstance(H, torch.Tensor)
+        ctx.h_device = H.device if ctx.h_is_tensor else None
+        return e.reshape(())
+
+    @staticmethod
+    def backward(ctx, gE):
+        sigma, epsilon = ctx.params
+        gx, gb, _ = ctx.cl.lj_adjoint(sigma, epsilon, gE.reshape(1))
+        gH = gb.to(ctx.h_device) if (ctx.h_is_tensor and ctx.needs_input_grad[1]) else None
+        return gx, gH, None, None, None, None, None
+
+
+def lj_energy(x, H, sigma, epsilon, cutoff, lcell=2, precision="fp32"):
+    return LJEnergy.apply(x, H, sigma, epsilon, cutoff, lcell, precision)

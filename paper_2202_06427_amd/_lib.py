@@ -1,0 +1,117 @@
+"""ctypes mirror of include/clmap.h (argument marshalling only).
+
+Loads libclmap.so from this package directory and raises if it is missing:
+there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libclmap.so")
+
+# clm_status
+CLM_OK = 0
+STATUS_NAMES = {0: "CLM_OK", 1: "CLM_E_INVALID_ARG", 2: "CLM_E_BAD_BOX", 3: "CLM_E_BAD_CUTOFF",
+                4: "CLM_E_CAPACITY", 5: "CLM_E_WORKSPACE", 6: "CLM_E_DEVICE", 7: "CLM_E_UNSUPPORTED"}
+
+# clm_precision
+CLM_FP64 = 0
+CLM_FP32_GUARD = 1
+
+# clm_map_kind
+MAP_KINDS = {
+    "count": 0, "sum_d": 1, "sum_inv_d": 2, "lj_e": 3, "lj_ef": 4, "lj_adjoint": 5,
+    "hist_dist": 6, "hist_relspeed": 7, "neighbor_list": 8,
+}
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class BoxInfo(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("lcell_requested", ctypes.c_int), ("lcell", ctypes.c_int),
+        ("small_box", ctypes.c_int), ("grid", ctypes.c_int * 3), ("ncells", ctypes.c_int64),
+        ("H", ctypes.c_double * 9), ("Hinv", ctypes.c_double * 9), ("widths", ctypes.c_double * 3),
+        ("volume", ctypes.c_double), ("cutoff", ctypes.c_double), ("rc2", ctypes.c_double),
+        ("guard_band", ctypes.c_double),
+    ]
+
+
+class CellListInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_x", ctypes.c_int64), ("n_y", ctypes.c_int64), ("ncells", ctypes.c_int64),
+        ("ntiles", ctypes.c_int64), ("nonempty_cells", ctypes.c_int64),
+        ("max_occupancy", ctypes.c_int64), ("candidate_pairs", ctypes.c_int64),
+    ]
+
+
+class MapParams(ctypes.Structure):
+    _fields_ = [
+        ("sigma", ctypes.c_double), ("epsilon", ctypes.c_double), ("near_factor", ctypes.c_double),
+        ("want_virial", ctypes.c_int), ("upstream_dev", _vp), ("nbins", ctypes.c_int),
+        ("hist_hi", ctypes.c_double), ("vel_x_dev", _vp), ("vel_y_dev", _vp),
+        ("want_sums", ctypes.c_int), ("capacity", ctypes.c_int64), ("with_distances", ctypes.c_int),
+    ]
+
+
+class MapOut(ctypes.Structure):
+    _fields_ = [
+        ("energy_dev", _vp), ("forces_dev", _vp), ("virial_dev", _vp), ("grad_box_dev", _vp),
+        ("hist_dev", _vp), ("hist_sums_dev", _vp), ("pairs_dev", _vp), ("dist_dev", _vp),
+        ("count_dev", _vp),
+    ]
+
+
+EXPORTS = [
+    "clm_context_create", "clm_context_set_stream", "clm_context_destroy", "clm_box_create",
+    "clm_box_from_lengths_angles", "clm_box_info_get", "clm_box_destroy",
+    "clm_celllist_workspace_bytes", "clm_celllist_create", "clm_celllist_build", "clm_map",
+    "clm_celllist_info_get", "clm_celllist_destroy", "clm_synchronize", "clm_last_error",
+    "clm_status_string",
+]
+
+_lib = None
+
+
+class ClmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libclmap.so not built: {LIB_PATH} (run paper_2202_06427_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    c_int, c_i64, c_d = ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    pvp = ctypes.POINTER(_vp)
+    L.clm_context_create.argtypes = [c_int, _vp, pvp]
+    L.clm_context_set_stream.argtypes = [_vp, _vp]
+    L.clm_context_destroy.argtypes = [_vp]
+    L.clm_box_create.argtypes = [c_int, _dp, c_d, c_int, pvp]
+    L.clm_box_from_lengths_angles.argtypes = [_dp, _dp, c_d, c_int, pvp]
+    L.clm_box_info_get.argtypes = [_vp, ctypes.POINTER(BoxInfo)]
+    L.clm_box_destroy.argtypes = [_vp]
+    L.clm_celllist_workspace_bytes.argtypes = [_vp, c_i64, c_i64, c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.clm_celllist_create.argtypes = [_vp, _vp, c_i64, c_i64, c_int, _vp, ctypes.c_size_t, pvp]
+    L.clm_celllist_build.argtypes = [_vp, _vp, _vp]
+    L.clm_map.argtypes = [_vp, c_int, ctypes.POINTER(MapParams), ctypes.POINTER(MapOut)]
+    L.clm_celllist_info_get.argtypes = [_vp, ctypes.POINTER(CellListInfo)]
+    L.clm_celllist_destroy.argtypes = [_vp]
+    L.clm_synchronize.argtypes = [_vp]
+    L.clm_last_error.restype = ctypes.c_char_p
+    L.clm_status_string.restype = ctypes.c_char_p
+    L.clm_status_string.argtypes = [c_int]
+    for name in EXPORTS:
+        getattr(L, name).restype = getattr(L, name).restype if name in ("clm_last_error", "clm_status_string") else c_int
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != CLM_OK:
+        raise ClmError(status, lib().clm_last_error().decode(errors="replace"))

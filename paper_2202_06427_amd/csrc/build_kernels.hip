@@ -1,0 +1,386 @@
+// build_kernels.hip -- cell-list construction on gfx950 (paper section 2.6:
+// particles assigned to cells by their coordinates, with a contiguous copy of
+// every cell's coordinates; section 2.8: cell side = cutoff / lcell).
+//
+// The build is a counting sort in HBM:
+//   bin      one thread per particle: canonical FP64 wrap into the primary
+//            cell, fractional cell index, rank = atomicAdd(count[cell])
+//   scan     exclusive prefix of the counts -> cell offsets
+//   tiles    one thread per cell row: greedy work units of <= 64 particles
+//   scatter  one thread per particle: FP32 cell-local offset, FP64 wrapped
+//            position, original index and wrap integers at offset+rank
+// Every kernel is HBM- or latency-bound; nothing here is a dense contraction.
+#include "clmap_internal.h"
+
+namespace clm {
+
+// Canonical wrap of one position (definitions in clmap.h).  Non-finite or
+// absurdly large inputs are clamped so that every index stays in bounds.
+__device__ __forceinline__ void wrap_one(const BuildGeom& g, const double* __restrict__ r,
+                                         double* f, int* w, double* rw) {
+  const int dim = g.dim;
+  double s[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      double acc = g.Hinv[a * 3 + 0] * r[0];
+      acc = acc + g.Hinv[a * 3 + 1] * r[1];
+      if (dim == 3) acc = acc + g.Hinv[a * 3 + 2] * r[2];
+      s[a] = acc;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      double fl = floor(s[a]);
+      double fa = s[a] - fl;
+      if (fa >= 1.0) {
+        fa = 0.0;
+        fl = fl + 1.0;
+      }
+      if (!(fa >= 0.0 && fa < 1.0)) fa = 0.0;              // NaN input
+      if (!(fl > -1073741824.0 && fl < 1073741824.0)) fl = 0.0;  // out of int range
+      f[a] = fa;
+      w[a] = (int)fl;
+    } else {
+      f[a] = 0.0;
+      w[a] = 0;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      double acc = g.H[a * 3 + 0] * f[0];
+      acc = acc + g.H[a * 3 + 1] * f[1];
+      if (dim == 3) acc = acc + g.H[a * 3 + 2] * f[2];
+      rw[a] = acc;
+    } else {
+      rw[a] = 0.0;
+    }
+  }
+}
+
+__device__ __forceinline__ void cell_of(const BuildGeom& g, const double* f, int* c) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a < g.dim) {
+      int k = (int)(f[a] * (double)g.n[a]);
+      c[a] = k >= g.n[a] ? g.n[a] - 1 : (k < 0 ? 0 : k);
+    } else {
+      c[a] = 0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) bin_kernel(const double* __restrict__ x, int n, BuildGeom g,
+                                                  uint32_t* __restrict__ count,
+                                                  uint32_t* __restrict__ cell,
+                                                  uint32_t* __restrict__ rank) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double r[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < g.dim; ++a) r[a] = x[(size_t)i * g.dim + a];
+  double f[3], rw[3];
+  int w[3], c[3];
+  wrap_one(g, r, f, w, rw);
+  cell_of(g, f, c);
+  uint32_t lin = (uint32_t)(c[0] + g.n[0] * (c[1] + g.n[1] * c[2]));
+  cell[i] = lin;
+  rank[i] = atomicAdd(&count[lin], 1u);
+}
+
+__global__ void __launch_bounds__(256) scatter_kernel(
+    const double* __restrict__ x, int n, BuildGeom g, const uint32_t* __restrict__ off,
+    const uint32_t* __restrict__ cell, const uint32_t* __restrict__ rank, float4* __restrict__ pos,
+    double4* __restrict__ r64, uint32_t* __restrict__ idx, int4* __restrict__ wrap) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double r[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < g.dim; ++a) r[a] = x[(size_t)i * g.dim + a];
+  double f[3], rw[3];
+  int w[3], c[3];
+  wrap_one(g, r, f, w, rw);
+  cell_of(g, f, c);
+  // cell origin H (c / n) in FP64, then the FP32 offset from it
+  double u[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) u[b] = (double)c[b] / (double)g.n[b];
+  float o[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double O = g.H[a * 3 + 0] * u[0] + g.H[a * 3 + 1] * u[1] + g.H[a * 3 + 2] * u[2];
+    o[a] = a < g.dim ? (float)(rw[a] - O) : 0.0f;
+  }
+  uint32_t dst = off[cell[i]] + rank[i];
+  pos[dst] = make_float4(o[0], o[1], o[2], 0.0f);
+  r64[dst] = make_double4(rw[0], rw[1], rw[2], 0.0);
+  idx[dst] = (uint32_t)i;
+  wrap[dst] = make_int4(w[0], w[1], w[2], 0);
+}
+
+// ---------------------------------------------------------------- scan
+// Exclusive prefix of n uint32 counts into out[0..n] (out[n] = total).
+// Three phases: per-block sums, one-block scan of the sums, per-block apply.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanChunk = kScanThreads * kScanPer;
+
+// Exclusive scan across the block; *total receives the block sum.  Every
+// thread of the block must call it (it contains barriers).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+  constexpr int kWaves = kScanThreads / kWave;
+  __shared__ uint32_t wsum[kWaves];
+  __shared__ uint32_t wpre[kWaves];
+  __shared__ uint32_t tot;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t t = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += t;
+  }
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int k = 0; k < kWaves; ++k) {
+      wpre[k] = s;
+      s += wsum[k];
+    }
+    tot = s;
+  }
+  __syncthreads();
+  uint32_t res = wpre[wid] + incl - v;
+  *total = tot;
+  __syncthreads();  // the shared slots are reused by the next call
+  return res;
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(const uint32_t* __restrict__ in,
+                                                                 int n, uint32_t* __restrict__ sums) {
+  const size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * kScanPer;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k)
+    if (base + k < (size_t)n) s += in[base + k];
+  __shared__ uint32_t red[kScanThreads / kWave];
+  for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int k = 0; k < kScanThreads / kWave; ++k) t += red[k];
+    sums[blockIdx.x] = t;
+  }
+}
+
+// One block: exclusive scan of nb block sums in place (chunks of 1024).
+__global__ void __launch_bounds__(kScanThreads) scan_top_kernel(uint32_t* __restrict__ sums, int nb) {
+  uint32_t carry = 0;
+  for (int base = 0; base < nb; base += kScanThreads) {
+    int i = base + threadIdx.x;
+    uint32_t v = i < nb ? sums[i] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(v, &tot);
+    if (i < nb) sums[i] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const uint32_t* __restrict__ in,
+                                                                  int n,
+                                                                  const uint32_t* __restrict__ sums,
+                                                                  uint32_t* __restrict__ out) {
+  const size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = base + k < (size_t)n ? in[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t ex = block_excl_scan(s, &tot) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < (size_t)n) out[base + k] = ex;
+    ex += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = sums[blockIdx.x] + tot;
+}
+
+// ---------------------------------------------------------------- tiles
+// One thread per cell row (cy, cz): greedy tiles of consecutive sorted
+// particles, whole cells only, <= 64 particles and <= smax cells; a cell with
+// more than 64 particles is split into chunks of 64.
+template <bool EMIT>
+__device__ uint32_t walk_row(const uint32_t* __restrict__ off, const TileGeom& g, int row,
+                             Tile* __restrict__ tiles, uint32_t t0) {
+  const int nx = g.n[0];
+  const uint32_t* o = off + (size_t)row * nx;
+  uint32_t nt = 0;
+  int cx = 0;
+  while (cx < nx) {
+    uint32_t a = o[cx], b = o[cx + 1];
+    uint32_t cnt = b - a;
+    if (cnt == 0) { ++cx; continue; }
+    if (cnt > (uint32_t)kTileMax) {
+      for (uint32_t s = a; s < b; s += kTileMax) {
+        if (EMIT && t0 + nt < g.max_tiles) {
+          uint32_t c = b - s < (uint32_t)kTileMax ? b - s : (uint32_t)kTileMax;
+          tiles[t0 + nt] = Tile{s, (uint32_t)row, (uint16_t)c, (uint16_t)cx, (uint16_t)cx, (uint16_t)g.job};
+        }
+        ++nt;
+      }
+      ++cx;
+      continue;
+    }
+    const int c0 = cx;
+    int last = cx;
+    uint32_t tcount = cnt;
+    ++cx;
+    while (cx < nx && cx - c0 < g.smax) {
+      uint32_t c2 = o[cx + 1] - o[cx];
+      if (c2 == 0) { ++cx; continue; }
+      if (tcount + c2 > (uint32_t)kTileMax) break;
+      tcount += c2;
+      last = cx;
+      ++cx;
+    }
+    if (EMIT && t0 + nt < g.max_tiles)
+      tiles[t0 + nt] = Tile{a, (uint32_t)row, (uint16_t)tcount, (uint16_t)c0, (uint16_t)last, (uint16_t)g.job};
+    ++nt;
+    cx = last + 1;
+  }
+  return nt;
+}
+
+__global__ void __launch_bounds__(256) tiles_count_kernel(const uint32_t* __restrict__ off, TileGeom g,
+                                                          uint32_t* __restrict__ row_tiles) {
+  int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= g.nrows) return;
+  row_tiles[row] = walk_row<false>(off, g, row, nullptr, 0);
+}
+
+__global__ void __launch_bounds__(256) tiles_emit_kernel(const uint32_t* __restrict__ off, TileGeom g,
+                                                         const uint32_t* __restrict__ row_off,
+                                                         Tile* __restrict__ tiles) {
+  int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= g.nrows) return;
+  walk_row<true>(off, g, row, tiles, row_off[row]);
+}
+
+// ---------------------------------------------------------------- small helpers
+__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long long v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void fill_f64_kernel(double* p, size_t n, double v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Sorted FP32 copy of the velocities and the largest |component| (as float
+// bits; all values are >= 0 so the unsigned order is the float order).
+__global__ void __launch_bounds__(256) gather_vel_kernel(const double* __restrict__ v, int dim,
+                                                         const uint32_t* __restrict__ idx, int n,
+                                                         float4* __restrict__ v32,
+                                                         unsigned int* __restrict__ vmax_bits) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  float m = 0.0f;
+  if (s < n) {
+    uint32_t i = idx[s];
+    float c[3] = {0.0f, 0.0f, 0.0f};
+    for (int a = 0; a < dim; ++a) {
+      double va = v[(size_t)i * dim + a];
+      c[a] = (float)va;
+      double av = fabs(va);
+      // round the magnitude up so that the bound covers the FP64 value
+      float af = (float)av;
+      if ((double)af < av) af = __int_as_float(__float_as_int(af) + 1);
+      if (!(af <= 3.0e38f)) af = 3.0e38f;
+      m = fmaxf(m, af);
+    }
+    v32[s] = make_float4(c[0], c[1], c[2], 0.0f);
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0 && m > 0.0f) atomicMax(vmax_bits, __float_as_uint(m));
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned grid_for(size_t n, int block) {
+  size_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (unsigned)g;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  fill_u32_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  fill_u64_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  fill_f64_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const double* x, int n, const BuildGeom& g, uint32_t* count, uint32_t* cell,
+                      uint32_t* rank, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  bin_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, n, g, count, cell, rank);
+  return hipGetLastError();
+}
+
+size_t scan_scratch_elems(int n) { return (size_t)(n + kScanChunk - 1) / kScanChunk + 1; }
+
+hipError_t launch_scan(const uint32_t* in, int n, uint32_t* sums, uint32_t* out, hipStream_t s) {
+  int nb = (n + kScanChunk - 1) / kScanChunk;
+  if (nb < 1) nb = 1;
+  scan_sums_kernel<<<nb, kScanThreads, 0, s>>>(in, n, sums);
+  scan_top_kernel<<<1, kScanThreads, 0, s>>>(sums, nb);
+  scan_apply_kernel<<<nb, kScanThreads, 0, s>>>(in, n, sums, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const double* x, int n, const BuildGeom& g, const uint32_t* off,
+                          const uint32_t* cell, const uint32_t* rank, float4* pos, double4* r64,
+                          uint32_t* idx, int4* wrap, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  scatter_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, n, g, off, cell, rank, pos, r64, idx, wrap);
+  return hipGetLastError();
+}
+
+hipError_t launch_tiles(const uint32_t* off, const TileGeom& g, uint32_t* row_tiles,
+                        uint32_t* row_off, uint32_t* scan_scratch, Tile* tiles, hipStream_t s) {
+  const int nb = (g.nrows + 255) / 256;
+  tiles_count_kernel<<<nb, 256, 0, s>>>(off, g, row_tiles);
+  hipError_t e = launch_scan(row_tiles, g.nrows, scan_scratch, row_off, s);
+  if (e != hipSuccess) return e;
+  tiles_emit_kernel<<<nb, 256, 0, s>>>(off, g, row_off, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_vel(const double* v, int dim, const uint32_t* idx, int n, float4* v32,
+                             unsigned int* vmax_bits, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  gather_vel_kernel<<<(n + 255) / 256, 256, 0, s>>>(v, dim, idx, n, v32, vmax_bits);
+  return hipGetLastError();
+}
+
+}  // namespace clm

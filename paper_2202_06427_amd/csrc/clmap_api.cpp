@@ -1,0 +1,833 @@
+// clmap_api.cpp -- the C-ABI of libclmap.so (declared in include/clmap.h).
+//
+// Host side only: argument validation, FP64 box geometry, workspace carving
+// and kernel launches on the caller's stream.  Every device buffer belongs
+// to the caller; this file never allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/clmap.h"
+#include "clmap_internal.h"
+
+using namespace clm;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static clm_status fail(clm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static clm_status fail(clm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define CLM_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(CLM_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));         \
+  } while (0)
+
+// ---------------------------------------------------------------- objects
+struct clm_context {
+  int device;
+  hipStream_t stream;
+};
+
+struct clm_box {
+  int dim;
+  int lcell_req, lcell;
+  int small;
+  int n[3];
+  int64_t ncells;
+  int smax;
+  double H[9];     // stride 3
+  double Hinv[9];  // stride 3
+  double w[3];
+  double V;
+  double rc, rc2;
+  double band;
+  float lo32, hi32;
+  double tK[27 * 4];
+  double sum_len;   // sum of the lattice-vector lengths
+};
+
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+struct SetBufs {
+  uint32_t* count = nullptr;  // ncells
+  uint32_t* off = nullptr;    // ncells + 1
+  uint32_t* cell = nullptr;   // n
+  uint32_t* rank = nullptr;   // n
+  float4* pos = nullptr;      // n + pad
+  double4* r64 = nullptr;
+  uint32_t* idx = nullptr;
+  int4* wrap = nullptr;
+  float4* vel32 = nullptr;
+};
+
+struct clm_celllist {
+  clm_context* ctx;
+  clm_box box;
+  int64_t nx, ny;
+  int cross;
+  clm_precision prec;
+  char* ws;
+  size_t ws_bytes;
+  SetBufs X, Y;
+  uint32_t* scan_scratch;
+  uint32_t* row_tiles;
+  uint32_t* row_off;      // nrows + 1; row_off[nrows] = number of tiles
+  Tile* tiles;
+  int max_tiles;
+  int nrows;
+  JobDesc* job_dev;
+  double* partials;
+  unsigned long long* pcount;
+  int max_parts;
+  double* E64;
+  float* E32;
+  double* bandq;
+  unsigned int* vmax_bits;
+  unsigned long long* nl_counter;
+  unsigned long long* cand;
+  int built;
+};
+
+// ---------------------------------------------------------------- geometry
+// Canonical inverse: adjugate / determinant, every operation rounded on its
+// own in the order written (the same definition the CPU oracle implements).
+static int box_inverse(int dim, const double* H, double* Hi /* stride 3 */) {
+  if (dim == 2) {
+    const double H00 = H[0], H01 = H[1], H10 = H[3], H11 = H[4];
+    double det = H00 * H11 - H01 * H10;
+    if (!(det > 0.0) || !std::isfinite(det)) return 0;
+    Hi[0] = H11 / det;
+    Hi[1] = -H01 / det;
+    Hi[3] = -H10 / det;
+    Hi[4] = H00 / det;
+    return 1;
+  }
+  const double H00 = H[0], H01 = H[1], H02 = H[2];
+  const double H10 = H[3], H11 = H[4], H12 = H[5];
+  const double H20 = H[6], H21 = H[7], H22 = H[8];
+  const double C00 = H11 * H22 - H12 * H21;
+  const double C01 = H12 * H20 - H10 * H22;
+  const double C02 = H10 * H21 - H11 * H20;
+  const double C10 = H02 * H21 - H01 * H22;
+  const double C11 = H00 * H22 - H02 * H20;
+  const double C12 = H01 * H20 - H00 * H21;
+  const double C20 = H01 * H12 - H02 * H11;
+  const double C21 = H02 * H10 - H00 * H12;
+  const double C22 = H00 * H11 - H01 * H10;
+  double det = (H00 * C00 + H01 * C01) + H02 * C02;
+  if (!(det > 0.0) || !std::isfinite(det)) return 0;
+  Hi[0] = C00 / det; Hi[1] = C10 / det; Hi[2] = C20 / det;
+  Hi[3] = C01 / det; Hi[4] = C11 / det; Hi[5] = C21 / det;
+  Hi[6] = C02 / det; Hi[7] = C12 / det; Hi[8] = C22 / det;
+  return 1;
+}
+
+static float round_down_f(double v) {
+  float f = (float)v;
+  if ((double)f > v) f = std::nextafter(f, -INFINITY);
+  return f;
+}
+static float round_up_f(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = std::nextafter(f, INFINITY);
+  return f;
+}
+
+static constexpr int64_t kMaxCells = int64_t(1) << 24;
+
+static clm_status box_setup(int dim, const double* Hin, double cutoff, int lcell, clm_box* B) {
+  if (dim != 2 && dim != 3) return fail(CLM_E_BAD_BOX, "dim must be 2 or 3 (got %d)", dim);
+  if (!Hin) return fail(CLM_E_INVALID_ARG, "H is NULL");
+  if (!(cutoff > 0.0) || !std::isfinite(cutoff))
+    return fail(CLM_E_BAD_CUTOFF, "cutoff must be finite and > 0");
+  if (lcell < 1 || lcell > 8) return fail(CLM_E_BAD_CUTOFF, "lcell must be in 1..8 (got %d)", lcell);
+  std::memset(B, 0, sizeof *B);
+  B->dim = dim;
+  for (int a = 0; a < dim; ++a)
+    for (int b = 0; b < dim; ++b) {
+      double v = Hin[a * dim + b];
+      if (!std::isfinite(v)) return fail(CLM_E_BAD_BOX, "H has a non-finite entry");
+      B->H[a * 3 + b] = v;
+    }
+  if (!box_inverse(dim, B->H, B->Hinv))
+    return fail(CLM_E_BAD_BOX, "det H must be > 0 (right-handed, non-degenerate cell)");
+  // sum of the lattice-vector lengths: bounds every minimum-image distance
+  // by half of it; cells flatter than 1:64 are rejected
+  double sum_len = 0.0;
+  for (int b = 0; b < dim; ++b) {
+    double s2 = 0.0;
+    for (int a = 0; a < dim; ++a) s2 += B->H[a * 3 + b] * B->H[a * 3 + b];
+    sum_len += std::sqrt(s2);
+  }
+  B->sum_len = sum_len;
+  // perpendicular widths: 1 / |row d of Hinv| (distance between the faces
+  // spanned by the other lattice vectors); volume |det H|
+  for (int d = 0; d < dim; ++d) {
+    double s = 0.0;
+    for (int b = 0; b < dim; ++b) s += B->Hinv[d * 3 + b] * B->Hinv[d * 3 + b];
+    B->w[d] = 1.0 / std::sqrt(s);
+  }
+  {
+    double wmin = B->w[0];
+    for (int d = 1; d < dim; ++d) wmin = std::min(wmin, B->w[d]);
+    if (!(sum_len <= 64.0 * wmin))
+      return fail(CLM_E_BAD_BOX, "cell too flat or skewed (sum of edge lengths > 64 x smallest width)");
+  }
+  if (dim == 2)
+    B->V = std::fabs(B->H[0] * B->H[4] - B->H[1] * B->H[3]);
+  else {
+    const double* H = B->H;
+    B->V = std::fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                     H[2] * (H[3] * H[7] - H[4] * H[6]));
+  }
+  B->rc = cutoff;
+  B->rc2 = cutoff * cutoff;
+  B->lcell_req = lcell;
+  for (int a = 0; a < 3; ++a) B->n[a] = 1;
+  // grid: cells of fractional width 1/n_d with w_d / n_d >= (rc / l)(1 + 1e-9),
+  // at least 2l+1 cells per axis (so the +-l neighbours are distinct cells)
+  B->small = 1;
+  for (int l = lcell; l >= 1; --l) {
+    int n[3] = {1, 1, 1};
+    bool ok = true;
+    double prod = 1.0;
+    for (int d = 0; d < dim; ++d) {
+      double m = std::floor(B->w[d] * (double)l / cutoff / (1.0 + 1e-9));
+      if (!(m >= 2.0 * l + 1.0)) { ok = false; break; }
+      if (m > 65535.0) m = 65535.0;
+      n[d] = (int)m;
+      prod *= m;
+    }
+    if (!ok) continue;
+    if (prod > (double)kMaxCells) {  // coarser cells stay correct (side >= rc/l)
+      double f = std::pow((double)kMaxCells / prod, 1.0 / dim);
+      prod = 1.0;
+      for (int d = 0; d < dim; ++d) {
+        n[d] = std::max(2 * l + 1, (int)std::floor(n[d] * f));
+        prod *= n[d];
+      }
+      if (prod > (double)kMaxCells) continue;
+    }
+    B->lcell = l;
+    B->small = 0;
+    for (int d = 0; d < dim; ++d) B->n[d] = n[d];
+    break;
+  }
+  if (B->small) B->lcell = 1;
+  B->ncells = (int64_t)B->n[0] * B->n[1] * B->n[2];
+  B->smax = std::max(1, std::min(kMaxSpan, B->n[0] - 2 * B->lcell));
+  // canonical image shifts t = H K for K in {-1,0,1}^3
+  for (int kz = -1; kz <= 1; ++kz)
+    for (int ky = -1; ky <= 1; ++ky)
+      for (int kx = -1; kx <= 1; ++kx) {
+        const double K[3] = {(double)kx, (double)ky, (double)kz};
+        double* t = &B->tK[kcode(kx, ky, kz) * 4];
+        for (int a = 0; a < 3; ++a) {
+          if (a >= dim) { t[a] = 0.0; continue; }
+          double acc = B->H[a * 3 + 0] * K[0];
+          acc = acc + B->H[a * 3 + 1] * K[1];
+          if (dim == 3) acc = acc + B->H[a * 3 + 2] * K[2];
+          t[a] = acc;
+        }
+        t[3] = 0.0;
+      }
+  // FP32 error band.  The FP32 displacement is D32 = fl32(o_j - q_i) with
+  // o_j = fl32(offset of j from its cell origin, |o_j,a| <= C_a, the
+  // Cartesian extent of one cell along a) and q_i = fl32(r'_i - O_u) (one
+  // rounding of an FP64 value with |q_a| <= C_a + |D_a|).  Three roundings
+  // of relative size u = 2^-24 give, per component,
+  //   |D32_a - D_a| <= u (2 C_a + 2 |D_a|) + e64,
+  // e64 covering the FP64 roundings of r', of the cell origins and of the
+  // canonical d2 itself.  Near any threshold X <= rc^2 a candidate has
+  // |D| <= 1.01 rc (a farther one has d2_32 > rc^2 whatever the rounding),
+  // so |d2_32 - d2| <= 2 (1.01 rc) |E| + |E|^2 + 4 u (1.02 rc^2) for the
+  // FMA chain of three roundings.  The band is twice that bound.
+  const double u = std::ldexp(1.0, -24);
+  double E2 = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    double C = 0.0, Hs = 0.0;
+    for (int b = 0; b < dim; ++b) {
+      C += std::fabs(B->H[a * 3 + b]) / (double)B->n[b];
+      Hs += std::fabs(B->H[a * 3 + b]);
+    }
+    double e64 = 64.0 * std::ldexp(1.0, -53) * (4.0 * Hs + 4.0 * cutoff);
+    double Ea = u * (2.0 * C + 2.02 * cutoff) * (1.0 + 1e-6) + e64;
+    E2 += Ea * Ea;
+  }
+  const double E = std::sqrt(E2);
+  const double b0 = 2.02 * cutoff * E + E2 + 4.08 * u * B->rc2 + 1e-12 * B->rc2;
+  B->band = 2.0 * b0;
+  B->lo32 = round_down_f(B->rc2 - B->band);
+  B->hi32 = round_up_f(B->rc2 + B->band);
+  return CLM_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+static const int kPadParticles = 64;
+
+static int64_t max_tiles_for(const clm_box& B, int64_t n) {
+  int64_t nrows = (int64_t)B.n[1] * B.n[2];
+  int64_t t = 5 * ((n + 63) / 64) + nrows * ((B.n[0] + B.smax - 1) / B.smax + 2) + 4;
+  return (t + 3) & ~(int64_t)3;
+}
+
+static void layout(clm_celllist* cl, char* base, size_t* total) {
+  const clm_box& B = cl->box;
+  Carve c;
+  auto set = [&](SetBufs& S, int64_t n) {
+    size_t o_count = c.take(sizeof(uint32_t) * B.ncells);
+    size_t o_off = c.take(sizeof(uint32_t) * (B.ncells + 1));
+    size_t o_cell = c.take(sizeof(uint32_t) * n);
+    size_t o_rank = c.take(sizeof(uint32_t) * n);
+    size_t o_pos = c.take(sizeof(float4) * (n + kPadParticles));
+    size_t o_r64 = c.take(sizeof(double4) * (n + kPadParticles));
+    size_t o_idx = c.take(sizeof(uint32_t) * (n + kPadParticles));
+    size_t o_wrap = c.take(sizeof(int4) * (n + kPadParticles));
+    size_t o_vel = c.take(sizeof(float4) * (n + kPadParticles));
+    if (base) {
+      S.count = (uint32_t*)(base + o_count);
+      S.off = (uint32_t*)(base + o_off);
+      S.cell = (uint32_t*)(base + o_cell);
+      S.rank = (uint32_t*)(base + o_rank);
+      S.pos = (float4*)(base + o_pos);
+      S.r64 = (double4*)(base + o_r64);
+      S.idx = (uint32_t*)(base + o_idx);
+      S.wrap = (int4*)(base + o_wrap);
+      S.vel32 = (float4*)(base + o_vel);
+    }
+  };
+  set(cl->X, cl->nx);
+  if (cl->cross) set(cl->Y, cl->ny);
+  const int nrows = (int)(B.n[1] * B.n[2]);
+  const int64_t maxt = max_tiles_for(B, cl->nx);
+  const int64_t brute_blocks = (cl->nx + 255) / 256 + 1;
+  const int64_t parts = std::max<int64_t>(maxt, brute_blocks);
+  const size_t scan_elems =
+      std::max(scan_scratch_elems((int)std::max<int64_t>(B.ncells, 1)), scan_scratch_elems(nrows));
+  size_t o_scan = c.take(sizeof(uint32_t) * scan_elems);
+  size_t o_rt = c.take(sizeof(uint32_t) * (nrows + 1));
+  size_t o_ro = c.take(sizeof(uint32_t) * (nrows + 1));
+  size_t o_tiles = c.take(sizeof(Tile) * maxt);
+  size_t o_job = c.take(sizeof(JobDesc));
+  size_t o_part = c.take(sizeof(double) * kPartialD * parts);
+  size_t o_pc = c.take(sizeof(unsigned long long) * parts);
+  size_t o_E64 = c.take(sizeof(double) * (kMaxBins + 1));
+  size_t o_E32 = c.take(sizeof(float) * (kMaxBins + 1));
+  size_t o_bq = c.take(sizeof(double) * 2);
+  size_t o_vm = c.take(sizeof(unsigned int) * 2);
+  size_t o_nlc = c.take(sizeof(unsigned long long) * 2);
+  size_t o_cand = c.take(sizeof(unsigned long long) * maxt);
+  if (base) {
+    cl->scan_scratch = (uint32_t*)(base + o_scan);
+    cl->row_tiles = (uint32_t*)(base + o_rt);
+    cl->row_off = (uint32_t*)(base + o_ro);
+    cl->tiles = (Tile*)(base + o_tiles);
+    cl->job_dev = (JobDesc*)(base + o_job);
+    cl->partials = (double*)(base + o_part);
+    cl->pcount = (unsigned long long*)(base + o_pc);
+    cl->E64 = (double*)(base + o_E64);
+    cl->E32 = (float*)(base + o_E32);
+    cl->bandq = (double*)(base + o_bq);
+    cl->vmax_bits = (unsigned int*)(base + o_vm);
+    cl->nl_counter = (unsigned long long*)(base + o_nlc);
+    cl->cand = (unsigned long long*)(base + o_cand);
+    cl->max_tiles = (int)maxt;
+    cl->max_parts = (int)parts;
+    cl->nrows = nrows;
+  }
+  *total = c.off;
+}
+
+// ---------------------------------------------------------------- API
+extern "C" {
+
+const char* clm_last_error(void) { return g_err.c_str(); }
+
+const char* clm_status_string(clm_status s) {
+  switch (s) {
+    case CLM_OK: return "CLM_OK";
+    case CLM_E_INVALID_ARG: return "CLM_E_INVALID_ARG";
+    case CLM_E_BAD_BOX: return "CLM_E_BAD_BOX";
+    case CLM_E_BAD_CUTOFF: return "CLM_E_BAD_CUTOFF";
+    case CLM_E_CAPACITY: return "CLM_E_CAPACITY";
+    case CLM_E_WORKSPACE: return "CLM_E_WORKSPACE";
+    case CLM_E_DEVICE: return "CLM_E_DEVICE";
+    case CLM_E_UNSUPPORTED: return "CLM_E_UNSUPPORTED";
+  }
+  return "unknown status";
+}
+
+clm_status clm_context_create(int hip_device, void* hip_stream, clm_context** out) {
+  if (!out) return fail(CLM_E_INVALID_ARG, "out is NULL");
+  int ndev = 0;
+  CLM_HIP(hipGetDeviceCount(&ndev));
+  if (hip_device < 0 || hip_device >= ndev)
+    return fail(CLM_E_INVALID_ARG, "device %d out of range (%d devices)", hip_device, ndev);
+  auto* c = new (std::nothrow) clm_context;
+  if (!c) return fail(CLM_E_INVALID_ARG, "out of host memory");
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return CLM_OK;
+}
+
+clm_status clm_context_set_stream(clm_context* ctx, void* hip_stream) {
+  if (!ctx) return fail(CLM_E_INVALID_ARG, "ctx is NULL");
+  ctx->stream = (hipStream_t)hip_stream;
+  return CLM_OK;
+}
+
+clm_status clm_context_destroy(clm_context* ctx) {
+  delete ctx;
+  return CLM_OK;
+}
+
+clm_status clm_box_create(int dim, const double* H, double cutoff, int lcell, clm_box** out) {
+  if (!out) return fail(CLM_E_INVALID_ARG, "out is NULL");
+  clm_box tmp;
+  clm_status s = box_setup(dim, H, cutoff, lcell, &tmp);
+  if (s != CLM_OK) return s;
+  auto* b = new (std::nothrow) clm_box(tmp);
+  if (!b) return fail(CLM_E_INVALID_ARG, "out of host memory");
+  *out = b;
+  return CLM_OK;
+}
+
+clm_status clm_box_from_lengths_angles(const double* len, const double* deg, double cutoff,
+                                       int lcell, clm_box** out) {
+  if (!len || !deg || !out) return fail(CLM_E_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 3; ++k)
+    if (!(len[k] > 0.0) || !std::isfinite(len[k]) || !(deg[k] > 0.0) || !(deg[k] < 180.0))
+      return fail(CLM_E_BAD_BOX, "lengths must be > 0 and angles in (0, 180)");
+  const double pi = 3.14159265358979323846;
+  const double ca = std::cos(deg[0] * pi / 180.0), cb = std::cos(deg[1] * pi / 180.0);
+  const double cg = std::cos(deg[2] * pi / 180.0), sg = std::sin(deg[2] * pi / 180.0);
+  const double cy = (ca - cb * cg) / sg;
+  const double cz2 = 1.0 - cb * cb - cy * cy;
+  if (!(cz2 > 0.0)) return fail(CLM_E_BAD_BOX, "angles do not form a cell");
+  const double a[3] = {len[0], 0.0, 0.0};
+  const double b[3] = {len[1] * cg, len[1] * sg, 0.0};
+  const double c[3] = {len[2] * cb, len[2] * cy, len[2] * std::sqrt(cz2)};
+  double H[9];
+  for (int r = 0; r < 3; ++r) {
+    H[r * 3 + 0] = a[r];
+    H[r * 3 + 1] = b[r];
+    H[r * 3 + 2] = c[r];
+  }
+  return clm_box_create(3, H, cutoff, lcell, out);
+}
+
+clm_status clm_box_info_get(const clm_box* B, clm_box_info* o) {
+  if (!B || !o) return fail(CLM_E_INVALID_ARG, "NULL argument");
+  std::memset(o, 0, sizeof *o);
+  o->dim = B->dim;
+  o->lcell_requested = B->lcell_req;
+  o->lcell = B->lcell;
+  o->small_box = B->small;
+  for (int d = 0; d < 3; ++d) o->grid[d] = B->n[d];
+  o->ncells = B->ncells;
+  for (int a = 0; a < B->dim; ++a)
+    for (int b = 0; b < B->dim; ++b) {
+      o->H[a * B->dim + b] = B->H[a * 3 + b];
+      o->Hinv[a * B->dim + b] = B->Hinv[a * 3 + b];
+    }
+  for (int d = 0; d < 3; ++d) o->widths[d] = d < B->dim ? B->w[d] : 0.0;
+  o->volume = B->V;
+  o->cutoff = B->rc;
+  o->rc2 = B->rc2;
+  o->guard_band = B->band;
+  return CLM_OK;
+}
+
+clm_status clm_box_destroy(clm_box* b) {
+  delete b;
+  return CLM_OK;
+}
+
+static clm_status check_sizes(const clm_box* box, int64_t n_x, int64_t n_y, clm_precision p) {
+  if (!box) return fail(CLM_E_INVALID_ARG, "box is NULL");
+  if (p != CLM_FP64 && p != CLM_FP32_GUARD) return fail(CLM_E_INVALID_ARG, "bad precision %d", (int)p);
+  const int64_t kMaxN = (int64_t)1 << 30;
+  if (n_x < 0 || n_y < 0 || n_x > kMaxN || n_y > kMaxN)
+    return fail(CLM_E_INVALID_ARG, "particle counts must be in [0, 2^30]");
+  return CLM_OK;
+}
+
+clm_status clm_celllist_workspace_bytes(const clm_box* box, int64_t n_x, int64_t n_y,
+                                        clm_precision precision, size_t* bytes) {
+  clm_status s = check_sizes(box, n_x, n_y, precision);
+  if (s != CLM_OK) return s;
+  if (!bytes) return fail(CLM_E_INVALID_ARG, "bytes is NULL");
+  clm_celllist tmp;
+  std::memset(&tmp, 0, sizeof tmp);
+  tmp.box = *box;
+  tmp.nx = n_x;
+  tmp.ny = n_y;
+  tmp.cross = n_y > 0;
+  layout(&tmp, nullptr, bytes);
+  return CLM_OK;
+}
+
+clm_status clm_celllist_create(clm_context* ctx, const clm_box* box, int64_t n_x, int64_t n_y,
+                               clm_precision precision, void* ws, size_t ws_bytes,
+                               clm_celllist** out) {
+  if (!ctx || !out) return fail(CLM_E_INVALID_ARG, "NULL argument");
+  clm_status s = check_sizes(box, n_x, n_y, precision);
+  if (s != CLM_OK) return s;
+  size_t need = 0;
+  clm_celllist_workspace_bytes(box, n_x, n_y, precision, &need);
+  if (!ws) return fail(CLM_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(CLM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(CLM_E_WORKSPACE, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+  auto* cl = new (std::nothrow) clm_celllist;
+  if (!cl) return fail(CLM_E_INVALID_ARG, "out of host memory");
+  std::memset(cl, 0, sizeof *cl);
+  cl->ctx = ctx;
+  cl->box = *box;
+  cl->nx = n_x;
+  cl->ny = n_y;
+  cl->cross = n_y > 0;
+  cl->prec = precision;
+  cl->ws = (char*)ws;
+  cl->ws_bytes = ws_bytes;
+  size_t tot = 0;
+  layout(cl, (char*)ws, &tot);
+  if (!cl->cross) cl->Y = cl->X;
+  *out = cl;
+  return CLM_OK;
+}
+
+static BuildGeom geom_of(const clm_box& B) {
+  BuildGeom g;
+  g.dim = B.dim;
+  for (int d = 0; d < 3; ++d) g.n[d] = B.n[d];
+  for (int k = 0; k < 9; ++k) {
+    g.H[k] = B.H[k];
+    g.Hinv[k] = B.Hinv[k];
+  }
+  return g;
+}
+
+static clm_status build_set(clm_celllist* cl, const double* x, int64_t n, SetBufs& S) {
+  hipStream_t st = cl->ctx->stream;
+  const BuildGeom g = geom_of(cl->box);
+  const int nc = (int)cl->box.ncells;
+  CLM_HIP(launch_fill_u32(S.count, (size_t)nc, 0u, st));
+  CLM_HIP(launch_bin(x, (int)n, g, S.count, S.cell, S.rank, st));
+  CLM_HIP(launch_scan(S.count, nc, cl->scan_scratch, S.off, st));
+  CLM_HIP(launch_scatter(x, (int)n, g, S.off, S.cell, S.rank, S.pos, S.r64, S.idx, S.wrap, st));
+  return CLM_OK;
+}
+
+clm_status clm_celllist_build(clm_celllist* cl, const double* x, const double* y) {
+  if (!cl) return fail(CLM_E_INVALID_ARG, "cell list is NULL");
+  if (cl->nx > 0 && !x) return fail(CLM_E_INVALID_ARG, "x is NULL");
+  if (cl->cross && cl->ny > 0 && !y) return fail(CLM_E_INVALID_ARG, "y is NULL for a cross set");
+  if (!cl->cross && y) return fail(CLM_E_INVALID_ARG, "y given but the cell list has n_y = 0");
+  CLM_HIP(hipSetDevice(cl->ctx->device));
+  clm_status s = build_set(cl, x, cl->nx, cl->X);
+  if (s != CLM_OK) return s;
+  if (cl->cross) {
+    s = build_set(cl, y, cl->ny, cl->Y);
+    if (s != CLM_OK) return s;
+  }
+  if (!cl->box.small) {
+    TileGeom tg;
+    for (int d = 0; d < 3; ++d) tg.n[d] = cl->box.n[d];
+    tg.smax = cl->box.smax;
+    tg.nrows = cl->nrows;
+    tg.job = 0;
+    tg.max_tiles = (uint32_t)cl->max_tiles;
+    CLM_HIP(launch_tiles(cl->X.off, tg, cl->row_tiles, cl->row_off, cl->scan_scratch, cl->tiles,
+                         cl->ctx->stream));
+  }
+  cl->built = 1;
+  return CLM_OK;
+}
+
+static int internal_kind(clm_map_kind k) {
+  switch (k) {
+    case CLM_MAP_COUNT: return K_COUNT;
+    case CLM_MAP_SUM_D: return K_SUM_D;
+    case CLM_MAP_SUM_INV_D: return K_SUM_INV_D;
+    case CLM_MAP_LJ_E: return K_LJ_E;
+    case CLM_MAP_LJ_EF: return K_LJ_F;
+    case CLM_MAP_LJ_ADJOINT: return K_LJ_F;
+    case CLM_MAP_HIST_DIST: return K_HIST_DIST;
+    case CLM_MAP_HIST_RELSPEED: return K_HIST_REL;
+    case CLM_MAP_NEIGHBOR_LIST: return K_NL;
+  }
+  return -1;
+}
+
+static JobDesc base_job(const clm_celllist* cl) {
+  JobDesc jd;
+  std::memset(&jd, 0, sizeof jd);
+  const clm_box& B = cl->box;
+  jd.dim = B.dim;
+  jd.lcell = B.lcell;
+  jd.cross = cl->cross;
+  for (int d = 0; d < 3; ++d) jd.n[d] = B.n[d];
+  jd.ncells = (int)B.ncells;
+  jd.nx = (int)cl->nx;
+  jd.ny = (int)(cl->cross ? cl->ny : cl->nx);
+  for (int k = 0; k < 9; ++k) jd.H[k] = B.H[k];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) jd.Hn[a * 3 + b] = B.H[a * 3 + b] / (double)B.n[b];
+  for (int k = 0; k < 27 * 4; ++k) jd.tK[k] = B.tK[k];
+  jd.rc2 = B.rc2;
+  jd.band = B.band;
+  jd.lo32 = B.lo32;
+  jd.hi32 = B.hi32;
+  jd.pos_x = cl->X.pos; jd.r64_x = cl->X.r64; jd.idx_x = cl->X.idx; jd.wrap_x = cl->X.wrap;
+  jd.off_x = cl->X.off;
+  jd.pos_y = cl->Y.pos; jd.r64_y = cl->Y.r64; jd.idx_y = cl->Y.idx; jd.wrap_y = cl->Y.wrap;
+  jd.off_y = cl->Y.off;
+  jd.vel32_x = cl->X.vel32;
+  jd.vel32_y = cl->Y.vel32;
+  jd.partials = cl->partials;
+  jd.pcount = cl->pcount;
+  jd.bandq = cl->bandq;
+  jd.E64 = cl->E64;
+  jd.E32 = cl->E32;
+  jd.nl_counter = cl->nl_counter;
+  jd.tile_begin = 0;
+  jd.tile_end = cl->max_tiles;
+  return jd;
+}
+
+clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
+                   const clm_map_out* O) {
+  if (!cl || !P || !O) return fail(CLM_E_INVALID_ARG, "NULL argument");
+  if (!cl->built) return fail(CLM_E_INVALID_ARG, "cell list not built");
+  const int k = internal_kind(kind);
+  if (k < 0) return fail(CLM_E_INVALID_ARG, "unknown map kind %d", (int)kind);
+  if (!O->count_dev) return fail(CLM_E_INVALID_ARG, "out->count_dev is required");
+  const clm_box& B = cl->box;
+  const int dim = B.dim;
+  const bool lj = kind == CLM_MAP_LJ_E || kind == CLM_MAP_LJ_EF || kind == CLM_MAP_LJ_ADJOINT;
+  const bool ljf = k == K_LJ_F;
+  if (lj && (!(P->sigma > 0.0) || !std::isfinite(P->sigma) || !std::isfinite(P->epsilon)))
+    return fail(CLM_E_INVALID_ARG, "LJ needs sigma > 0 and finite epsilon");
+  if (ljf && cl->cross) return fail(CLM_E_UNSUPPORTED, "LJ forces need a single set");
+  if (ljf && !O->forces_dev) return fail(CLM_E_INVALID_ARG, "out->forces_dev is required");
+  if (kind == CLM_MAP_LJ_ADJOINT && !P->upstream_dev)
+    return fail(CLM_E_INVALID_ARG, "params->upstream_dev is required for LJ_ADJOINT");
+  if (ljf && P->want_virial && !O->virial_dev)
+    return fail(CLM_E_INVALID_ARG, "want_virial needs out->virial_dev");
+  if ((kind == CLM_MAP_SUM_D || kind == CLM_MAP_SUM_INV_D || lj) && !O->energy_dev)
+    return fail(CLM_E_INVALID_ARG, "out->energy_dev is required");
+  const bool hist = k == K_HIST_DIST || k == K_HIST_REL;
+  if (hist) {
+    if (P->nbins < 1 || P->nbins > kMaxBins)
+      return fail(CLM_E_INVALID_ARG, "nbins must be in 1..%d", kMaxBins);
+    if (!(P->hist_hi > 0.0) || !std::isfinite(P->hist_hi))
+      return fail(CLM_E_INVALID_ARG, "hist_hi must be finite and > 0");
+    if (!O->hist_dev) return fail(CLM_E_INVALID_ARG, "out->hist_dev is required");
+  }
+  if (k == K_HIST_REL) {
+    if (!P->vel_x_dev || (cl->cross && !P->vel_y_dev))
+      return fail(CLM_E_INVALID_ARG, "relative-speed histogram needs velocities");
+    if (P->want_sums && !O->hist_sums_dev) return fail(CLM_E_INVALID_ARG, "want_sums needs hist_sums_dev");
+  }
+  if (k == K_NL) {
+    if (P->capacity < 0) return fail(CLM_E_INVALID_ARG, "capacity must be >= 0");
+    if (P->capacity > 0 && !O->pairs_dev) return fail(CLM_E_INVALID_ARG, "pairs_dev is NULL");
+    if (P->capacity > 0 && P->with_distances && !O->dist_dev)
+      return fail(CLM_E_INVALID_ARG, "with_distances needs dist_dev");
+  }
+  hipStream_t st = cl->ctx->stream;
+  CLM_HIP(hipSetDevice(cl->ctx->device));
+
+  JobDesc jd = base_job(cl);
+  const int k_launch = (ljf && P->want_virial) ? K_LJ_FV : k;
+  jd.kind = k_launch;
+  jd.full_shell = ljf ? 1 : 0;
+  if (lj) {
+    jd.s2 = P->sigma * P->sigma;
+    jd.s2f = (float)jd.s2;
+    double nf = P->near_factor > 0.0 ? P->near_factor : 1.0;
+    double near = nf * P->sigma;
+    jd.near2f = round_up_f(near * near);
+    jd.eps = P->epsilon;
+    jd.upstream = kind == CLM_MAP_LJ_ADJOINT ? P->upstream_dev : nullptr;
+    jd.scale = kind == CLM_MAP_LJ_EF ? -1.0 : 1.0;
+    jd.want_virial = ljf && P->want_virial ? 1 : 0;
+    jd.forces = O->forces_dev;
+  }
+  if (hist) {
+    jd.nbins = P->nbins;
+    jd.hist_hi = P->hist_hi;
+    jd.inv_h = (float)((double)P->nbins / P->hist_hi);
+    jd.hist = (unsigned long long*)O->hist_dev;
+    jd.hist_sums = O->hist_sums_dev;
+    jd.want_sums = (k == K_HIST_REL && P->want_sums) ? 1 : 0;
+    jd.vel64_x = P->vel_x_dev;
+    jd.vel64_y = cl->cross ? P->vel_y_dev : P->vel_x_dev;
+  }
+  if (k == K_NL) {
+    jd.pairs = O->pairs_dev;
+    jd.dist = P->with_distances ? O->dist_dev : nullptr;
+    jd.with_dist = P->with_distances && O->dist_dev ? 1 : 0;
+    jd.capacity = P->capacity;
+  }
+  CLM_HIP(launch_set_job(jd, cl->job_dev, st));
+  if (hist) {
+    const int force_last = (k == K_HIST_DIST && P->hist_hi == B.rc) ? 1 : 0;
+    CLM_HIP(launch_hist_edges(cl->E64, cl->E32, P->nbins, P->hist_hi, force_last, B.rc2, st));
+    CLM_HIP(launch_fill_u64((unsigned long long*)O->hist_dev, (size_t)P->nbins + 1, 0ull, st));
+    if (jd.want_sums) CLM_HIP(launch_fill_f64(O->hist_sums_dev, (size_t)P->nbins, 0.0, st));
+  }
+  if (k == K_HIST_REL) {
+    CLM_HIP(launch_fill_u32(cl->vmax_bits, 1, 0u, st));
+    CLM_HIP(launch_gather_vel(P->vel_x_dev, dim, cl->X.idx, (int)cl->nx, cl->X.vel32, cl->vmax_bits, st));
+    if (cl->cross)
+      CLM_HIP(launch_gather_vel(P->vel_y_dev, dim, cl->Y.idx, (int)cl->ny, cl->Y.vel32, cl->vmax_bits, st));
+    CLM_HIP(launch_relspeed_band(cl->vmax_bits, P->hist_hi, dim, cl->bandq, st));
+  }
+  if (k == K_NL) CLM_HIP(launch_fill_u64(cl->nl_counter, 1, 0ull, st));
+
+  FinalArgs F;
+  std::memset(&F, 0, sizeof F);
+  F.kind = k;
+  F.dim = dim;
+  F.want_virial = jd.want_virial;
+  F.eps = lj ? P->epsilon : 0.0;
+  F.upstream = jd.upstream;
+  F.box_mult = 1.0;
+  F.energy = O->energy_dev;
+  F.virial = jd.want_virial ? O->virial_dev : nullptr;
+  F.grad_box = ljf ? O->grad_box_dev : nullptr;
+  F.count = (unsigned long long*)O->count_dev;
+
+  if (B.small) {
+    BruteArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.dim = dim;
+    A.n_x = (int)cl->nx;
+    A.n_y = (int)(cl->cross ? cl->ny : cl->nx);
+    A.cross = cl->cross;
+    A.kind = k;
+    for (int q = 0; q < 9; ++q) {
+      A.H[q] = B.H[q];
+      A.Hinv[q] = B.Hinv[q];
+    }
+    for (int d = 0; d < 3; ++d) A.w[d] = B.w[d];
+    A.rc = B.rc;
+    A.rc2 = B.rc2;
+    A.reach = std::min(B.rc, 0.5 * B.sum_len) * (1.0 + 1e-6);
+    const double pairs = (double)A.n_x * (double)(cl->cross ? A.n_y : A.n_x);
+    if (pairs > 4.0e9)
+      return fail(CLM_E_UNSUPPORTED,
+                  "box has fewer than 3 cells per axis and %.3g candidate pairs: the brute-force "
+                  "minimum-image path serves at most 4e9", pairs);
+    if (k == K_HIST_DIST || k == K_HIST_REL) {
+      // the brute path accumulates straight into the (zeroed) global histogram
+    }
+    int nblocks = 0;
+    CLM_HIP(launch_brute(cl->job_dev, A, &nblocks, st));
+    F.nparts = nblocks;
+    F.nparts_dev = nullptr;
+  } else {
+    CLM_HIP(launch_sweep(dim, cl->prec == CLM_FP32_GUARD, k_launch, cl->job_dev, cl->tiles,
+                         &cl->row_off[cl->nrows], cl->max_tiles, hist ? P->nbins : 0, st));
+    F.nparts = cl->max_tiles;
+    F.nparts_dev = &cl->row_off[cl->nrows];
+    F.halve_count = ljf && !cl->cross ? 1 : 0;
+  }
+  CLM_HIP(launch_finalize(cl->job_dev, F, st));
+  return CLM_OK;
+}
+
+clm_status clm_celllist_info_get(clm_celllist* cl, clm_celllist_info* o) {
+  if (!cl || !o) return fail(CLM_E_INVALID_ARG, "NULL argument");
+  if (!cl->built) return fail(CLM_E_INVALID_ARG, "cell list not built");
+  std::memset(o, 0, sizeof *o);
+  hipStream_t st = cl->ctx->stream;
+  CLM_HIP(hipSetDevice(cl->ctx->device));
+  o->n_x = cl->nx;
+  o->n_y = cl->ny;
+  o->ncells = cl->box.ncells;
+  const int nc = (int)cl->box.ncells;
+  uint32_t* hoff = new (std::nothrow) uint32_t[nc + 1];
+  if (!hoff) return fail(CLM_E_INVALID_ARG, "out of host memory");
+  CLM_HIP(hipMemcpyAsync(hoff, cl->X.off, sizeof(uint32_t) * (nc + 1), hipMemcpyDeviceToHost, st));
+  CLM_HIP(hipStreamSynchronize(st));
+  int64_t ne = 0, mo = 0;
+  for (int c = 0; c < nc; ++c) {
+    int64_t m = hoff[c + 1] - hoff[c];
+    ne += m > 0;
+    mo = std::max(mo, m);
+  }
+  if (cl->cross) {
+    CLM_HIP(hipMemcpyAsync(hoff, cl->Y.off, sizeof(uint32_t) * (nc + 1), hipMemcpyDeviceToHost, st));
+    CLM_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < nc; ++c) mo = std::max<int64_t>(mo, hoff[c + 1] - hoff[c]);
+  }
+  delete[] hoff;
+  o->nonempty_cells = ne;
+  o->max_occupancy = mo;
+  if (cl->box.small) {
+    o->ntiles = 0;
+    o->candidate_pairs = cl->cross ? cl->nx * cl->ny : cl->nx * (cl->nx - 1) / 2;
+    return CLM_OK;
+  }
+  uint32_t nt = 0;
+  CLM_HIP(hipMemcpyAsync(&nt, &cl->row_off[cl->nrows], sizeof nt, hipMemcpyDeviceToHost, st));
+  CLM_HIP(hipStreamSynchronize(st));
+  if ((int64_t)nt > cl->max_tiles)
+    return fail(CLM_E_DEVICE, "internal: %u tiles exceed the bound %d", nt, cl->max_tiles);
+  o->ntiles = nt;
+  // candidates: the sweep's half shell (full shell for cross sets)
+  JobDesc jd = base_job(cl);
+  CLM_HIP(launch_set_job(jd, cl->job_dev, st));
+  CLM_HIP(launch_candidates(cl->job_dev, cl->tiles, (int)nt, 0, cl->cand, st));
+  unsigned long long* hc = new (std::nothrow) unsigned long long[nt + 1];
+  if (!hc) return fail(CLM_E_INVALID_ARG, "out of host memory");
+  if (nt) CLM_HIP(hipMemcpyAsync(hc, cl->cand, sizeof(unsigned long long) * nt, hipMemcpyDeviceToHost, st));
+  CLM_HIP(hipStreamSynchronize(st));
+  int64_t tot = 0;
+  for (uint32_t t = 0; t < nt; ++t) tot += (int64_t)hc[t];
+  delete[] hc;
+  o->candidate_pairs = tot;
+  return CLM_OK;
+}
+
+clm_status clm_celllist_destroy(clm_celllist* cl) {
+  delete cl;
+  return CLM_OK;
+}
+
+clm_status clm_synchronize(clm_context* ctx) {
+  if (!ctx) return fail(CLM_E_INVALID_ARG, "ctx is NULL");
+  CLM_HIP(hipSetDevice(ctx->device));
+  CLM_HIP(hipStreamSynchronize(ctx->stream));
+  return CLM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,186 @@
+// clmap_internal.h -- device-side data structures of libclmap (gfx950).
+//
+// Data layout in HBM after a build (n = particles of one set, sorted by cell,
+// cells linearised x-fastest: c = cx + nx*(cy + ny*cz)):
+//   pos   float4[n]   FP32 offset of the wrapped position from its cell origin
+//                     (x, y, z[, unused]); used by the FP32 sweep (16 B, one
+//                     scalar-cache line holds 4 particles)
+//   r64   double4[n]  FP64 wrapped position r' (canonical, see clmap.h)
+//   idx   uint32[n]   original index of each sorted slot
+//   wrap  int4[n]     wrap integers w (r' = r - H w)
+//   off   uint32[ncells+1] exclusive prefix of the cell occupancies
+// plus the tile list (work units of <= 64 consecutive sorted particles of one
+// cell row) and per-tile FP64 partials.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clm {
+
+constexpr int kWave = 64;        // CDNA wavefront
+constexpr int kTileMax = 64;     // particles per tile: one per lane
+constexpr int kMaxSpan = 16;     // most cells a tile may span along x
+constexpr int kBlock = 256;      // threads per block in the sweep (4 waves)
+constexpr int kNLStage = 256;    // per-wave LDS staging slots for neighbour pairs
+constexpr int kPartialD = 20;    // doubles per tile partial
+constexpr int kMaxBins = 1000;  // keeps 4 waves of private histograms within 64 KiB LDS
+
+// Per-tile partial slots (doubles).
+enum : int {
+  P_SUM = 0,      // energy / sum of d / sum of 1/d (unscaled)
+  P_VIR = 1,      // 9: virial (unscaled)
+  P_BOX = 10,     // 9: box-gradient accumulator B (unscaled); dE/dH = -24 eps B
+  P_FREE = 19
+};
+
+enum Kind : int {
+  K_COUNT = 0, K_SUM_D = 1, K_SUM_INV_D = 2, K_LJ_E = 3, K_LJ_F = 4, K_LJ_FV = 5,
+  K_HIST_DIST = 6, K_HIST_REL = 7, K_NL = 8
+};
+
+struct Tile {
+  uint32_t start;   // first sorted index (x set)
+  uint32_t row;     // cy + ny*cz
+  uint16_t count;   // particles, 1..64
+  uint16_t cx0;     // first cell (x) of the tile
+  uint16_t cx1;     // last non-empty cell (x) of the tile
+  uint16_t job;     // job descriptor index
+};
+static_assert(sizeof(Tile) == 16, "tile is 16 bytes");
+
+// Everything the sweep needs about one job, resident in device memory and
+// read through the scalar cache (all fields are wave-uniform).
+struct JobDesc {
+  // geometry
+  int dim, lcell, full_shell, cross;
+  int n[3];
+  int ncells;
+  int nx, ny;            // particles of x and y (y == x for a single set)
+  int pad0;
+  double H[9];           // row-major, stride 3 (2D uses the 2x2 top-left)
+  double Hn[9];          // H[a][b] / n[b]: cell-origin matrix (origin of cell u = Hn u)
+  double tK[27 * 4];     // canonical image shifts H K, K in {-1,0,1}^3, index
+                         // (Kx+1) + 3 (Ky+1) + 9 (Kz+1), 4 doubles per entry
+  double rc2;
+  double band;           // absolute band on FP32 squared distances
+  float lo32, hi32;      // FP32 membership thresholds rc2 -+ band (rounded outwards)
+  // sorted data
+  const float4* pos_x; const double4* r64_x; const uint32_t* idx_x; const int4* wrap_x;
+  const uint32_t* off_x;
+  const float4* pos_y; const double4* r64_y; const uint32_t* idx_y; const int4* wrap_y;
+  const uint32_t* off_y;
+  // map
+  int kind;
+  int nbins;
+  double s2;             // sigma^2
+  float s2f, near2f;     // sigma^2 and (near_factor sigma)^2 in FP32
+  double eps;
+  const double* upstream;    // LJ adjoint: g (device), NULL -> scale
+  double scale;              // multiplier of dE/dr when upstream == NULL
+  int want_virial, want_sums, with_dist, pad1;
+  double hist_hi;
+  float inv_h, pad2;
+  const double* E64;         // nbins+1 edges (squared), canonical
+  const float* E32;          // the same rounded to FP32
+  double* bandq;             // relative-speed band (device scalar, set by the prep kernel)
+  const float4* vel32_x;     // sorted FP32 velocities
+  const float4* vel32_y;
+  const double* vel64_x;     // raw FP64 velocities (original order)
+  const double* vel64_y;
+  // outputs
+  double* partials;          // per tile kPartialD
+  unsigned long long* pcount;// per tile pair count
+  double* forces;            // n_x*dim, original order
+  unsigned long long* hist;  // nbins+1
+  double* hist_sums;         // nbins
+  int32_t* pairs;
+  double* dist;
+  unsigned long long* nl_counter;
+  long long capacity;
+  int tile_begin, tile_end;  // this job's tiles
+};
+
+// Dynamic LDS bytes per wave of the sweep: histogram kinds keep a private
+// histogram (nbins+1 u32), per-bin FP64 sums and the FP32 edge table; the
+// neighbour list keeps a staging area (pairs, distances, fill counter).
+__host__ __device__ inline size_t sweep_lds_per_wave(int kind, int nbins) {
+  if (kind == K_HIST_DIST || kind == K_HIST_REL) {
+    size_t b = (size_t)(nbins + 1) * 4 + 8 + (size_t)nbins * 8 + (size_t)(nbins + 1) * 4;
+    return (b + 15) & ~(size_t)15;
+  }
+  if (kind == K_NL) return (size_t)kNLStage * 16 + 16;
+  return 0;
+}
+
+__host__ __device__ inline int kcode(int px, int py, int pz) {
+  return (px + 1) + 3 * (py + 1) + 9 * (pz + 1);
+}
+
+// ---------------------------------------------------------------- launch parameters
+struct BuildGeom {
+  int dim;
+  int n[3];
+  double H[9];     // row-major stride 3
+  double Hinv[9];  // row-major stride 3 (canonical adjugate / determinant)
+};
+
+struct TileGeom {
+  int n[3];
+  int smax;
+  int nrows;
+  int job;
+  uint32_t max_tiles;
+};
+
+struct BruteArgs {
+  int dim, n_x, n_y, cross, kind;
+  double H[9], Hinv[9], w[3];
+  double rc, rc2;
+  double reach;   // min(rc, half the sum of lattice-vector lengths) (1 + 1e-6)
+};
+
+struct FinalArgs {
+  int nparts;                      // used when nparts_dev is NULL
+  const uint32_t* nparts_dev;      // device count of partials (tiles)
+  int kind, dim, want_virial;
+  int halve_count;                 // full-shell sweep: every pair was counted from both ends
+  double eps;
+  const double* upstream;          // LJ adjoint: g
+  double box_mult;                 // when upstream is NULL
+  double* energy;
+  double* virial;
+  double* grad_box;
+  unsigned long long* count;
+};
+
+// ---------------------------------------------------------------- launchers
+// Host wrappers (defined next to their kernels); all enqueue on `s`.
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
+hipError_t launch_bin(const double* x, int n, const BuildGeom& g, uint32_t* count, uint32_t* cell,
+                      uint32_t* rank, hipStream_t s);
+hipError_t launch_scan(const uint32_t* in, int n, uint32_t* sums_scratch, uint32_t* out,
+                       hipStream_t s);
+size_t scan_scratch_elems(int n);
+hipError_t launch_scatter(const double* x, int n, const BuildGeom& g, const uint32_t* off,
+                          const uint32_t* cell, const uint32_t* rank, float4* pos, double4* r64,
+                          uint32_t* idx, int4* wrap, hipStream_t s);
+hipError_t launch_tiles(const uint32_t* off, const TileGeom& g, uint32_t* row_tiles,
+                        uint32_t* row_off, uint32_t* scan_scratch, Tile* tiles, hipStream_t s);
+hipError_t launch_gather_vel(const double* v, int dim, const uint32_t* idx, int n, float4* v32,
+                             unsigned int* vmax_bits, hipStream_t s);
+hipError_t launch_set_job(const JobDesc& jd, JobDesc* dst, hipStream_t s);
+hipError_t launch_hist_edges(double* E64, float* E32, int nbins, double hi, int force_last,
+                             double rc2, hipStream_t s);
+hipError_t launch_relspeed_band(const unsigned int* vmax_bits, double hi, int dim, double* bandq,
+                                hipStream_t s);
+hipError_t launch_sweep(int dim, bool fp32, int kind, const JobDesc* jobs, const Tile* tiles,
+                        const uint32_t* ntiles_dev, int max_tiles, int nbins, hipStream_t s);
+hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, int* nblocks_out, hipStream_t s);
+hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, hipStream_t s);
+hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
+                             unsigned long long* out, hipStream_t s);
+
+}  // namespace clm

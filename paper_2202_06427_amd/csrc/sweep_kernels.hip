@@ -1,0 +1,1025 @@
+// sweep_kernels.hip -- the cell-pair sweep and its fused map-reduce back ends
+// on gfx950 (paper section 2.8: loop over each cell and its neighbour cells,
+// half of them for symmetric pairs; sections 2.3/2.7: a function applied to
+// every pair within the cutoff and reduced; section 2.8: per-task output
+// copies summed at the end).
+//
+// Work decomposition: one wavefront per tile of <= 64 consecutive sorted
+// particles (one per lane) of one cell row.  For every neighbour cell the
+// wave visits, the cell's particles are streamed in order; the j-th record is
+// the same for all 64 lanes, so it is read with scalar loads into SGPRs and
+// consumed as an SGPR operand by the vector ALU (no LDS broadcast, whose VGPR
+// write-back would cost as much as the arithmetic).
+//
+// Half shell (single set, symmetric maps): neighbour cells with offset
+// (dz, dy) > 0 lexicographically, plus the home row where j > i in sorted
+// order (the sorted order follows the cells along x).  Full shell (LJ
+// forces as a gather, cross sets): every neighbour cell.
+//
+// Precision forms:
+//  FP64 (canonical): D = (r'_j - r'_i) + H K, d2 = (Dx^2 + Dy^2) + Dz^2 with
+//   separately rounded operations -- exactly the pair set of clmap.h.
+//  FP32 + guard: q_i = fl32(r'_i - O_u) (i relative to the visited cell's
+//   origin, computed in FP64) and o_j (FP32 offset of j from its cell
+//   origin): D = o_j - q_i, d2 by FMA.  A rigorous bound on |d2_32 - d2|
+//   (the band, computed on the host) classifies each candidate as certainly
+//   in, certainly out, or uncertain; uncertain candidates (and histogram
+//   values within the band of a bin edge, and LJ pairs closer than the near
+//   threshold) are recomputed in canonical FP64 inline.
+#include "clmap_internal.h"
+
+namespace clm {
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int lane_rank(unsigned long long mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---------------------------------------------------------------- histogram bins
+// Canonical bin of v against E64[0..nb] (first k with v <= E_{k+1}; v = 0 ->
+// bin 0; beyond E_nb -> nb).  Binary search, FP64.
+__device__ __forceinline__ int bin64(const double* __restrict__ E, int nb, double v) {
+  if (!(v <= E[nb])) return nb;
+  int lo = 0, hi = nb;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (v <= E[mid]) hi = mid; else lo = mid + 1;
+  }
+  return lo == 0 ? 0 : lo - 1;
+}
+
+// FP32 bin with certainty flag: the bin is certain when v is farther than
+// band from both edges of the bin chosen against the FP32 table.  Et is the
+// FP32 edge table in LDS; band covers the FP32 error of v and of Et.
+__device__ __forceinline__ int bin32(const float* __restrict__ Et, int nb, float inv_h, float v,
+                                     float band, bool* certain) {
+  float sq = __builtin_sqrtf(v);
+  int k = (int)ceilf(sq * inv_h) - 1;
+  k = k < 0 ? 0 : (k > nb ? nb : k);
+  if (k < nb && v <= Et[k] && k > 0) --k;
+  else if (k < nb && v > Et[k + 1]) ++k;
+  if (k >= nb) {
+    *certain = (v - Et[nb]) > band;
+    return nb;
+  }
+  float lo = Et[k], hi = Et[k + 1];
+  *certain = (k == 0 ? true : (v - lo) > band) && (hi - v) > band && v > lo && v <= hi;
+  return k;
+}
+
+// ---------------------------------------------------------------- uniform loads
+// A load through the constant address space with a wave-uniform address is
+// emitted as a scalar (SMEM) load into SGPRs.
+// (The host compilation pass never runs device code; it only needs a body.)
+template <typename T>
+__device__ __forceinline__ T ldu(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(4))) T*)(p);
+#else
+  return *p;
+#endif
+}
+
+// ---------------------------------------------------------------- per-wave LDS
+struct WaveLds {
+  uint32_t* hist;     // nbins+1
+  double* hsum;       // nbins
+  float* E32;         // nbins+1
+  uint32_t* nl_ij;    // kNLStage*2
+  double* nl_d;       // kNLStage
+  int* nl_fill;       // 1
+};
+
+// ---------------------------------------------------------------- the sweep
+// All members of Sweep are per-lane registers or wave-uniform values loaded
+// with scalar loads; every method is inlined so nothing lives in memory.
+template <int DIM, bool FP32, int KIND>
+struct Sweep {
+  static constexpr bool kLJF = KIND == K_LJ_F || KIND == K_LJ_FV;
+  static constexpr bool kVir = KIND == K_LJ_FV;
+  static constexpr bool kLJ = KIND == K_LJ_E || kLJF;
+  static constexpr bool kHist = KIND == K_HIST_DIST || KIND == K_HIST_REL;
+  static constexpr bool kRel = KIND == K_HIST_REL;
+  static constexpr bool kNL = KIND == K_NL;
+  static constexpr bool kSum = KIND == K_SUM_D || KIND == K_SUM_INV_D || kLJ;
+
+  // ---- uniform job constants
+  const JobDesc* J;
+  int cross, full, l, nx, ny, nz;
+  double Hn[9];      // H[a][b] / n[b]
+  double rc2;
+  float lo32, hi32;
+  float s2f, near2f;
+  double s2;
+  int nbins;
+  float inv_h;
+  float bandh;       // histogram edge band (FP32)
+  int want_sums, with_dist;
+  const float4* P;       // j positions (FP32)
+  const double4* R;      // j positions (FP64)
+  const uint32_t* IDXJ;  // j original indices
+  const float4* VJ;      // j velocities FP32
+  const double* VJ64;    // j velocities FP64 (original order)
+  const uint32_t* OFF;
+  const double* E64;
+  WaveLds L;
+  // ---- per lane
+  int lane;
+  bool active;
+  uint32_t i, i_orig;
+  double ri[3];
+  float vi[3];
+  double vi64[3];
+  double accE;
+  double G[3];
+  double S[3];       // per visited cell: sum of f_s D (folded into G and B)
+  double W[6];
+  double B[9];
+  unsigned long long cnt_wave, cnt_lane;
+  // ---- visit
+  float q[3];
+  double t[3];
+  int p[3];
+
+  __device__ __forceinline__ void load_job(const JobDesc* job) {
+    J = job;
+    cross = ldu(&J->cross);
+    full = ldu(&J->full_shell) || cross;
+    l = ldu(&J->lcell);
+    nx = ldu(&J->n[0]);
+    ny = ldu(&J->n[1]);
+    nz = ldu(&J->n[2]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Hn[k] = ldu(&J->Hn[k]);
+    rc2 = ldu(&J->rc2);
+    lo32 = ldu(&J->lo32);
+    hi32 = ldu(&J->hi32);
+    bandh = hi32 - lo32;
+    if constexpr (kLJ) {
+      s2 = ldu(&J->s2);
+      s2f = ldu(&J->s2f);
+      near2f = ldu(&J->near2f);
+    }
+    if constexpr (kHist) {
+      nbins = ldu(&J->nbins);
+      inv_h = ldu(&J->inv_h);
+      E64 = ldu(&J->E64);
+    }
+    if constexpr (kRel) {
+      want_sums = ldu(&J->want_sums);
+      VJ = cross ? ldu(&J->vel32_y) : ldu(&J->vel32_x);
+      VJ64 = cross ? ldu(&J->vel64_y) : ldu(&J->vel64_x);
+      bandh = (float)ldu(ldu(&J->bandq));
+    }
+    if constexpr (kNL) with_dist = ldu(&J->with_dist);
+    P = cross ? ldu(&J->pos_y) : ldu(&J->pos_x);
+    R = cross ? ldu(&J->r64_y) : ldu(&J->r64_x);
+    IDXJ = cross ? ldu(&J->idx_y) : ldu(&J->idx_x);
+    OFF = cross ? ldu(&J->off_y) : ldu(&J->off_x);
+  }
+
+  // ---------------- neighbour-list staging
+  __device__ __forceinline__ void nl_emit(uint32_t a, uint32_t b, double d, unsigned long long g) {
+    if ((long long)g < ldu(&J->capacity)) {
+      int32_t* pairs = ldu(&J->pairs);
+      pairs[2 * g] = (int32_t)a;
+      pairs[2 * g + 1] = (int32_t)b;
+      if (with_dist) ldu(&J->dist)[g] = d;
+    }
+  }
+
+  __device__ __forceinline__ void nl_flush() {
+    int n = uniform(*(volatile int*)L.nl_fill);
+    n = n > kNLStage ? kNLStage : n;
+    if (n > 0) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(ldu(&J->nl_counter), (unsigned long long)n);
+      base = __shfl(base, 0, kWave);
+      for (int s = lane; s < n; s += kWave) nl_emit(L.nl_ij[2 * s], L.nl_ij[2 * s + 1], L.nl_d[s], base + s);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) *L.nl_fill = 0;
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  __device__ __forceinline__ void nl_pair(uint32_t j, uint32_t* a, uint32_t* b) {
+    uint32_t jo = ldu(&IDXJ[j]);
+    uint32_t x0 = i_orig, x1 = jo;
+    if (!cross && x0 > x1) { uint32_t tmp = x0; x0 = x1; x1 = tmp; }
+    *a = x0;
+    *b = x1;
+  }
+
+  // certain members of one iteration (same j for every lane)
+  __device__ __forceinline__ void nl_stage_wave(bool in, uint32_t j, double d) {
+    unsigned long long m = __ballot(in);
+    if (m == 0) return;
+    int cnt = __popcll(m);
+    int base = uniform(*(volatile int*)L.nl_fill);
+    if (base + cnt > kNLStage) {
+      nl_flush();
+      base = 0;
+    }
+    if (in) {
+      int slot = base + lane_rank(m);
+      uint32_t a, b;
+      nl_pair(j, &a, &b);
+      L.nl_ij[2 * slot] = a;
+      L.nl_ij[2 * slot + 1] = b;
+      L.nl_d[slot] = d;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) *L.nl_fill = base + cnt;
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // a single lane (divergent FP64 path): straight to global memory
+  __device__ __forceinline__ void nl_one(uint32_t j, double d) {
+    uint32_t a, b;
+    nl_pair(j, &a, &b);
+    unsigned long long g = atomicAdd(ldu(&J->nl_counter), 1ull);
+    nl_emit(a, b, d, g);
+  }
+
+  // ---------------- FP64 epilogue for one member pair (canonical d2, D)
+  __device__ __forceinline__ void pair64(double d2, const double* D, uint32_t j, bool count_it) {
+    if (count_it) cnt_lane += 1;
+    if constexpr (KIND == K_SUM_D) accE += sqrt(d2);
+    if constexpr (KIND == K_SUM_INV_D) accE += 1.0 / sqrt(d2);
+    if constexpr (kLJ) {
+      double x = s2 / d2;
+      double x3 = x * x * x;
+      double u = x3 * x3 - x3;
+      if constexpr (KIND == K_LJ_E) {
+        accE += u;
+      } else {
+        double f = (2.0 * x3 * x3 - x3) / d2;  // f_s / (24 eps)
+        accE += 0.5 * u;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) S[a] += f * D[a];
+        if constexpr (kVir) {
+          W[0] += 0.5 * f * D[0] * D[0];
+          W[1] += 0.5 * f * D[0] * D[1];
+          W[3] += 0.5 * f * D[1] * D[1];
+          if (DIM == 3) {
+            W[2] += 0.5 * f * D[0] * D[2];
+            W[4] += 0.5 * f * D[1] * D[2];
+            W[5] += 0.5 * f * D[2] * D[2];
+          }
+        }
+      }
+    }
+    if constexpr (KIND == K_HIST_DIST) {
+      int k = bin64(E64, nbins, d2);
+      atomicAdd(&L.hist[k], 1u);
+    }
+    if constexpr (kRel) {
+      uint32_t jo = ldu(&IDXJ[j]);
+      double dv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) dv[a] = ldu(&VJ64[(size_t)jo * DIM + a]) - vi64[a];
+      double qq = dv[0] * dv[0] + dv[1] * dv[1];
+      if (DIM == 3) qq = qq + dv[2] * dv[2];
+      int k = bin64(E64, nbins, qq);
+      atomicAdd(&L.hist[k], 1u);
+      if (want_sums && k < nbins) atomicAdd(&L.hsum[k], sqrt(qq));
+    }
+    if constexpr (kNL) nl_one(j, sqrt(d2));
+  }
+
+  // ---------------- uncertain / near candidate: canonical FP64
+  __device__ __forceinline__ void special(uint32_t j, bool count_it) {
+    const double4 rj = ldu(&R[j]);
+    double D[3];
+    D[0] = (rj.x - ri[0]) + t[0];
+    D[1] = (rj.y - ri[1]) + t[1];
+    double d2 = D[0] * D[0] + D[1] * D[1];
+    if (DIM == 3) {
+      D[2] = (rj.z - ri[2]) + t[2];
+      d2 = d2 + D[2] * D[2];
+    } else {
+      D[2] = 0.0;
+    }
+    if (d2 <= rc2) pair64(d2, D, j, count_it);
+  }
+
+  // ---------------- one candidate
+  // FILTER: 0 none, 1 j > i (home row), 2 j != i (own cell, full shell)
+  // Returns 0 (done), 1 (special, membership known) or 3 (special, band:
+  // membership decided in FP64 and counted there).
+  template <int FILTER>
+  __device__ __forceinline__ uint32_t cand32(uint32_t j, const float4& pj, float& visE, float* g32,
+                                             float* w32) {
+    bool valid = active;
+    if (FILTER == 1) valid = valid && (j > i);
+    if (FILTER == 2) valid = valid && (j != i);
+    const float dx = pj.x - q[0];
+    const float dy = pj.y - q[1];
+    const float dz = DIM == 3 ? pj.z - q[2] : 0.0f;
+    const float d2 = DIM == 3 ? __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))
+                              : __builtin_fmaf(dy, dy, dx * dx);
+    const bool in = valid && d2 <= lo32;
+    const bool band = valid && d2 > lo32 && d2 <= hi32;
+    bool spec = band;
+    cnt_wave += (unsigned long long)__popcll(__ballot(in));
+    if constexpr (KIND == K_SUM_D || KIND == K_SUM_INV_D) {
+      const float r = __builtin_amdgcn_rsqf(d2);
+      const float term = KIND == K_SUM_D ? d2 * r : r;
+      visE += in ? term : 0.0f;
+    } else if constexpr (kLJ) {
+      const bool nearp = in && d2 < near2f;
+      const bool fast = in && !nearp;
+      spec = spec || nearp;
+      const float r = __builtin_amdgcn_rcpf(d2);
+      const float x = s2f * r;
+      const float x3 = x * x * x;
+      const float u = __builtin_fmaf(x3, x3, -x3);
+      visE += fast ? u : 0.0f;
+      if constexpr (kLJF) {
+        const float f = fast ? x3 * __builtin_fmaf(2.0f, x3, -1.0f) * r : 0.0f;
+        g32[0] = __builtin_fmaf(f, dx, g32[0]);
+        g32[1] = __builtin_fmaf(f, dy, g32[1]);
+        if (DIM == 3) g32[2] = __builtin_fmaf(f, dz, g32[2]);
+        if constexpr (kVir) {
+          w32[0] = __builtin_fmaf(f * dx, dx, w32[0]);
+          w32[1] = __builtin_fmaf(f * dx, dy, w32[1]);
+          w32[3] = __builtin_fmaf(f * dy, dy, w32[3]);
+          if (DIM == 3) {
+            w32[2] = __builtin_fmaf(f * dx, dz, w32[2]);
+            w32[4] = __builtin_fmaf(f * dy, dz, w32[4]);
+            w32[5] = __builtin_fmaf(f * dz, dz, w32[5]);
+          }
+        }
+      }
+    } else if constexpr (kHist) {
+      float v = d2;
+      if constexpr (kRel) {
+        const float4 vj = ldu(&VJ[j]);
+        const float ex = vj.x - vi[0], ey = vj.y - vi[1];
+        const float ez = DIM == 3 ? vj.z - vi[2] : 0.0f;
+        v = DIM == 3 ? __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex))
+                     : __builtin_fmaf(ey, ey, ex * ex);
+      }
+      if (in) {
+        bool certain;
+        const int k = bin32(L.E32, nbins, inv_h, v, bandh, &certain);
+        if (certain) {
+          atomicAdd(&L.hist[k], 1u);
+          if (kRel && want_sums && k < nbins) atomicAdd(&L.hsum[k], (double)__builtin_sqrtf(v));
+        } else {
+          spec = true;
+        }
+      }
+    } else if constexpr (kNL) {
+      nl_stage_wave(in, j, (double)__builtin_sqrtf(d2));
+    }
+    return spec ? (band ? 3u : 1u) : 0u;
+  }
+
+  template <int FILTER>
+  __device__ __forceinline__ void cand64(uint32_t j, const double4& rj) {
+    bool valid = active;
+    if (FILTER == 1) valid = valid && (j > i);
+    if (FILTER == 2) valid = valid && (j != i);
+    double D[3];
+    D[0] = (rj.x - ri[0]) + t[0];
+    D[1] = (rj.y - ri[1]) + t[1];
+    double d2 = D[0] * D[0] + D[1] * D[1];
+    if (DIM == 3) {
+      D[2] = (rj.z - ri[2]) + t[2];
+      d2 = d2 + D[2] * D[2];
+    } else {
+      D[2] = 0.0;
+    }
+    const bool in = valid && d2 <= rc2;
+    cnt_wave += (unsigned long long)__popcll(__ballot(in));
+    if constexpr (kNL) {
+      nl_stage_wave(in, j, sqrt(d2));
+    } else if constexpr (KIND != K_COUNT) {
+      if (in) pair64(d2, D, j, false);
+    }
+  }
+
+  // ---------------- one visited cell: j in [jb, je)
+  // G += S, B += S p^T / 2 at the end of a visited cell
+  __device__ __forceinline__ void fold_visit() {
+    if constexpr (kLJF) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) G[a] += S[a];
+      if (p[0] != 0 || p[1] != 0 || p[2] != 0) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int b = 0; b < DIM; ++b) B[a * 3 + b] += 0.5 * S[a] * (double)p[b];
+      }
+    }
+  }
+
+  template <int FILTER>
+  __device__ __forceinline__ void visit(uint32_t jb, uint32_t je) {
+    if constexpr (kLJF) {
+      S[0] = 0.0; S[1] = 0.0; S[2] = 0.0;
+    }
+    if constexpr (FP32) {
+      float visE = 0.0f;
+      float g32[3] = {0.0f, 0.0f, 0.0f};
+      float w32[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      uint32_t j = jb;
+      for (; j + 4 <= je; j += 4) {
+        const float4 p0 = ldu(&P[j]), p1 = ldu(&P[j + 1]), p2 = ldu(&P[j + 2]), p3 = ldu(&P[j + 3]);
+        uint32_t sb = cand32<FILTER>(j, p0, visE, g32, w32);
+        sb |= cand32<FILTER>(j + 1, p1, visE, g32, w32) << 2;
+        sb |= cand32<FILTER>(j + 2, p2, visE, g32, w32) << 4;
+        sb |= cand32<FILTER>(j + 3, p3, visE, g32, w32) << 6;
+        if (sb) {
+#pragma unroll 1
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t bits = (sb >> (2 * k)) & 3u;
+            if (bits) special(j + (uint32_t)k, bits == 3u);
+          }
+        }
+      }
+      for (; j < je; ++j) {
+        const uint32_t bits = cand32<FILTER>(j, ldu(&P[j]), visE, g32, w32);
+        if (bits) special(j, bits == 3u);
+      }
+      if constexpr (kSum) accE += kLJF ? 0.5 * (double)visE : (double)visE;
+      if constexpr (kLJF) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) S[a] += (double)g32[a];
+        if constexpr (kVir) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) W[k] += 0.5 * (double)w32[k];
+        }
+      }
+      fold_visit();
+    } else {
+      for (uint32_t j = jb; j < je; ++j) cand64<FILTER>(j, ldu(&R[j]));
+      fold_visit();
+    }
+  }
+
+  // ---------------- one tile
+  __device__ __forceinline__ void run(const Tile& T, int tile_id) {
+    const int cy = (int)(T.row % (uint32_t)ny);
+    const int cz = DIM == 3 ? (int)(T.row / (uint32_t)ny) : 0;
+    const int count = T.count;
+    const int cx0 = T.cx0, cx1 = T.cx1;
+    active = lane < count;
+    i = T.start + (uint32_t)(active ? lane : count - 1);
+    i_orig = ldu(&J->idx_x)[i];
+    {
+      const double4 r = ldu(&J->r64_x)[i];
+      ri[0] = r.x; ri[1] = r.y; ri[2] = r.z;
+    }
+    if constexpr (kRel) {
+      const float4 v = ldu(&J->vel32_x)[i];
+      vi[0] = v.x; vi[1] = v.y; vi[2] = v.z;
+      const double* v64 = ldu(&J->vel64_x);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) vi64[a] = v64[(size_t)i_orig * DIM + a];
+    }
+    accE = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) G[a] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) W[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) B[k] = 0.0;
+    cnt_wave = 0;
+    cnt_lane = 0;
+
+    const int dzlo = DIM == 3 ? -l : 0, dzhi = DIM == 3 ? l : 0;
+    for (int dz = dzlo; dz <= dzhi; ++dz) {
+      for (int dy = -l; dy <= l; ++dy) {
+        if (!full && (dz < 0 || (dz == 0 && dy < 0))) continue;
+        const bool home = !full && dz == 0 && dy == 0;
+        const int uy = cy + dy, uz = cz + dz;
+        int uyw = uy, uzw = uz, py = 0, pz = 0;
+        if (uyw < 0) { uyw += ny; py = -1; } else if (uyw >= ny) { uyw -= ny; py = 1; }
+        if (DIM == 3) {
+          if (uzw < 0) { uzw += nz; pz = -1; } else if (uzw >= nz) { uzw -= nz; pz = 1; }
+        }
+        const int rowbase = (uyw + ny * uzw) * nx;
+        const int xlo = home ? cx0 : cx0 - l;
+        const int xhi = cx1 + l;
+        for (int ux = xlo; ux <= xhi; ++ux) {
+          int uxw = ux, px = 0;
+          if (uxw < 0) { uxw += nx; px = -1; } else if (uxw >= nx) { uxw -= nx; px = 1; }
+          const int c = rowbase + uxw;
+          const uint32_t jb = ldu(&OFF[c]), je = ldu(&OFF[c + 1]);
+          if (jb == je) continue;
+          p[0] = px; p[1] = py; p[2] = pz;
+          const int kc = kcode(px, py, pz);
+          t[0] = ldu(&J->tK[kc * 4 + 0]);
+          t[1] = ldu(&J->tK[kc * 4 + 1]);
+          t[2] = ldu(&J->tK[kc * 4 + 2]);
+          if constexpr (FP32) {
+            // origin of the visited cell (unwrapped index u), FP64
+            const double u0 = (double)ux, u1 = (double)uy, u2 = DIM == 3 ? (double)uz : 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+              const double O = (Hn[a * 3 + 0] * u0 + Hn[a * 3 + 1] * u1) + Hn[a * 3 + 2] * u2;
+              q[a] = (float)(ri[a] - O);
+            }
+            if (DIM == 2) q[2] = 0.0f;
+          }
+          const bool own = !cross && dz == 0 && dy == 0 && px == 0 && ux >= cx0 && ux <= cx1;
+          if (home && px == 0)
+            visit<1>(jb, je);
+          else if (full && own)
+            visit<2>(jb, je);
+          else
+            visit<0>(jb, je);
+        }
+      }
+    }
+
+    // ---- tile epilogue
+    if constexpr (kLJF) {
+      const double* up = ldu(&J->upstream);
+      const double mult = up ? ldu(up) : ldu(&J->scale);
+      const double sc = mult * 24.0 * ldu(&J->eps);
+      double* forces = ldu(&J->forces);
+      if (active) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) forces[(size_t)i_orig * DIM + a] = sc * G[a];
+      }
+      const int4 w = ldu(&J->wrap_x)[i];
+      const int wv[3] = {w.x, w.y, w.z};
+      if (active) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int b = 0; b < DIM; ++b) B[a * 3 + b] += G[a] * (double)wv[b];
+      }
+    }
+    if constexpr (kNL) nl_flush();
+    const unsigned long long cnt = cnt_wave + wave_sum_u64(cnt_lane);
+    double* Pp = ldu(&J->partials) + (size_t)tile_id * kPartialD;
+    const double e = wave_sum_d(active ? accE : 0.0);
+    if (lane == 0) {
+      ldu(&J->pcount)[tile_id] = cnt;
+      Pp[P_SUM] = e;
+    }
+    if constexpr (kLJF) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const double b = wave_sum_d(active ? B[k] : 0.0);
+        if (lane == 0) Pp[P_BOX + k] = b;
+      }
+      if constexpr (kVir) {
+        constexpr int map[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+        double ws[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ws[k] = wave_sum_d(active ? W[k] : 0.0);
+        if (lane == 0) {
+#pragma unroll
+          for (int m = 0; m < 9; ++m) Pp[P_VIR + m] = ws[map[m]];
+        }
+      }
+    }
+  }
+};
+
+template <int DIM, bool FP32, int KIND>
+__global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict__ jobs,
+                                                       const Tile* __restrict__ tiles,
+                                                       const uint32_t* __restrict__ ntiles_dev) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr bool kHist = KIND == K_HIST_DIST || KIND == K_HIST_REL;
+  constexpr bool kNL = KIND == K_NL;
+  const int lane = (int)__lane_id();
+  const int wid = uniform((int)(threadIdx.x / kWave));
+  // the tile count is produced on the device; never trust it past the array
+  const int ntiles = min((int)ldu(ntiles_dev), (int)(gridDim.x * (kBlock / kWave)));
+  // XCD-aware order: consecutive tiles (neighbouring cells, shared rows in
+  // L2) go to the same XCD, assuming round-robin dispatch of blocks to XCDs.
+  const int nblk = gridDim.x;
+  int b = blockIdx.x;
+  if (nblk >= 8) {
+    const int per = nblk / 8, rem = nblk % 8;
+    const int xcd = b % 8, k = b / 8;
+    b = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
+  }
+  const int tile_id = uniform(b * (kBlock / kWave) + wid);
+  if (tile_id >= ntiles) return;
+  const Tile T = ldu(&tiles[tile_id]);
+
+  Sweep<DIM, FP32, KIND> S;
+  S.lane = lane;
+  S.load_job(&jobs[T.job]);
+  if constexpr (kHist || kNL) {
+    const int nb = kHist ? S.nbins : 0;
+    unsigned char* base = smem + sweep_lds_per_wave(KIND, nb) * wid;
+    if constexpr (kHist) {
+      S.L.hist = (uint32_t*)base;
+      S.L.hsum = (double*)(((uintptr_t)(base + (size_t)(nb + 1) * 4) + 7) & ~(uintptr_t)7);
+      S.L.E32 = (float*)((unsigned char*)S.L.hsum + (size_t)nb * 8);
+      const float* E32g = ldu(&S.J->E32);
+      for (int k = lane; k <= nb; k += kWave) {
+        S.L.hist[k] = 0u;
+        S.L.E32[k] = E32g[k];
+        if (k < nb) S.L.hsum[k] = 0.0;
+      }
+    } else {
+      S.L.nl_ij = (uint32_t*)base;
+      S.L.nl_d = (double*)(base + (size_t)kNLStage * 8);
+      S.L.nl_fill = (int*)(base + (size_t)kNLStage * 16);
+      if (lane == 0) *S.L.nl_fill = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  }
+  S.run(T, tile_id);
+  if constexpr (kHist) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int nb = S.nbins;
+    unsigned long long* hist = ldu(&S.J->hist);
+    double* hsums = ldu(&S.J->hist_sums);
+    for (int k = lane; k <= nb; k += kWave) {
+      const uint32_t c = S.L.hist[k];
+      if (c) atomicAdd(&hist[k], (unsigned long long)c);
+      if (KIND == K_HIST_REL && S.want_sums && k < nb) {
+        const double sm = S.L.hsum[k];
+        if (sm != 0.0) atomicAdd(&hsums[k], sm);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- small box
+// Brute force over all pairs with the exact minimum-image search (used when
+// the grid has fewer than 3 cells on an axis).  FP64 only.  One thread per i.
+__device__ __forceinline__ double min_image64(const BruteArgs& A, const double* ri, const double* rj,
+                                              double* D, int* Kb) {
+  const int dim = A.dim;
+  double dr[3] = {rj[0] - ri[0], rj[1] - ri[1], dim == 3 ? rj[2] - ri[2] : 0.0};
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int d = 0; d < dim; ++d) {
+    double fs = A.Hinv[d * 3 + 0] * dr[0] + A.Hinv[d * 3 + 1] * dr[1] + A.Hinv[d * 3 + 2] * dr[2];
+    // images farther than half the sum of the lattice-vector lengths can never
+    // be the nearest one, so the search radius is min(rc, reach_max)
+    double R = A.reach / A.w[d] * (1.0 + 1e-6) + 1e-9;
+    lo[d] = (int)ceil(-fs - R);
+    hi[d] = (int)floor(-fs + R);
+  }
+  double best = __builtin_inf();
+  for (int k0 = lo[0]; k0 <= hi[0]; ++k0)
+    for (int k1 = lo[1]; k1 <= hi[1]; ++k1)
+      for (int k2 = (dim == 3 ? lo[2] : 0); k2 <= (dim == 3 ? hi[2] : 0); ++k2) {
+        double K[3] = {(double)k0, (double)k1, (double)k2};
+        double E[3];
+        for (int a = 0; a < dim; ++a) {
+          double tt = A.H[a * 3 + 0] * K[0];
+          tt = tt + A.H[a * 3 + 1] * K[1];
+          if (dim == 3) tt = tt + A.H[a * 3 + 2] * K[2];
+          E[a] = (rj[a] - ri[a]) + tt;
+        }
+        double d2 = E[0] * E[0] + E[1] * E[1];
+        if (dim == 3) d2 = d2 + E[2] * E[2];
+        if (d2 < best) {
+          best = d2;
+          for (int a = 0; a < 3; ++a) {
+            D[a] = a < dim ? E[a] : 0.0;
+            Kb[a] = a == 0 ? k0 : (a == 1 ? k1 : k2);
+          }
+        }
+      }
+  return best;
+}
+
+__global__ void __launch_bounds__(256) brute_kernel(const JobDesc* __restrict__ jobs, BruteArgs A) {
+  const JobDesc& J = jobs[0];
+  const int dim = A.dim;
+  const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = ii < A.n_x;
+  double accE = 0.0, G[3] = {0, 0, 0}, W[9] = {0}, B[9] = {0};
+  unsigned long long cnt = 0;
+  uint32_t io = 0;
+  if (act) {
+    const int i = ii;
+    io = J.idx_x[i];
+    const double4 r = J.r64_x[i];
+    const double ri[3] = {r.x, r.y, r.z};
+    double vi[3] = {0, 0, 0};
+    if (A.kind == K_HIST_REL)
+      for (int a = 0; a < dim; ++a) vi[a] = J.vel64_x[(size_t)io * dim + a];
+    const int ny = A.cross ? A.n_y : A.n_x;
+    const double4* __restrict__ R = A.cross ? J.r64_y : J.r64_x;
+    const uint32_t* __restrict__ IX = A.cross ? J.idx_y : J.idx_x;
+    const bool gather = A.kind == K_LJ_F;
+    for (int j = (A.cross || gather) ? 0 : i + 1; j < ny; ++j) {
+      if (!A.cross && j == i) continue;
+      const double4 rr = R[j];
+      const double rj[3] = {rr.x, rr.y, rr.z};
+      double D[3];
+      int K[3];
+      double d2 = min_image64(A, ri, rj, D, K);
+      if (!(d2 <= A.rc2)) continue;
+      const bool own = A.cross || !gather || i < j;  // unordered contributions once
+      if (own) cnt += 1;
+      switch (A.kind) {
+        case K_SUM_D: accE += sqrt(d2); break;
+        case K_SUM_INV_D: accE += 1.0 / sqrt(d2); break;
+        case K_LJ_E: case K_LJ_F: {
+          double x = J.s2 / d2, x3 = x * x * x;
+          double u = x3 * x3 - x3;
+          if (A.kind == K_LJ_E) { accE += u; break; }
+          double f = (2.0 * x3 * x3 - x3) / d2;
+          accE += 0.5 * u;
+          for (int a = 0; a < dim; ++a) G[a] += f * D[a];
+          for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) {
+              W[a * 3 + b] += 0.5 * f * D[a] * D[b];
+              B[a * 3 + b] += 0.5 * f * D[a] * (double)K[b];
+            }
+          break;
+        }
+        case K_HIST_DIST: {
+          int k = bin64(J.E64, J.nbins, d2);
+          atomicAdd(&J.hist[k], 1ull);
+          break;
+        }
+        case K_HIST_REL: {
+          uint32_t jo = IX[j];
+          const double* vv = A.cross ? J.vel64_y : J.vel64_x;
+          double dv[3] = {0, 0, 0};
+          for (int a = 0; a < dim; ++a) dv[a] = vv[(size_t)jo * dim + a] - vi[a];
+          double qq = dv[0] * dv[0] + dv[1] * dv[1];
+          if (dim == 3) qq = qq + dv[2] * dv[2];
+          int k = bin64(J.E64, J.nbins, qq);
+          atomicAdd(&J.hist[k], 1ull);
+          if (J.want_sums && k < J.nbins) atomicAdd(&J.hist_sums[k], sqrt(qq));
+          break;
+        }
+        case K_NL: {
+          uint32_t jo = IX[j];
+          uint32_t a = io, b = jo;
+          if (!A.cross && a > b) { uint32_t tt = a; a = b; b = tt; }
+          unsigned long long g = atomicAdd(J.nl_counter, 1ull);
+          if ((long long)g < J.capacity) {
+            J.pairs[2 * g] = (int32_t)a;
+            J.pairs[2 * g + 1] = (int32_t)b;
+            if (J.with_dist) J.dist[g] = sqrt(d2);
+          }
+          break;
+        }
+        default: break;
+      }
+    }
+    if (A.kind == K_LJ_F) {
+      double mult = J.upstream ? *J.upstream : J.scale;
+      double s = mult * 24.0 * J.eps;
+      for (int a = 0; a < dim; ++a) J.forces[(size_t)io * dim + a] = s * G[a];
+      const int4 w = J.wrap_x[i];
+      const int wv[3] = {w.x, w.y, w.z};
+      for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) B[a * 3 + b] += G[a] * (double)wv[b];
+    }
+  }
+  // block reduction into per-block partials (slots of the tile partial array)
+  __shared__ double red[256];
+  __shared__ unsigned long long redc[256];
+  double* Pp = J.partials + (size_t)blockIdx.x * kPartialD;
+  auto reduce_d = [&](double v) -> double {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+  };
+  redc[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) redc[threadIdx.x] += redc[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) J.pcount[blockIdx.x] = redc[0];
+  double e = reduce_d(accE);
+  if (threadIdx.x == 0) Pp[P_SUM] = e;
+  if (A.kind == K_LJ_F) {
+    for (int k = 0; k < 9; ++k) {
+      double v = reduce_d(W[k]);
+      if (threadIdx.x == 0) Pp[P_VIR + k] = v;
+      double b = reduce_d(B[k]);
+      if (threadIdx.x == 0) Pp[P_BOX + k] = b;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+// Fixed-order reduction of the per-tile partials of one job into the outputs.
+__global__ void __launch_bounds__(256) finalize_kernel(const JobDesc* __restrict__ jobs, FinalArgs F) {
+  const JobDesc& J = jobs[0];
+  __shared__ double red[256];
+  __shared__ unsigned long long redc[256];
+  const int tid = threadIdx.x;
+  const int nparts = F.nparts_dev ? min((int)*F.nparts_dev, F.nparts) : F.nparts;
+  unsigned long long c = 0;
+  for (int k = tid; k < nparts; k += 256) c += J.pcount[k];
+  redc[tid] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) redc[tid] += redc[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0 && F.count) *F.count = F.halve_count ? redc[0] / 2 : redc[0];
+  __syncthreads();
+  const int nslots = (F.kind == K_LJ_F) ? kPartialD : 1;
+  for (int slot = 0; slot < nslots; ++slot) {
+    double v = 0.0;
+    for (int k = tid; k < nparts; k += 256) v += J.partials[(size_t)k * kPartialD + slot];
+    red[tid] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      double tot = red[0];
+      if (slot == P_SUM && F.energy) {
+        double m = (F.kind == K_LJ_E || F.kind == K_LJ_F) ? 4.0 * F.eps : 1.0;
+        *F.energy = m * tot;
+      } else if (slot >= P_VIR && slot < P_VIR + 9 && F.virial && F.want_virial) {
+        int k = slot - P_VIR, a = k / 3, b = k % 3;
+        if (a < F.dim && b < F.dim) F.virial[a * F.dim + b] = 24.0 * F.eps * tot;
+      } else if (slot >= P_BOX && slot < P_BOX + 9 && F.grad_box) {
+        int k = slot - P_BOX, a = k / 3, b = k % 3;
+        double g = F.upstream ? *F.upstream : F.box_mult;
+        if (a < F.dim && b < F.dim) F.grad_box[a * F.dim + b] = -24.0 * F.eps * g * tot;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Relative-speed band from the largest velocity component (see clmap_api).
+__global__ void relspeed_band_kernel(const unsigned int* __restrict__ vmax_bits, double hi, int dim,
+                                     double* __restrict__ bandq) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double u = 5.9604644775390625e-08;  // 2^-24
+    double vmax = (double)__uint_as_float(*vmax_bits);
+    // per-component error of the FP32 velocity difference near an edge
+    // (|dv| <= 1.01 hi): u (|v_i| + |v_j| + |dv|), plus FP64 slack
+    double Ea = u * (2.0 * vmax + 1.01 * hi) * (1.0 + 1e-6) + 1e-300;
+    double E = sqrt((double)dim) * Ea;
+    // error of q = |dv|^2 (FMA chain: 3 roundings), doubled for safety, plus
+    // the FP32 rounding of the edge table
+    double b = 2.0 * (2.02 * hi * E + E * E + 4.1 * u * hi * hi) + 2.0 * u * hi * hi;
+    *bandq = b;
+  }
+}
+
+// Candidate pairs per tile (pairs the sweep tests with a valid lane), for
+// reporting only.
+__global__ void __launch_bounds__(256) candidates_kernel(const JobDesc* __restrict__ jobs,
+                                                         const Tile* __restrict__ tiles, int ntiles,
+                                                         int full, unsigned long long* out) {
+  const JobDesc& J = jobs[0];
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const Tile T = tiles[t];
+  const int l = J.lcell, nx = J.n[0], ny = J.n[1], nz = J.n[2];
+  const int dim = J.dim;
+  const int cy = (int)(T.row % (uint32_t)ny), cz = dim == 3 ? (int)(T.row / (uint32_t)ny) : 0;
+  const bool fs = full || J.cross;
+  const uint32_t* off = J.cross ? J.off_y : J.off_x;
+  unsigned long long c = 0;
+  for (int dz = dim == 3 ? -l : 0; dz <= (dim == 3 ? l : 0); ++dz)
+    for (int dy = -l; dy <= l; ++dy) {
+      if (!fs && (dz < 0 || (dz == 0 && dy < 0))) continue;
+      const bool home = !fs && dz == 0 && dy == 0;
+      const int uy = (cy + dy + ny) % ny, uz = dim == 3 ? (cz + dz + nz) % nz : 0;
+      const int rowbase = (uy + ny * uz) * nx;
+      const int xlo = home ? (int)T.cx0 : (int)T.cx0 - l, xhi = (int)T.cx1 + l;
+      for (int ux = xlo; ux <= xhi; ++ux) {
+        const bool wrapped = ux < 0 || ux >= nx;
+        const int cc = rowbase + ((ux % nx) + nx) % nx;
+        const uint32_t jb = off[cc], je = off[cc + 1];
+        for (int k = 0; k < T.count; ++k) {
+          const uint32_t i = T.start + (uint32_t)k;
+          if (home && !wrapped) {
+            uint32_t lo = jb > i + 1 ? jb : i + 1;
+            c += je > lo ? je - lo : 0;
+          } else if (fs && !J.cross && dz == 0 && dy == 0 && !wrapped && i >= jb && i < je) {
+            c += je - jb - 1;
+          } else {
+            c += je - jb;
+          }
+        }
+      }
+    }
+  out[t] = c;
+}
+
+// ---------------------------------------------------------------- job tables
+__global__ void set_job_kernel(JobDesc jd, JobDesc* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = jd;
+}
+
+// Canonical histogram edges: h = hi/nb, e_k = k*h, E_k = e_k*e_k (FP64, each
+// operation rounded on its own); E_nb = rc2 for a distance histogram up to
+// the cutoff.  E32 = nearest FP32 value.
+__global__ void hist_edges_kernel(double* E64, float* E32, int nb, double hi, int force_last,
+                                  double rc2) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > nb) return;
+  double h = hi / (double)nb;
+  double e = (double)k * h;
+  double E = e * e;
+  if (force_last && k == nb) E = rc2;
+  E64[k] = E;
+  E32[k] = (float)E;
+}
+
+// ---------------------------------------------------------------- launchers
+template <int DIM, bool FP32>
+static hipError_t sweep_dispatch(int kind, dim3 grid, size_t lds, const JobDesc* jobs,
+                                 const Tile* tiles, const uint32_t* nt, hipStream_t s) {
+  switch (kind) {
+    case K_COUNT: sweep_kernel<DIM, FP32, K_COUNT><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    case K_SUM_D: sweep_kernel<DIM, FP32, K_SUM_D><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    case K_SUM_INV_D: sweep_kernel<DIM, FP32, K_SUM_INV_D><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    case K_LJ_E: sweep_kernel<DIM, FP32, K_LJ_E><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    case K_LJ_F: sweep_kernel<DIM, FP32, K_LJ_F><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    case K_LJ_FV: sweep_kernel<DIM, FP32, K_LJ_FV><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    case K_HIST_DIST: sweep_kernel<DIM, FP32, K_HIST_DIST><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    case K_HIST_REL: sweep_kernel<DIM, FP32, K_HIST_REL><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    case K_NL: sweep_kernel<DIM, FP32, K_NL><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(int dim, bool fp32, int kind, const JobDesc* jobs, const Tile* tiles,
+                        const uint32_t* ntiles_dev, int max_tiles, int nbins, hipStream_t s) {
+  if (max_tiles <= 0) return hipSuccess;
+  const int waves = kBlock / kWave;
+  dim3 grid((max_tiles + waves - 1) / waves);
+  size_t lds = sweep_lds_per_wave(kind, nbins) * waves;
+  if (dim == 3)
+    return fp32 ? sweep_dispatch<3, true>(kind, grid, lds, jobs, tiles, ntiles_dev, s)
+                : sweep_dispatch<3, false>(kind, grid, lds, jobs, tiles, ntiles_dev, s);
+  return fp32 ? sweep_dispatch<2, true>(kind, grid, lds, jobs, tiles, ntiles_dev, s)
+              : sweep_dispatch<2, false>(kind, grid, lds, jobs, tiles, ntiles_dev, s);
+}
+
+hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, int* nblocks_out, hipStream_t s) {
+  int nb = (A.n_x + 255) / 256;
+  if (nb < 1) nb = 1;
+  *nblocks_out = nb;
+  brute_kernel<<<nb, 256, 0, s>>>(jobs, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, hipStream_t s) {
+  finalize_kernel<<<1, 256, 0, s>>>(jobs, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
+                             unsigned long long* out, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  candidates_kernel<<<(ntiles + 255) / 256, 256, 0, s>>>(jobs, tiles, ntiles, full, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_job(const JobDesc& jd, JobDesc* dst, hipStream_t s) {
+  set_job_kernel<<<1, 64, 0, s>>>(jd, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_edges(double* E64, float* E32, int nbins, double hi, int force_last,
+                             double rc2, hipStream_t s) {
+  hist_edges_kernel<<<(nbins + 1 + 255) / 256, 256, 0, s>>>(E64, E32, nbins, hi, force_last, rc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_relspeed_band(const unsigned int* vmax_bits, double hi, int dim, double* bandq,
+                                hipStream_t s) {
+  relspeed_band_kernel<<<1, 64, 0, s>>>(vmax_bits, hi, dim, bandq);
+  return hipGetLastError();
+}
+
+}  // namespace clm

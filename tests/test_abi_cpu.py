@@ -1,0 +1,169 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/clmap.h declares, validates its arguments, and sets up box geometry
+(host FP64) exactly as the canonical definitions say."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_2202_06427_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "clmap.h")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:clm_status|const char\*)\s+(clm_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def _box(dim, H, rc, lcell=1):
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    h = ctypes.c_void_p()
+    st = L.lib().clm_box_create(dim, H.ctypes.data_as(_dp), rc, lcell, ctypes.byref(h))
+    return st, h
+
+
+def _info(h):
+    bi = L.BoxInfo()
+    assert L.lib().clm_box_info_get(h, ctypes.byref(bi)) == 0
+    return bi
+
+
+@pytest.mark.parametrize("dim,H,rc,lcell,status", [
+    (4, np.eye(4), 1.0, 1, 2),
+    (1, np.eye(1), 1.0, 1, 2),
+    (3, np.diag([10.0, 10.0, -10.0]), 1.0, 1, 2),       # left-handed / det < 0
+    (3, np.zeros((3, 3)), 1.0, 1, 2),                  # degenerate
+    (3, np.diag([10.0, np.nan, 10.0]), 1.0, 1, 2),     # non-finite
+    (3, np.eye(3) * 10, 0.0, 1, 3),                    # cutoff 0
+    (3, np.eye(3) * 10, -1.0, 1, 3),
+    (3, np.eye(3) * 10, float("inf"), 1, 3),
+    (3, np.eye(3) * 10, 1.0, 0, 3),                    # lcell 0
+    (2, np.eye(2) * 10, 1.0, 1, 0),
+])
+def test_box_validation(dim, H, rc, lcell, status):
+    st, h = _box(dim, H, rc, lcell)
+    assert st == status, L.lib().clm_last_error()
+    if st == 0:
+        L.lib().clm_box_destroy(h)
+    else:
+        assert len(L.lib().clm_last_error()) > 0
+
+
+BOXES = [
+    np.diag([46.42] * 3),
+    W.triclinic_h((215.4, 215.4, 215.4), (80.0, 95.0, 100.0)),
+    W.triclinic_h((20.0, 22.0, 21.0), (70.0, 110.0, 75.0)),
+    np.array([[10.0, 0.0, 0.0], [0.0, 10.0, 0.0], [0.0, 20.0, 10.0]]),  # Code 3 triclinic
+    np.array([[24.0, -7.0], [0.0, 22.0]]),
+    np.eye(2),
+]
+
+
+@pytest.mark.parametrize("k", range(len(BOXES)))
+def test_inverse_matches_canonical_definition_bitwise(k):
+    H = BOXES[k]
+    dim = H.shape[0]
+    st, h = _box(dim, H, 0.01 * H[0, 0], 1)
+    assert st == 0
+    bi = _info(h)
+    Hinv = np.array(bi.Hinv[: dim * dim]).reshape(dim, dim)
+    assert np.array_equal(Hinv, oracle.box_inverse(H))  # same written definition, bit for bit
+    w, V = oracle.box_widths(H)
+    assert np.allclose(bi.widths[:dim], w, rtol=1e-13)
+    assert math.isclose(bi.volume, V, rel_tol=1e-13)
+    L.lib().clm_box_destroy(h)
+
+
+@pytest.mark.parametrize("k", range(len(BOXES)))
+@pytest.mark.parametrize("lcell", [1, 2, 3])
+def test_grid_covers_the_cutoff(k, lcell):
+    H = BOXES[k]
+    dim = H.shape[0]
+    w, _ = oracle.box_widths(H)
+    for rc in (w.min() / 3.5, w.min() / 7.3, w.min() / 20.0):
+        st, h = _box(dim, H, rc, lcell)
+        assert st == 0
+        bi = _info(h)
+        assert not bi.small_box
+        lc = bi.lcell
+        assert 1 <= lc <= lcell
+        for d in range(dim):
+            n = bi.grid[d]
+            assert n >= 2 * lc + 1
+            assert w[d] / n >= rc / lc  # cell width along every face normal >= rc / lcell
+        assert bi.guard_band > 0 and bi.guard_band < 1e-4 * bi.rc2
+        assert bi.rc2 == rc * rc
+        L.lib().clm_box_destroy(h)
+
+
+def test_small_box_flag_and_lcell_fallback():
+    st, h = _box(3, np.eye(3) * 10.0, 4.0, 1)  # 2 cells per axis: brute force
+    assert st == 0 and _info(h).small_box == 1
+    L.lib().clm_box_destroy(h)
+    # 2l+1 cells of side >= rc/l fit when rc <= L l / (2l+1): rc 4.1 needs l = 3
+    st, h = _box(3, np.eye(3) * 10.0, 4.1, 1)
+    assert st == 0 and _info(h).small_box == 1
+    L.lib().clm_box_destroy(h)
+    st, h = _box(3, np.eye(3) * 10.0, 4.1, 3)
+    bi = _info(h)
+    assert st == 0 and bi.small_box == 0 and bi.lcell == 3 and list(bi.grid) == [7, 7, 7]
+    L.lib().clm_box_destroy(h)
+
+
+def test_lengths_angles_constructor():
+    la = np.array([215.4, 215.4, 215.4])
+    an = np.array([80.0, 95.0, 100.0])
+    h = ctypes.c_void_p()
+    assert L.lib().clm_box_from_lengths_angles(la.ctypes.data_as(_dp), an.ctypes.data_as(_dp), 12.0, 2,
+                                               ctypes.byref(h)) == 0
+    bi = _info(h)
+    H = np.array(bi.H[:9]).reshape(3, 3)
+    assert np.allclose(H, oracle.box_from_lengths_angles(la, an), rtol=1e-14, atol=1e-12)
+    assert list(bi.grid) == [35, 34, 35] and bi.lcell == 2
+    L.lib().clm_box_destroy(h)
+    bad = np.array([80.0, 80.0, 170.0])
+    assert L.lib().clm_box_from_lengths_angles(la.ctypes.data_as(_dp), bad.ctypes.data_as(_dp), 12.0, 2,
+                                               ctypes.byref(h)) == 2
+
+
+def test_workspace_bytes():
+    st, h = _box(3, BOXES[1], 12.0, 2)
+    sizes = []
+    for n in (0, 1, 1000, 1_000_000):
+        b = ctypes.c_size_t(0)
+        assert L.lib().clm_celllist_workspace_bytes(h, n, 0, L.CLM_FP32_GUARD, ctypes.byref(b)) == 0
+        sizes.append(b.value)
+    assert sizes == sorted(sizes) and sizes[-1] > 1_000_000 * 64
+    b = ctypes.c_size_t(0)
+    assert L.lib().clm_celllist_workspace_bytes(h, -1, 0, 1, ctypes.byref(b)) == 1
+    assert L.lib().clm_celllist_workspace_bytes(h, 10, 0, 7, ctypes.byref(b)) == 1
+    assert L.lib().clm_celllist_workspace_bytes(None, 10, 0, 1, ctypes.byref(b)) == 1
+    L.lib().clm_box_destroy(h)
+
+
+def test_null_arguments_are_rejected_not_crashed():
+    lib = L.lib()
+    assert lib.clm_map(None, 0, None, None) == 1
+    assert lib.clm_celllist_build(None, None, None) == 1
+    assert lib.clm_celllist_info_get(None, None) == 1
+    assert lib.clm_synchronize(None) == 1
+    assert lib.clm_box_info_get(None, None) == 1
+    assert lib.clm_status_string(4) == b"CLM_E_CAPACITY"
