@@ -1,0 +1,188 @@
+"""Benchmark: within-cutoff pairs/s of the cell-list hot path on one MI355X.
+
+Workload (the headline configuration): 1,000,000 uniform-random particles in
+a triclinic periodic box (lengths 215.4, angles 80/95/100 degrees), cutoff
+12, Lennard-Jones energy + forces (sigma 3.4, epsilon 0.238) through the
+adjoint sweep.  One step = one pass of the whole hot path over the resident
+positions: bin (wrap, cell index, prefix scan, tiles, scatter) + the
+full-shell LJ sweep with fused energy/force/box-gradient reduction +
+finalize.  The FP32+guard form is the headline value; the plain FP64 form is
+reported beside it.
+
+Prints ONE JSON line (see the repository's benchmark contract).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks used as roofline denominators
+HBM_PEAK_GBS = 8000.0
+VALU_FP32_NONPACKED_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+VALU_FP32_PACKED_TFLOPS = 157.3     # needs packed FP32, which this build does not emit
+VALU_FP64_TFLOPS = 78.6
+
+# algorithmic work per unit (what the method must do)
+FLOPS_PER_CANDIDATE = 8        # 3 sub, 3 mul, 2 add (distance test)
+FLOPS_PER_LJ_PAIR = 20         # 1 reciprocal + ~19 flops: energy + force on both particles
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--lcell", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def time_steps(clm, cl, xt, steps, warmup, sigma, eps):
+    import torch
+    for _ in range(warmup):
+        cl.build(xt)
+        out = cl.lj_forces(sigma, eps)
+    torch.cuda.synchronize()
+    clm.set_timing(True)
+    clm.stats(reset=True)
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        cl.build(xt)
+        out = cl.lj_forces(sigma, eps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = clm.stats(reset=True)
+    clm.set_timing(False)
+    return {
+        "ms_per_step": ev0.elapsed_time(ev1) / steps,
+        "wall_ms_per_step": 1e3 * wall / steps,
+        "sweep_ms": st["sweep_ms"] / max(st["sweeps"], 1),
+        "build_ms": st["build_ms"] / max(st["builds"], 1),
+        "count": int(out["count"].item()),
+        "energy": float(out["energy"].item()),
+    }
+
+
+def cpu_baseline(cfg, nthreads):
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.compute(cfg["x"], cfg["H"], cfg["cutoff"], lj=(cfg["sigma"], cfg["epsilon"]),
+                       lj_grad=True, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return r, dt
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (single-GPU workload; no collectives). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2202_06427_amd as clm
+    import workloads as W
+
+    cfg = W.config2(n=args.n)
+    sigma, eps = cfg["sigma"], cfg["epsilon"]
+    xt = torch.from_numpy(cfg["x"]).to("cuda:0")
+    box = clm.Box(cfg["H"], cfg["cutoff"], args.lcell)
+    binfo = box.info()
+    log(f"box grid {binfo['grid']} lcell {binfo['lcell']} band {binfo['guard_band']:.3e}")
+
+    res = {}
+    for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
+        cl = clm.CellList(xt, box, precision=prec)
+        info = cl.info()
+        r = time_steps(clm, cl, xt, args.steps, args.warmup, sigma, eps)
+        r["info"] = info
+        res[prec] = r
+        log(f"{prec}: {r['ms_per_step']:.3f} ms/step (sweep {r['sweep_ms']:.3f} ms, build "
+            f"{r['build_ms']:.3f} ms) pairs {r['count']} cand(half) {info['candidate_pairs']}")
+        del cl
+        torch.cuda.empty_cache()
+
+    main_r = res["fp32"]
+    pairs = main_r["count"]
+    value = pairs / (main_r["ms_per_step"] * 1e-3)
+    cand = main_r["info"]["candidate_pairs"]
+    flops = cand * FLOPS_PER_CANDIDATE + pairs * FLOPS_PER_LJ_PAIR
+    achieved = flops / (main_r["sweep_ms"] * 1e-3) / 1e12
+    line = {
+        "metric": "within-cutoff pairs/s at 1M particles, FP32 vs FP64; served p50/p99 latency",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "uniform-1e6-triclinic-215.4-80/95/100-rc12 LJ energy+forces (bin + sweep + reduce)",
+            "n": args.n, "cutoff": cfg["cutoff"], "lcell": binfo["lcell"], "grid": binfo["grid"],
+            "sigma": sigma, "epsilon": eps, "pairs": pairs, "candidate_pairs_half_shell": cand,
+        },
+        "phases_ms": {"build": main_r["build_ms"], "sweep": main_r["sweep_ms"]},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "sweep_kernel<3,fp32,LJ forces>",
+            "achieved": achieved,
+            "peak": VALU_FP32_NONPACKED_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / VALU_FP32_NONPACKED_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": flops,
+            "peak_if_packed_fp32": VALU_FP32_PACKED_TFLOPS,
+        },
+    }
+    if "fp64" in res:
+        r64 = res["fp64"]
+        line["fp64"] = {
+            "value": r64["count"] / (r64["ms_per_step"] * 1e-3),
+            "ms_per_step": r64["ms_per_step"],
+            "sweep_ms": r64["sweep_ms"],
+            "build_ms": r64["build_ms"],
+            "pairs": r64["count"],
+            "energy": r64["energy"],
+        }
+        line["fp32_over_fp64"] = value / line["fp64"]["value"]
+        line["energy_rel_diff_fp32_fp64"] = abs(main_r["energy"] - r64["energy"]) / abs(r64["energy"])
+    if not args.no_cpu_baseline:
+        nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        log(f"cpu baseline: oracle on the full workload with {nth} threads ...")
+        r, dt = cpu_baseline(cfg, nth)
+        line["cpu_baseline"] = {
+            "value": r["count"] / dt,
+            "unit": "pairs/s",
+            "cores": nth,
+            "kind": "oracle",
+            "sample": f"the full workload once (n={args.n}, LJ energy+forces, FP64 plain cell list), {dt:.1f} s",
+            "pairs": r["count"],
+            "pairs_match_gpu": r["count"] == pairs,
+            "energy_rel_err_fp32": abs(main_r["energy"] - r["lj_energy"]) / abs(r["lj_energy"]),
+        }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

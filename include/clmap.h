@@ -182,6 +182,21 @@ clm_status clm_celllist_info_get(clm_celllist* cl, clm_celllist_info* out);
 clm_status clm_celllist_destroy(clm_celllist* cl);
 
 clm_status clm_synchronize(clm_context* ctx);
+
+/* Kernel timing (tracing aid).  When enabled, the library records HIP events
+ * on the context's stream around every build (bin + scan + tiles + scatter)
+ * and around every sweep kernel of clm_map.  clm_stats_get synchronizes,
+ * returns the accumulated times and counts, and clears them when reset != 0.
+ * Events are host-side runtime objects; no device memory is allocated. */
+typedef struct clm_stats {
+  int64_t builds;
+  int64_t sweeps;
+  double build_ms;   /* sum of build durations */
+  double sweep_ms;   /* sum of sweep-kernel durations */
+  double last_sweep_ms;
+} clm_stats;
+clm_status clm_context_set_timing(clm_context* ctx, int enable);
+clm_status clm_stats_get(clm_context* ctx, clm_stats* out, int reset);
 const char* clm_last_error(void);
 const char* clm_status_string(clm_status s);
 

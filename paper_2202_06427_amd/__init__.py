@@ -41,6 +41,20 @@ def _context(device):
     return h
 
 
+def set_timing(enable, device=None):
+    """Record HIP events around every build and sweep kernel on `device`."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    L.check(L.lib().clm_context_set_timing(_context(dev), int(bool(enable))))
+
+
+def stats(reset=True, device=None):
+    """Accumulated build / sweep kernel times (ms) since the last reset (synchronizes)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    st = L.Stats()
+    L.check(L.lib().clm_stats_get(_context(dev), ctypes.byref(st), int(bool(reset))))
+    return {k: getattr(st, k) for k, _ in L.Stats._fields_}
+
+
 # ---------------------------------------------------------------- box
 class Box:
     """Periodic box: H with the lattice vectors as columns (paper Code 3), a
@@ -89,8 +103,8 @@ class Box:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and L._lib is not None:
-            L.lib().clm_box_destroy(h)
+        if h is not None and L is not None and L._lib is not None:
+            L._lib.clm_box_destroy(h)
             self._h = None
 
 
@@ -164,8 +178,8 @@ class CellList:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and L._lib is not None:
-            L.lib().clm_celllist_destroy(h)
+        if h is not None and L is not None and L._lib is not None:
+            L._lib.clm_celllist_destroy(h)
             self._h = None
 
     # ------------------------------------------------------------ maps

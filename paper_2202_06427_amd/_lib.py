@@ -63,12 +63,19 @@ class MapOut(ctypes.Structure):
     ]
 
 
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("builds", ctypes.c_int64), ("sweeps", ctypes.c_int64), ("build_ms", ctypes.c_double),
+        ("sweep_ms", ctypes.c_double), ("last_sweep_ms", ctypes.c_double),
+    ]
+
+
 EXPORTS = [
     "clm_context_create", "clm_context_set_stream", "clm_context_destroy", "clm_box_create",
     "clm_box_from_lengths_angles", "clm_box_info_get", "clm_box_destroy",
     "clm_celllist_workspace_bytes", "clm_celllist_create", "clm_celllist_build", "clm_map",
     "clm_celllist_info_get", "clm_celllist_destroy", "clm_synchronize", "clm_last_error",
-    "clm_status_string",
+    "clm_status_string", "clm_context_set_timing", "clm_stats_get",
 ]
 
 _lib = None
@@ -103,6 +110,8 @@ def lib():
     L.clm_celllist_info_get.argtypes = [_vp, ctypes.POINTER(CellListInfo)]
     L.clm_celllist_destroy.argtypes = [_vp]
     L.clm_synchronize.argtypes = [_vp]
+    L.clm_context_set_timing.argtypes = [_vp, c_int]
+    L.clm_stats_get.argtypes = [_vp, ctypes.POINTER(Stats), c_int]
     L.clm_last_error.restype = ctypes.c_char_p
     L.clm_status_string.restype = ctypes.c_char_p
     L.clm_status_string.argtypes = [c_int]

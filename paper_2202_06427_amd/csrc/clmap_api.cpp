@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/clmap.h"
 #include "clmap_internal.h"
@@ -40,9 +41,51 @@ static clm_status fail(clm_status s, const char* fmt, ...) {
   } while (0)
 
 // ---------------------------------------------------------------- objects
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
 struct clm_context {
   int device;
   hipStream_t stream;
+  bool timing = false;
+  std::vector<EventPair> pool;               // reusable events
+  std::vector<EventPair> build_ev, sweep_ev; // recorded, not yet read
+};
+
+static clm_status take_events(clm_context* c, EventPair* out) {
+  if (!c->pool.empty()) {
+    *out = c->pool.back();
+    c->pool.pop_back();
+    return CLM_OK;
+  }
+  CLM_HIP(hipEventCreate(&out->a));
+  CLM_HIP(hipEventCreate(&out->b));
+  return CLM_OK;
+}
+
+// Records a start event when timing is on; `stop` records the end.
+struct Timed {
+  clm_context* c;
+  std::vector<EventPair>* dst;
+  EventPair ev;
+  bool on = false;
+  Timed(clm_context* ctx, std::vector<EventPair>* d) : c(ctx), dst(d) {}
+  clm_status start() {
+    if (!c->timing || dst->size() >= 4096) return CLM_OK;
+    clm_status s = take_events(c, &ev);
+    if (s != CLM_OK) return s;
+    CLM_HIP(hipEventRecord(ev.a, c->stream));
+    on = true;
+    return CLM_OK;
+  }
+  clm_status stop() {
+    if (!on) return CLM_OK;
+    CLM_HIP(hipEventRecord(ev.b, c->stream));
+    dst->push_back(ev);
+    on = false;
+    return CLM_OK;
+  }
 };
 
 struct clm_box {
@@ -109,6 +152,8 @@ struct clm_celllist {
   unsigned int* vmax_bits;
   unsigned long long* nl_counter;
   unsigned long long* cand;
+  double* fin_scratch;
+  unsigned long long* fin_count;
   int built;
 };
 
@@ -341,6 +386,8 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
   size_t o_vm = c.take(sizeof(unsigned int) * 2);
   size_t o_nlc = c.take(sizeof(unsigned long long) * 2);
   size_t o_cand = c.take(sizeof(unsigned long long) * maxt);
+  size_t o_fin = c.take(sizeof(double) * kPartialD * kFinalBlocks);
+  size_t o_finc = c.take(sizeof(unsigned long long) * kFinalBlocks);
   if (base) {
     cl->scan_scratch = (uint32_t*)(base + o_scan);
     cl->row_tiles = (uint32_t*)(base + o_rt);
@@ -355,6 +402,8 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
     cl->vmax_bits = (unsigned int*)(base + o_vm);
     cl->nl_counter = (unsigned long long*)(base + o_nlc);
     cl->cand = (unsigned long long*)(base + o_cand);
+    cl->fin_scratch = (double*)(base + o_fin);
+    cl->fin_count = (unsigned long long*)(base + o_finc);
     cl->max_tiles = (int)maxt;
     cl->max_parts = (int)parts;
     cl->nrows = nrows;
@@ -402,7 +451,48 @@ clm_status clm_context_set_stream(clm_context* ctx, void* hip_stream) {
 }
 
 clm_status clm_context_destroy(clm_context* ctx) {
+  if (!ctx) return CLM_OK;
+  for (auto* v : {&ctx->pool, &ctx->build_ev, &ctx->sweep_ev})
+    for (auto& e : *v) {
+      if (e.a) (void)hipEventDestroy(e.a);
+      if (e.b) (void)hipEventDestroy(e.b);
+    }
   delete ctx;
+  return CLM_OK;
+}
+
+clm_status clm_context_set_timing(clm_context* ctx, int enable) {
+  if (!ctx) return fail(CLM_E_INVALID_ARG, "ctx is NULL");
+  ctx->timing = enable != 0;
+  return CLM_OK;
+}
+
+clm_status clm_stats_get(clm_context* ctx, clm_stats* out, int reset) {
+  if (!ctx || !out) return fail(CLM_E_INVALID_ARG, "NULL argument");
+  CLM_HIP(hipSetDevice(ctx->device));
+  std::memset(out, 0, sizeof *out);
+  auto sum = [&](std::vector<EventPair>& v, double* total, double* last) -> clm_status {
+    for (auto& e : v) {
+      CLM_HIP(hipEventSynchronize(e.b));
+      float ms = 0.0f;
+      CLM_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+      *total += ms;
+      if (last) *last = ms;
+    }
+    return CLM_OK;
+  };
+  clm_status s = sum(ctx->build_ev, &out->build_ms, nullptr);
+  if (s != CLM_OK) return s;
+  s = sum(ctx->sweep_ev, &out->sweep_ms, &out->last_sweep_ms);
+  if (s != CLM_OK) return s;
+  out->builds = (int64_t)ctx->build_ev.size();
+  out->sweeps = (int64_t)ctx->sweep_ev.size();
+  if (reset) {
+    for (auto& e : ctx->build_ev) ctx->pool.push_back(e);
+    for (auto& e : ctx->sweep_ev) ctx->pool.push_back(e);
+    ctx->build_ev.clear();
+    ctx->sweep_ev.clear();
+  }
   return CLM_OK;
 }
 
@@ -550,7 +640,10 @@ clm_status clm_celllist_build(clm_celllist* cl, const double* x, const double* y
   if (cl->cross && cl->ny > 0 && !y) return fail(CLM_E_INVALID_ARG, "y is NULL for a cross set");
   if (!cl->cross && y) return fail(CLM_E_INVALID_ARG, "y given but the cell list has n_y = 0");
   CLM_HIP(hipSetDevice(cl->ctx->device));
-  clm_status s = build_set(cl, x, cl->nx, cl->X);
+  Timed tb(cl->ctx, &cl->ctx->build_ev);
+  clm_status s = tb.start();
+  if (s != CLM_OK) return s;
+  s = build_set(cl, x, cl->nx, cl->X);
   if (s != CLM_OK) return s;
   if (cl->cross) {
     s = build_set(cl, y, cl->ny, cl->Y);
@@ -566,6 +659,8 @@ clm_status clm_celllist_build(clm_celllist* cl, const double* x, const double* y
     CLM_HIP(launch_tiles(cl->X.off, tg, cl->row_tiles, cl->row_off, cl->scan_scratch, cl->tiles,
                          cl->ctx->stream));
   }
+  s = tb.stop();
+  if (s != CLM_OK) return s;
   cl->built = 1;
   return CLM_OK;
 }
@@ -750,17 +845,27 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
       // the brute path accumulates straight into the (zeroed) global histogram
     }
     int nblocks = 0;
+    Timed ts(cl->ctx, &cl->ctx->sweep_ev);
+    clm_status s0 = ts.start();
+    if (s0 != CLM_OK) return s0;
     CLM_HIP(launch_brute(cl->job_dev, A, &nblocks, st));
+    s0 = ts.stop();
+    if (s0 != CLM_OK) return s0;
     F.nparts = nblocks;
     F.nparts_dev = nullptr;
   } else {
+    Timed ts(cl->ctx, &cl->ctx->sweep_ev);
+    clm_status s0 = ts.start();
+    if (s0 != CLM_OK) return s0;
     CLM_HIP(launch_sweep(dim, cl->prec == CLM_FP32_GUARD, k_launch, cl->job_dev, cl->tiles,
                          &cl->row_off[cl->nrows], cl->max_tiles, hist ? P->nbins : 0, st));
+    s0 = ts.stop();
+    if (s0 != CLM_OK) return s0;
     F.nparts = cl->max_tiles;
     F.nparts_dev = &cl->row_off[cl->nrows];
     F.halve_count = ljf && !cl->cross ? 1 : 0;
   }
-  CLM_HIP(launch_finalize(cl->job_dev, F, st));
+  CLM_HIP(launch_finalize(cl->job_dev, F, cl->fin_scratch, cl->fin_count, st));
   return CLM_OK;
 }
 

@@ -101,16 +101,25 @@ struct JobDesc {
   int tile_begin, tile_end;  // this job's tiles
 };
 
-// Dynamic LDS bytes per wave of the sweep: histogram kinds keep a private
-// histogram (nbins+1 u32), per-bin FP64 sums and the FP32 edge table; the
-// neighbour list keeps a staging area (pairs, distances, fill counter).
-__host__ __device__ inline size_t sweep_lds_per_wave(int kind, int nbins) {
-  if (kind == K_HIST_DIST || kind == K_HIST_REL) {
-    size_t b = (size_t)(nbins + 1) * 4 + 8 + (size_t)nbins * 8 + (size_t)(nbins + 1) * 4;
-    return (b + 15) & ~(size_t)15;
-  }
-  if (kind == K_NL) return (size_t)kNLStage * 16 + 16;
-  return 0;
+// Dynamic LDS bytes per wave of the sweep.  The FP32 form keeps a ring
+// queue of candidates to re-evaluate in FP64 (kQueueCap entries of 8 bytes)
+// and, for LJ forces, per-lane FP64 force accumulators fed by that queue.
+// Histogram kinds add a private histogram (nbins+1 u32), per-bin FP64 sums
+// and the FP32 edge table; the neighbour list adds a staging area.
+constexpr int kQueueCap = 512;  // power of two
+__host__ __device__ inline size_t sweep_lds_queue_bytes(int kind, bool fp32) {
+  if (!fp32) return 0;
+  size_t b = (size_t)kQueueCap * 8;
+  if (kind == K_LJ_F || kind == K_LJ_FV) b += (size_t)kWave * 3 * 8;
+  return b;
+}
+__host__ __device__ inline size_t sweep_lds_per_wave(int kind, int nbins, bool fp32) {
+  size_t b = sweep_lds_queue_bytes(kind, fp32);
+  if (kind == K_HIST_DIST || kind == K_HIST_REL)
+    b += (size_t)(nbins + 1) * 4 + 8 + (size_t)nbins * 8 + (size_t)(nbins + 1) * 4;
+  else if (kind == K_NL)
+    b += (size_t)kNLStage * 16 + 16;
+  return (b + 15) & ~(size_t)15;
 }
 
 __host__ __device__ inline int kcode(int px, int py, int pz) {
@@ -179,7 +188,9 @@ hipError_t launch_relspeed_band(const unsigned int* vmax_bits, double hi, int di
 hipError_t launch_sweep(int dim, bool fp32, int kind, const JobDesc* jobs, const Tile* tiles,
                         const uint32_t* ntiles_dev, int max_tiles, int nbins, hipStream_t s);
 hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, int* nblocks_out, hipStream_t s);
-hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, hipStream_t s);
+hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, double* scratch,
+                           unsigned long long* scratch_count, hipStream_t s);
+constexpr int kFinalBlocks = 128;  // first-level blocks of the two-level finalize
 hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
                              unsigned long long* out, hipStream_t s);
 

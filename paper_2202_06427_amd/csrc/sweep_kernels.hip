@@ -138,6 +138,12 @@ struct Sweep {
   const uint32_t* OFF;
   const double* E64;
   WaveLds L;
+  // FP64 re-evaluation queue (FP32 form): ring of kQueueCap entries
+  // (j, lane | kcode << 8 | count_it << 16) in LDS; head/tail are uniform
+  uint2* Q;
+  double* GA;          // per-lane FP64 force accumulators fed by the queue
+  uint32_t qhead, qtail;
+  uint32_t tstart;
   // ---- per lane
   int lane;
   bool active;
@@ -302,29 +308,107 @@ struct Sweep {
     if constexpr (kNL) nl_one(j, sqrt(d2));
   }
 
-  // ---------------- uncertain / near candidate: canonical FP64
-  __device__ __forceinline__ void special(uint32_t j, bool count_it) {
-    const double4 rj = ldu(&R[j]);
+  // ---------------- FP64 re-evaluation queue (FP32 form)
+  // Append this iteration's special lanes (uniform control flow).
+  __device__ __forceinline__ void enqueue(bool spec, uint32_t j, int kc, bool band) {
+    const unsigned long long m = __ballot(spec);
+    if (m == 0) return;
+    if (spec) {
+      const uint32_t slot = (qtail + (uint32_t)lane_rank(m)) & (uint32_t)(kQueueCap - 1);
+      Q[slot] = make_uint2(j, (uint32_t)lane | ((uint32_t)kc << 8) | (band ? (1u << 16) : 0u));
+    }
+    qtail += (uint32_t)__popcll(m);
+  }
+
+  // Canonical FP64 evaluation of one queued candidate by this lane; results
+  // of the owning lane's particle go through LDS atomics.
+  __device__ __forceinline__ void process(const uint2 e) {
+    const uint32_t j = e.x;
+    const int own = (int)(e.y & 63u);
+    const int kc = (int)((e.y >> 8) & 31u);
+    const bool count_it = ((e.y >> 16) & 1u) != 0u;
+    const uint32_t iL = tstart + (uint32_t)own;
+    const double4 rI = ldu(&J->r64_x)[iL];
+    const double4 rJ = R[j];
+    const double* tk = &J->tK[kc * 4];
     double D[3];
-    D[0] = (rj.x - ri[0]) + t[0];
-    D[1] = (rj.y - ri[1]) + t[1];
+    D[0] = (rJ.x - rI.x) + tk[0];
+    D[1] = (rJ.y - rI.y) + tk[1];
     double d2 = D[0] * D[0] + D[1] * D[1];
     if (DIM == 3) {
-      D[2] = (rj.z - ri[2]) + t[2];
+      D[2] = (rJ.z - rI.z) + tk[2];
       d2 = d2 + D[2] * D[2];
     } else {
       D[2] = 0.0;
     }
-    if (d2 <= rc2) pair64(d2, D, j, count_it);
+    if (!(d2 <= rc2)) return;
+    if (count_it) cnt_lane += 1;
+    if constexpr (KIND == K_SUM_D) accE += sqrt(d2);
+    if constexpr (KIND == K_SUM_INV_D) accE += 1.0 / sqrt(d2);
+    if constexpr (kLJ) {
+      const double x = s2 / d2;
+      const double x3 = x * x * x;
+      const double u = x3 * x3 - x3;
+      if constexpr (KIND == K_LJ_E) {
+        accE += u;
+      } else {
+        const double f = (2.0 * x3 * x3 - x3) / d2;
+        accE += 0.5 * u;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) atomicAdd(&GA[own * 3 + a], f * D[a]);
+        const int pk[3] = {kc % 3 - 1, (kc / 3) % 3 - 1, kc / 9 - 1};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int b = 0; b < DIM; ++b) B[a * 3 + b] += 0.5 * f * D[a] * (double)pk[b];
+        if constexpr (kVir) {
+          W[0] += 0.5 * f * D[0] * D[0];
+          W[1] += 0.5 * f * D[0] * D[1];
+          W[3] += 0.5 * f * D[1] * D[1];
+          if (DIM == 3) {
+            W[2] += 0.5 * f * D[0] * D[2];
+            W[4] += 0.5 * f * D[1] * D[2];
+            W[5] += 0.5 * f * D[2] * D[2];
+          }
+        }
+      }
+    }
+    if constexpr (KIND == K_HIST_DIST) atomicAdd(&L.hist[bin64(E64, nbins, d2)], 1u);
+    if constexpr (kRel) {
+      const uint32_t io = ldu(&J->idx_x)[iL];
+      const double* v64 = ldu(&J->vel64_x);
+      const uint32_t jo = IDXJ[j];
+      double dv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) dv[a] = VJ64[(size_t)jo * DIM + a] - v64[(size_t)io * DIM + a];
+      double qq = dv[0] * dv[0] + dv[1] * dv[1];
+      if (DIM == 3) qq = qq + dv[2] * dv[2];
+      const int k = bin64(E64, nbins, qq);
+      atomicAdd(&L.hist[k], 1u);
+      if (want_sums && k < nbins) atomicAdd(&L.hsum[k], sqrt(qq));
+    }
+    if constexpr (kNL) {
+      uint32_t a = ldu(&J->idx_x)[iL], b = IDXJ[j];
+      if (!cross && a > b) { uint32_t tmp = a; a = b; b = tmp; }
+      const unsigned long long g = atomicAdd(ldu(&J->nl_counter), 1ull);
+      nl_emit(a, b, sqrt(d2), g);
+    }
+  }
+
+  // Process queued entries 64 at a time (all: also a final partial batch).
+  __device__ __forceinline__ void drain(bool all) {
+    while (qtail - qhead >= (uint32_t)kWave || (all && qtail != qhead)) {
+      const uint32_t nb = min(qtail - qhead, (uint32_t)kWave);
+      if ((uint32_t)lane < nb) process(Q[(qhead + (uint32_t)lane) & (uint32_t)(kQueueCap - 1)]);
+      qhead += nb;
+    }
   }
 
   // ---------------- one candidate
   // FILTER: 0 none, 1 j > i (home row), 2 j != i (own cell, full shell)
-  // Returns 0 (done), 1 (special, membership known) or 3 (special, band:
-  // membership decided in FP64 and counted there).
   template <int FILTER>
-  __device__ __forceinline__ uint32_t cand32(uint32_t j, const float4& pj, float& visE, float* g32,
-                                             float* w32) {
+  __device__ __forceinline__ void cand32(uint32_t j, const float4& pj, float& visE, float* g32,
+                                         float* w32, int kc) {
     bool valid = active;
     if (FILTER == 1) valid = valid && (j > i);
     if (FILTER == 2) valid = valid && (j != i);
@@ -388,7 +472,7 @@ struct Sweep {
     } else if constexpr (kNL) {
       nl_stage_wave(in, j, (double)__builtin_sqrtf(d2));
     }
-    return spec ? (band ? 3u : 1u) : 0u;
+    enqueue(spec, j, kc, band);
   }
 
   template <int FILTER>
@@ -439,24 +523,19 @@ struct Sweep {
       float visE = 0.0f;
       float g32[3] = {0.0f, 0.0f, 0.0f};
       float w32[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      const int kc = kcode(p[0], p[1], p[2]);
       uint32_t j = jb;
       for (; j + 4 <= je; j += 4) {
         const float4 p0 = ldu(&P[j]), p1 = ldu(&P[j + 1]), p2 = ldu(&P[j + 2]), p3 = ldu(&P[j + 3]);
-        uint32_t sb = cand32<FILTER>(j, p0, visE, g32, w32);
-        sb |= cand32<FILTER>(j + 1, p1, visE, g32, w32) << 2;
-        sb |= cand32<FILTER>(j + 2, p2, visE, g32, w32) << 4;
-        sb |= cand32<FILTER>(j + 3, p3, visE, g32, w32) << 6;
-        if (sb) {
-#pragma unroll 1
-          for (int k = 0; k < 4; ++k) {
-            const uint32_t bits = (sb >> (2 * k)) & 3u;
-            if (bits) special(j + (uint32_t)k, bits == 3u);
-          }
-        }
+        cand32<FILTER>(j, p0, visE, g32, w32, kc);
+        cand32<FILTER>(j + 1, p1, visE, g32, w32, kc);
+        cand32<FILTER>(j + 2, p2, visE, g32, w32, kc);
+        cand32<FILTER>(j + 3, p3, visE, g32, w32, kc);
+        drain(false);
       }
       for (; j < je; ++j) {
-        const uint32_t bits = cand32<FILTER>(j, ldu(&P[j]), visE, g32, w32);
-        if (bits) special(j, bits == 3u);
+        cand32<FILTER>(j, ldu(&P[j]), visE, g32, w32, kc);
+        drain(false);
       }
       if constexpr (kSum) accE += kLJF ? 0.5 * (double)visE : (double)visE;
       if constexpr (kLJF) {
@@ -503,6 +582,14 @@ struct Sweep {
     for (int k = 0; k < 9; ++k) B[k] = 0.0;
     cnt_wave = 0;
     cnt_lane = 0;
+    tstart = T.start;
+    qhead = 0;
+    qtail = 0;
+    if constexpr (FP32 && kLJF) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) GA[lane * 3 + a] = 0.0;
+      __builtin_amdgcn_wave_barrier();
+    }
 
     const int dzlo = DIM == 3 ? -l : 0, dzhi = DIM == 3 ? l : 0;
     for (int dz = dzlo; dz <= dzhi; ++dz) {
@@ -551,6 +638,13 @@ struct Sweep {
     }
 
     // ---- tile epilogue
+    if constexpr (FP32) drain(true);
+    if constexpr (FP32 && kLJF) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) G[a] += GA[lane * 3 + a];
+    }
     if constexpr (kLJF) {
       const double* up = ldu(&J->upstream);
       const double mult = up ? ldu(up) : ldu(&J->scale);
@@ -572,7 +666,9 @@ struct Sweep {
     if constexpr (kNL) nl_flush();
     const unsigned long long cnt = cnt_wave + wave_sum_u64(cnt_lane);
     double* Pp = ldu(&J->partials) + (size_t)tile_id * kPartialD;
-    const double e = wave_sum_d(active ? accE : 0.0);
+    // every lane may hold queued FP64 contributions of other lanes' particles:
+    // reduce over all lanes (inactive lanes contribute nothing of their own)
+    const double e = wave_sum_d(accE);
     if (lane == 0) {
       ldu(&J->pcount)[tile_id] = cnt;
       Pp[P_SUM] = e;
@@ -580,14 +676,14 @@ struct Sweep {
     if constexpr (kLJF) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        const double b = wave_sum_d(active ? B[k] : 0.0);
+        const double b = wave_sum_d(B[k]);
         if (lane == 0) Pp[P_BOX + k] = b;
       }
       if constexpr (kVir) {
         constexpr int map[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
         double ws[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) ws[k] = wave_sum_d(active ? W[k] : 0.0);
+        for (int k = 0; k < 6; ++k) ws[k] = wave_sum_d(W[k]);
         if (lane == 0) {
 #pragma unroll
           for (int m = 0; m < 9; ++m) Pp[P_VIR + m] = ws[map[m]];
@@ -624,9 +720,14 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
   Sweep<DIM, FP32, KIND> S;
   S.lane = lane;
   S.load_job(&jobs[T.job]);
-  if constexpr (kHist || kNL) {
+  {
     const int nb = kHist ? S.nbins : 0;
-    unsigned char* base = smem + sweep_lds_per_wave(KIND, nb) * wid;
+    unsigned char* base = smem + sweep_lds_per_wave(KIND, nb, FP32) * wid;
+    if constexpr (FP32) {
+      S.Q = (uint2*)base;
+      S.GA = (double*)(base + (size_t)kQueueCap * 8);
+    }
+    base += sweep_lds_queue_bytes(KIND, FP32);
     if constexpr (kHist) {
       S.L.hist = (uint32_t*)base;
       S.L.hsum = (double*)(((uintptr_t)(base + (size_t)(nb + 1) * 4) + 7) & ~(uintptr_t)7);
@@ -637,7 +738,7 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
         S.L.E32[k] = E32g[k];
         if (k < nb) S.L.hsum[k] = 0.0;
       }
-    } else {
+    } else if constexpr (kNL) {
       S.L.nl_ij = (uint32_t*)base;
       S.L.nl_d = (double*)(base + (size_t)kNLStage * 8);
       S.L.nl_fill = (int*)(base + (size_t)kNLStage * 16);
@@ -830,43 +931,79 @@ __global__ void __launch_bounds__(256) brute_kernel(const JobDesc* __restrict__ 
 
 // ---------------------------------------------------------------- finalize
 // Fixed-order reduction of the per-tile partials of one job into the outputs.
-__global__ void __launch_bounds__(256) finalize_kernel(const JobDesc* __restrict__ jobs, FinalArgs F) {
+// Two-level fixed-order reduction of the per-tile partials of one job:
+// block b sums a contiguous range of tiles (strided by thread, then a tree in
+// shared memory); one block then sums the block results in order.
+__device__ __forceinline__ int final_slots(int kind) {
+  return (kind == K_LJ_F || kind == K_LJ_FV) ? kPartialD : 1;
+}
+
+__global__ void __launch_bounds__(256) finalize1_kernel(const JobDesc* __restrict__ jobs, FinalArgs F,
+                                                        double* __restrict__ scratch,
+                                                        unsigned long long* __restrict__ scount) {
   const JobDesc& J = jobs[0];
   __shared__ double red[256];
   __shared__ unsigned long long redc[256];
   const int tid = threadIdx.x;
   const int nparts = F.nparts_dev ? min((int)*F.nparts_dev, F.nparts) : F.nparts;
+  const int chunk = (nparts + gridDim.x - 1) / gridDim.x;
+  const int lo = blockIdx.x * chunk, hi = min(nparts, lo + chunk);
   unsigned long long c = 0;
-  for (int k = tid; k < nparts; k += 256) c += J.pcount[k];
+  for (int k = lo + tid; k < hi; k += 256) c += J.pcount[k];
   redc[tid] = c;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) redc[tid] += redc[tid + s];
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) redc[tid] += redc[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) scount[blockIdx.x] = redc[0];
+  const int nslots = final_slots(F.kind);
+  for (int slot = 0; slot < nslots; ++slot) {
+    double v = 0.0;
+    for (int k = lo + tid; k < hi; k += 256) v += J.partials[(size_t)k * kPartialD + slot];
+    red[tid] = v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    if (tid == 0) scratch[(size_t)blockIdx.x * kPartialD + slot] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kFinalBlocks) finalize2_kernel(FinalArgs F,
+                                                                 const double* __restrict__ scratch,
+                                                                 const unsigned long long* __restrict__ scount) {
+  __shared__ double red[kFinalBlocks];
+  __shared__ unsigned long long redc[kFinalBlocks];
+  const int tid = threadIdx.x;
+  redc[tid] = scount[tid];
+  __syncthreads();
+  for (int st = kFinalBlocks / 2; st > 0; st >>= 1) {
+    if (tid < st) redc[tid] += redc[tid + st];
     __syncthreads();
   }
   if (tid == 0 && F.count) *F.count = F.halve_count ? redc[0] / 2 : redc[0];
-  __syncthreads();
-  const int nslots = (F.kind == K_LJ_F) ? kPartialD : 1;
+  const int nslots = final_slots(F.kind);
   for (int slot = 0; slot < nslots; ++slot) {
-    double v = 0.0;
-    for (int k = tid; k < nparts; k += 256) v += J.partials[(size_t)k * kPartialD + slot];
-    red[tid] = v;
+    red[tid] = scratch[(size_t)tid * kPartialD + slot];
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
+    for (int st = kFinalBlocks / 2; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
       __syncthreads();
     }
     if (tid == 0) {
-      double tot = red[0];
+      const double tot = red[0];
       if (slot == P_SUM && F.energy) {
-        double m = (F.kind == K_LJ_E || F.kind == K_LJ_F) ? 4.0 * F.eps : 1.0;
-        *F.energy = m * tot;
+        const bool lj = F.kind == K_LJ_E || F.kind == K_LJ_F || F.kind == K_LJ_FV;
+        *F.energy = (lj ? 4.0 * F.eps : 1.0) * tot;
       } else if (slot >= P_VIR && slot < P_VIR + 9 && F.virial && F.want_virial) {
-        int k = slot - P_VIR, a = k / 3, b = k % 3;
+        const int k = slot - P_VIR, a = k / 3, b = k % 3;
         if (a < F.dim && b < F.dim) F.virial[a * F.dim + b] = 24.0 * F.eps * tot;
       } else if (slot >= P_BOX && slot < P_BOX + 9 && F.grad_box) {
-        int k = slot - P_BOX, a = k / 3, b = k % 3;
-        double g = F.upstream ? *F.upstream : F.box_mult;
+        const int k = slot - P_BOX, a = k / 3, b = k % 3;
+        const double g = F.upstream ? *F.upstream : F.box_mult;
         if (a < F.dim && b < F.dim) F.grad_box[a * F.dim + b] = -24.0 * F.eps * g * tot;
       }
     }
@@ -977,7 +1114,7 @@ hipError_t launch_sweep(int dim, bool fp32, int kind, const JobDesc* jobs, const
   if (max_tiles <= 0) return hipSuccess;
   const int waves = kBlock / kWave;
   dim3 grid((max_tiles + waves - 1) / waves);
-  size_t lds = sweep_lds_per_wave(kind, nbins) * waves;
+  size_t lds = sweep_lds_per_wave(kind, nbins, fp32) * waves;
   if (dim == 3)
     return fp32 ? sweep_dispatch<3, true>(kind, grid, lds, jobs, tiles, ntiles_dev, s)
                 : sweep_dispatch<3, false>(kind, grid, lds, jobs, tiles, ntiles_dev, s);
@@ -993,8 +1130,10 @@ hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, int* nblocks_ou
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, hipStream_t s) {
-  finalize_kernel<<<1, 256, 0, s>>>(jobs, F);
+hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, double* scratch,
+                           unsigned long long* scount, hipStream_t s) {
+  finalize1_kernel<<<kFinalBlocks, 256, 0, s>>>(jobs, F, scratch, scount);
+  finalize2_kernel<<<1, kFinalBlocks, 0, s>>>(F, scratch, scount);
   return hipGetLastError();
 }
 
