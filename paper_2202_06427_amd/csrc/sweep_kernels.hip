@@ -317,7 +317,7 @@ struct Sweep {
       const uint32_t slot = (qtail + (uint32_t)lane_rank(m)) & (uint32_t)(kQueueCap - 1);
       Q[slot] = make_uint2(j, (uint32_t)lane | ((uint32_t)kc << 8) | (band ? (1u << 16) : 0u));
     }
-    qtail += (uint32_t)__popcll(m);
+    qtail = (uint32_t)uniform((int)(qtail + (uint32_t)__popcll(m)));
   }
 
   // Canonical FP64 evaluation of one queued candidate by this lane; results
@@ -400,25 +400,27 @@ struct Sweep {
     while (qtail - qhead >= (uint32_t)kWave || (all && qtail != qhead)) {
       const uint32_t nb = min(qtail - qhead, (uint32_t)kWave);
       if ((uint32_t)lane < nb) process(Q[(qhead + (uint32_t)lane) & (uint32_t)(kQueueCap - 1)]);
-      qhead += nb;
+      qhead = (uint32_t)uniform((int)(qhead + nb));
     }
   }
 
   // ---------------- one candidate
   // FILTER: 0 none, 1 j > i (home row), 2 j != i (own cell, full shell)
+  // One candidate (same j in every lane).  Inactive lanes sit 1e18 away, so
+  // only the home-row / own-cell filters need a per-lane test.
   template <int FILTER>
   __device__ __forceinline__ void cand32(uint32_t j, const float4& pj, float& visE, float* g32,
                                          float* w32, int kc) {
-    bool valid = active;
-    if (FILTER == 1) valid = valid && (j > i);
-    if (FILTER == 2) valid = valid && (j != i);
     const float dx = pj.x - q[0];
     const float dy = pj.y - q[1];
     const float dz = DIM == 3 ? pj.z - q[2] : 0.0f;
     const float d2 = DIM == 3 ? __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))
                               : __builtin_fmaf(dy, dy, dx * dx);
-    const bool in = valid && d2 <= lo32;
-    const bool band = valid && d2 > lo32 && d2 <= hi32;
+    bool ok = true;
+    if (FILTER == 1) ok = j > i;
+    if (FILTER == 2) ok = j != i;
+    const bool in = ok && d2 <= lo32;
+    const bool band = ok && !(d2 <= lo32) && d2 <= hi32;
     bool spec = band;
     cnt_wave += (unsigned long long)__popcll(__ballot(in));
     if constexpr (KIND == K_SUM_D || KIND == K_SUM_INV_D) {
@@ -426,14 +428,13 @@ struct Sweep {
       const float term = KIND == K_SUM_D ? d2 * r : r;
       visE += in ? term : 0.0f;
     } else if constexpr (kLJ) {
-      const bool nearp = in && d2 < near2f;
+      const bool nearp = ok && d2 < near2f;  // near2f < lo32: near pairs are members
       const bool fast = in && !nearp;
       spec = spec || nearp;
       const float r = __builtin_amdgcn_rcpf(d2);
       const float x = s2f * r;
       const float x3 = x * x * x;
-      const float u = __builtin_fmaf(x3, x3, -x3);
-      visE += fast ? u : 0.0f;
+      visE += fast ? __builtin_fmaf(x3, x3, -x3) : 0.0f;
       if constexpr (kLJF) {
         const float f = fast ? x3 * __builtin_fmaf(2.0f, x3, -1.0f) * r : 0.0f;
         g32[0] = __builtin_fmaf(f, dx, g32[0]);
@@ -477,9 +478,9 @@ struct Sweep {
 
   template <int FILTER>
   __device__ __forceinline__ void cand64(uint32_t j, const double4& rj) {
-    bool valid = active;
-    if (FILTER == 1) valid = valid && (j > i);
-    if (FILTER == 2) valid = valid && (j != i);
+    bool valid = true;
+    if (FILTER == 1) valid = j > i;
+    if (FILTER == 2) valid = j != i;
     double D[3];
     D[0] = (rj.x - ri[0]) + t[0];
     D[1] = (rj.y - ri[1]) + t[1];
@@ -563,8 +564,11 @@ struct Sweep {
     i = T.start + (uint32_t)(active ? lane : count - 1);
     i_orig = ldu(&J->idx_x)[i];
     {
+      // inactive lanes are placed 1e100 away: no candidate can reach them
       const double4 r = ldu(&J->r64_x)[i];
-      ri[0] = r.x; ri[1] = r.y; ri[2] = r.z;
+      ri[0] = active ? r.x : 1e100;
+      ri[1] = active ? r.y : 1e100;
+      ri[2] = active ? r.z : 1e100;
     }
     if constexpr (kRel) {
       const float4 v = ldu(&J->vel32_x)[i];
@@ -622,7 +626,7 @@ struct Sweep {
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
               const double O = (Hn[a * 3 + 0] * u0 + Hn[a * 3 + 1] * u1) + Hn[a * 3 + 2] * u2;
-              q[a] = (float)(ri[a] - O);
+              q[a] = active ? (float)(ri[a] - O) : 1e18f;
             }
             if (DIM == 2) q[2] = 0.0f;
           }
@@ -703,17 +707,21 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
   const int lane = (int)__lane_id();
   const int wid = uniform((int)(threadIdx.x / kWave));
   // the tile count is produced on the device; never trust it past the array
-  const int ntiles = min((int)ldu(ntiles_dev), (int)(gridDim.x * (kBlock / kWave)));
-  // XCD-aware order: consecutive tiles (neighbouring cells, shared rows in
-  // L2) go to the same XCD, assuming round-robin dispatch of blocks to XCDs.
-  const int nblk = gridDim.x;
+  constexpr int kWpb = kBlock / kWave;
+  const int ntiles = min((int)ldu(ntiles_dev), (int)(gridDim.x * kWpb));
+  // The grid is sized by an upper bound on the tile count; only the first
+  // nblk blocks have work.  Blocks are dispatched to the 8 XCDs round-robin,
+  // so block b (b < nblk) runs on XCD b % 8: give each XCD a contiguous
+  // range of tiles (neighbouring cells share their rows in that XCD's L2).
+  const int nblk = (ntiles + kWpb - 1) / kWpb;
   int b = blockIdx.x;
+  if (b >= nblk) return;
   if (nblk >= 8) {
     const int per = nblk / 8, rem = nblk % 8;
     const int xcd = b % 8, k = b / 8;
     b = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
   }
-  const int tile_id = uniform(b * (kBlock / kWave) + wid);
+  const int tile_id = uniform(b * kWpb + wid);
   if (tile_id >= ntiles) return;
   const Tile T = ldu(&tiles[tile_id]);
 
