@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     return ap.parse_args()
 
 
@@ -77,6 +78,38 @@ def time_steps(clm, cl, xt, steps, warmup, sigma, eps):
         "count": int(out["count"].item()),
         "energy": float(out["energy"].item()),
     }
+
+
+def served(n_requests, seed=5):
+    """Served mix: closed-loop capacity, then Poisson arrivals at 0.8x of it."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2202_06427_amd.serve import Job, Server
+
+    reqs = W.serve_requests(seed=seed, count=n_requests)
+    xs = [W.request_positions(r) for r in reqs]
+
+    def jobs(rate):
+        g = np.random.Generator(np.random.PCG64(seed + 1))
+        t, out = 0.0, []
+        for r, x in zip(reqs, xs):
+            t += g.exponential(1.0 / rate) if rate else 0.0
+            out.append(Job(r["id"], x, r["H"], r["cutoff"], r["kind"], arrival=t))
+        return out
+
+    warm = Server(hbm_budget=8 << 30)
+    warm.run(jobs(None)[: min(64, n_requests)], realtime=False)
+    closed = Server(hbm_budget=8 << 30).run(jobs(None), realtime=False)
+    cap = closed["jobs_per_s"]
+    rate = 0.8 * cap
+    opened = Server(hbm_budget=8 << 30).run(jobs(rate), realtime=True)
+    return {"requests": n_requests, "capacity_jobs_per_s": cap, "rate_jobs_per_s": rate,
+            "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"], "mean_ms": opened["mean_ms"],
+            "pairs_per_s": opened["pairs_per_s"], "mean_batch": opened["mean_batch"],
+            "closed_loop_p50_ms": closed["p50_ms"], "closed_loop_p99_ms": closed["p99_ms"],
+            "hbm_budget_bytes": 8 << 30, "peak_hbm_bytes": opened["peak_hbm_bytes"],
+            "nl_retries": opened["nl_retries"], "failed": opened["failed"] + closed["failed"]}
 
 
 def cpu_baseline(cfg, nthreads):
@@ -167,6 +200,10 @@ def main():
         }
         line["fp32_over_fp64"] = value / line["fp64"]["value"]
         line["energy_rel_diff_fp32_fp64"] = abs(main_r["energy"] - r64["energy"]) / abs(r64["energy"])
+    if args.serve_requests > 0:
+        log(f"served mix: {args.serve_requests} requests ...")
+        line["served"] = served(args.serve_requests)
+        log(f"served: {line['served']}")
     if not args.no_cpu_baseline:
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
         log(f"cpu baseline: oracle on the full workload with {nth} threads ...")

@@ -177,6 +177,20 @@ clm_status clm_celllist_build(clm_celllist* cl, const double* x_dev, const doubl
 /* Map one kind over the pair set and reduce it (async). */
 clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* params,
                    const clm_map_out* out);
+/* Batched map (serving): one sweep launch covers the tiles of every job.
+ * All cell lists must share the context, dim and precision and be built;
+ * params[k] / outs[k] are job k's arguments as for clm_map (histograms of a
+ * batch share nbins).  Jobs whose box has fewer than 3 cells per axis run as
+ * separate brute-force launches.  Each job's results equal those of
+ * clm_map on that job alone (sums up to FP64 summation order).  The batch
+ * workspace (device, 256-byte aligned, caller-owned) holds the job
+ * descriptors and the concatenated tile list; it may be reused after the
+ * batch has run. */
+clm_status clm_map_batch_workspace_bytes(int njobs, clm_celllist* const* cls, size_t* bytes);
+clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
+                         const clm_map_params* params, const clm_map_out* outs, void* workspace_dev,
+                         size_t workspace_bytes);
+
 /* Host-side counters of the last build (synchronizes the stream). */
 clm_status clm_celllist_info_get(clm_celllist* cl, clm_celllist_info* out);
 clm_status clm_celllist_destroy(clm_celllist* cl);

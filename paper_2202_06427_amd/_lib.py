@@ -75,7 +75,8 @@ EXPORTS = [
     "clm_box_from_lengths_angles", "clm_box_info_get", "clm_box_destroy",
     "clm_celllist_workspace_bytes", "clm_celllist_create", "clm_celllist_build", "clm_map",
     "clm_celllist_info_get", "clm_celllist_destroy", "clm_synchronize", "clm_last_error",
-    "clm_status_string", "clm_context_set_timing", "clm_stats_get",
+    "clm_status_string", "clm_context_set_timing", "clm_stats_get", "clm_map_batch_workspace_bytes",
+    "clm_map_batch",
 ]
 
 _lib = None
@@ -112,6 +113,9 @@ def lib():
     L.clm_synchronize.argtypes = [_vp]
     L.clm_context_set_timing.argtypes = [_vp, c_int]
     L.clm_stats_get.argtypes = [_vp, ctypes.POINTER(Stats), c_int]
+    L.clm_map_batch_workspace_bytes.argtypes = [c_int, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t)]
+    L.clm_map_batch.argtypes = [c_int, ctypes.POINTER(_vp), c_int, ctypes.POINTER(MapParams),
+                                ctypes.POINTER(MapOut), _vp, ctypes.c_size_t]
     L.clm_last_error.restype = ctypes.c_char_p
     L.clm_status_string.restype = ctypes.c_char_p
     L.clm_status_string.argtypes = [c_int]

@@ -716,8 +716,11 @@ static JobDesc base_job(const clm_celllist* cl) {
   return jd;
 }
 
-clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
-                   const clm_map_out* O) {
+// Validates one map request, enqueues its per-job preparation kernels
+// (histogram edges, zeroed outputs, sorted velocities) and fills the job
+// descriptor and finalize arguments.
+static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
+                              const clm_map_out* O, JobDesc* jdo, FinalArgs* Fo, int* k_launch_out) {
   if (!cl || !P || !O) return fail(CLM_E_INVALID_ARG, "NULL argument");
   if (!cl->built) return fail(CLM_E_INVALID_ARG, "cell list not built");
   const int k = internal_kind(kind);
@@ -766,8 +769,8 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
   if (lj) {
     jd.s2 = P->sigma * P->sigma;
     jd.s2f = (float)jd.s2;
-    double nf = P->near_factor > 0.0 ? P->near_factor : 1.0;
-    double near = nf * P->sigma;
+    const double nf = P->near_factor > 0.0 ? P->near_factor : 1.0;
+    const double near = nf * P->sigma;
     jd.near2f = round_up_f(near * near);
     jd.eps = P->epsilon;
     jd.upstream = kind == CLM_MAP_LJ_ADJOINT ? P->upstream_dev : nullptr;
@@ -791,7 +794,6 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
     jd.with_dist = P->with_distances && O->dist_dev ? 1 : 0;
     jd.capacity = P->capacity;
   }
-  CLM_HIP(launch_set_job(jd, cl->job_dev, st));
   if (hist) {
     const int force_last = (k == K_HIST_DIST && P->hist_hi == B.rc) ? 1 : 0;
     CLM_HIP(launch_hist_edges(cl->E64, cl->E32, P->nbins, P->hist_hi, force_last, B.rc2, st));
@@ -809,7 +811,7 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
 
   FinalArgs F;
   std::memset(&F, 0, sizeof F);
-  F.kind = k;
+  F.kind = k_launch;
   F.dim = dim;
   F.want_virial = jd.want_virial;
   F.eps = lj ? P->epsilon : 0.0;
@@ -819,15 +821,34 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
   F.virial = jd.want_virial ? O->virial_dev : nullptr;
   F.grad_box = ljf ? O->grad_box_dev : nullptr;
   F.count = (unsigned long long*)O->count_dev;
+  F.halve_count = (ljf && !cl->cross && !B.small) ? 1 : 0;
+  *jdo = jd;
+  *Fo = F;
+  *k_launch_out = k_launch;
+  return CLM_OK;
+}
 
+clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
+                   const clm_map_out* O) {
+  JobDesc jd;
+  FinalArgs F;
+  int k_launch = 0;
+  clm_status s = prepare_job(cl, kind, P, O, &jd, &F, &k_launch);
+  if (s != CLM_OK) return s;
+  const clm_box& B = cl->box;
+  hipStream_t st = cl->ctx->stream;
+  CLM_HIP(launch_set_job(jd, cl->job_dev, st));
+  Timed ts(cl->ctx, &cl->ctx->sweep_ev);
+  s = ts.start();
+  if (s != CLM_OK) return s;
   if (B.small) {
     BruteArgs A;
     std::memset(&A, 0, sizeof A);
-    A.dim = dim;
+    A.dim = B.dim;
     A.n_x = (int)cl->nx;
     A.n_y = (int)(cl->cross ? cl->ny : cl->nx);
     A.cross = cl->cross;
-    A.kind = k;
+    A.kind = internal_kind(kind);
     for (int q = 0; q < 9; ++q) {
       A.H[q] = B.H[q];
       A.Hinv[q] = B.Hinv[q];
@@ -841,31 +862,120 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
       return fail(CLM_E_UNSUPPORTED,
                   "box has fewer than 3 cells per axis and %.3g candidate pairs: the brute-force "
                   "minimum-image path serves at most 4e9", pairs);
-    if (k == K_HIST_DIST || k == K_HIST_REL) {
-      // the brute path accumulates straight into the (zeroed) global histogram
-    }
     int nblocks = 0;
-    Timed ts(cl->ctx, &cl->ctx->sweep_ev);
-    clm_status s0 = ts.start();
-    if (s0 != CLM_OK) return s0;
     CLM_HIP(launch_brute(cl->job_dev, A, &nblocks, st));
-    s0 = ts.stop();
-    if (s0 != CLM_OK) return s0;
     F.nparts = nblocks;
     F.nparts_dev = nullptr;
   } else {
-    Timed ts(cl->ctx, &cl->ctx->sweep_ev);
-    clm_status s0 = ts.start();
-    if (s0 != CLM_OK) return s0;
-    CLM_HIP(launch_sweep(dim, cl->prec == CLM_FP32_GUARD, k_launch, cl->job_dev, cl->tiles,
+    const bool hist = k_launch == K_HIST_DIST || k_launch == K_HIST_REL;
+    CLM_HIP(launch_sweep(B.dim, cl->prec == CLM_FP32_GUARD, k_launch, cl->job_dev, cl->tiles,
                          &cl->row_off[cl->nrows], cl->max_tiles, hist ? P->nbins : 0, st));
-    s0 = ts.stop();
-    if (s0 != CLM_OK) return s0;
     F.nparts = cl->max_tiles;
     F.nparts_dev = &cl->row_off[cl->nrows];
-    F.halve_count = ljf && !cl->cross ? 1 : 0;
   }
+  s = ts.stop();
+  if (s != CLM_OK) return s;
   CLM_HIP(launch_finalize(cl->job_dev, F, cl->fin_scratch, cl->fin_count, st));
+  return CLM_OK;
+}
+
+// ---------------------------------------------------------------- batched maps
+static size_t batch_layout(int njobs, int64_t tiles, size_t* o_jobs, size_t* o_fin, size_t* o_tiles,
+                           size_t* o_total) {
+  Carve c;
+  *o_jobs = c.take(sizeof(JobDesc) * njobs);
+  *o_fin = c.take(sizeof(FinalArgs) * njobs);
+  *o_tiles = c.take(sizeof(Tile) * (size_t)std::max<int64_t>(tiles, 4));
+  *o_total = c.take(sizeof(uint32_t) * 4);
+  return c.off;
+}
+
+static int64_t batch_tiles(int njobs, clm_celllist* const* cls) {
+  int64_t t = 0;
+  for (int k = 0; k < njobs; ++k)
+    if (cls[k] && !cls[k]->box.small) t += cls[k]->max_tiles;
+  return (t + 3) & ~(int64_t)3;
+}
+
+clm_status clm_map_batch_workspace_bytes(int njobs, clm_celllist* const* cls, size_t* bytes) {
+  if (njobs < 1 || njobs > 4096 || !cls || !bytes)
+    return fail(CLM_E_INVALID_ARG, "njobs must be in 1..4096 with non-NULL arrays");
+  size_t a, b, c, d;
+  *bytes = batch_layout(njobs, batch_tiles(njobs, cls), &a, &b, &c, &d);
+  return CLM_OK;
+}
+
+clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
+                         const clm_map_params* P, const clm_map_out* O, void* ws, size_t ws_bytes) {
+  if (njobs < 1 || njobs > 4096 || !cls || !P || !O)
+    return fail(CLM_E_INVALID_ARG, "njobs must be in 1..4096 with non-NULL arrays");
+  for (int k = 0; k < njobs; ++k)
+    if (!cls[k]) return fail(CLM_E_INVALID_ARG, "cell list %d is NULL", k);
+  clm_context* ctx = cls[0]->ctx;
+  const int dim = cls[0]->box.dim;
+  const clm_precision prec = cls[0]->prec;
+  for (int k = 1; k < njobs; ++k) {
+    if (cls[k]->ctx != ctx) return fail(CLM_E_INVALID_ARG, "all cell lists must share one context");
+    if (cls[k]->box.dim != dim || cls[k]->prec != prec)
+      return fail(CLM_E_INVALID_ARG, "all cell lists of a batch need the same dim and precision");
+    if ((kind == CLM_MAP_HIST_DIST || kind == CLM_MAP_HIST_RELSPEED) && P[k].nbins != P[0].nbins)
+      return fail(CLM_E_INVALID_ARG, "all histograms of a batch need the same nbins");
+  }
+  size_t need = 0, o_jobs, o_fin, o_tiles, o_total;
+  need = batch_layout(njobs, batch_tiles(njobs, cls), &o_jobs, &o_fin, &o_tiles, &o_total);
+  if (!ws || ((uintptr_t)ws & 255) != 0 || ws_bytes < need)
+    return fail(CLM_E_WORKSPACE, "batch workspace: %zu bytes (256-aligned) needed, %zu given", need,
+                ws_bytes);
+  char* base = (char*)ws;
+  JobDesc* jobs_dev = (JobDesc*)(base + o_jobs);
+  FinalArgs* fin_dev = (FinalArgs*)(base + o_fin);
+  Tile* tiles_dev = (Tile*)(base + o_tiles);
+  uint32_t* total_dev = (uint32_t*)(base + o_total);
+  std::vector<JobDesc> jds;
+  std::vector<FinalArgs> fas;
+  jds.reserve(njobs);
+  fas.reserve(njobs);
+  int k_launch = -1, nbins = 0;
+  for (int k = 0; k < njobs; ++k) {
+    if (cls[k]->box.small) {  // brute-force minimum image: a job of its own
+      clm_status s = clm_map(cls[k], kind, &P[k], &O[k]);
+      if (s != CLM_OK) return s;
+      continue;
+    }
+    JobDesc jd;
+    FinalArgs F;
+    int kl = 0;
+    clm_status s = prepare_job(cls[k], kind, &P[k], &O[k], &jd, &F, &kl);
+    if (s != CLM_OK) return s;
+    if (k_launch >= 0 && kl != k_launch)
+      return fail(CLM_E_INVALID_ARG, "all jobs of a batch must launch the same map (virial flags differ)");
+    k_launch = kl;
+    nbins = jd.nbins;
+    jd.own_tiles = cls[k]->tiles;
+    jd.own_ntiles = &cls[k]->row_off[cls[k]->nrows];
+    jd.own_max_tiles = cls[k]->max_tiles;
+    jds.push_back(jd);
+    fas.push_back(F);
+  }
+  if (jds.empty()) return CLM_OK;
+  const int nb = (int)jds.size();
+  hipStream_t st = ctx->stream;
+  CLM_HIP(hipSetDevice(ctx->device));
+  // pageable host -> device: the runtime stages the data before returning
+  CLM_HIP(hipMemcpyAsync(jobs_dev, jds.data(), sizeof(JobDesc) * nb, hipMemcpyHostToDevice, st));
+  CLM_HIP(hipMemcpyAsync(fin_dev, fas.data(), sizeof(FinalArgs) * nb, hipMemcpyHostToDevice, st));
+  CLM_HIP(launch_gather_tiles(jobs_dev, nb, tiles_dev, total_dev, st));
+  int64_t maxt = 0;
+  for (const JobDesc& jd : jds) maxt += jd.own_max_tiles;
+  maxt = (maxt + 3) & ~(int64_t)3;
+  Timed ts(ctx, &ctx->sweep_ev);
+  clm_status s = ts.start();
+  if (s != CLM_OK) return s;
+  CLM_HIP(launch_sweep(dim, prec == CLM_FP32_GUARD, k_launch, jobs_dev, tiles_dev, total_dev,
+                       (int)std::min<int64_t>(maxt, INT32_MAX), nbins, st));
+  s = ts.stop();
+  if (s != CLM_OK) return s;
+  CLM_HIP(launch_finalize_batch(jobs_dev, fin_dev, nb, st));
   return CLM_OK;
 }
 

@@ -98,7 +98,12 @@ struct JobDesc {
   double* dist;
   unsigned long long* nl_counter;
   long long capacity;
-  int tile_begin, tile_end;  // this job's tiles
+  int tile_begin, tile_end;  // this job's tiles in the launched tile list
+  // the job's own tile list (built by its cell list)
+  const Tile* own_tiles;
+  const uint32_t* own_ntiles;  // device count
+  int own_max_tiles;
+  int pad3;
 };
 
 // Dynamic LDS bytes per wave of the sweep.  The FP32 form keeps a ring
@@ -191,6 +196,9 @@ hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, int* nblocks_ou
 hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, double* scratch,
                            unsigned long long* scratch_count, hipStream_t s);
 constexpr int kFinalBlocks = 128;  // first-level blocks of the two-level finalize
+hipError_t launch_gather_tiles(JobDesc* jobs, int njobs, Tile* tiles, uint32_t* total,
+                              hipStream_t s);
+hipError_t launch_finalize_batch(const JobDesc* jobs, const FinalArgs* F, int njobs, hipStream_t s);
 hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
                              unsigned long long* out, hipStream_t s);
 

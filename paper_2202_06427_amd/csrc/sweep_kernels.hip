@@ -669,12 +669,13 @@ struct Sweep {
     }
     if constexpr (kNL) nl_flush();
     const unsigned long long cnt = cnt_wave + wave_sum_u64(cnt_lane);
-    double* Pp = ldu(&J->partials) + (size_t)tile_id * kPartialD;
+    const int local = tile_id - ldu(&J->tile_begin);  // this job's tile index
+    double* Pp = ldu(&J->partials) + (size_t)local * kPartialD;
     // every lane may hold queued FP64 contributions of other lanes' particles:
     // reduce over all lanes (inactive lanes contribute nothing of their own)
     const double e = wave_sum_d(accE);
     if (lane == 0) {
-      ldu(&J->pcount)[tile_id] = cnt;
+      ldu(&J->pcount)[local] = cnt;
       Pp[P_SUM] = e;
     }
     if constexpr (kLJF) {
@@ -1098,7 +1099,93 @@ __global__ void hist_edges_kernel(double* E64, float* E32, int nb, double hi, in
   E32[k] = (float)E;
 }
 
+// ---------------------------------------------------------------- batched jobs
+// Block b appends job b's tiles to the launched list: its offset is the sum
+// of the preceding jobs' (device) tile counts; the job id and offset are
+// recorded for the sweep and the finalize.
+__global__ void __launch_bounds__(256) gather_tiles_kernel(JobDesc* __restrict__ jobs, int njobs,
+                                                           Tile* __restrict__ tiles,
+                                                           uint32_t* __restrict__ total) {
+  const int b = blockIdx.x;
+  __shared__ int begin_s;
+  if (threadIdx.x == 0) {
+    int beg = 0;
+    for (int k = 0; k < b; ++k) beg += min((int)*jobs[k].own_ntiles, jobs[k].own_max_tiles);
+    begin_s = beg;
+    const int cnt = min((int)*jobs[b].own_ntiles, jobs[b].own_max_tiles);
+    jobs[b].tile_begin = beg;
+    jobs[b].tile_end = beg + cnt;
+    if (b == njobs - 1) *total = (uint32_t)(beg + cnt);
+  }
+  __syncthreads();
+  const int beg = begin_s;
+  const int cnt = min((int)*jobs[b].own_ntiles, jobs[b].own_max_tiles);
+  const Tile* src = jobs[b].own_tiles;
+  for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+    Tile t = src[k];
+    t.job = (uint16_t)b;
+    tiles[beg + k] = t;
+  }
+}
+
+// One block per job: fixed-order reduction of the job's tile partials.
+__global__ void __launch_bounds__(256) finalize_batch_kernel(const JobDesc* __restrict__ jobs,
+                                                             const FinalArgs* __restrict__ FA) {
+  const JobDesc& J = jobs[blockIdx.x];
+  const FinalArgs F = FA[blockIdx.x];
+  __shared__ double red[256];
+  __shared__ unsigned long long redc[256];
+  const int tid = threadIdx.x;
+  const int nparts = J.tile_end - J.tile_begin;
+  unsigned long long c = 0;
+  for (int k = tid; k < nparts; k += 256) c += J.pcount[k];
+  redc[tid] = c;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) redc[tid] += redc[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0 && F.count) *F.count = F.halve_count ? redc[0] / 2 : redc[0];
+  const int nslots = final_slots(F.kind);
+  for (int slot = 0; slot < nslots; ++slot) {
+    double v = 0.0;
+    for (int k = tid; k < nparts; k += 256) v += J.partials[(size_t)k * kPartialD + slot];
+    red[tid] = v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double tot = red[0];
+      if (slot == P_SUM && F.energy) {
+        const bool lj = F.kind == K_LJ_E || F.kind == K_LJ_F || F.kind == K_LJ_FV;
+        *F.energy = (lj ? 4.0 * F.eps : 1.0) * tot;
+      } else if (slot >= P_VIR && slot < P_VIR + 9 && F.virial && F.want_virial) {
+        const int k = slot - P_VIR, a = k / 3, b = k % 3;
+        if (a < F.dim && b < F.dim) F.virial[a * F.dim + b] = 24.0 * F.eps * tot;
+      } else if (slot >= P_BOX && slot < P_BOX + 9 && F.grad_box) {
+        const int k = slot - P_BOX, a = k / 3, b = k % 3;
+        const double g = F.upstream ? *F.upstream : F.box_mult;
+        if (a < F.dim && b < F.dim) F.grad_box[a * F.dim + b] = -24.0 * F.eps * g * tot;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- launchers
+hipError_t launch_gather_tiles(JobDesc* jobs, int njobs, Tile* tiles, uint32_t* total,
+                               hipStream_t s) {
+  gather_tiles_kernel<<<njobs, 256, 0, s>>>(jobs, njobs, tiles, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const JobDesc* jobs, const FinalArgs* F, int njobs, hipStream_t s) {
+  finalize_batch_kernel<<<njobs, 256, 0, s>>>(jobs, F);
+  return hipGetLastError();
+}
+
 template <int DIM, bool FP32>
 static hipError_t sweep_dispatch(int kind, dim3 grid, size_t lds, const JobDesc* jobs,
                                  const Tile* tiles, const uint32_t* nt, hipStream_t s) {

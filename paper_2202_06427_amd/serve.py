@@ -1,0 +1,323 @@
+"""Continuous-batching request loop for pair-map jobs on one GPU.
+
+A job is one pair map over its own particle set and box (the paper's
+map_pairwise call on a fresh CellList, sections 2.6-2.7): LJ energy+forces,
+a neighbour list, or a distance histogram (g(r) counts).  The loop
+
+  * admits arrived jobs in FIFO order while their HBM footprint fits the
+    budget and a slot is free (the footprint is known before any device work:
+    workspace + positions + outputs);
+  * uploads the positions and enqueues each admitted job's cell-list build;
+  * launches every admitted job of one map kind as ONE batched sweep
+    (clm_map_batch): their tiles run side by side in a single kernel;
+  * keeps going while those batches run: jobs arriving meanwhile are admitted
+    and launched in the next batch as budget and slots free up;
+  * retires a batch when its event has completed, records each job's latency
+    (arrival -> results complete on the device) and frees its footprint.
+
+The scheduler is host code; the executor does the device work (all pair
+work runs in libclmap's kernels).
+"""
+import collections
+import ctypes
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import Box, CellList, _context, _ptr
+from . import _lib as L
+
+KINDS = ("lj", "nl", "gr")
+
+
+class Job:
+    __slots__ = ("id", "x", "H", "cutoff", "kind", "arrival", "params", "lcell", "box", "cl",
+                 "xdev", "out", "footprint", "admitted", "done", "result", "status", "capacity",
+                 "retries")
+
+    def __init__(self, jid, x, H, cutoff, kind, arrival=0.0, params=None, lcell=2):
+        if kind not in KINDS:
+            raise ValueError(f"kind must be one of {KINDS}")
+        self.id = jid
+        self.x = x
+        self.H = np.asarray(H, dtype=np.float64)
+        self.cutoff = float(cutoff)
+        self.kind = kind
+        self.arrival = float(arrival)
+        self.params = dict(params or {})
+        self.lcell = lcell
+        self.box = self.cl = self.xdev = self.out = None
+        self.footprint = 0
+        self.admitted = self.done = None
+        self.result = None
+        self.status = "pending"
+        self.capacity = 0
+        self.retries = 0
+
+
+def expected_pairs(n, H, cutoff):
+    """Mean pair count of n uniform points (used to size neighbour lists)."""
+    dim = H.shape[0]
+    V = abs(np.linalg.det(H))
+    p = (4.0 / 3.0) * math.pi * cutoff ** 3 / V if dim == 3 else math.pi * cutoff ** 2 / V
+    return 0.5 * n * (n - 1) * min(1.0, p)
+
+
+class GpuExecutor:
+    """Device work of the server: cell lists, batched sweeps, events."""
+
+    def __init__(self, device="cuda:0", precision="fp32", lj=(3.4, 0.238), gr_bins=128):
+        self.device = torch.device(device)
+        self.precision = precision
+        self.lj = lj
+        self.gr_bins = gr_bins
+
+    def footprint(self, job):
+        n, dim = job.x.shape
+        box = Box(job.H, job.cutoff, job.lcell)
+        p = L.CLM_FP32_GUARD if self.precision == "fp32" else L.CLM_FP64
+        nb = ctypes.c_size_t(0)
+        L.check(L.lib().clm_celllist_workspace_bytes(box._h, n, 0, p, ctypes.byref(nb)))
+        out = 64
+        if job.kind == "lj":
+            out += n * dim * 8 + dim * dim * 8
+        elif job.kind == "nl":
+            job.capacity = int(1.25 * expected_pairs(n, job.H, job.cutoff) + 4096)
+            out += job.capacity * (8 + 8)
+        else:
+            out += (self.gr_bins + 1) * 8
+        job.box = box
+        return int(nb.value) + n * dim * 8 + out + 4096
+
+    def start(self, job):
+        xt = job.x if isinstance(job.x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(job.x))
+        job.xdev = xt.to(self.device)
+        job.cl = CellList(job.xdev, job.box, precision=self.precision)  # enqueues the build
+        n, dim = job.xdev.shape
+        dev = self.device
+        o = {"energy": torch.empty(1, dtype=torch.float64, device=dev),
+             "count": torch.empty(1, dtype=torch.int64, device=dev)}
+        if job.kind == "lj":
+            o["forces"] = torch.empty((n, dim), dtype=torch.float64, device=dev)
+            o["grad_box"] = torch.empty((dim, dim), dtype=torch.float64, device=dev)
+        elif job.kind == "nl":
+            cap = max(job.capacity, 1)
+            o["pairs"] = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+            o["dist"] = torch.empty(cap, dtype=torch.float64, device=dev)
+        else:
+            o["hist"] = torch.empty(self.gr_bins + 1, dtype=torch.int64, device=dev)
+        job.out = o
+
+    def _params(self, job):
+        o = job.out
+        if job.kind == "lj":
+            s, e = job.params.get("lj", self.lj)
+            P = L.MapParams(sigma=s, epsilon=e)
+            O = L.MapOut(energy_dev=_ptr(o["energy"]), forces_dev=_ptr(o["forces"]),
+                         grad_box_dev=_ptr(o["grad_box"]), count_dev=_ptr(o["count"]))
+            return L.MAP_KINDS["lj_ef"], P, O
+        if job.kind == "nl":
+            P = L.MapParams(capacity=job.capacity, with_distances=1)
+            O = L.MapOut(pairs_dev=_ptr(o["pairs"]), dist_dev=_ptr(o["dist"]), count_dev=_ptr(o["count"]))
+            return L.MAP_KINDS["neighbor_list"], P, O
+        P = L.MapParams(nbins=self.gr_bins, hist_hi=job.cutoff)
+        O = L.MapOut(hist_dev=_ptr(o["hist"]), count_dev=_ptr(o["count"]))
+        return L.MAP_KINDS["hist_dist"], P, O
+
+    def launch(self, jobs):
+        """One batched sweep over jobs of one kind; returns a completion handle."""
+        _context(self.device)
+        n = len(jobs)
+        cls = (ctypes.c_void_p * n)(*[j.cl._h for j in jobs])
+        Ps = (L.MapParams * n)()
+        Os = (L.MapOut * n)()
+        mk = None
+        for k, job in enumerate(jobs):
+            mk, Ps[k], Os[k] = self._params(job)
+        nb = ctypes.c_size_t(0)
+        L.check(L.lib().clm_map_batch_workspace_bytes(n, cls, ctypes.byref(nb)))
+        raw = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        ws = raw[(-raw.data_ptr()) % 256:]
+        L.check(L.lib().clm_map_batch(n, cls, mk, Ps, Os, _ptr(ws), int(nb.value)))
+        ev = torch.cuda.Event()
+        ev.record()
+        return (ev, raw)
+
+    def done(self, handle, block=False):
+        ev, _ = handle
+        if block:
+            ev.synchronize()
+            return True
+        return ev.query()
+
+    def finish(self, job):
+        o = job.out
+        cnt = int(o["count"].item())
+        if job.kind == "nl" and cnt > job.capacity:
+            # capacity estimate exceeded: re-run this job alone with the exact size
+            job.retries += 1
+            pairs, dist = job.cl.neighbor_list(capacity=cnt)
+            o["pairs"], o["dist"] = pairs, dist
+            job.capacity = cnt
+        res = {"count": cnt}
+        if job.kind == "lj":
+            res["energy"] = float(o["energy"].item())
+            res["forces"] = o["forces"]
+            res["grad_box"] = o["grad_box"]
+        elif job.kind == "nl":
+            res["pairs"] = o["pairs"][:cnt]
+            res["dist"] = o["dist"][:cnt]
+        else:
+            res["hist"] = o["hist"]
+        job.result = res
+        job.cl = None  # the workspace returns to the allocator (stream-ordered)
+        job.xdev = None
+
+    def drain(self):
+        torch.cuda.synchronize(self.device)
+
+
+class Server:
+    def __init__(self, executor=None, hbm_budget=8 << 30, max_slots=256, max_batch=64, **kw):
+        self.ex = executor if executor is not None else GpuExecutor(**kw)
+        self.budget = int(hbm_budget)
+        self.max_slots = int(max_slots)
+        self.max_batch = int(max_batch)
+        self.pending = collections.deque()
+        self.ready = []           # admitted and built (enqueued), not yet mapped
+        self.inflight = []        # (handle, [jobs])
+        self.used = 0
+        self.active = 0
+        self.peak_used = 0
+        self.finished = []
+        self.t0 = None
+        self.batch_sizes = []
+
+    def submit(self, job):
+        self.pending.append(job)
+
+    def clock(self):
+        return time.perf_counter() - self.t0
+
+    # ------------------------------------------------------------ admission
+    def _admit(self, now):
+        admitted = 0
+        while self.pending and self.pending[0].arrival <= now and self.active < self.max_slots:
+            job = self.pending[0]
+            if job.footprint == 0:
+                job.footprint = self.ex.footprint(job)
+            if job.footprint > self.budget:
+                self.pending.popleft()
+                job.status = "rejected: footprint above the HBM budget"
+                job.done = now
+                self.finished.append(job)
+                continue
+            if self.used + job.footprint > self.budget:
+                break  # FIFO: wait until running jobs release memory
+            self.pending.popleft()
+            job.admitted = now
+            try:
+                self.ex.start(job)
+            except Exception as e:  # a failing job does not stop the others
+                job.status = f"failed: {e}"
+                job.done = now
+                self.finished.append(job)
+                continue
+            self.used += job.footprint
+            self.peak_used = max(self.peak_used, self.used)
+            self.active += 1
+            job.status = "admitted"
+            self.ready.append(job)
+            admitted += 1
+        return admitted
+
+    def _launch(self):
+        groups = collections.defaultdict(list)
+        for job in self.ready:
+            groups[job.kind].append(job)
+        self.ready = []
+        for _, jobs in groups.items():
+            for s in range(0, len(jobs), self.max_batch):
+                chunk = jobs[s: s + self.max_batch]
+                try:
+                    h = self.ex.launch(chunk)
+                except Exception as e:
+                    for job in chunk:
+                        self._release(job, f"failed: {e}")
+                    continue
+                self.inflight.append((h, chunk))
+                self.batch_sizes.append(len(chunk))
+                for job in chunk:
+                    job.status = "running"
+
+    def _retire(self, block_first=False):
+        keep = []
+        for k, (h, jobs) in enumerate(self.inflight):
+            if self.ex.done(h, block=block_first and k == 0):
+                for job in jobs:
+                    try:
+                        self.ex.finish(job)
+                        status = "done"
+                    except Exception as e:
+                        status = f"failed: {e}"
+                    self._release(job, status)
+            else:
+                keep.append((h, jobs))
+        self.inflight = keep
+
+    def _release(self, job, status):
+        job.done = self.clock()
+        job.status = status
+        self.used -= job.footprint
+        self.active -= 1
+        self.finished.append(job)
+
+    # ------------------------------------------------------------ loop
+    def run(self, jobs, realtime=True):
+        """Serve `jobs` (arrival times in seconds from the start).  With
+        realtime=False every job is available at once (closed loop)."""
+        for j in sorted(jobs, key=lambda j: j.arrival):
+            if not realtime:
+                j.arrival = 0.0
+            self.submit(j)
+        self.t0 = time.perf_counter()
+        while self.pending or self.ready or self.inflight:
+            self._retire()
+            if self._admit(self.clock()):
+                self._launch()
+                continue
+            if self.pending and self.pending[0].arrival <= self.clock():
+                # the head job waits for memory or a slot: block on the oldest batch
+                if self.inflight:
+                    self._retire(block_first=True)
+                continue
+            if self.inflight:
+                time.sleep(0.0001)
+            elif self.pending:
+                time.sleep(max(0.0, min(self.pending[0].arrival - self.clock(), 0.002)))
+        self.ex.drain()
+        return self.summary()
+
+    def summary(self):
+        done = [j for j in self.finished if j.status == "done"]
+        failed = [j for j in self.finished if j.status.startswith("failed")]
+        lat = np.array([j.done - j.arrival for j in done]) if done else np.zeros(1)
+        wall = max((j.done for j in done), default=0.0)
+        pairs = sum(j.result["count"] for j in done)
+        return {
+            "jobs": len(done),
+            "failed": len(failed),
+            "rejected": len(self.finished) - len(done) - len(failed),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3),
+            "wall_s": wall,
+            "jobs_per_s": len(done) / wall if wall > 0 else 0.0,
+            "pairs_per_s": pairs / wall if wall > 0 else 0.0,
+            "batches": len(self.batch_sizes),
+            "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+            "peak_hbm_bytes": self.peak_used,
+            "nl_retries": sum(j.retries for j in done),
+        }

@@ -1,0 +1,85 @@
+"""Serving on the GPU: jobs of different sizes, boxes, cutoffs and map kinds
+arrive while others run, are admitted by HBM footprint and share batched
+sweeps; every job's result must equal the same job run alone (integers
+exactly, FP32 energies within 1e-6, forces within 1e-5 of the largest)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def clm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2202_06427_amd as clm
+    return clm
+
+
+def _jobs(count, rate, n_hi, seed=5):
+    from paper_2202_06427_amd.serve import Job
+    reqs = W.serve_requests(seed=seed, count=count, n_hi=n_hi)
+    g = W.rng(77)
+    t = 0.0
+    jobs = []
+    for r in reqs:
+        t += g.exponential(1.0 / rate)
+        jobs.append(Job(r["id"], W.request_positions(r), r["H"], r["cutoff"], r["kind"], arrival=t))
+    return jobs
+
+
+def _alone(clm, job):
+    x = torch.from_numpy(np.ascontiguousarray(job.x)).to("cuda:0")
+    cl = clm.CellList(x, clm.Box(job.H, job.cutoff, 2), precision="fp32")
+    if job.kind == "lj":
+        return cl.lj_forces(3.4, 0.238)
+    if job.kind == "nl":
+        p, d = cl.neighbor_list()
+        return {"pairs": p, "count": torch.tensor([len(p)])}
+    h, c = cl.histogram(128, job.cutoff)
+    return {"hist": h, "count": c}
+
+
+def _pairs_sorted(p):
+    p = p.cpu().numpy().astype(np.int64)
+    return p[np.lexsort((p[:, 1], p[:, 0]))]
+
+
+def test_results_same_alone_and_in_the_mix(clm):
+    from paper_2202_06427_amd.serve import Server
+    jobs = _jobs(48, rate=4000.0, n_hi=30_000)
+    srv = Server(hbm_budget=192 << 20, max_slots=12, max_batch=8)
+    summary = srv.run(jobs, realtime=True)
+    assert summary["jobs"] == 48 and summary["failed"] == 0 and summary["rejected"] == 0
+    assert summary["mean_batch"] > 1.0, "jobs must share batched sweeps"
+    assert summary["peak_hbm_bytes"] <= 192 << 20
+    for job in jobs:
+        a = _alone(clm, job)
+        r = job.result
+        assert r["count"] == int(a["count"].item()), job.id
+        if job.kind == "lj":
+            ea = a["energy"].item()
+            assert abs(r["energy"] - ea) <= 1e-6 * abs(ea)
+            Fa, Fm = a["forces"].cpu().numpy(), r["forces"].cpu().numpy()
+            assert np.abs(Fa - Fm).max() <= 1e-5 * np.abs(Fa).max()
+        elif job.kind == "nl":
+            assert np.array_equal(_pairs_sorted(r["pairs"]), _pairs_sorted(a["pairs"]))
+        else:
+            assert torch.equal(r["hist"].cpu(), a["hist"].cpu())
+    # and against the oracle for a few jobs of each kind
+    for job in jobs[:9]:
+        ref = oracle.compute(job.x, job.H, job.cutoff)
+        assert job.result["count"] == ref["count"]
+
+
+def test_small_budget_forces_queueing(clm):
+    from paper_2202_06427_amd.serve import Server
+    jobs = _jobs(16, rate=1e6, n_hi=20_000, seed=9)
+    srv = Server(hbm_budget=48 << 20, max_slots=64, max_batch=16)
+    summary = srv.run(jobs, realtime=True)
+    assert summary["jobs"] + summary["rejected"] == 16
+    assert srv.peak_used <= 48 << 20
