@@ -47,7 +47,24 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration(mib, reps=4):
+    """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+    counter readings give the scale factor for the sweep's readings."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read_per_copy": n * 4,
+                      "copy_calibration_bytes_written_per_copy": n * 4, "copies": reps}), flush=True)
 
 
 def time_steps(clm, cl, xt, steps, warmup, sigma, eps):
@@ -123,6 +140,9 @@ def cpu_baseline(cfg, nthreads):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (single-GPU workload; no collectives). "
               "Run with --gpus 1.", file=sys.stderr)
