@@ -32,6 +32,28 @@ FLOPS_PER_CANDIDATE = 8        # 3 sub, 3 mul, 2 add (distance test)
 FLOPS_PER_LJ_PAIR = 20         # 1 reciprocal + ~19 flops: energy + force on both particles
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_lj_forces_uniform1e6_hbm_traffic.md")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2202_06427_amd", "csrc", "sweep_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline sweep from the committed counter
+    summary, or None when the sweep source has changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        sha = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    fields = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith(("-", "|", "`")))
+    if fields.get("sweep_kernels.hip sha256 prefix", "").strip() != sha:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -203,7 +225,8 @@ def main():
             "peak": VALU_FP32_NONPACKED_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / VALU_FP32_NONPACKED_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flops_per_launch": flops,
             "peak_if_packed_fp32": VALU_FP32_PACKED_TFLOPS,
         },
