@@ -232,9 +232,9 @@ struct Sweep {
   }
 
   // certain members of one iteration (same j for every lane)
-  __device__ __forceinline__ void nl_stage_wave(bool in, uint32_t j, double d) {
-    unsigned long long m = __ballot(in);
+  __device__ __forceinline__ void nl_stage_wave(unsigned long long m, uint32_t j, double d) {
     if (m == 0) return;
+    const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
     int cnt = __popcll(m);
     int base = uniform(*(volatile int*)L.nl_fill);
     if (base + cnt > kNLStage) {
@@ -310,14 +310,18 @@ struct Sweep {
 
   // ---------------- FP64 re-evaluation queue (FP32 form)
   // Append this iteration's special lanes (uniform control flow).
-  __device__ __forceinline__ void enqueue(bool spec, uint32_t j, int kc, bool band) {
-    const unsigned long long m = __ballot(spec);
+  // m: lanes to queue, band: lanes whose membership FP64 decides (counted
+  // there); both are wave masks.
+  __device__ __forceinline__ void enqueue(unsigned long long m, uint32_t j, int kc,
+                                          unsigned long long band) {
     if (m == 0) return;
-    if (spec) {
-      const uint32_t slot = (qtail + (uint32_t)lane_rank(m)) & (uint32_t)(kQueueCap - 1);
-      Q[slot] = make_uint2(j, (uint32_t)lane | ((uint32_t)kc << 8) | (band ? (1u << 16) : 0u));
+    const uint32_t t0 = (uint32_t)uniform((int)qtail);
+    if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+      const uint32_t slot = (t0 + (uint32_t)lane_rank(m)) & (uint32_t)(kQueueCap - 1);
+      const bool b = __builtin_amdgcn_inverse_ballot_w64(band);
+      Q[slot] = make_uint2(j, (uint32_t)lane | ((uint32_t)kc << 8) | (b ? (1u << 16) : 0u));
     }
-    qtail = (uint32_t)uniform((int)(qtail + (uint32_t)__popcll(m)));
+    qtail = (uint32_t)uniform((int)(t0 + (uint32_t)__popcll(m)));
   }
 
   // Canonical FP64 evaluation of one queued candidate by this lane; results
@@ -397,11 +401,14 @@ struct Sweep {
 
   // Process queued entries 64 at a time (all: also a final partial batch).
   __device__ __forceinline__ void drain(bool all) {
-    while (qtail - qhead >= (uint32_t)kWave || (all && qtail != qhead)) {
-      const uint32_t nb = min(qtail - qhead, (uint32_t)kWave);
-      if ((uint32_t)lane < nb) process(Q[(qhead + (uint32_t)lane) & (uint32_t)(kQueueCap - 1)]);
-      qhead = (uint32_t)uniform((int)(qhead + nb));
+    uint32_t h = (uint32_t)uniform((int)qhead);
+    const uint32_t tl = (uint32_t)uniform((int)qtail);
+    while (tl - h >= (uint32_t)kWave || (all && tl != h)) {
+      const uint32_t nb = min(tl - h, (uint32_t)kWave);
+      if ((uint32_t)lane < nb) process(Q[(h + (uint32_t)lane) & (uint32_t)(kQueueCap - 1)]);
+      h = (uint32_t)uniform((int)(h + nb));
     }
+    qhead = h;
   }
 
   // ---------------- one candidate
@@ -416,21 +423,27 @@ struct Sweep {
     const float dz = DIM == 3 ? pj.z - q[2] : 0.0f;
     const float d2 = DIM == 3 ? __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))
                               : __builtin_fmaf(dy, dy, dx * dx);
-    bool ok = true;
-    if (FILTER == 1) ok = j > i;
-    if (FILTER == 2) ok = j != i;
-    const bool in = ok && d2 <= lo32;
-    const bool band = ok && !(d2 <= lo32) && d2 <= hi32;
-    bool spec = band;
-    cnt_wave += (unsigned long long)__popcll(__ballot(in));
+    // classification as wave masks (one compare each, logic on the scalar unit)
+    unsigned long long okm = ~0ull;
+    if (FILTER == 1) okm = __builtin_amdgcn_ballot_w64(j > i);
+    if (FILTER == 2) okm = __builtin_amdgcn_ballot_w64(j != i);
+    const unsigned long long mlo = __builtin_amdgcn_ballot_w64(d2 <= lo32);
+    const unsigned long long mhi = __builtin_amdgcn_ballot_w64(d2 <= hi32);
+    const unsigned long long in_m = mlo & okm;
+    const unsigned long long band_m = mhi & ~mlo & okm;
+    unsigned long long spec_m = band_m;
+    const bool in = __builtin_amdgcn_inverse_ballot_w64(in_m);
+    bool spec = false;  // per-lane extra reasons (histogram edges)
+    cnt_wave += (unsigned long long)__popcll(in_m);
     if constexpr (KIND == K_SUM_D || KIND == K_SUM_INV_D) {
       const float r = __builtin_amdgcn_rsqf(d2);
       const float term = KIND == K_SUM_D ? d2 * r : r;
       visE += in ? term : 0.0f;
     } else if constexpr (kLJ) {
-      const bool nearp = ok && d2 < near2f;  // near2f < lo32: near pairs are members
-      const bool fast = in && !nearp;
-      spec = spec || nearp;
+      // near2f < lo32: near pairs are members, evaluated in FP64
+      const unsigned long long near_m = __builtin_amdgcn_ballot_w64(d2 < near2f) & okm;
+      const bool fast = __builtin_amdgcn_inverse_ballot_w64(in_m & ~near_m);
+      spec_m |= near_m;
       const float r = __builtin_amdgcn_rcpf(d2);
       const float x = s2f * r;
       const float x3 = x * x * x;
@@ -471,9 +484,10 @@ struct Sweep {
         }
       }
     } else if constexpr (kNL) {
-      nl_stage_wave(in, j, (double)__builtin_sqrtf(d2));
+      nl_stage_wave(in_m, j, (double)__builtin_sqrtf(d2));
     }
-    enqueue(spec, j, kc, band);
+    if constexpr (kHist) spec_m |= __builtin_amdgcn_ballot_w64(spec);
+    enqueue(spec_m, j, kc, band_m);
   }
 
   template <int FILTER>
@@ -494,7 +508,7 @@ struct Sweep {
     const bool in = valid && d2 <= rc2;
     cnt_wave += (unsigned long long)__popcll(__ballot(in));
     if constexpr (kNL) {
-      nl_stage_wave(in, j, sqrt(d2));
+      nl_stage_wave(__builtin_amdgcn_ballot_w64(in), j, sqrt(d2));
     } else if constexpr (KIND != K_COUNT) {
       if (in) pair64(d2, D, j, false);
     }
