@@ -121,11 +121,11 @@ struct Sweep {
   // ---- uniform job constants
   const JobDesc* J;
   int cross, full, l, nx, ny, nz;
-  double Hn[9];      // H[a][b] / n[b]
+  double Hn0[3];     // H[a][0] / n[0]: origin step between cells of a row
   double rc2;
   float lo32, hi32;
   float s2f, near2f;
-  double s2;
+  double s2, inv_s2;
   int nbins;
   float inv_h;
   float bandh;       // histogram edge band (FP32)
@@ -171,13 +171,14 @@ struct Sweep {
     ny = ldu(&J->n[1]);
     nz = ldu(&J->n[2]);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Hn[k] = ldu(&J->Hn[k]);
+    for (int a = 0; a < 3; ++a) Hn0[a] = ldu(&J->Hn[a * 3]);
     rc2 = ldu(&J->rc2);
     lo32 = ldu(&J->lo32);
     hi32 = ldu(&J->hi32);
     bandh = hi32 - lo32;
     if constexpr (kLJ) {
       s2 = ldu(&J->s2);
+      inv_s2 = 1.0 / s2;
       s2f = ldu(&J->s2f);
       near2f = ldu(&J->near2f);
     }
@@ -412,21 +413,26 @@ struct Sweep {
   }
 
   // ---------------- one candidate
-  // FILTER: 0 none, 1 j > i (home row), 2 j != i (own cell, full shell)
-  // One candidate (same j in every lane).  Inactive lanes sit 1e18 away, so
-  // only the home-row / own-cell filters need a per-lane test.
-  template <int FILTER>
-  __device__ __forceinline__ void cand32(uint32_t j, const float4& pj, float& visE, float* g32,
-                                         float* w32, int kc) {
+  // Lanes of this tile that may pair with candidate j (a wave mask, built on
+  // the scalar unit from the tile's first sorted index): mode 0 all, mode 1
+  // j > i (home row of the half shell), mode 2 j != i (own cells, full shell).
+  // Lane L holds sorted index tstart + L; inactive lanes sit far away.
+  __device__ __forceinline__ unsigned long long filter_mask(int mode, uint32_t j) const {
+    if (mode == 0) return ~0ull;
+    const int k = (int)(j - tstart);
+    if (mode == 1) return k <= 0 ? 0ull : (k >= kWave ? ~0ull : ((1ull << k) - 1ull));
+    return (k >= 0 && k < kWave) ? ~(1ull << k) : ~0ull;
+  }
+
+  // One candidate (same j in every lane), okm: filter_mask.
+  __device__ __forceinline__ void cand32(uint32_t j, const float4& pj, unsigned long long okm,
+                                         float& visE, float* g32, float* w32, int kc) {
     const float dx = pj.x - q[0];
     const float dy = pj.y - q[1];
     const float dz = DIM == 3 ? pj.z - q[2] : 0.0f;
     const float d2 = DIM == 3 ? __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))
                               : __builtin_fmaf(dy, dy, dx * dx);
     // classification as wave masks (one compare each, logic on the scalar unit)
-    unsigned long long okm = ~0ull;
-    if (FILTER == 1) okm = __builtin_amdgcn_ballot_w64(j > i);
-    if (FILTER == 2) okm = __builtin_amdgcn_ballot_w64(j != i);
     const unsigned long long mlo = __builtin_amdgcn_ballot_w64(d2 <= lo32);
     const unsigned long long mhi = __builtin_amdgcn_ballot_w64(d2 <= hi32);
     const unsigned long long in_m = mlo & okm;
@@ -444,12 +450,15 @@ struct Sweep {
       const unsigned long long near_m = __builtin_amdgcn_ballot_w64(d2 < near2f) & okm;
       const bool fast = __builtin_amdgcn_inverse_ballot_w64(in_m & ~near_m);
       spec_m |= near_m;
-      const float r = __builtin_amdgcn_rcpf(d2);
-      const float x = s2f * r;
+      // x = s^2/d^2 masked once: u and f vanish together on other lanes.
+      // f s^2 = (2 x^6 - x^3) x = (2u + x^3) x; the 1/s^2 is applied when
+      // the visit's sums are folded into FP64.
+      const float x = fast ? s2f * __builtin_amdgcn_rcpf(d2) : 0.0f;
       const float x3 = x * x * x;
-      visE += fast ? __builtin_fmaf(x3, x3, -x3) : 0.0f;
+      const float u = __builtin_fmaf(x3, x3, -x3);
+      visE += u;
       if constexpr (kLJF) {
-        const float f = fast ? x3 * __builtin_fmaf(2.0f, x3, -1.0f) * r : 0.0f;
+        const float f = __builtin_fmaf(2.0f, u, x3) * x;
         g32[0] = __builtin_fmaf(f, dx, g32[0]);
         g32[1] = __builtin_fmaf(f, dy, g32[1]);
         if (DIM == 3) g32[2] = __builtin_fmaf(f, dz, g32[2]);
@@ -490,11 +499,7 @@ struct Sweep {
     enqueue(spec_m, j, kc, band_m);
   }
 
-  template <int FILTER>
-  __device__ __forceinline__ void cand64(uint32_t j, const double4& rj) {
-    bool valid = true;
-    if (FILTER == 1) valid = j > i;
-    if (FILTER == 2) valid = j != i;
+  __device__ __forceinline__ void cand64(uint32_t j, const double4& rj, unsigned long long okm) {
     double D[3];
     D[0] = (rj.x - ri[0]) + t[0];
     D[1] = (rj.y - ri[1]) + t[1];
@@ -505,10 +510,11 @@ struct Sweep {
     } else {
       D[2] = 0.0;
     }
-    const bool in = valid && d2 <= rc2;
-    cnt_wave += (unsigned long long)__popcll(__ballot(in));
+    const unsigned long long in_m = __builtin_amdgcn_ballot_w64(d2 <= rc2) & okm;
+    const bool in = __builtin_amdgcn_inverse_ballot_w64(in_m);
+    cnt_wave += (unsigned long long)__popcll(in_m);
     if constexpr (kNL) {
-      nl_stage_wave(__builtin_amdgcn_ballot_w64(in), j, sqrt(d2));
+      nl_stage_wave(in_m, j, sqrt(d2));
     } else if constexpr (KIND != K_COUNT) {
       if (in) pair64(d2, D, j, false);
     }
@@ -529,41 +535,66 @@ struct Sweep {
     }
   }
 
-  template <int FILTER>
-  __device__ __forceinline__ void visit(uint32_t jb, uint32_t je) {
-    if constexpr (kLJF) {
-      S[0] = 0.0; S[1] = 0.0; S[2] = 0.0;
+  // FP32 form: the visit's FP32 sums go straight into the FP64 lane
+  // accumulators (G, and B when the visited cell is a periodic image).
+  // The unfiltered loop (nearly every visit) and the filtered one are
+  // separate so the common one computes no masks.
+  template <bool FILT>
+  __device__ __forceinline__ void loop32(uint32_t jb, uint32_t je, int mode, float& visE, float* g32,
+                                         float* w32, int kc) {
+    uint32_t j = jb;
+    for (; j + 4 <= je; j += 4) {
+      const float4 p0 = ldu(&P[j]), p1 = ldu(&P[j + 1]), p2 = ldu(&P[j + 2]), p3 = ldu(&P[j + 3]);
+      cand32(j, p0, FILT ? filter_mask(mode, j) : ~0ull, visE, g32, w32, kc);
+      cand32(j + 1, p1, FILT ? filter_mask(mode, j + 1) : ~0ull, visE, g32, w32, kc);
+      cand32(j + 2, p2, FILT ? filter_mask(mode, j + 2) : ~0ull, visE, g32, w32, kc);
+      cand32(j + 3, p3, FILT ? filter_mask(mode, j + 3) : ~0ull, visE, g32, w32, kc);
+      drain(false);
     }
+    // at most 3 more candidates: the ring (kQueueCap >= 4 * 64 + 63 + 3 * 64)
+    // holds them without a drain in between
+    for (; j < je; ++j) cand32(j, ldu(&P[j]), FILT ? filter_mask(mode, j) : ~0ull, visE, g32, w32, kc);
+    drain(false);
+  }
+
+  __device__ __forceinline__ void visit(uint32_t jb, uint32_t je, int mode) {
     if constexpr (FP32) {
       float visE = 0.0f;
       float g32[3] = {0.0f, 0.0f, 0.0f};
       float w32[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       const int kc = kcode(p[0], p[1], p[2]);
-      uint32_t j = jb;
-      for (; j + 4 <= je; j += 4) {
-        const float4 p0 = ldu(&P[j]), p1 = ldu(&P[j + 1]), p2 = ldu(&P[j + 2]), p3 = ldu(&P[j + 3]);
-        cand32<FILTER>(j, p0, visE, g32, w32, kc);
-        cand32<FILTER>(j + 1, p1, visE, g32, w32, kc);
-        cand32<FILTER>(j + 2, p2, visE, g32, w32, kc);
-        cand32<FILTER>(j + 3, p3, visE, g32, w32, kc);
-        drain(false);
-      }
-      for (; j < je; ++j) {
-        cand32<FILTER>(j, ldu(&P[j]), visE, g32, w32, kc);
-        drain(false);
-      }
+      if (mode == 0)
+        loop32<false>(jb, je, 0, visE, g32, w32, kc);
+      else
+        loop32<true>(jb, je, mode, visE, g32, w32, kc);
       if constexpr (kSum) accE += kLJF ? 0.5 * (double)visE : (double)visE;
       if constexpr (kLJF) {
+        double ga[3];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) S[a] += (double)g32[a];
+        for (int a = 0; a < DIM; ++a) {
+          ga[a] = (double)g32[a] * inv_s2;
+          G[a] += ga[a];
+        }
+        if (p[0] != 0 || p[1] != 0 || p[2] != 0) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) B[a * 3 + b] += 0.5 * ga[a] * (double)p[b];
+        }
         if constexpr (kVir) {
 #pragma unroll
-          for (int k = 0; k < 6; ++k) W[k] += 0.5 * (double)w32[k];
+          for (int k = 0; k < 6; ++k) W[k] += 0.5 * inv_s2 * (double)w32[k];
         }
       }
-      fold_visit();
     } else {
-      for (uint32_t j = jb; j < je; ++j) cand64<FILTER>(j, ldu(&R[j]));
+      if constexpr (kLJF) {
+        S[0] = 0.0; S[1] = 0.0; S[2] = 0.0;
+      }
+      if (mode == 0) {
+        for (uint32_t j = jb; j < je; ++j) cand64(j, ldu(&R[j]), ~0ull);
+      } else {
+        for (uint32_t j = jb; j < je; ++j) cand64(j, ldu(&R[j]), filter_mask(mode, j));
+      }
       fold_visit();
     }
   }
@@ -623,6 +654,13 @@ struct Sweep {
         const int rowbase = (uyw + ny * uzw) * nx;
         const int xlo = home ? cx0 : cx0 - l;
         const int xhi = cx1 + l;
+        // origin of the row's cell 0 (unwrapped row index), FP64
+        double Orow[3] = {0.0, 0.0, 0.0};
+        if constexpr (FP32) {
+          const double u1 = (double)uy, u2 = DIM == 3 ? (double)uz : 0.0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) Orow[a] = ldu(&J->Hn[a * 3 + 1]) * u1 + ldu(&J->Hn[a * 3 + 2]) * u2;
+        }
         for (int ux = xlo; ux <= xhi; ++ux) {
           int uxw = ux, px = 0;
           if (uxw < 0) { uxw += nx; px = -1; } else if (uxw >= nx) { uxw -= nx; px = 1; }
@@ -636,21 +674,16 @@ struct Sweep {
           t[2] = ldu(&J->tK[kc * 4 + 2]);
           if constexpr (FP32) {
             // origin of the visited cell (unwrapped index u), FP64
-            const double u0 = (double)ux, u1 = (double)uy, u2 = DIM == 3 ? (double)uz : 0.0;
+            const double u0 = (double)ux;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-              const double O = (Hn[a * 3 + 0] * u0 + Hn[a * 3 + 1] * u1) + Hn[a * 3 + 2] * u2;
+              const double O = Orow[a] + Hn0[a] * u0;
               q[a] = active ? (float)(ri[a] - O) : 1e18f;
             }
             if (DIM == 2) q[2] = 0.0f;
           }
           const bool own = !cross && dz == 0 && dy == 0 && px == 0 && ux >= cx0 && ux <= cx1;
-          if (home && px == 0)
-            visit<1>(jb, je);
-          else if (full && own)
-            visit<2>(jb, je);
-          else
-            visit<0>(jb, je);
+          visit(jb, je, (home && px == 0) ? 1 : ((full && own) ? 2 : 0));
         }
       }
     }
