@@ -105,6 +105,8 @@ typedef struct clm_box_info {
   double cutoff;
   double rc2;           /* fl(cutoff * cutoff), the membership threshold */
   double guard_band;    /* absolute band on FP32 squared distances, see clm_precision */
+  int lcell_x;          /* effective neighbour reach in cells along the row (first) axis */
+  int pad;
 } clm_box_info;
 
 typedef struct clm_celllist_info {
@@ -155,6 +157,12 @@ clm_status clm_context_destroy(clm_context* ctx);
 /* Box (host only, no device work): H as above, cutoff rc > 0, lcell >= 1
  * (cell side ~ rc/lcell, the paper's lcell, section 2.8). */
 clm_status clm_box_create(int dim, const double* H, double cutoff, int lcell, clm_box** out);
+/* The same with a separate reach along the row (first fractional) axis:
+ * cells there are ~ rc/lcell_x thick, on the other axes ~ rc/lcell
+ * (lcell_x = 0: lcell).  Any lcell_x >= 1 gives the same pair set; a finer
+ * row axis packs more particles into each work tile of whole cells. */
+clm_status clm_box_create_ex(int dim, const double* H, double cutoff, int lcell, int lcell_x,
+                             clm_box** out);
 /* Triclinic box from lengths (a, b, c) and angles in degrees (alpha =
  * angle(b,c), beta = angle(a,c), gamma = angle(a,b)); a along x, b in xy. */
 clm_status clm_box_from_lengths_angles(const double* lengths, const double* angles_deg,

@@ -58,9 +58,11 @@ def stats(reset=True, device=None):
 # ---------------------------------------------------------------- box
 class Box:
     """Periodic box: H with the lattice vectors as columns (paper Code 3), a
-    cutoff, and lcell (cell side about cutoff/lcell, paper section 2.8)."""
+    cutoff, and lcell (cell side about cutoff/lcell, paper section 2.8).
+    lcell_x (default: lcell) sets the cell thickness along the first
+    fractional axis separately; the pair set does not depend on it."""
 
-    def __init__(self, H, cutoff, lcell=2):
+    def __init__(self, H, cutoff, lcell=2, lcell_x=None):
         H = np.ascontiguousarray(np.asarray(H, dtype=np.float64))
         if H.ndim != 2 or H.shape[0] != H.shape[1]:
             raise ValueError("H must be a square matrix")
@@ -69,8 +71,8 @@ class Box:
         self.cutoff = float(cutoff)
         self.lcell_requested = int(lcell)
         h = ctypes.c_void_p()
-        L.check(L.lib().clm_box_create(self.dim, H.ctypes.data_as(_dp), self.cutoff, int(lcell),
-                                       ctypes.byref(h)))
+        L.check(L.lib().clm_box_create_ex(self.dim, H.ctypes.data_as(_dp), self.cutoff, int(lcell),
+                                          int(lcell_x or 0), ctypes.byref(h)))
         self._h = h
 
     @classmethod
@@ -94,7 +96,7 @@ class Box:
         L.check(L.lib().clm_box_info_get(self._h, ctypes.byref(bi)))
         d = bi.dim
         return {
-            "dim": d, "lcell_requested": bi.lcell_requested, "lcell": bi.lcell,
+            "dim": d, "lcell_requested": bi.lcell_requested, "lcell": bi.lcell, "lcell_x": bi.lcell_x,
             "small_box": bool(bi.small_box), "grid": list(bi.grid[:d]), "ncells": bi.ncells,
             "H": np.array(bi.H[: d * d]).reshape(d, d), "Hinv": np.array(bi.Hinv[: d * d]).reshape(d, d),
             "widths": list(bi.widths[:d]), "volume": bi.volume, "cutoff": bi.cutoff, "rc2": bi.rc2,

@@ -34,7 +34,7 @@ class BoxInfo(ctypes.Structure):
         ("small_box", ctypes.c_int), ("grid", ctypes.c_int * 3), ("ncells", ctypes.c_int64),
         ("H", ctypes.c_double * 9), ("Hinv", ctypes.c_double * 9), ("widths", ctypes.c_double * 3),
         ("volume", ctypes.c_double), ("cutoff", ctypes.c_double), ("rc2", ctypes.c_double),
-        ("guard_band", ctypes.c_double),
+        ("guard_band", ctypes.c_double), ("lcell_x", ctypes.c_int), ("pad", ctypes.c_int),
     ]
 
 
@@ -72,6 +72,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = [
     "clm_context_create", "clm_context_set_stream", "clm_context_destroy", "clm_box_create",
+    "clm_box_create_ex",
     "clm_box_from_lengths_angles", "clm_box_info_get", "clm_box_destroy",
     "clm_celllist_workspace_bytes", "clm_celllist_create", "clm_celllist_build", "clm_map",
     "clm_celllist_info_get", "clm_celllist_destroy", "clm_synchronize", "clm_last_error",
@@ -101,6 +102,7 @@ def lib():
     L.clm_context_set_stream.argtypes = [_vp, _vp]
     L.clm_context_destroy.argtypes = [_vp]
     L.clm_box_create.argtypes = [c_int, _dp, c_d, c_int, pvp]
+    L.clm_box_create_ex.argtypes = [c_int, _dp, c_d, c_int, c_int, pvp]
     L.clm_box_from_lengths_angles.argtypes = [_dp, _dp, c_d, c_int, pvp]
     L.clm_box_info_get.argtypes = [_vp, ctypes.POINTER(BoxInfo)]
     L.clm_box_destroy.argtypes = [_vp]

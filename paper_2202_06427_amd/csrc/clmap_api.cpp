@@ -91,6 +91,7 @@ struct Timed {
 struct clm_box {
   int dim;
   int lcell_req, lcell;
+  int lcx_req, lcx;  // along the first fractional axis (rows run along it)
   int small;
   int n[3];
   int64_t ncells;
@@ -204,12 +205,16 @@ static float round_up_f(double v) {
 
 static constexpr int64_t kMaxCells = int64_t(1) << 24;
 
-static clm_status box_setup(int dim, const double* Hin, double cutoff, int lcell, clm_box* B) {
+static clm_status box_setup(int dim, const double* Hin, double cutoff, int lcell, int lcell_x,
+                            clm_box* B) {
   if (dim != 2 && dim != 3) return fail(CLM_E_BAD_BOX, "dim must be 2 or 3 (got %d)", dim);
   if (!Hin) return fail(CLM_E_INVALID_ARG, "H is NULL");
   if (!(cutoff > 0.0) || !std::isfinite(cutoff))
     return fail(CLM_E_BAD_CUTOFF, "cutoff must be finite and > 0");
   if (lcell < 1 || lcell > 8) return fail(CLM_E_BAD_CUTOFF, "lcell must be in 1..8 (got %d)", lcell);
+  if (lcell_x == 0) lcell_x = lcell;
+  if (lcell_x < 1 || lcell_x > 8)
+    return fail(CLM_E_BAD_CUTOFF, "lcell_x must be 0 or in 1..8 (got %d)", lcell_x);
   std::memset(B, 0, sizeof *B);
   B->dim = dim;
   for (int a = 0; a < dim; ++a)
@@ -252,39 +257,49 @@ static clm_status box_setup(int dim, const double* Hin, double cutoff, int lcell
   B->rc = cutoff;
   B->rc2 = cutoff * cutoff;
   B->lcell_req = lcell;
+  B->lcx_req = lcell_x;
   for (int a = 0; a < 3; ++a) B->n[a] = 1;
-  // grid: cells of fractional width 1/n_d with w_d / n_d >= (rc / l)(1 + 1e-9),
-  // at least 2l+1 cells per axis (so the +-l neighbours are distinct cells)
+  // grid: cells of fractional width 1/n_d with w_d / n_d >= (rc / l_d)(1 + 1e-9),
+  // at least 2 l_d + 1 cells per axis (so the +-l_d neighbours are distinct
+  // cells).  l_d = lcell on the cross-row axes; the row axis may use a finer
+  // lcell_x (more, thinner cells per row: fuller tiles).  When an axis is too
+  // short both levels step down together.
   B->small = 1;
-  for (int l = lcell; l >= 1; --l) {
+  for (int l = lcell, lx = lcell_x; l >= 1 && lx >= 1; --l, --lx) {
     int n[3] = {1, 1, 1};
+    int ld[3] = {lx, l, l};
     bool ok = true;
     double prod = 1.0;
     for (int d = 0; d < dim; ++d) {
-      double m = std::floor(B->w[d] * (double)l / cutoff / (1.0 + 1e-9));
-      if (!(m >= 2.0 * l + 1.0)) { ok = false; break; }
+      double m = std::floor(B->w[d] * (double)ld[d] / cutoff / (1.0 + 1e-9));
+      if (!(m >= 2.0 * ld[d] + 1.0)) { ok = false; break; }
       if (m > 65535.0) m = 65535.0;
       n[d] = (int)m;
       prod *= m;
     }
-    if (!ok) continue;
+    if (!ok) {
+      if (l == 1 && lx > 1) l = 2;  // keep lcell 1 on the cross-row axes, refine x less
+      else if (lx == 1 && l > 1) lx = 2;
+      continue;
+    }
     if (prod > (double)kMaxCells) {  // coarser cells stay correct (side >= rc/l)
       double f = std::pow((double)kMaxCells / prod, 1.0 / dim);
       prod = 1.0;
       for (int d = 0; d < dim; ++d) {
-        n[d] = std::max(2 * l + 1, (int)std::floor(n[d] * f));
+        n[d] = std::max(2 * ld[d] + 1, (int)std::floor(n[d] * f));
         prod *= n[d];
       }
       if (prod > (double)kMaxCells) continue;
     }
     B->lcell = l;
+    B->lcx = lx;
     B->small = 0;
     for (int d = 0; d < dim; ++d) B->n[d] = n[d];
     break;
   }
-  if (B->small) B->lcell = 1;
+  if (B->small) B->lcell = B->lcx = 1;
   B->ncells = (int64_t)B->n[0] * B->n[1] * B->n[2];
-  B->smax = std::max(1, std::min(kMaxSpan, B->n[0] - 2 * B->lcell));
+  B->smax = std::max(1, std::min(kMaxSpan, B->n[0] - 2 * B->lcx));
   // canonical image shifts t = H K for K in {-1,0,1}^3
   for (int kz = -1; kz <= 1; ++kz)
     for (int ky = -1; ky <= 1; ++ky)
@@ -496,15 +511,20 @@ clm_status clm_stats_get(clm_context* ctx, clm_stats* out, int reset) {
   return CLM_OK;
 }
 
-clm_status clm_box_create(int dim, const double* H, double cutoff, int lcell, clm_box** out) {
+clm_status clm_box_create_ex(int dim, const double* H, double cutoff, int lcell, int lcell_x,
+                             clm_box** out) {
   if (!out) return fail(CLM_E_INVALID_ARG, "out is NULL");
   clm_box tmp;
-  clm_status s = box_setup(dim, H, cutoff, lcell, &tmp);
+  clm_status s = box_setup(dim, H, cutoff, lcell, lcell_x, &tmp);
   if (s != CLM_OK) return s;
   auto* b = new (std::nothrow) clm_box(tmp);
   if (!b) return fail(CLM_E_INVALID_ARG, "out of host memory");
   *out = b;
   return CLM_OK;
+}
+
+clm_status clm_box_create(int dim, const double* H, double cutoff, int lcell, clm_box** out) {
+  return clm_box_create_ex(dim, H, cutoff, lcell, 0, out);
 }
 
 clm_status clm_box_from_lengths_angles(const double* len, const double* deg, double cutoff,
@@ -537,6 +557,7 @@ clm_status clm_box_info_get(const clm_box* B, clm_box_info* o) {
   o->dim = B->dim;
   o->lcell_requested = B->lcell_req;
   o->lcell = B->lcell;
+  o->lcell_x = B->lcx;
   o->small_box = B->small;
   for (int d = 0; d < 3; ++d) o->grid[d] = B->n[d];
   o->ncells = B->ncells;
@@ -686,6 +707,7 @@ static JobDesc base_job(const clm_celllist* cl) {
   const clm_box& B = cl->box;
   jd.dim = B.dim;
   jd.lcell = B.lcell;
+  jd.lcell_x = B.lcx;
   jd.cross = cl->cross;
   for (int d = 0; d < 3; ++d) jd.n[d] = B.n[d];
   jd.ncells = (int)B.ncells;

@@ -54,6 +54,7 @@ static_assert(sizeof(Tile) == 16, "tile is 16 bytes");
 struct JobDesc {
   // geometry
   int dim, lcell, full_shell, cross;
+  int lcell_x, pad_lx;       // neighbour reach in cells along the row axis
   int n[3];
   int ncells;
   int nx, ny;            // particles of x and y (y == x for a single set)

@@ -120,7 +120,7 @@ struct Sweep {
 
   // ---- uniform job constants
   const JobDesc* J;
-  int cross, full, l, nx, ny, nz;
+  int cross, full, l, lx, nx, ny, nz;
   double Hn0[3];     // H[a][0] / n[0]: origin step between cells of a row
   double rc2;
   float lo32, hi32;
@@ -167,6 +167,7 @@ struct Sweep {
     cross = ldu(&J->cross);
     full = ldu(&J->full_shell) || cross;
     l = ldu(&J->lcell);
+    lx = ldu(&J->lcell_x);
     nx = ldu(&J->n[0]);
     ny = ldu(&J->n[1]);
     nz = ldu(&J->n[2]);
@@ -652,8 +653,8 @@ struct Sweep {
           if (uzw < 0) { uzw += nz; pz = -1; } else if (uzw >= nz) { uzw -= nz; pz = 1; }
         }
         const int rowbase = (uyw + ny * uzw) * nx;
-        const int xlo = home ? cx0 : cx0 - l;
-        const int xhi = cx1 + l;
+        const int xlo = home ? cx0 : cx0 - lx;
+        const int xhi = cx1 + lx;
         // origin of the row's cell 0 (unwrapped row index), FP64
         double Orow[3] = {0.0, 0.0, 0.0};
         if constexpr (FP32) {
@@ -1093,7 +1094,7 @@ __global__ void __launch_bounds__(256) candidates_kernel(const JobDesc* __restri
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntiles) return;
   const Tile T = tiles[t];
-  const int l = J.lcell, nx = J.n[0], ny = J.n[1], nz = J.n[2];
+  const int l = J.lcell, lx = J.lcell_x, nx = J.n[0], ny = J.n[1], nz = J.n[2];
   const int dim = J.dim;
   const int cy = (int)(T.row % (uint32_t)ny), cz = dim == 3 ? (int)(T.row / (uint32_t)ny) : 0;
   const bool fs = full || J.cross;
@@ -1105,7 +1106,7 @@ __global__ void __launch_bounds__(256) candidates_kernel(const JobDesc* __restri
       const bool home = !fs && dz == 0 && dy == 0;
       const int uy = (cy + dy + ny) % ny, uz = dim == 3 ? (cz + dz + nz) % nz : 0;
       const int rowbase = (uy + ny * uz) * nx;
-      const int xlo = home ? (int)T.cx0 : (int)T.cx0 - l, xhi = (int)T.cx1 + l;
+      const int xlo = home ? (int)T.cx0 : (int)T.cx0 - lx, xhi = (int)T.cx1 + lx;
       for (int ux = xlo; ux <= xhi; ++ux) {
         const bool wrapped = ux < 0 || ux >= nx;
         const int cc = rowbase + ((ux % nx) + nx) % nx;

@@ -114,6 +114,33 @@ def test_grid_covers_the_cutoff(k, lcell):
         L.lib().clm_box_destroy(h)
 
 
+@pytest.mark.parametrize("k", range(len(BOXES)))
+@pytest.mark.parametrize("lcell,lcell_x", [(1, 2), (2, 3), (2, 4), (3, 1)])
+def test_grid_covers_the_cutoff_row_axis_refined(k, lcell, lcell_x):
+    """A separate reach along the row axis: every axis d still has cells of
+    width >= rc / l_d and at least 2 l_d + 1 of them."""
+    H = np.ascontiguousarray(BOXES[k], dtype=np.float64)
+    dim = H.shape[0]
+    w, _ = oracle.box_widths(H)
+    for rc in (w.min() / 3.5, w.min() / 7.3, w.min() / 20.0):
+        h = ctypes.c_void_p()
+        st = L.lib().clm_box_create_ex(dim, H.ctypes.data_as(_dp), rc, lcell, lcell_x, ctypes.byref(h))
+        assert st == 0
+        bi = _info(h)
+        if bi.small_box:
+            L.lib().clm_box_destroy(h)
+            continue
+        lds = [bi.lcell_x] + [bi.lcell] * (dim - 1)
+        assert 1 <= bi.lcell <= lcell and 1 <= bi.lcell_x <= lcell_x
+        for d in range(dim):
+            n = bi.grid[d]
+            assert n >= 2 * lds[d] + 1
+            assert w[d] / n >= rc / lds[d]
+        L.lib().clm_box_destroy(h)
+    h = ctypes.c_void_p()
+    assert L.lib().clm_box_create_ex(dim, H.ctypes.data_as(_dp), 1.0, 2, 9, ctypes.byref(h)) == 3
+
+
 def test_small_box_flag_and_lcell_fallback():
     st, h = _box(3, np.eye(3) * 10.0, 4.0, 1)  # 2 cells per axis: brute force
     assert st == 0 and _info(h).small_box == 1

@@ -48,12 +48,12 @@ def _sorted_pairs(pairs):
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("lcell", [1, 2, 3])
-def test_neighbor_list_and_sums_exact(clm, name, precision, lcell):
+@pytest.mark.parametrize("lcell,lcell_x", [(1, None), (2, None), (3, None), (1, 2), (2, 3), (2, 4)])
+def test_neighbor_list_and_sums_exact(clm, name, precision, lcell, lcell_x):
     H, n, rc = CASES[name]
     x = W.uniform_in_box(n, H, 1000 + n)
     ref = oracle.compute(x, H, rc, nl=True, sum_d=True, sum_inv_d=True)
-    box = clm.Box(H, rc, lcell)
+    box = clm.Box(H, rc, lcell, lcell_x)
     cl = clm.CellList(T(x), box, precision=precision)
     pairs, dist = cl.neighbor_list()
     p, order = _sorted_pairs(pairs)
@@ -89,8 +89,8 @@ def _pair_force_abs_sums(x, H, rc, ref, sigma, eps):
 
 @pytest.mark.parametrize("name", ["cube3", "tric3", "skew3", "tric2"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("lcell", [1, 2])
-def test_lj_energy_forces_box_gradient(clm, name, precision, lcell):
+@pytest.mark.parametrize("lcell,lcell_x", [(1, None), (2, None), (2, 3)])
+def test_lj_energy_forces_box_gradient(clm, name, precision, lcell, lcell_x):
     H, n, rc = CASES[name]
     dim = H.shape[0]
     sigma, eps = 1.1, 0.3
@@ -100,7 +100,7 @@ def test_lj_energy_forces_box_gradient(clm, name, precision, lcell):
     s = (grid + 0.5 + 0.3 * (W.rng(7).random(grid.shape) - 0.5)) / m
     x = s @ H.T + (H @ np.array([3, -2, 5][:dim]))  # positions outside the primary cell
     ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
-    box = clm.Box(H, rc, lcell)
+    box = clm.Box(H, rc, lcell, lcell_x)
     cl = clm.CellList(T(x), box, precision=precision)
     e, c = cl.lj_energy(sigma, eps)
     assert int(c.item()) == ref["count"]
