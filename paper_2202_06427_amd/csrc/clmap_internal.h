@@ -21,7 +21,9 @@ namespace clm {
 constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kTileMax = 64;     // particles per tile: one per lane
 constexpr int kMaxSpan = 16;     // most cells a tile may span along x
-constexpr int kBlock = 256;      // threads per block in the sweep (4 waves)
+constexpr int kBlock = 256;      // register budget of the sweep: up to 4 waves per block
+constexpr int kSweepWaves = 1;   // waves (tiles) per launched sweep block: each wave
+                                 // frees its slot as soon as its tile is done
 constexpr int kNLStage = 256;    // per-wave LDS staging slots for neighbour pairs
 constexpr int kPartialD = 20;    // doubles per tile partial
 constexpr int kMaxBins = 1000;  // keeps 4 waves of private histograms within 64 KiB LDS

@@ -756,7 +756,7 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
   const int lane = (int)__lane_id();
   const int wid = uniform((int)(threadIdx.x / kWave));
   // the tile count is produced on the device; never trust it past the array
-  constexpr int kWpb = kBlock / kWave;
+  constexpr int kWpb = kSweepWaves;
   const int ntiles = min((int)ldu(ntiles_dev), (int)(gridDim.x * kWpb));
   // The grid is sized by an upper bound on the tile count; only the first
   // nblk blocks have work.  Blocks are dispatched to the 8 XCDs round-robin,
@@ -1238,15 +1238,15 @@ template <int DIM, bool FP32>
 static hipError_t sweep_dispatch(int kind, dim3 grid, size_t lds, const JobDesc* jobs,
                                  const Tile* tiles, const uint32_t* nt, hipStream_t s) {
   switch (kind) {
-    case K_COUNT: sweep_kernel<DIM, FP32, K_COUNT><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
-    case K_SUM_D: sweep_kernel<DIM, FP32, K_SUM_D><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
-    case K_SUM_INV_D: sweep_kernel<DIM, FP32, K_SUM_INV_D><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
-    case K_LJ_E: sweep_kernel<DIM, FP32, K_LJ_E><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
-    case K_LJ_F: sweep_kernel<DIM, FP32, K_LJ_F><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
-    case K_LJ_FV: sweep_kernel<DIM, FP32, K_LJ_FV><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
-    case K_HIST_DIST: sweep_kernel<DIM, FP32, K_HIST_DIST><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
-    case K_HIST_REL: sweep_kernel<DIM, FP32, K_HIST_REL><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
-    case K_NL: sweep_kernel<DIM, FP32, K_NL><<<grid, kBlock, lds, s>>>(jobs, tiles, nt); break;
+    case K_COUNT: sweep_kernel<DIM, FP32, K_COUNT><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_SUM_D: sweep_kernel<DIM, FP32, K_SUM_D><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_SUM_INV_D: sweep_kernel<DIM, FP32, K_SUM_INV_D><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_LJ_E: sweep_kernel<DIM, FP32, K_LJ_E><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_LJ_F: sweep_kernel<DIM, FP32, K_LJ_F><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_LJ_FV: sweep_kernel<DIM, FP32, K_LJ_FV><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_HIST_DIST: sweep_kernel<DIM, FP32, K_HIST_DIST><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_HIST_REL: sweep_kernel<DIM, FP32, K_HIST_REL><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_NL: sweep_kernel<DIM, FP32, K_NL><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1255,7 +1255,7 @@ static hipError_t sweep_dispatch(int kind, dim3 grid, size_t lds, const JobDesc*
 hipError_t launch_sweep(int dim, bool fp32, int kind, const JobDesc* jobs, const Tile* tiles,
                         const uint32_t* ntiles_dev, int max_tiles, int nbins, hipStream_t s) {
   if (max_tiles <= 0) return hipSuccess;
-  const int waves = kBlock / kWave;
+  const int waves = kSweepWaves;
   dim3 grid((max_tiles + waves - 1) / waves);
   size_t lds = sweep_lds_per_wave(kind, nbins, fp32) * waves;
   if (dim == 3)
