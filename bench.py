@@ -126,8 +126,10 @@ def served(n_requests, seed=5):
     import workloads as W
     from paper_2202_06427_amd.serve import Job, Server
 
+    import torch
     reqs = W.serve_requests(seed=seed, count=n_requests)
-    xs = [W.request_positions(r) for r in reqs]
+    # request payloads arrive in pinned host buffers (as from a network stack)
+    xs = [torch.from_numpy(W.request_positions(r)).pin_memory() for r in reqs]
 
     def jobs(rate):
         g = np.random.Generator(np.random.PCG64(seed + 1))

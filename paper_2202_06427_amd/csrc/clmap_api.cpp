@@ -155,6 +155,7 @@ struct clm_celllist {
   unsigned long long* cand;
   double* fin_scratch;
   unsigned long long* fin_count;
+  double* brute_fb;       // small boxes: per-chunk LJ force rows
   int built;
 };
 
@@ -384,8 +385,12 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
   if (cl->cross) set(cl->Y, cl->ny);
   const int nrows = (int)(B.n[1] * B.n[2]);
   const int64_t maxt = max_tiles_for(B, cl->nx);
-  const int64_t brute_blocks = (cl->nx + 255) / 256 + 1;
-  const int64_t parts = std::max<int64_t>(maxt, brute_blocks);
+  // brute-force path (small boxes): partial rows per (64 particles, j chunk)
+  // and per-chunk force rows
+  const int64_t nyb = cl->cross ? cl->ny : cl->nx;
+  const int64_t brute_rows =
+      B.small ? std::max<int64_t>(1, (cl->nx + kWave - 1) / kWave) * brute_chunks(nyb) : 1;
+  const int64_t parts = std::max<int64_t>(maxt, brute_rows);
   const size_t scan_elems =
       std::max(scan_scratch_elems((int)std::max<int64_t>(B.ncells, 1)), scan_scratch_elems(nrows));
   size_t o_scan = c.take(sizeof(uint32_t) * scan_elems);
@@ -403,6 +408,7 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
   size_t o_cand = c.take(sizeof(unsigned long long) * maxt);
   size_t o_fin = c.take(sizeof(double) * kPartialD * kFinalBlocks);
   size_t o_finc = c.take(sizeof(unsigned long long) * kFinalBlocks);
+  size_t o_fb = B.small ? c.take(sizeof(double) * 3 * (size_t)brute_chunks(nyb) * (size_t)cl->nx) : 0;
   if (base) {
     cl->scan_scratch = (uint32_t*)(base + o_scan);
     cl->row_tiles = (uint32_t*)(base + o_rt);
@@ -419,6 +425,7 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
     cl->cand = (unsigned long long*)(base + o_cand);
     cl->fin_scratch = (double*)(base + o_fin);
     cl->fin_count = (unsigned long long*)(base + o_finc);
+    cl->brute_fb = B.small ? (double*)(base + o_fb) : nullptr;
     cl->max_tiles = (int)maxt;
     cl->max_parts = (int)parts;
     cl->nrows = nrows;
@@ -885,7 +892,7 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
                   "box has fewer than 3 cells per axis and %.3g candidate pairs: the brute-force "
                   "minimum-image path serves at most 4e9", pairs);
     int nblocks = 0;
-    CLM_HIP(launch_brute(cl->job_dev, A, &nblocks, st));
+    CLM_HIP(launch_brute(cl->job_dev, A, cl->brute_fb, &nblocks, st));
     F.nparts = nblocks;
     F.nparts_dev = nullptr;
   } else {

@@ -195,7 +195,14 @@ hipError_t launch_relspeed_band(const unsigned int* vmax_bits, double hi, int di
                                 hipStream_t s);
 hipError_t launch_sweep(int dim, bool fp32, int kind, const JobDesc* jobs, const Tile* tiles,
                         const uint32_t* ntiles_dev, int max_tiles, int nbins, hipStream_t s);
-hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, int* nblocks_out, hipStream_t s);
+// Brute-force path: j chunks per 64 particles (enough waves to fill the chip
+// for a few thousand particles); partial rows = ceil(n_x / 64) * chunks.
+__host__ __device__ inline int brute_chunks(int64_t ny) {
+  int64_t c = (ny + 127) / 128;
+  return (int)(c < 1 ? 1 : (c > 32 ? 32 : c));
+}
+hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, double* FB, int* nparts_out,
+                        hipStream_t s);
 hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, double* scratch,
                            unsigned long long* scratch_count, hipStream_t s);
 constexpr int kFinalBlocks = 128;  // first-level blocks of the two-level finalize

@@ -863,27 +863,34 @@ __device__ __forceinline__ double min_image64(const BruteArgs& A, const double* 
   return best;
 }
 
-__global__ void __launch_bounds__(256) brute_kernel(const JobDesc* __restrict__ jobs, BruteArgs A) {
+// Small boxes: every pair by brute force with the minimum image found by a
+// per-pair search.  The work is split over (64 particles i) x (a chunk of j):
+// one wave per block, its partial sums in partial row blockIdx.x + nib *
+// blockIdx.y; LJ forces go to per-chunk rows of FB (fixed-order sum later).
+__global__ void __launch_bounds__(64) brute_kernel(const JobDesc* __restrict__ jobs, BruteArgs A,
+                                                   int jchunk, double* __restrict__ FB) {
   const JobDesc& J = jobs[0];
   const int dim = A.dim;
-  const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)threadIdx.x;
+  const int ii = blockIdx.x * kWave + lane;
   const bool act = ii < A.n_x;
+  const int ny = A.cross ? A.n_y : A.n_x;
+  const int jlo = blockIdx.y * jchunk, jhi = min(ny, jlo + jchunk);
   double accE = 0.0, G[3] = {0, 0, 0}, W[9] = {0}, B[9] = {0};
   unsigned long long cnt = 0;
-  uint32_t io = 0;
   if (act) {
     const int i = ii;
-    io = J.idx_x[i];
+    const uint32_t io = J.idx_x[i];
     const double4 r = J.r64_x[i];
     const double ri[3] = {r.x, r.y, r.z};
     double vi[3] = {0, 0, 0};
     if (A.kind == K_HIST_REL)
       for (int a = 0; a < dim; ++a) vi[a] = J.vel64_x[(size_t)io * dim + a];
-    const int ny = A.cross ? A.n_y : A.n_x;
     const double4* __restrict__ R = A.cross ? J.r64_y : J.r64_x;
     const uint32_t* __restrict__ IX = A.cross ? J.idx_y : J.idx_x;
     const bool gather = A.kind == K_LJ_F;
-    for (int j = (A.cross || gather) ? 0 : i + 1; j < ny; ++j) {
+    const int j0 = (A.cross || gather) ? jlo : max(jlo, i + 1);
+    for (int j = j0; j < jhi; ++j) {
       if (!A.cross && j == i) continue;
       const double4 rr = R[j];
       const double rj[3] = {rr.x, rr.y, rr.z};
@@ -943,47 +950,51 @@ __global__ void __launch_bounds__(256) brute_kernel(const JobDesc* __restrict__ 
       }
     }
     if (A.kind == K_LJ_F) {
-      double mult = J.upstream ? *J.upstream : J.scale;
-      double s = mult * 24.0 * J.eps;
-      for (int a = 0; a < dim; ++a) J.forces[(size_t)io * dim + a] = s * G[a];
+      // this chunk's share of the force on i, and of the wrap term G w^T
+      // (linear in G, so it can be summed per chunk)
+      double* fb = FB + ((size_t)blockIdx.y * A.n_x + i) * 3;
+      for (int a = 0; a < 3; ++a) fb[a] = a < dim ? G[a] : 0.0;
       const int4 w = J.wrap_x[i];
       const int wv[3] = {w.x, w.y, w.z};
       for (int a = 0; a < dim; ++a)
         for (int b = 0; b < dim; ++b) B[a * 3 + b] += G[a] * (double)wv[b];
     }
   }
-  // block reduction into per-block partials (slots of the tile partial array)
-  __shared__ double red[256];
-  __shared__ unsigned long long redc[256];
-  double* Pp = J.partials + (size_t)blockIdx.x * kPartialD;
-  auto reduce_d = [&](double v) -> double {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    double r = red[0];
-    __syncthreads();
-    return r;
-  };
-  redc[threadIdx.x] = cnt;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) redc[threadIdx.x] += redc[threadIdx.x + s];
-    __syncthreads();
+  const int row = blockIdx.x + gridDim.x * blockIdx.y;
+  double* Pp = J.partials + (size_t)row * kPartialD;
+  const unsigned long long c = wave_sum_u64(cnt);
+  const double e = wave_sum_d(accE);
+  if (lane == 0) {
+    J.pcount[row] = c;
+    Pp[P_SUM] = e;
   }
-  if (threadIdx.x == 0) J.pcount[blockIdx.x] = redc[0];
-  double e = reduce_d(accE);
-  if (threadIdx.x == 0) Pp[P_SUM] = e;
   if (A.kind == K_LJ_F) {
+#pragma unroll
     for (int k = 0; k < 9; ++k) {
-      double v = reduce_d(W[k]);
-      if (threadIdx.x == 0) Pp[P_VIR + k] = v;
-      double b = reduce_d(B[k]);
-      if (threadIdx.x == 0) Pp[P_BOX + k] = b;
+      const double v = wave_sum_d(W[k]);
+      const double b = wave_sum_d(B[k]);
+      if (lane == 0) {
+        Pp[P_VIR + k] = v;
+        Pp[P_BOX + k] = b;
+      }
     }
   }
+}
+
+// Forces of the brute-force path: the per-chunk rows summed in chunk order.
+__global__ void __launch_bounds__(256) brute_forces_kernel(const JobDesc* __restrict__ jobs, int n,
+                                                           int dim, int nchunks,
+                                                           const double* __restrict__ FB) {
+  const JobDesc& J = jobs[0];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double G[3] = {0, 0, 0};
+  for (int c = 0; c < nchunks; ++c)
+    for (int a = 0; a < 3; ++a) G[a] += FB[((size_t)c * n + i) * 3 + a];
+  const double mult = J.upstream ? *J.upstream : J.scale;
+  const double s = mult * 24.0 * J.eps;
+  const uint32_t io = J.idx_x[i];
+  for (int a = 0; a < dim; ++a) J.forces[(size_t)io * dim + a] = s * G[a];
 }
 
 // ---------------------------------------------------------------- finalize
@@ -1265,11 +1276,16 @@ hipError_t launch_sweep(int dim, bool fp32, int kind, const JobDesc* jobs, const
               : sweep_dispatch<2, false>(kind, grid, lds, jobs, tiles, ntiles_dev, s);
 }
 
-hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, int* nblocks_out, hipStream_t s) {
-  int nb = (A.n_x + 255) / 256;
-  if (nb < 1) nb = 1;
-  *nblocks_out = nb;
-  brute_kernel<<<nb, 256, 0, s>>>(jobs, A);
+hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, double* FB, int* nparts_out,
+                        hipStream_t s) {
+  const int ny = A.cross ? A.n_y : A.n_x;
+  const int nib = std::max(1, (A.n_x + kWave - 1) / kWave);
+  const int njb = brute_chunks(ny);
+  const int jchunk = std::max(1, (ny + njb - 1) / njb);
+  *nparts_out = nib * njb;
+  brute_kernel<<<dim3(nib, njb), kWave, 0, s>>>(jobs, A, jchunk, FB);
+  if (A.kind == K_LJ_F && A.n_x > 0)
+    brute_forces_kernel<<<(A.n_x + 255) / 256, 256, 0, s>>>(jobs, A.n_x, A.dim, njb, FB);
   return hipGetLastError();
 }
 

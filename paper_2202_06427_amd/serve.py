@@ -35,7 +35,7 @@ KINDS = ("lj", "nl", "gr")
 class Job:
     __slots__ = ("id", "x", "H", "cutoff", "kind", "arrival", "params", "lcell", "box", "cl",
                  "xdev", "out", "footprint", "admitted", "done", "result", "status", "capacity",
-                 "retries")
+                 "retries", "host")
 
     def __init__(self, jid, x, H, cutoff, kind, arrival=0.0, params=None, lcell=2):
         if kind not in KINDS:
@@ -55,6 +55,7 @@ class Job:
         self.status = "pending"
         self.capacity = 0
         self.retries = 0
+        self.host = None  # (host counts, host energies, index) of its batch
 
 
 def expected_pairs(n, H, cutoff):
@@ -93,12 +94,12 @@ class GpuExecutor:
 
     def start(self, job):
         xt = job.x if isinstance(job.x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(job.x))
-        job.xdev = xt.to(self.device)
+        # a payload in pinned host memory is copied without blocking the host
+        job.xdev = xt.to(self.device, non_blocking=xt.is_pinned())
         job.cl = CellList(job.xdev, job.box, precision=self.precision)  # enqueues the build
         n, dim = job.xdev.shape
         dev = self.device
-        o = {"energy": torch.empty(1, dtype=torch.float64, device=dev),
-             "count": torch.empty(1, dtype=torch.int64, device=dev)}
+        o = {}  # energy and count are slices of the batch's buffers (launch)
         if job.kind == "lj":
             o["forces"] = torch.empty((n, dim), dtype=torch.float64, device=dev)
             o["grad_box"] = torch.empty((dim, dim), dtype=torch.float64, device=dev)
@@ -127,9 +128,17 @@ class GpuExecutor:
         return L.MAP_KINDS["hist_dist"], P, O
 
     def launch(self, jobs):
-        """One batched sweep over jobs of one kind; returns a completion handle."""
+        """One batched sweep over jobs of one kind; returns a completion handle.
+        The batch's counts and energies land in one device buffer each and are
+        copied to pinned host memory in stream order, so retiring a batch
+        never waits on work launched after it."""
         _context(self.device)
         n = len(jobs)
+        cnt_dev = torch.empty(n, dtype=torch.int64, device=self.device)
+        e_dev = torch.empty(n, dtype=torch.float64, device=self.device)
+        for k, job in enumerate(jobs):
+            job.out["count"] = cnt_dev[k:k + 1]
+            job.out["energy"] = e_dev[k:k + 1]
         cls = (ctypes.c_void_p * n)(*[j.cl._h for j in jobs])
         Ps = (L.MapParams * n)()
         Os = (L.MapOut * n)()
@@ -141,8 +150,14 @@ class GpuExecutor:
         raw = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
         ws = raw[(-raw.data_ptr()) % 256:]
         L.check(L.lib().clm_map_batch(n, cls, mk, Ps, Os, _ptr(ws), int(nb.value)))
+        cnt_host = torch.empty(n, dtype=torch.int64, pin_memory=True)
+        e_host = torch.empty(n, dtype=torch.float64, pin_memory=True)
+        cnt_host.copy_(cnt_dev, non_blocking=True)
+        e_host.copy_(e_dev, non_blocking=True)
         ev = torch.cuda.Event()
         ev.record()
+        for k, job in enumerate(jobs):
+            job.host = (cnt_host, e_host, k)
         return (ev, raw)
 
     def done(self, handle, block=False):
@@ -153,8 +168,10 @@ class GpuExecutor:
         return ev.query()
 
     def finish(self, job):
+        """Results of a job whose batch has completed (host values already copied)."""
         o = job.out
-        cnt = int(o["count"].item())
+        cnt_host, e_host, k = job.host
+        cnt = int(cnt_host[k])
         if job.kind == "nl" and cnt > job.capacity:
             # capacity estimate exceeded: re-run this job alone with the exact size
             job.retries += 1
@@ -163,7 +180,7 @@ class GpuExecutor:
             job.capacity = cnt
         res = {"count": cnt}
         if job.kind == "lj":
-            res["energy"] = float(o["energy"].item())
+            res["energy"] = float(e_host[k])
             res["forces"] = o["forces"]
             res["grad_box"] = o["grad_box"]
         elif job.kind == "nl":

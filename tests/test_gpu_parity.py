@@ -255,6 +255,16 @@ def test_all_particles_in_one_cell_and_heavy_tiles(clm):
         assert np.array_equal(p[:, 0], ref["nl_i"]) and np.array_equal(p[:, 1], ref["nl_j"])
         s, _ = cl.sum_inv_d()
         assert abs(s.item() / ref["sum_inv_d"] - 1) < (1e-12 if precision == "fp64" else 1e-6)
+    # LJ forces with the heavy cell: many tiles of one cell, and overlapping
+    # pairs far inside sigma (re-evaluated in FP64)
+    sigma, eps = 0.2, 0.01
+    refl = oracle.compute(x, H, 3.0, lj=(sigma, eps), lj_grad=True)
+    cl = clm.CellList(T(x), clm.Box(H, 3.0, 2), precision="fp32")
+    out = cl.lj_forces(sigma, eps)
+    assert int(out["count"].item()) == refl["count"]
+    F = out["forces"].cpu().numpy()
+    rel = np.linalg.norm(F + refl["lj_grad"], axis=1).max() / np.linalg.norm(refl["lj_grad"], axis=1).max()
+    assert rel <= 1e-6
 
 
 def test_autograd_lj_energy(clm):
