@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=1000.0,
+                    help="Poisson arrival rate of the served mix (jobs/s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -119,8 +121,9 @@ def time_steps(clm, cl, xt, steps, warmup, sigma, eps):
     }
 
 
-def served(n_requests, seed=5):
-    """Served mix: closed-loop capacity, then Poisson arrivals at 0.8x of it."""
+def served(n_requests, rate, seed=5):
+    """Served mix: closed-loop capacity (every job available at once), then
+    Poisson arrivals at a fixed rate (jobs/s) with p50/p99 latency."""
     import numpy as np
 
     import workloads as W
@@ -143,10 +146,10 @@ def served(n_requests, seed=5):
     warm.run(jobs(None)[: min(64, n_requests)], realtime=False)
     closed = Server(hbm_budget=8 << 30).run(jobs(None), realtime=False)
     cap = closed["jobs_per_s"]
-    rate = 0.8 * cap
     opened = Server(hbm_budget=8 << 30).run(jobs(rate), realtime=True)
     return {"requests": n_requests, "capacity_jobs_per_s": cap, "rate_jobs_per_s": rate,
             "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"], "mean_ms": opened["mean_ms"],
+            "mean_admission_wait_ms": opened["mean_admission_wait_ms"],
             "pairs_per_s": opened["pairs_per_s"], "mean_batch": opened["mean_batch"],
             "closed_loop_p50_ms": closed["p50_ms"], "closed_loop_p99_ms": closed["p99_ms"],
             "hbm_budget_bytes": 8 << 30, "peak_hbm_bytes": opened["peak_hbm_bytes"],
@@ -247,7 +250,7 @@ def main():
         line["energy_rel_diff_fp32_fp64"] = abs(main_r["energy"] - r64["energy"]) / abs(r64["energy"])
     if args.serve_requests > 0:
         log(f"served mix: {args.serve_requests} requests ...")
-        line["served"] = served(args.serve_requests)
+        line["served"] = served(args.serve_requests, args.serve_rate)
         log(f"served: {line['served']}")
     if not args.no_cpu_baseline:
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)

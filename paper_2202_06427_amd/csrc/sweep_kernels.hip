@@ -50,6 +50,15 @@ __device__ __forceinline__ int lane_rank(unsigned long long mask) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// 1/v for the FP64 pair terms: the hardware reciprocal refined by one Newton
+// step (error ~1 ulp; one reciprocal serves both s^2/d^2 and f = (...)/d^2
+// instead of two IEEE divisions).  Membership never depends on it.
+__device__ __forceinline__ double rcp64(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  const double e = __builtin_fma(-v, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // ---------------------------------------------------------------- histogram bins
 // Canonical bin of v against E64[0..nb] (first k with v <= E_{k+1}; v = 0 ->
 // bin 0; beyond E_nb -> nb).  Binary search, FP64.
@@ -270,13 +279,14 @@ struct Sweep {
     if constexpr (KIND == K_SUM_D) accE += sqrt(d2);
     if constexpr (KIND == K_SUM_INV_D) accE += 1.0 / sqrt(d2);
     if constexpr (kLJ) {
-      double x = s2 / d2;
+      const double r = rcp64(d2);
+      double x = s2 * r;
       double x3 = x * x * x;
       double u = x3 * x3 - x3;
       if constexpr (KIND == K_LJ_E) {
         accE += u;
       } else {
-        double f = (2.0 * x3 * x3 - x3) / d2;  // f_s / (24 eps)
+        double f = (2.0 * x3 * x3 - x3) * r;  // f_s / (24 eps)
         accE += 0.5 * u;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) S[a] += f * D[a];
@@ -352,13 +362,14 @@ struct Sweep {
     if constexpr (KIND == K_SUM_D) accE += sqrt(d2);
     if constexpr (KIND == K_SUM_INV_D) accE += 1.0 / sqrt(d2);
     if constexpr (kLJ) {
-      const double x = s2 / d2;
+      const double r = rcp64(d2);
+      const double x = s2 * r;
       const double x3 = x * x * x;
       const double u = x3 * x3 - x3;
       if constexpr (KIND == K_LJ_E) {
         accE += u;
       } else {
-        const double f = (2.0 * x3 * x3 - x3) / d2;
+        const double f = (2.0 * x3 * x3 - x3) * r;
         accE += 0.5 * u;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) atomicAdd(&GA[own * 3 + a], f * D[a]);
@@ -904,10 +915,11 @@ __global__ void __launch_bounds__(64) brute_kernel(const JobDesc* __restrict__ j
         case K_SUM_D: accE += sqrt(d2); break;
         case K_SUM_INV_D: accE += 1.0 / sqrt(d2); break;
         case K_LJ_E: case K_LJ_F: {
-          double x = J.s2 / d2, x3 = x * x * x;
+          const double r = rcp64(d2);
+          double x = J.s2 * r, x3 = x * x * x;
           double u = x3 * x3 - x3;
           if (A.kind == K_LJ_E) { accE += u; break; }
-          double f = (2.0 * x3 * x3 - x3) / d2;
+          double f = (2.0 * x3 * x3 - x3) * r;
           accE += 0.5 * u;
           for (int a = 0; a < dim; ++a) G[a] += f * D[a];
           for (int a = 0; a < dim; ++a)

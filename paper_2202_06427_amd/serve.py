@@ -321,6 +321,7 @@ class Server:
         done = [j for j in self.finished if j.status == "done"]
         failed = [j for j in self.finished if j.status.startswith("failed")]
         lat = np.array([j.done - j.arrival for j in done]) if done else np.zeros(1)
+        wait = np.array([j.admitted - j.arrival for j in done]) if done else np.zeros(1)
         wall = max((j.done for j in done), default=0.0)
         pairs = sum(j.result["count"] for j in done)
         return {
@@ -330,6 +331,8 @@ class Server:
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3),
+            "mean_admission_wait_ms": float(wait.mean() * 1e3),
+            "p99_admission_wait_ms": float(np.percentile(wait, 99) * 1e3),
             "wall_s": wall,
             "jobs_per_s": len(done) / wall if wall > 0 else 0.0,
             "pairs_per_s": pairs / wall if wall > 0 else 0.0,
