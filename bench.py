@@ -30,6 +30,7 @@ VALU_FP64_TFLOPS = 78.6
 # algorithmic work per unit (what the method must do)
 FLOPS_PER_CANDIDATE = 8        # 3 sub, 3 mul, 2 add (distance test)
 FLOPS_PER_LJ_PAIR = 20         # 1 reciprocal + ~19 flops: energy + force on both particles
+BUILD_BYTES_PER_PARTICLE = 44  # 24 read + 16 (FP32 record) + 4 (index) written, 3D
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_lj_forces_uniform1e6_hbm_traffic.md")
@@ -71,6 +72,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=1000.0,
                     help="Poisson arrival rate of the served mix (jobs/s)")
+    ap.add_argument("--build-n-large", type=int, default=16_000_000,
+                    help="particle count of the second build-bandwidth point (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -156,6 +159,34 @@ def served(n_requests, rate, seed=5):
             "nl_retries": opened["nl_retries"], "failed": opened["failed"] + closed["failed"]}
 
 
+def build_roofline(clm, W, n, lcell, steps=5):
+    """Build-only timing (bin + scan + tiles + scatter) of n uniform particles
+    in the headline triclinic box shape scaled to the same density."""
+    import numpy as np
+    import torch
+    c = W.config2(n=1000)
+    H = c["H"] * (n / 1_000_000) ** (1.0 / 3.0)
+    x = W.uniform_in_box(n, H, 21)
+    xt = torch.from_numpy(x).to("cuda:0")
+    del x
+    cl = clm.CellList(xt, clm.Box(H, c["cutoff"], lcell), precision="fp32")
+    for _ in range(2):
+        cl.build(xt)
+    torch.cuda.synchronize()
+    clm.set_timing(True)
+    clm.stats(reset=True)
+    for _ in range(steps):
+        cl.build(xt)
+    torch.cuda.synchronize()
+    st = clm.stats(reset=True)
+    clm.set_timing(False)
+    ms = st["build_ms"] / max(st["builds"], 1)
+    gbs = BUILD_BYTES_PER_PARTICLE * n / (ms * 1e-3) / 1e9
+    del cl, xt
+    torch.cuda.empty_cache()
+    return {"n": n, "build_ms": ms, "algorithmic_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
 def cpu_baseline(cfg, nthreads):
     import oracle
     t0 = time.perf_counter()
@@ -189,8 +220,8 @@ def main():
     res = {}
     for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
         cl = clm.CellList(xt, box, precision=prec)
-        info = cl.info()
         r = time_steps(clm, cl, xt, args.steps, args.warmup, sigma, eps)
+        info = cl.info()  # after the timed steps: re-evaluation counts of the last map
         r["info"] = info
         res[prec] = r
         log(f"{prec}: {r['ms_per_step']:.3f} ms/step (sweep {r['sweep_ms']:.3f} ms, build "
@@ -200,6 +231,7 @@ def main():
 
     main_r = res["fp32"]
     pairs = main_r["count"]
+    guard = main_r["info"]
     value = pairs / (main_r["ms_per_step"] * 1e-3)
     cand = main_r["info"]["candidate_pairs"]
     flops = cand * FLOPS_PER_CANDIDATE + pairs * FLOPS_PER_LJ_PAIR
@@ -233,9 +265,21 @@ def main():
             "traffic": measured_traffic(),
             "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flops_per_launch": flops,
+            "frac_in_cutoff_only": pairs * FLOPS_PER_LJ_PAIR / (main_r["sweep_ms"] * 1e-3) / 1e12
+            / VALU_FP32_NONPACKED_TFLOPS,
             "peak_if_packed_fp32": VALU_FP32_PACKED_TFLOPS,
         },
+        "guard": {"band_retests": guard["guard_retests"], "near_pair_evaluations": guard["near_evaluations"],
+                  "fraction_of_pairs": (guard["guard_retests"] + guard["near_evaluations"]) / max(2 * pairs, 1)},
     }
+    b1 = {"n": args.n, "build_ms": main_r["build_ms"],
+          "algorithmic_GBs": BUILD_BYTES_PER_PARTICLE * args.n / (main_r["build_ms"] * 1e-3) / 1e9}
+    b1["frac"] = b1["algorithmic_GBs"] / HBM_PEAK_GBS
+    line["build_roofline"] = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "bytes_per_particle": BUILD_BYTES_PER_PARTICLE, "points": [b1]}
+    if args.build_n_large > 0:
+        log(f"build-only timing at n={args.build_n_large} ...")
+        line["build_roofline"]["points"].append(build_roofline(clm, W, args.build_n_large, args.lcell))
     if "fp64" in res:
         r64 = res["fp64"]
         line["fp64"] = {

@@ -117,6 +117,10 @@ typedef struct clm_celllist_info {
   int64_t max_occupancy;   /* most particles in one cell (x or y) */
   int64_t candidate_pairs; /* pairs the sweep tests (half shell; full shell for
                               LJ_EF/LJ_ADJOINT and cross sets counts both) */
+  int64_t guard_retests;   /* last map, FP32_GUARD: candidates within the band of rc^2
+                              decided in FP64 */
+  int64_t near_evaluations;/* last map, FP32_GUARD: other FP64 re-evaluations (LJ pairs
+                              closer than near_factor*sigma, histogram values near an edge) */
 } clm_celllist_info;
 
 typedef struct clm_map_params {

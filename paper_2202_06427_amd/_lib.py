@@ -43,6 +43,7 @@ class CellListInfo(ctypes.Structure):
         ("n_x", ctypes.c_int64), ("n_y", ctypes.c_int64), ("ncells", ctypes.c_int64),
         ("ntiles", ctypes.c_int64), ("nonempty_cells", ctypes.c_int64),
         ("max_occupancy", ctypes.c_int64), ("candidate_pairs", ctypes.c_int64),
+        ("guard_retests", ctypes.c_int64), ("near_evaluations", ctypes.c_int64),
     ]
 
 

@@ -153,6 +153,7 @@ struct clm_celllist {
   unsigned int* vmax_bits;
   unsigned long long* nl_counter;
   unsigned long long* cand;
+  unsigned long long* guard;  // [2] re-evaluation counts of the last map
   double* fin_scratch;
   unsigned long long* fin_count;
   double* brute_fb;       // small boxes: per-chunk LJ force rows
@@ -406,6 +407,7 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
   size_t o_vm = c.take(sizeof(unsigned int) * 2);
   size_t o_nlc = c.take(sizeof(unsigned long long) * 2);
   size_t o_cand = c.take(sizeof(unsigned long long) * maxt);
+  size_t o_guard = c.take(sizeof(unsigned long long) * 2);
   size_t o_fin = c.take(sizeof(double) * kPartialD * kFinalBlocks);
   size_t o_finc = c.take(sizeof(unsigned long long) * kFinalBlocks);
   size_t o_fb = B.small ? c.take(sizeof(double) * 3 * (size_t)brute_chunks(nyb) * (size_t)cl->nx) : 0;
@@ -423,6 +425,7 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
     cl->vmax_bits = (unsigned int*)(base + o_vm);
     cl->nl_counter = (unsigned long long*)(base + o_nlc);
     cl->cand = (unsigned long long*)(base + o_cand);
+    cl->guard = (unsigned long long*)(base + o_guard);
     cl->fin_scratch = (double*)(base + o_fin);
     cl->fin_count = (unsigned long long*)(base + o_finc);
     cl->brute_fb = B.small ? (double*)(base + o_fb) : nullptr;
@@ -687,6 +690,7 @@ clm_status clm_celllist_build(clm_celllist* cl, const double* x, const double* y
     CLM_HIP(launch_tiles(cl->X.off, tg, cl->row_tiles, cl->row_off, cl->scan_scratch, cl->tiles,
                          cl->ctx->stream));
   }
+  CLM_HIP(launch_fill_u64(cl->guard, 2, 0ull, cl->ctx->stream));
   s = tb.stop();
   if (s != CLM_OK) return s;
   cl->built = 1;
@@ -740,6 +744,7 @@ static JobDesc base_job(const clm_celllist* cl) {
   jd.E64 = cl->E64;
   jd.E32 = cl->E32;
   jd.nl_counter = cl->nl_counter;
+  jd.guard = cl->guard;
   jd.tile_begin = 0;
   jd.tile_end = cl->max_tiles;
   return jd;
@@ -837,6 +842,7 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     CLM_HIP(launch_relspeed_band(cl->vmax_bits, P->hist_hi, dim, cl->bandq, st));
   }
   if (k == K_NL) CLM_HIP(launch_fill_u64(cl->nl_counter, 1, 0ull, st));
+  CLM_HIP(launch_fill_u64(cl->guard, 2, 0ull, st));
 
   FinalArgs F;
   std::memset(&F, 0, sizeof F);
@@ -1036,6 +1042,13 @@ clm_status clm_celllist_info_get(clm_celllist* cl, clm_celllist_info* o) {
   delete[] hoff;
   o->nonempty_cells = ne;
   o->max_occupancy = mo;
+  {
+    unsigned long long g[2] = {0, 0};
+    CLM_HIP(hipMemcpyAsync(g, cl->guard, sizeof g, hipMemcpyDeviceToHost, st));
+    CLM_HIP(hipStreamSynchronize(st));
+    o->guard_retests = (int64_t)g[0];
+    o->near_evaluations = (int64_t)g[1];
+  }
   if (cl->box.small) {
     o->ntiles = 0;
     o->candidate_pairs = cl->cross ? cl->nx * cl->ny : cl->nx * (cl->nx - 1) / 2;

@@ -93,6 +93,7 @@ struct JobDesc {
   const double* vel64_y;
   // outputs
   double* partials;          // per tile kPartialD
+  unsigned long long* guard; // [2] FP32 form: band re-tests, other FP64 re-evaluations
   unsigned long long* pcount;// per tile pair count
   double* forces;            // n_x*dim, original order
   unsigned long long* hist;  // nbins+1

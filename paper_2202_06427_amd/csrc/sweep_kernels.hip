@@ -166,6 +166,7 @@ struct Sweep {
   double W[6];
   double B[9];
   unsigned long long cnt_wave, cnt_lane;
+  uint32_t nband, nnear;   // FP64 re-evaluations queued by this tile (uniform)
   // ---- visit
   float q[3];
   double t[3];
@@ -327,6 +328,8 @@ struct Sweep {
   __device__ __forceinline__ void enqueue(unsigned long long m, uint32_t j, int kc,
                                           unsigned long long band) {
     if (m == 0) return;
+    nband += (uint32_t)__popcll(band);
+    nnear += (uint32_t)__popcll(m & ~band);
     const uint32_t t0 = (uint32_t)uniform((int)qtail);
     if (__builtin_amdgcn_inverse_ballot_w64(m)) {
       const uint32_t slot = (t0 + (uint32_t)lane_rank(m)) & (uint32_t)(kQueueCap - 1);
@@ -643,6 +646,8 @@ struct Sweep {
     for (int k = 0; k < 9; ++k) B[k] = 0.0;
     cnt_wave = 0;
     cnt_lane = 0;
+    nband = 0;
+    nnear = 0;
     tstart = T.start;
     qhead = 0;
     qtail = 0;
@@ -736,6 +741,11 @@ struct Sweep {
     if (lane == 0) {
       ldu(&J->pcount)[local] = cnt;
       Pp[P_SUM] = e;
+      if (FP32 && (nband | nnear)) {
+        unsigned long long* g = ldu(&J->guard);
+        atomicAdd(&g[0], (unsigned long long)nband);
+        atomicAdd(&g[1], (unsigned long long)nnear);
+      }
     }
     if constexpr (kLJF) {
 #pragma unroll
