@@ -61,15 +61,16 @@ __device__ __forceinline__ double rcp64(double v) {
 
 // ---------------------------------------------------------------- histogram bins
 // Canonical bin of v against E64[0..nb] (first k with v <= E_{k+1}; v = 0 ->
-// bin 0; beyond E_nb -> nb).  Binary search, FP64.
-__device__ __forceinline__ int bin64(const double* __restrict__ E, int nb, double v) {
+// bin 0; beyond E_nb -> nb), FP64.  The edges are (k h)^2 (the last possibly
+// rc^2), so the smallest m with v <= E_m is guessed from sqrt(v) / h and
+// settled against the table itself: the result depends only on the table.
+__device__ __forceinline__ int bin64(const double* __restrict__ E, int nb, double inv_h, double v) {
   if (!(v <= E[nb])) return nb;
-  int lo = 0, hi = nb;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (v <= E[mid]) hi = mid; else lo = mid + 1;
-  }
-  return lo == 0 ? 0 : lo - 1;
+  const double g = ceil(sqrt(v) * inv_h);
+  int m = g > 0.0 ? (g < (double)nb ? (int)g : nb) : 0;
+  while (m > 0 && v <= E[m - 1]) --m;
+  while (!(v <= E[m])) ++m;  // stops at nb at the latest: v <= E_nb
+  return m == 0 ? 0 : m - 1;
 }
 
 // FP32 bin with certainty flag: the bin is certain when v is farther than
@@ -137,6 +138,7 @@ struct Sweep {
   double s2, inv_s2;
   int nbins;
   float inv_h;
+  double inv_h64;
   float bandh;       // histogram edge band (FP32)
   int want_sums, with_dist;
   const float4* P;       // j positions (FP32)
@@ -196,6 +198,7 @@ struct Sweep {
     if constexpr (kHist) {
       nbins = ldu(&J->nbins);
       inv_h = ldu(&J->inv_h);
+      inv_h64 = (double)nbins / ldu(&J->hist_hi);
       E64 = ldu(&J->E64);
     }
     if constexpr (kRel) {
@@ -304,7 +307,7 @@ struct Sweep {
       }
     }
     if constexpr (KIND == K_HIST_DIST) {
-      int k = bin64(E64, nbins, d2);
+      int k = bin64(E64, nbins, inv_h64, d2);
       atomicAdd(&L.hist[k], 1u);
     }
     if constexpr (kRel) {
@@ -314,7 +317,7 @@ struct Sweep {
       for (int a = 0; a < DIM; ++a) dv[a] = ldu(&VJ64[(size_t)jo * DIM + a]) - vi64[a];
       double qq = dv[0] * dv[0] + dv[1] * dv[1];
       if (DIM == 3) qq = qq + dv[2] * dv[2];
-      int k = bin64(E64, nbins, qq);
+      int k = bin64(E64, nbins, inv_h64, qq);
       atomicAdd(&L.hist[k], 1u);
       if (want_sums && k < nbins) atomicAdd(&L.hsum[k], sqrt(qq));
     }
@@ -393,7 +396,7 @@ struct Sweep {
         }
       }
     }
-    if constexpr (KIND == K_HIST_DIST) atomicAdd(&L.hist[bin64(E64, nbins, d2)], 1u);
+    if constexpr (KIND == K_HIST_DIST) atomicAdd(&L.hist[bin64(E64, nbins, inv_h64, d2)], 1u);
     if constexpr (kRel) {
       const uint32_t io = ldu(&J->idx_x)[iL];
       const double* v64 = ldu(&J->vel64_x);
@@ -403,7 +406,7 @@ struct Sweep {
       for (int a = 0; a < DIM; ++a) dv[a] = VJ64[(size_t)jo * DIM + a] - v64[(size_t)io * DIM + a];
       double qq = dv[0] * dv[0] + dv[1] * dv[1];
       if (DIM == 3) qq = qq + dv[2] * dv[2];
-      const int k = bin64(E64, nbins, qq);
+      const int k = bin64(E64, nbins, inv_h64, qq);
       atomicAdd(&L.hist[k], 1u);
       if (want_sums && k < nbins) atomicAdd(&L.hsum[k], sqrt(qq));
     }
@@ -940,7 +943,7 @@ __global__ void __launch_bounds__(64) brute_kernel(const JobDesc* __restrict__ j
           break;
         }
         case K_HIST_DIST: {
-          int k = bin64(J.E64, J.nbins, d2);
+          int k = bin64(J.E64, J.nbins, (double)J.nbins / J.hist_hi, d2);
           atomicAdd(&J.hist[k], 1ull);
           break;
         }
@@ -951,7 +954,7 @@ __global__ void __launch_bounds__(64) brute_kernel(const JobDesc* __restrict__ j
           for (int a = 0; a < dim; ++a) dv[a] = vv[(size_t)jo * dim + a] - vi[a];
           double qq = dv[0] * dv[0] + dv[1] * dv[1];
           if (dim == 3) qq = qq + dv[2] * dv[2];
-          int k = bin64(J.E64, J.nbins, qq);
+          int k = bin64(J.E64, J.nbins, (double)J.nbins / J.hist_hi, qq);
           atomicAdd(&J.hist[k], 1ull);
           if (J.want_sums && k < J.nbins) atomicAdd(&J.hist_sums[k], sqrt(qq));
           break;

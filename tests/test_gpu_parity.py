@@ -198,11 +198,44 @@ def test_small_box_minimum_image(clm, precision):
     p, order = _sorted_pairs(pairs)
     assert np.array_equal(p[:, 0], ref["nl_i"]) and np.array_equal(p[:, 1], ref["nl_j"])
     assert np.array_equal(d.cpu().numpy()[order], ref["nl_d"])
-    out = cl.lj_forces(1.0, 0.5)
+    out = cl.lj_forces(1.0, 0.5, virial=True)
+    assert int(out["count"].item()) == ref["count"]
     assert abs(out["energy"].item() / ref["lj_energy"] - 1) < 1e-12
     assert np.allclose(out["forces"].cpu().numpy(), -ref["lj_grad"], rtol=1e-10, atol=1e-12 * np.abs(ref["lj_grad"]).max())
+    # box gradient and virial: the brute-force path sums per j-chunk partials
+    assert np.abs(out["grad_box"].cpu().numpy() - ref["dEdH"]).max() <= 1e-11 * np.abs(ref["dEdH"]).max()
+    assert np.abs(out["virial"].cpu().numpy() - ref["virial"]).max() <= 1e-11 * np.abs(ref["virial"]).max()
     h, _ = cl.histogram(16, rc)
     assert np.array_equal(h.cpu().numpy().astype(np.uint64), ref["hist"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_small_box_many_chunks_2d_and_cross(clm, precision):
+    """Brute-force path with thousands of particles (many i blocks x j
+    chunks), in 2D and for a cross set."""
+    H2 = np.array([[9.0, 2.0], [0.0, 8.5]])
+    x2 = W.uniform_in_box(3000, H2, 52)
+    rc = 5.0
+    ref = oracle.compute(x2, H2, rc, lj=(0.7, 0.2), lj_grad=True, sum_inv_d=True)
+    box2 = clm.Box(H2, rc, 1)
+    assert box2.info()["small_box"]
+    cl = clm.CellList(T(x2), box2, precision=precision)
+    out = cl.lj_forces(0.7, 0.2)
+    assert int(out["count"].item()) == ref["count"]
+    assert abs(out["energy"].item() / ref["lj_energy"] - 1) < 1e-12
+    G = ref["lj_grad"]
+    assert np.linalg.norm(out["forces"].cpu().numpy() + G, axis=1).max() <= 1e-10 * np.linalg.norm(G, axis=1).max()
+    assert np.abs(out["grad_box"].cpu().numpy() - ref["dEdH"]).max() <= 1e-11 * np.abs(ref["dEdH"]).max()
+    s, c = cl.sum_inv_d()
+    assert int(c.item()) == ref["count"] and abs(s.item() / ref["sum_inv_d"] - 1) < 1e-12
+    H3 = W.triclinic_h((10.0, 11.0, 10.5), (85.0, 95.0, 100.0))
+    xa, ya = W.uniform_in_box(700, H3, 53), W.uniform_in_box(1900, H3, 54)
+    refc = oracle.compute(xa, H3, 6.0, ya, nl=True)
+    clc = clm.CellList(T(xa), clm.Box(H3, 6.0, 1), y=T(ya), precision=precision)
+    pairs, _ = clc.neighbor_list()
+    p, _ = _sorted_pairs(pairs)
+    assert len(p) == refc["count"]
+    assert np.array_equal(p[:, 0], refc["nl_i"]) and np.array_equal(p[:, 1], refc["nl_j"])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
