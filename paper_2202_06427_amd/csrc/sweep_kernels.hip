@@ -4,8 +4,8 @@
 // every pair within the cutoff and reduced; section 2.8: per-task output
 // copies summed at the end).
 //
-// Work decomposition: one wavefront per tile of <= 64 consecutive sorted
-// particles (one per lane) of one cell row.  For every neighbour cell the
+// Work decomposition: one wavefront (one launched block) per tile of <= 64
+// consecutive sorted particles (one per lane) of one cell row.  For every neighbour cell the
 // wave visits, the cell's particles are streamed in order; the j-th record is
 // the same for all 64 lanes, so it is read with scalar loads into SGPRs and
 // consumed as an SGPR operand by the vector ALU (no LDS broadcast, whose VGPR
@@ -164,7 +164,7 @@ struct Sweep {
   double vi64[3];
   double accE;
   double G[3];
-  double S[3];       // per visited cell: sum of f_s D (folded into G and B)
+  double S[3];       // FP64 form, per visited cell: sum of f_s D (folded into G and B)
   double W[6];
   double B[9];
   unsigned long long cnt_wave, cnt_lane;
@@ -848,7 +848,9 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
 
 // ---------------------------------------------------------------- small box
 // Brute force over all pairs with the exact minimum-image search (used when
-// the grid has fewer than 3 cells on an axis).  FP64 only.  One thread per i.
+// not even cells as wide as the cutoff fit three times along every axis),
+// FP64 only.  The nearest image of one pair: every K whose image can lie
+// within the reach.
 __device__ __forceinline__ double min_image64(const BruteArgs& A, const double* ri, const double* rj,
                                               double* D, int* Kb) {
   const int dim = A.dim;
@@ -887,10 +889,9 @@ __device__ __forceinline__ double min_image64(const BruteArgs& A, const double* 
   return best;
 }
 
-// Small boxes: every pair by brute force with the minimum image found by a
-// per-pair search.  The work is split over (64 particles i) x (a chunk of j):
-// one wave per block, its partial sums in partial row blockIdx.x + nib *
-// blockIdx.y; LJ forces go to per-chunk rows of FB (fixed-order sum later).
+// The work is split over (64 particles i) x (a chunk of j): one wave per
+// block, its partial sums in partial row blockIdx.x + gridDim.x * blockIdx.y;
+// LJ forces go to per-chunk rows of FB (summed in chunk order afterwards).
 __global__ void __launch_bounds__(64) brute_kernel(const JobDesc* __restrict__ jobs, BruteArgs A,
                                                    int jchunk, double* __restrict__ FB) {
   const JobDesc& J = jobs[0];
@@ -1023,10 +1024,10 @@ __global__ void __launch_bounds__(256) brute_forces_kernel(const JobDesc* __rest
 }
 
 // ---------------------------------------------------------------- finalize
-// Fixed-order reduction of the per-tile partials of one job into the outputs.
-// Two-level fixed-order reduction of the per-tile partials of one job:
-// block b sums a contiguous range of tiles (strided by thread, then a tree in
-// shared memory); one block then sums the block results in order.
+// Two-level fixed-order reduction of the per-tile partials of one job into
+// the outputs: block b sums a contiguous range of tiles (strided by thread,
+// then a tree in shared memory); one block then sums the block results in
+// order.
 __device__ __forceinline__ int final_slots(int kind) {
   return (kind == K_LJ_F || kind == K_LJ_FV) ? kPartialD : 1;
 }
