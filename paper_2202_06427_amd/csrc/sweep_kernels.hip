@@ -168,7 +168,7 @@ struct Sweep {
   double W[6];
   double B[9];
   unsigned long long cnt_wave, cnt_lane;
-  uint32_t nband, nnear;   // FP64 re-evaluations queued by this tile (uniform)
+  uint32_t qband, qnear;   // FP64 re-evaluations done by this lane (summed per tile)
   // ---- visit
   float q[3];
   double t[3];
@@ -331,8 +331,6 @@ struct Sweep {
   __device__ __forceinline__ void enqueue(unsigned long long m, uint32_t j, int kc,
                                           unsigned long long band) {
     if (m == 0) return;
-    nband += (uint32_t)__popcll(band);
-    nnear += (uint32_t)__popcll(m & ~band);
     const uint32_t t0 = (uint32_t)uniform((int)qtail);
     if (__builtin_amdgcn_inverse_ballot_w64(m)) {
       const uint32_t slot = (t0 + (uint32_t)lane_rank(m)) & (uint32_t)(kQueueCap - 1);
@@ -424,7 +422,13 @@ struct Sweep {
     const uint32_t tl = (uint32_t)uniform((int)qtail);
     while (tl - h >= (uint32_t)kWave || (all && tl != h)) {
       const uint32_t nb = min(tl - h, (uint32_t)kWave);
-      if ((uint32_t)lane < nb) process(Q[(h + (uint32_t)lane) & (uint32_t)(kQueueCap - 1)]);
+      if ((uint32_t)lane < nb) {
+        const uint2 e = Q[(h + (uint32_t)lane) & (uint32_t)(kQueueCap - 1)];
+        const uint32_t b = (e.y >> 16) & 1u;  // band entries carry count_it
+        qband += b;
+        qnear += 1u - b;
+        process(e);
+      }
       h = (uint32_t)uniform((int)(h + nb));
     }
     qhead = h;
@@ -649,8 +653,8 @@ struct Sweep {
     for (int k = 0; k < 9; ++k) B[k] = 0.0;
     cnt_wave = 0;
     cnt_lane = 0;
-    nband = 0;
-    nnear = 0;
+    qband = 0;
+    qnear = 0;
     tstart = T.start;
     qhead = 0;
     qtail = 0;
@@ -741,14 +745,17 @@ struct Sweep {
     // every lane may hold queued FP64 contributions of other lanes' particles:
     // reduce over all lanes (inactive lanes contribute nothing of their own)
     const double e = wave_sum_d(accE);
+    if constexpr (FP32) {
+      const unsigned long long gb = wave_sum_u64(qband), gn = wave_sum_u64(qnear);
+      if (lane == 0 && (gb | gn)) {
+        unsigned long long* g = ldu(&J->guard);
+        atomicAdd(&g[0], gb);
+        atomicAdd(&g[1], gn);
+      }
+    }
     if (lane == 0) {
       ldu(&J->pcount)[local] = cnt;
       Pp[P_SUM] = e;
-      if (FP32 && (nband | nnear)) {
-        unsigned long long* g = ldu(&J->guard);
-        atomicAdd(&g[0], (unsigned long long)nband);
-        atomicAdd(&g[1], (unsigned long long)nnear);
-      }
     }
     if constexpr (kLJF) {
 #pragma unroll
