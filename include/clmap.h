@@ -136,6 +136,9 @@ typedef struct clm_map_params {
   int want_sums;                /* HIST_RELSPEED: per-bin FP64 sum of |v_j - v_i| */
   int64_t capacity;             /* NEIGHBOR_LIST: pair slots available in pairs_dev */
   int with_distances;           /* NEIGHBOR_LIST: also write d (FP64) */
+  double cutoff;                /* every kind: membership cutoff of this map, 0 < cutoff <=
+                                   the box cutoff (0: the box cutoff).  The cell grid stays
+                                   the box's; pairs are those with min-image d <= cutoff. */
 } clm_map_params;
 
 typedef struct clm_map_out {

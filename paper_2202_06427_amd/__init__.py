@@ -55,6 +55,10 @@ def stats(reset=True, device=None):
     return {k: getattr(st, k) for k, _ in L.Stats._fields_}
 
 
+def _rc(cutoff):
+    return 0.0 if cutoff is None else float(cutoff)
+
+
 # ---------------------------------------------------------------- box
 class Box:
     """Periodic box: H with the lattice vectors as columns (paper Code 3), a
@@ -194,67 +198,73 @@ class CellList:
         c = torch.empty(1, dtype=torch.int64, device=self.device)
         return e, c
 
-    def count(self):
+    # Every map takes an optional cutoff <= the box cutoff (None: the box's);
+    # the cell grid stays the box's.
+    def count(self, cutoff=None):
         """Number of pairs within the cutoff (device tensor, int64[1])."""
         _, c = self._scalars()
         o = L.MapOut(count_dev=_ptr(c))
-        self._map("count", L.MapParams(), o)
+        self._map("count", L.MapParams(cutoff=_rc(cutoff)), o)
         return c
 
-    def sum_d(self):
+    def sum_d(self, cutoff=None):
         """Sum of d over the pairs (paper Code 1)."""
         e, c = self._scalars()
-        self._map("sum_d", L.MapParams(), L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
+        self._map("sum_d", L.MapParams(cutoff=_rc(cutoff)), L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
         return e, c
 
-    def sum_inv_d(self):
+    def sum_inv_d(self, cutoff=None):
         """Sum of 1/d over the pairs (paper Code 5)."""
         e, c = self._scalars()
-        self._map("sum_inv_d", L.MapParams(), L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
+        self._map("sum_inv_d", L.MapParams(cutoff=_rc(cutoff)),
+                  L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
         return e, c
 
-    def lj_energy(self, sigma, epsilon, near_factor=1.0):
+    def lj_energy(self, sigma, epsilon, near_factor=1.0, cutoff=None):
         """Lennard-Jones energy 4 eps ((s/d)^12 - (s/d)^6) (paper Code 6)."""
         e, c = self._scalars()
-        P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor)
+        P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, cutoff=_rc(cutoff))
         self._map("lj_e", P, L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
         return e, c
 
-    def lj_forces(self, sigma, epsilon, near_factor=1.0, virial=False):
+    def lj_forces(self, sigma, epsilon, near_factor=1.0, virial=False, cutoff=None):
         """Energy, forces (-dE/dr, paper Code 7), dE/dH and optionally the virial."""
         e, c = self._scalars()
         f = torch.empty((self.nx, self.dim), dtype=torch.float64, device=self.device)
         gb = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device)
         w = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device) if virial else None
-        P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, want_virial=int(virial))
+        P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, want_virial=int(virial),
+                        cutoff=_rc(cutoff))
         o = L.MapOut(energy_dev=_ptr(e), forces_dev=_ptr(f), grad_box_dev=_ptr(gb),
                      virial_dev=_ptr(w), count_dev=_ptr(c))
         self._map("lj_ef", P, o)
         return {"energy": e, "forces": f, "grad_box": gb, "virial": w, "count": c}
 
-    def lj_adjoint(self, sigma, epsilon, upstream, near_factor=1.0):
+    def lj_adjoint(self, sigma, epsilon, upstream, near_factor=1.0, cutoff=None):
         """g dE/dr and g dE/dH for an upstream gradient g (device float64[1])."""
         e, c = self._scalars()
         up = upstream.detach().to(device=self.device, dtype=torch.float64).reshape(1).contiguous()
         gx = torch.empty((self.nx, self.dim), dtype=torch.float64, device=self.device)
         gb = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device)
-        P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, upstream_dev=_ptr(up))
+        P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, upstream_dev=_ptr(up),
+                        cutoff=_rc(cutoff))
         o = L.MapOut(energy_dev=_ptr(e), forces_dev=_ptr(gx), grad_box_dev=_ptr(gb), count_dev=_ptr(c))
         self._map("lj_adjoint", P, o)
         self._keep_up = up
         return gx, gb, e
 
-    def histogram(self, nbins, hi=None):
+    def histogram(self, nbins, hi=None, cutoff=None):
         """Histogram of d on (0, hi] (right-closed bins, paper Code 10); the
         last slot counts pairs beyond hi."""
-        hi = self.box.cutoff if hi is None else float(hi)
+        rc = self.box.cutoff if cutoff is None else float(cutoff)
+        hi = rc if hi is None else float(hi)
         h = torch.empty(nbins + 1, dtype=torch.int64, device=self.device)
         _, c = self._scalars()
-        P = L.MapParams(nbins=nbins, hist_hi=hi)
+        P = L.MapParams(nbins=nbins, hist_hi=hi, cutoff=_rc(cutoff))
         self._map("hist_dist", P, L.MapOut(hist_dev=_ptr(h), count_dev=_ptr(c)))
         return h, c
 
-    def relspeed_histogram(self, v, nbins, hi, vy=None, sums=True):
+    def relspeed_histogram(self, v, nbins, hi, vy=None, sums=True, cutoff=None):
         """Histogram of |v_j - v_i| over the pairs and per-bin sums (paper Code 10)."""
         vx = _as_coords(v, self.dim, "v")
         vyy = _as_coords(vy, self.dim, "vy") if self.cross else None
@@ -262,12 +272,12 @@ class CellList:
         s = torch.empty(nbins, dtype=torch.float64, device=self.device) if sums else None
         _, c = self._scalars()
         P = L.MapParams(nbins=nbins, hist_hi=float(hi), vel_x_dev=_ptr(vx), vel_y_dev=_ptr(vyy),
-                        want_sums=int(sums))
+                        want_sums=int(sums), cutoff=_rc(cutoff))
         self._map("hist_relspeed", P, L.MapOut(hist_dev=_ptr(h), hist_sums_dev=_ptr(s), count_dev=_ptr(c)))
         self._keep_v = (vx, vyy)
         return h, s, c
 
-    def neighbor_list(self, capacity=None, distances=True):
+    def neighbor_list(self, capacity=None, distances=True, cutoff=None):
         """Pairs (i, j) within the cutoff (single set: i < j) and their d.
 
         Synchronizes to read the pair count; grows the buffers and re-runs
@@ -277,7 +287,7 @@ class CellList:
             pairs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.device)
             dist = torch.empty(max(cap, 1), dtype=torch.float64, device=self.device) if distances else None
             _, c = self._scalars()
-            P = L.MapParams(capacity=cap, with_distances=int(distances))
+            P = L.MapParams(capacity=cap, with_distances=int(distances), cutoff=_rc(cutoff))
             self._map("neighbor_list", P, L.MapOut(pairs_dev=_ptr(pairs), dist_dev=_ptr(dist), count_dev=_ptr(c)))
             n = int(c.item())
             if n <= cap:

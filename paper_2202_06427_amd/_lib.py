@@ -53,6 +53,7 @@ class MapParams(ctypes.Structure):
         ("want_virial", ctypes.c_int), ("upstream_dev", _vp), ("nbins", ctypes.c_int),
         ("hist_hi", ctypes.c_double), ("vel_x_dev", _vp), ("vel_y_dev", _vp),
         ("want_sums", ctypes.c_int), ("capacity", ctypes.c_int64), ("with_distances", ctypes.c_int),
+        ("cutoff", ctypes.c_double),
     ]
 
 

@@ -207,6 +207,40 @@ static float round_up_f(double v) {
 
 static constexpr int64_t kMaxCells = int64_t(1) << 24;
 
+// FP32 error band for membership at cutoff rc (<= the box cutoff: the grid's
+// cells are fixed by the box).  The FP32 displacement is D32 = fl32(o_j - q_i)
+// with o_j = fl32(offset of j from its cell origin, |o_j,a| <= C_a, the
+// Cartesian extent of one cell along a) and q_i = fl32(r'_i - O_u) (one
+// rounding of an FP64 value with |q_a| <= C_a + |D_a|).  Three roundings of
+// relative size u = 2^-24 give, per component,
+//   |D32_a - D_a| <= u (2 C_a + 2 |D_a|) + e64,
+// e64 covering the FP64 roundings of r', of the cell origins and of the
+// canonical d2 itself.  Near any threshold X <= rc^2 a candidate has
+// |D| <= 1.01 rc (a farther one has d2_32 > rc^2 whatever the rounding), so
+// |d2_32 - d2| <= 2 (1.01 rc) |E| + |E|^2 + 4 u (1.02 rc^2) for the FMA chain
+// of three roundings.  The band is twice that bound.
+static void map_band(const clm_box& B, double rc, double* band, float* lo32, float* hi32) {
+  const int dim = B.dim;
+  const double rc2 = rc * rc;
+  const double u = std::ldexp(1.0, -24);
+  double E2 = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    double C = 0.0, Hs = 0.0;
+    for (int b = 0; b < dim; ++b) {
+      C += std::fabs(B.H[a * 3 + b]) / (double)B.n[b];
+      Hs += std::fabs(B.H[a * 3 + b]);
+    }
+    double e64 = 64.0 * std::ldexp(1.0, -53) * (4.0 * Hs + 4.0 * rc);
+    double Ea = u * (2.0 * C + 2.02 * rc) * (1.0 + 1e-6) + e64;
+    E2 += Ea * Ea;
+  }
+  const double E = std::sqrt(E2);
+  const double b0 = 2.02 * rc * E + E2 + 4.08 * u * rc2 + 1e-12 * rc2;
+  *band = 2.0 * b0;
+  *lo32 = round_down_f(rc2 - *band);
+  *hi32 = round_up_f(rc2 + *band);
+}
+
 static clm_status box_setup(int dim, const double* Hin, double cutoff, int lcell, int lcell_x,
                             clm_box* B) {
   if (dim != 2 && dim != 3) return fail(CLM_E_BAD_BOX, "dim must be 2 or 3 (got %d)", dim);
@@ -317,34 +351,7 @@ static clm_status box_setup(int dim, const double* Hin, double cutoff, int lcell
         }
         t[3] = 0.0;
       }
-  // FP32 error band.  The FP32 displacement is D32 = fl32(o_j - q_i) with
-  // o_j = fl32(offset of j from its cell origin, |o_j,a| <= C_a, the
-  // Cartesian extent of one cell along a) and q_i = fl32(r'_i - O_u) (one
-  // rounding of an FP64 value with |q_a| <= C_a + |D_a|).  Three roundings
-  // of relative size u = 2^-24 give, per component,
-  //   |D32_a - D_a| <= u (2 C_a + 2 |D_a|) + e64,
-  // e64 covering the FP64 roundings of r', of the cell origins and of the
-  // canonical d2 itself.  Near any threshold X <= rc^2 a candidate has
-  // |D| <= 1.01 rc (a farther one has d2_32 > rc^2 whatever the rounding),
-  // so |d2_32 - d2| <= 2 (1.01 rc) |E| + |E|^2 + 4 u (1.02 rc^2) for the
-  // FMA chain of three roundings.  The band is twice that bound.
-  const double u = std::ldexp(1.0, -24);
-  double E2 = 0.0;
-  for (int a = 0; a < dim; ++a) {
-    double C = 0.0, Hs = 0.0;
-    for (int b = 0; b < dim; ++b) {
-      C += std::fabs(B->H[a * 3 + b]) / (double)B->n[b];
-      Hs += std::fabs(B->H[a * 3 + b]);
-    }
-    double e64 = 64.0 * std::ldexp(1.0, -53) * (4.0 * Hs + 4.0 * cutoff);
-    double Ea = u * (2.0 * C + 2.02 * cutoff) * (1.0 + 1e-6) + e64;
-    E2 += Ea * Ea;
-  }
-  const double E = std::sqrt(E2);
-  const double b0 = 2.02 * cutoff * E + E2 + 4.08 * u * B->rc2 + 1e-12 * B->rc2;
-  B->band = 2.0 * b0;
-  B->lo32 = round_down_f(B->rc2 - B->band);
-  B->hi32 = round_up_f(B->rc2 + B->band);
+  map_band(*B, cutoff, &B->band, &B->lo32, &B->hi32);
   return CLM_OK;
 }
 
@@ -793,10 +800,22 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     if (P->capacity > 0 && P->with_distances && !O->dist_dev)
       return fail(CLM_E_INVALID_ARG, "with_distances needs dist_dev");
   }
+  // membership cutoff of this map (the grid stays the box's)
+  double rcm = B.rc;
+  if (P->cutoff != 0.0) {
+    if (!(P->cutoff > 0.0) || !std::isfinite(P->cutoff) || P->cutoff > B.rc)
+      return fail(CLM_E_BAD_CUTOFF, "params->cutoff must be in (0, box cutoff %g] (got %g)", B.rc,
+                  P->cutoff);
+    rcm = P->cutoff;
+  }
   hipStream_t st = cl->ctx->stream;
   CLM_HIP(hipSetDevice(cl->ctx->device));
 
   JobDesc jd = base_job(cl);
+  if (rcm != B.rc) {
+    jd.rc2 = rcm * rcm;
+    map_band(B, rcm, &jd.band, &jd.lo32, &jd.hi32);
+  }
   const int k_launch = (ljf && P->want_virial) ? K_LJ_FV : k;
   jd.kind = k_launch;
   jd.full_shell = ljf ? 1 : 0;
@@ -829,8 +848,8 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     jd.capacity = P->capacity;
   }
   if (hist) {
-    const int force_last = (k == K_HIST_DIST && P->hist_hi == B.rc) ? 1 : 0;
-    CLM_HIP(launch_hist_edges(cl->E64, cl->E32, P->nbins, P->hist_hi, force_last, B.rc2, st));
+    const int force_last = (k == K_HIST_DIST && P->hist_hi == rcm) ? 1 : 0;
+    CLM_HIP(launch_hist_edges(cl->E64, cl->E32, P->nbins, P->hist_hi, force_last, jd.rc2, st));
     CLM_HIP(launch_fill_u64((unsigned long long*)O->hist_dev, (size_t)P->nbins + 1, 0ull, st));
     if (jd.want_sums) CLM_HIP(launch_fill_f64(O->hist_sums_dev, (size_t)P->nbins, 0.0, st));
   }
@@ -889,9 +908,9 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
       A.Hinv[q] = B.Hinv[q];
     }
     for (int d = 0; d < 3; ++d) A.w[d] = B.w[d];
-    A.rc = B.rc;
-    A.rc2 = B.rc2;
-    A.reach = std::min(B.rc, 0.5 * B.sum_len) * (1.0 + 1e-6);
+    A.rc = P->cutoff != 0.0 ? P->cutoff : B.rc;
+    A.rc2 = A.rc * A.rc;
+    A.reach = std::min(A.rc, 0.5 * B.sum_len) * (1.0 + 1e-6);
     const double pairs = (double)A.n_x * (double)(cl->cross ? A.n_y : A.n_x);
     if (pairs > 4.0e9)
       return fail(CLM_E_UNSUPPORTED,

@@ -316,3 +316,52 @@ def test_autograd_lj_energy(clm):
         gx = xt.grad.cpu().numpy()
         assert np.abs(gx - 2.5 * ref["lj_grad"]).max() <= tol * np.abs(ref["lj_grad"]).max() * 2.5
         assert np.abs(Ht.grad.numpy() - 2.5 * ref["dEdH"]).max() <= tol * np.abs(ref["dEdH"]).max() * 2.5
+
+
+@pytest.mark.parametrize("name", ["cube3", "tric3", "tric2", "small3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_map_cutoff_below_the_box_cutoff(clm, name, precision):
+    """A map with its own cutoff rm < rc over the cell list built for rc
+    gives the pair set and sums of the definition at rm."""
+    if name == "small3":
+        H, n, rc = W.triclinic_h((10.0, 11.0, 10.5), (85.0, 95.0, 100.0)), 500, 7.0
+    else:
+        H, n, rc = CASES[name]
+    dim = H.shape[0]
+    x = W.uniform_in_box(n, H, 4000 + n)
+    v = W.rng(6).normal(size=(n, dim))
+    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision=precision)
+    assert cl.box.info()["small_box"] == (name == "small3")
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    for rm in (0.61 * rc, rc):
+        ref = oracle.compute(x, H, rm, nl=True, sum_d=True, hist=(24, rm), rel_hist=(16, 5.0),
+                             vel_x=v)
+        pairs, dist = cl.neighbor_list(cutoff=rm)
+        p, order = _sorted_pairs(pairs)
+        assert np.array_equal(p[:, 0], ref["nl_i"]) and np.array_equal(p[:, 1], ref["nl_j"])
+        assert int(cl.count(cutoff=rm).item()) == ref["count"]
+        sd, c = cl.sum_d(cutoff=rm)
+        assert int(c.item()) == ref["count"] and abs(sd.item() / ref["sum_d"] - 1) < tol
+        h, _ = cl.histogram(24, cutoff=rm)
+        assert np.array_equal(h.cpu().numpy().astype(np.uint64), ref["hist"])
+        hr, _, c = cl.relspeed_histogram(T(v), 16, 5.0, cutoff=rm)
+        assert np.array_equal(hr.cpu().numpy().astype(np.uint64), ref["rel_hist"])
+        assert int(c.item()) == ref["count"]
+    # forces on a jittered lattice (no coincident pairs)
+    m = int(round(n ** (1.0 / dim)))
+    grid = np.stack(np.meshgrid(*([np.arange(m)] * dim), indexing="ij"), -1).reshape(-1, dim)
+    s = (grid + 0.5 + 0.3 * (W.rng(8).random(grid.shape) - 0.5)) / m
+    xl = s @ H.T
+    rm = 0.7 * rc
+    ref = oracle.compute(xl, H, rm, lj=(1.1, 0.3), lj_grad=True, nl=True)
+    cll = clm.CellList(T(xl), clm.Box(H, rc, 2), precision=precision)
+    out = cll.lj_forces(1.1, 0.3, virial=True, cutoff=rm)
+    assert int(out["count"].item()) == ref["count"]
+    assert abs(out["energy"].item() - ref["lj_energy"]) <= tol * abs(ref["lj_energy"])
+    scale = _pair_force_abs_sums(xl, H, rm, ref, 1.1, 0.3)
+    err = np.linalg.norm(out["forces"].cpu().numpy() + ref["lj_grad"], axis=1) / np.maximum(scale, 1e-300)
+    assert err.max() <= (1e-11 if precision == "fp64" else 1e-5)
+    tolB = 1e-11 if precision == "fp64" else 1e-5
+    assert np.abs(out["grad_box"].cpu().numpy() - ref["dEdH"]).max() <= tolB * np.abs(ref["dEdH"]).max()
+    with pytest.raises(clm.ClmError):
+        cl.count(cutoff=1.01 * rc)
