@@ -34,6 +34,7 @@ class _Request(ctypes.Structure):
         ("hist_nbins", ctypes.c_int), ("hist_hi", ctypes.c_double),
         ("rel_nbins", ctypes.c_int), ("rel_hi", ctypes.c_double),
         ("vel_x", _dp), ("vel_y", _dp), ("nl_capacity", ctypes.c_int64),
+        ("frame_x", _i64p),
     ]
 
 
@@ -138,12 +139,14 @@ def pair_d2(xi, xj, H, reach):
 
 def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, lj=None,
             lj_grad=False, hist=None, rel_hist=None, vel_x=None, vel_y=None, nl=False,
-            nl_capacity=None, method=METHOD_AUTO, nthreads=0):
+            nl_capacity=None, method=METHOD_AUTO, nthreads=0, frame=None):
     """Run the oracle; returns a dict of the requested outputs.
 
     lj = (sigma, epsilon); hist = (nbins, hi); rel_hist = (nbins, hi) with
     vel_x (and vel_y for a cross set).  Neighbour-list indices are 0-based,
-    sorted by (i, j); single set has i < j.
+    sorted by (i, j); single set has i < j.  frame: (nx, dim) integers that
+    replace the canonical wrap integers (positions kept in the wrap of an
+    earlier step; single set only).
     """
     x = _f64(x)
     H = _f64(H)
@@ -180,6 +183,12 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
     req.want = want
     req.method = method
     req.nthreads = nthreads
+    fr = None
+    if frame is not None:
+        fr = np.ascontiguousarray(frame, dtype=np.int64)
+        if fr.shape != (nx, dim):
+            raise ValueError("frame must be (nx, dim) integers")
+        req.frame_x = _p(fr, _i64p)
     res = _Result()
     keep = []
     grad = None
@@ -201,14 +210,15 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
         cap = int(nl_capacity) if nl_capacity is not None else None
         if cap is None:
             # first pass for the count, then the list
-            r0 = compute(x, H, cutoff, yy, count=True, method=method, nthreads=nthreads)
+            r0 = compute(x, H, cutoff, yy, count=True, method=method, nthreads=nthreads,
+                         frame=frame)
             cap = int(r0["count"])
         req.nl_capacity = cap
         nli = np.zeros(max(cap, 1), dtype=np.int64)
         nlj = np.zeros(max(cap, 1), dtype=np.int64)
         nld = np.zeros(max(cap, 1))
         res.nl_i, res.nl_j, res.nl_d = _p(nli, _i64p), _p(nlj, _i64p), _p(nld)
-    keep.append((vx, vy))
+    keep.append((vx, vy, fr))
     rc = lib().clmo_compute(dim, _p(H), float(cutoff), _p(x), nx, _p(yy), ny,
                             ctypes.byref(req), ctypes.byref(res))
     _check(rc, "compute")
@@ -274,3 +284,62 @@ def paper_ghost_grid(H, cutoff, lcell=1):
     _check(lib().clmo_paper_ghost_grid(dim, _p(H), float(cutoff), int(lcell), _p(n, _ip), _p(s)),
            "paper_ghost_grid")
     return n.astype(int), s
+
+
+# ---------------------------------------------------------------- molecular dynamics
+def md_run(x, v, H, cutoff, sigma, epsilon, mass, dt, nsteps, *, skin=0.0, rescale_every=0,
+           target_ke=None, nthreads=0):
+    """Velocity-Verlet trajectory with Lennard-Jones forces (paper section 4.2:
+    a Neon fluid with LJ interactions only, fixed time step, velocity
+    rescaling every few steps).  Plain FP64, test infrastructure.
+
+    Step k = 1..nsteps, with h = (dt / 2) / mass:
+      v = v + h F;  x = x + dt v;  F = -dE/dx (pairs within `cutoff`);
+      v = v + h F;  KE = mass / 2 * sum_i |v_i|^2;
+      if rescale_every and k % rescale_every == 0: v = sqrt(target_ke / KE) v.
+    Positions are never wrapped (the pair map wraps them).  With skin > 0
+    the pair distances are taken in the frame of the last rebuild: a rebuild
+    (frame = the canonical wrap integers of x) happens at k = 0 and whenever
+    some particle has moved by more than skin / 2 since the last one
+    (|x - x_ref|^2 > (skin / 2)^2).  Returns a dict with x, v, F and
+    per-step arrays energy (potential), ke, count and rebuilt."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    H = _f64(H)
+    n, dim = x.shape
+    h = (0.5 * dt) / mass
+    lim2 = (0.5 * skin) * (0.5 * skin)
+
+    def forces(frame):
+        r = compute(x, H, cutoff, lj=(sigma, epsilon), lj_grad=True, nthreads=nthreads,
+                    frame=frame)
+        return -r["lj_grad"], r["lj_energy"], r["count"]
+
+    frame = wrap(x, H)[2] if skin > 0 else None
+    xref = x.copy()
+    F, E, c = forces(frame)
+    rec = {"energy": [E], "ke": [0.5 * mass * float(np.sum(np.sum(v * v, axis=1)))],
+           "count": [c], "rebuilt": [True]}
+    for k in range(1, nsteps + 1):
+        v = v + h * F
+        x = x + dt * v
+        rebuilt = False
+        if skin > 0:
+            d = x - xref
+            if float(np.max(np.sum(d * d, axis=1))) > lim2:
+                frame = wrap(x, H)[2]
+                xref = x.copy()
+                rebuilt = True
+        F, E, c = forces(frame)
+        v = v + h * F
+        ke = 0.5 * mass * float(np.sum(np.sum(v * v, axis=1)))
+        rec["energy"].append(E)
+        rec["ke"].append(ke)
+        rec["count"].append(c)
+        rec["rebuilt"].append(rebuilt)
+        if rescale_every and k % rescale_every == 0:
+            v = np.sqrt(target_ke / ke) * v
+    out = {"x": x, "v": v, "F": F}
+    for key, val in rec.items():
+        out[key] = np.array(val)
+    return out

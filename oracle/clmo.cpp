@@ -150,6 +150,23 @@ void wrap_one(const Box& B, const double* r, double* rw, double* f, int64_t* w) 
   }
 }
 
+/* Frame position of one particle for given integers w'': f = s - w''. */
+void frame_one(const Box& B, const double* r, const int64_t* wf, double* rw, double* f) {
+  const int dim = B.dim;
+  double s[3];
+  for (int a = 0; a < dim; ++a) {
+    double acc = B.hi(a, 0) * r[0];
+    for (int b = 1; b < dim; ++b) acc = acc + B.hi(a, b) * r[b];
+    s[a] = acc;
+  }
+  for (int a = 0; a < dim; ++a) f[a] = s[a] - (double)wf[a];
+  for (int a = 0; a < dim; ++a) {
+    double acc = B.h(a, 0) * f[0];
+    for (int b = 1; b < dim; ++b) acc = acc + B.h(a, b) * f[b];
+    rw[a] = acc;
+  }
+}
+
 /* t = H K (canonical order). */
 void shift(const Box& B, const int* K, double* t) {
   for (int a = 0; a < B.dim; ++a) {
@@ -248,7 +265,9 @@ struct Ctx {
   bool cross;
   int64_t nx, ny;
   std::vector<double> xw, fx, yw, fy;   /* wrapped positions and fractions */
-  std::vector<int64_t> wx, wy;          /* wrap integers */
+  std::vector<int64_t> wx, wy;          /* wrap integers (the frame's, when one is given) */
+  std::vector<double> cfx;              /* canonical fractions (cell membership) */
+  std::vector<int64_t> dwx;             /* canonical minus frame integers */
   const double* vx = nullptr;
   const double* vy = nullptr;
   std::vector<double> Ehist, Erel;
@@ -397,6 +416,7 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
   if (cross && ny < 0) return CLMO_EINVAL;
   const int want = req->want;
   if ((want & CLMO_W_LJ) && res->lj_grad && cross) return CLMO_EINVAL;
+  if (req->frame_x && cross) return CLMO_EINVAL;
   if ((want & CLMO_W_HIST_DIST) && (req->hist_nbins < 1 || !(req->hist_hi > 0) || !res->hist))
     return CLMO_EINVAL;
   if ((want & CLMO_W_HIST_REL) &&
@@ -417,6 +437,18 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
   C.fx.resize(nx * dim);
   C.wx.resize(nx * dim);
   for (int64_t i = 0; i < nx; ++i) wrap_one(B, &x[i * dim], &C.xw[i * dim], &C.fx[i * dim], &C.wx[i * dim]);
+  const bool framed = req->frame_x != nullptr;
+  if (framed) {
+    /* cells come from the canonical fractions; distances from the frame */
+    C.cfx = C.fx;
+    C.dwx.resize(nx * dim);
+    for (int64_t i = 0; i < nx; ++i)
+      frame_one(B, &x[i * dim], &req->frame_x[i * dim], &C.xw[i * dim], &C.fx[i * dim]);
+    for (int64_t k = 0; k < nx * dim; ++k) {
+      C.dwx[k] = C.wx[k] - req->frame_x[k];
+      C.wx[k] = req->frame_x[k];
+    }
+  }
   if (cross) {
     C.yw.resize(ny * dim);
     C.fy.resize(ny * dim);
@@ -483,7 +515,8 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
     const int ncell = dim == 3 ? n[0] * n[1] * n[2] : n[0] * n[1];
     /* plain per-cell particle lists */
     std::vector<std::vector<int64_t>> xcells(ncell), ycells;
-    for (int64_t i = 0; i < nx; ++i) xcells[cell_of(&C.fx[i * dim], n, dim)].push_back(i);
+    const std::vector<double>& cf = framed ? C.cfx : C.fx;
+    for (int64_t i = 0; i < nx; ++i) xcells[cell_of(&cf[i * dim], n, dim)].push_back(i);
     if (cross) {
       ycells.assign(ncell, std::vector<int64_t>());
       for (int64_t j = 0; j < ny; ++j) ycells[cell_of(&C.fy[j * dim], n, dim)].push_back(j);
@@ -514,10 +547,18 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
               shift(B, K, t);
               for (int64_t j : jcells[cn]) {
                 if (!cross && j == i) continue;
-                double d2 = pair_d2(B, &C.xw[i * dim], &yw[j * dim], t, D);
+                int Kp[3] = {K[0], K[1], K[2]};
+                double tp[3] = {t[0], t[1], t[2]};
+                if (framed) {
+                  /* the same real displacement in the frame: K - dw_j + dw_i */
+                  for (int a = 0; a < dim; ++a)
+                    Kp[a] = (int)((int64_t)K[a] - C.dwx[j * dim + a] + C.dwx[i * dim + a]);
+                  shift(B, Kp, tp);
+                }
+                double d2 = pair_d2(B, &C.xw[i * dim], &yw[j * dim], tp, D);
                 if (!(d2 <= B.rc2)) continue;
                 if (grad) lj_grad_add(*req, dim, d2, D, g);
-                if (cross || i < j) accumulate(C, partial[c], relsum_part[c], tid, i, j, d2, D, K);
+                if (cross || i < j) accumulate(C, partial[c], relsum_part[c], tid, i, j, d2, D, Kp);
               }
             }
         if (grad)

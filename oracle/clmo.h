@@ -37,6 +37,12 @@
  *  Minimum image: d2(i,j) = min over all K of d2(i,j,K).
  *  Membership: d2 <= rc2 with rc2 = rc*rc; self pairs excluded; single set:
  *  unordered pairs i<j once; cross set: every (i in x, j in y).
+ *  Frame (positions kept in the wrap of an earlier step, as between
+ *  rebuilds of a list reused over molecular-dynamics steps): given integer
+ *  vectors w''_i, the frame position is r''_a = (H_a0*f0 + H_a1*f1) + H_a2*f2
+ *  with f_a = s_a - w''_a (no floor).  Displacements, the minimum image and
+ *  membership are then the definitions above with r'' in place of r'.  With
+ *  w'' equal to the canonical w this is the canonical computation exactly.
  *  Histogram edges: h = hi/nb, e_k = k*h, E_k = e_k*e_k (k = 0..nb); for a
  *  distance histogram with hi == rc, E_nb = rc2.  A value v goes to the
  *  first bin k (0-based) with v <= E_{k+1} (v = 0 goes to bin 0); values
@@ -77,6 +83,7 @@ typedef struct clmo_request {
   const double* vel_x;            /* nx*dim velocities (relative speed) */
   const double* vel_y;            /* ny*dim velocities of the cross set */
   int64_t nl_capacity;            /* entries available in nl_i/nl_j/nl_d */
+  const int64_t* frame_x;         /* nx*dim frame integers w'' (single set), or NULL */
 } clmo_request;
 
 typedef struct clmo_result {

@@ -60,6 +60,13 @@ __device__ __forceinline__ void wrap_one(const BuildGeom& g, const double* __res
   }
 }
 
+// Every build kernel takes a gate: a device flag that, when it reads 0, makes
+// the kernel return at once (a rebuild decided on the device, with no host
+// round trip).  NULL means always run.
+__device__ __forceinline__ bool gate_closed(const uint32_t* gate) {
+  return gate != nullptr && *gate == 0u;
+}
+
 __device__ __forceinline__ void cell_of(const BuildGeom& g, const double* f, int* c) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -75,9 +82,10 @@ __device__ __forceinline__ void cell_of(const BuildGeom& g, const double* f, int
 __global__ void __launch_bounds__(256) bin_kernel(const double* __restrict__ x, int n, BuildGeom g,
                                                   uint32_t* __restrict__ count,
                                                   uint32_t* __restrict__ cell,
-                                                  uint32_t* __restrict__ rank) {
+                                                  uint32_t* __restrict__ rank,
+                                                  const uint32_t* __restrict__ gate) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || gate_closed(gate)) return;
   double r[3] = {0.0, 0.0, 0.0};
   for (int a = 0; a < g.dim; ++a) r[a] = x[(size_t)i * g.dim + a];
   double f[3], rw[3];
@@ -92,9 +100,10 @@ __global__ void __launch_bounds__(256) bin_kernel(const double* __restrict__ x, 
 __global__ void __launch_bounds__(256) scatter_kernel(
     const double* __restrict__ x, int n, BuildGeom g, const uint32_t* __restrict__ off,
     const uint32_t* __restrict__ cell, const uint32_t* __restrict__ rank, float4* __restrict__ pos,
-    double4* __restrict__ r64, uint32_t* __restrict__ idx, int4* __restrict__ wrap) {
+    double4* __restrict__ r64, uint32_t* __restrict__ idx, int4* __restrict__ wrap,
+    const uint32_t* __restrict__ gate) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || gate_closed(gate)) return;
   double r[3] = {0.0, 0.0, 0.0};
   for (int a = 0; a < g.dim; ++a) r[a] = x[(size_t)i * g.dim + a];
   double f[3], rw[3];
@@ -157,7 +166,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
 }
 
 __global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(const uint32_t* __restrict__ in,
-                                                                 int n, uint32_t* __restrict__ sums) {
+                                                                 int n, uint32_t* __restrict__ sums,
+                                                                 const uint32_t* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   const size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * kScanPer;
   uint32_t s = 0;
 #pragma unroll
@@ -175,7 +186,9 @@ __global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(const uint32_t*
 }
 
 // One block: exclusive scan of nb block sums in place (chunks of 1024).
-__global__ void __launch_bounds__(kScanThreads) scan_top_kernel(uint32_t* __restrict__ sums, int nb) {
+__global__ void __launch_bounds__(kScanThreads) scan_top_kernel(uint32_t* __restrict__ sums, int nb,
+                                                                const uint32_t* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   uint32_t carry = 0;
   for (int base = 0; base < nb; base += kScanThreads) {
     int i = base + threadIdx.x;
@@ -191,7 +204,9 @@ __global__ void __launch_bounds__(kScanThreads) scan_top_kernel(uint32_t* __rest
 __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const uint32_t* __restrict__ in,
                                                                   int n,
                                                                   const uint32_t* __restrict__ sums,
-                                                                  uint32_t* __restrict__ out) {
+                                                                  uint32_t* __restrict__ out,
+                                                                  const uint32_t* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   const size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * kScanPer;
   uint32_t v[kScanPer];
   uint32_t s = 0;
@@ -257,32 +272,37 @@ __device__ uint32_t walk_row(const uint32_t* __restrict__ off, const TileGeom& g
 }
 
 __global__ void __launch_bounds__(256) tiles_count_kernel(const uint32_t* __restrict__ off, TileGeom g,
-                                                          uint32_t* __restrict__ row_tiles) {
+                                                          uint32_t* __restrict__ row_tiles,
+                                                          const uint32_t* __restrict__ gate) {
   int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= g.nrows) return;
+  if (row >= g.nrows || gate_closed(gate)) return;
   row_tiles[row] = walk_row<false>(off, g, row, nullptr, 0);
 }
 
 __global__ void __launch_bounds__(256) tiles_emit_kernel(const uint32_t* __restrict__ off, TileGeom g,
                                                          const uint32_t* __restrict__ row_off,
-                                                         Tile* __restrict__ tiles) {
+                                                         Tile* __restrict__ tiles,
+                                                         const uint32_t* __restrict__ gate) {
   int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= g.nrows) return;
+  if (row >= g.nrows || gate_closed(gate)) return;
   walk_row<true>(off, g, row, tiles, row_off[row]);
 }
 
 // ---------------------------------------------------------------- small helpers
-__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
+__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v, const uint32_t* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long long v) {
+__global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long long v, const uint32_t* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ void fill_f64_kernel(double* p, size_t n, double v) {
+__global__ void fill_f64_kernel(double* p, size_t n, double v, const uint32_t* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -322,57 +342,59 @@ static inline unsigned grid_for(size_t n, int block) {
   return (unsigned)g;
 }
 
-hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s, const uint32_t* gate) {
   if (n == 0) return hipSuccess;
-  fill_u32_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
+  fill_u32_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, v, gate);
   return hipGetLastError();
 }
 
-hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s) {
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s, const uint32_t* gate) {
   if (n == 0) return hipSuccess;
-  fill_u64_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
+  fill_u64_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, v, gate);
   return hipGetLastError();
 }
 
-hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s) {
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s, const uint32_t* gate) {
   if (n == 0) return hipSuccess;
-  fill_f64_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, v);
+  fill_f64_kernel<<<grid_for(n, 256), 256, 0, s>>>(p, n, v, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_bin(const double* x, int n, const BuildGeom& g, uint32_t* count, uint32_t* cell,
-                      uint32_t* rank, hipStream_t s) {
+                      uint32_t* rank, hipStream_t s, const uint32_t* gate) {
   if (n == 0) return hipSuccess;
-  bin_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, n, g, count, cell, rank);
+  bin_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, n, g, count, cell, rank, gate);
   return hipGetLastError();
 }
 
 size_t scan_scratch_elems(int n) { return (size_t)(n + kScanChunk - 1) / kScanChunk + 1; }
 
-hipError_t launch_scan(const uint32_t* in, int n, uint32_t* sums, uint32_t* out, hipStream_t s) {
+hipError_t launch_scan(const uint32_t* in, int n, uint32_t* sums, uint32_t* out, hipStream_t s,
+                       const uint32_t* gate) {
   int nb = (n + kScanChunk - 1) / kScanChunk;
   if (nb < 1) nb = 1;
-  scan_sums_kernel<<<nb, kScanThreads, 0, s>>>(in, n, sums);
-  scan_top_kernel<<<1, kScanThreads, 0, s>>>(sums, nb);
-  scan_apply_kernel<<<nb, kScanThreads, 0, s>>>(in, n, sums, out);
+  scan_sums_kernel<<<nb, kScanThreads, 0, s>>>(in, n, sums, gate);
+  scan_top_kernel<<<1, kScanThreads, 0, s>>>(sums, nb, gate);
+  scan_apply_kernel<<<nb, kScanThreads, 0, s>>>(in, n, sums, out, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_scatter(const double* x, int n, const BuildGeom& g, const uint32_t* off,
                           const uint32_t* cell, const uint32_t* rank, float4* pos, double4* r64,
-                          uint32_t* idx, int4* wrap, hipStream_t s) {
+                          uint32_t* idx, int4* wrap, hipStream_t s, const uint32_t* gate) {
   if (n == 0) return hipSuccess;
-  scatter_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, n, g, off, cell, rank, pos, r64, idx, wrap);
+  scatter_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, n, g, off, cell, rank, pos, r64, idx, wrap, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_tiles(const uint32_t* off, const TileGeom& g, uint32_t* row_tiles,
-                        uint32_t* row_off, uint32_t* scan_scratch, Tile* tiles, hipStream_t s) {
+                        uint32_t* row_off, uint32_t* scan_scratch, Tile* tiles, hipStream_t s,
+                        const uint32_t* gate) {
   const int nb = (g.nrows + 255) / 256;
-  tiles_count_kernel<<<nb, 256, 0, s>>>(off, g, row_tiles);
-  hipError_t e = launch_scan(row_tiles, g.nrows, scan_scratch, row_off, s);
+  tiles_count_kernel<<<nb, 256, 0, s>>>(off, g, row_tiles, gate);
+  hipError_t e = launch_scan(row_tiles, g.nrows, scan_scratch, row_off, s, gate);
   if (e != hipSuccess) return e;
-  tiles_emit_kernel<<<nb, 256, 0, s>>>(off, g, row_off, tiles);
+  tiles_emit_kernel<<<nb, 256, 0, s>>>(off, g, row_off, tiles, gate);
   return hipGetLastError();
 }
 

@@ -173,20 +173,26 @@ struct FinalArgs {
 };
 
 // ---------------------------------------------------------------- launchers
-// Host wrappers (defined next to their kernels); all enqueue on `s`.
-hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
-hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
+// Host wrappers (defined next to their kernels); all enqueue on `s`.  The
+// build launchers take an optional device gate: their kernels return at once
+// when it reads 0 (NULL: always run).
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s,
+                           const uint32_t* gate = nullptr);
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s,
+                           const uint32_t* gate = nullptr);
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s,
+                           const uint32_t* gate = nullptr);
 hipError_t launch_bin(const double* x, int n, const BuildGeom& g, uint32_t* count, uint32_t* cell,
-                      uint32_t* rank, hipStream_t s);
+                      uint32_t* rank, hipStream_t s, const uint32_t* gate = nullptr);
 hipError_t launch_scan(const uint32_t* in, int n, uint32_t* sums_scratch, uint32_t* out,
-                       hipStream_t s);
+                       hipStream_t s, const uint32_t* gate = nullptr);
 size_t scan_scratch_elems(int n);
 hipError_t launch_scatter(const double* x, int n, const BuildGeom& g, const uint32_t* off,
                           const uint32_t* cell, const uint32_t* rank, float4* pos, double4* r64,
-                          uint32_t* idx, int4* wrap, hipStream_t s);
+                          uint32_t* idx, int4* wrap, hipStream_t s, const uint32_t* gate = nullptr);
 hipError_t launch_tiles(const uint32_t* off, const TileGeom& g, uint32_t* row_tiles,
-                        uint32_t* row_off, uint32_t* scan_scratch, Tile* tiles, hipStream_t s);
+                        uint32_t* row_off, uint32_t* scan_scratch, Tile* tiles, hipStream_t s,
+                        const uint32_t* gate = nullptr);
 hipError_t launch_gather_vel(const double* v, int dim, const uint32_t* idx, int n, float4* v32,
                              unsigned int* vmax_bits, hipStream_t s);
 hipError_t launch_set_job(const JobDesc& jd, JobDesc* dst, hipStream_t s);

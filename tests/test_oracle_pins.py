@@ -421,3 +421,159 @@ def test_thread_count_does_not_change_results():
     b = oracle.compute(x, H, 6.0, nthreads=7, **kw)
     assert a["lj_energy"] == b["lj_energy"] and a["sum_inv_d"] == b["sum_inv_d"]
     assert np.array_equal(a["lj_grad"], b["lj_grad"])
+
+
+# ---------------------------------------------------------------- frames (positions kept in an earlier wrap)
+def _framed_case(seed=61):
+    H = BOXES["tric3"]
+    x = W.uniform_in_box(700, H, seed)
+    g = W.rng(seed + 1)
+    k = g.integers(-1, 2, size=x.shape)
+    frame = oracle.wrap(x, H)[2] + k            # some particles one image away
+    return H, x, frame
+
+
+def test_frame_equal_to_the_canonical_wrap_is_the_canonical_computation():
+    H, x, _ = _framed_case()
+    rc = 4.0
+    a = oracle.compute(x, H, rc, nl=True, lj=(1.0, 0.5), lj_grad=True, sum_d=True)
+    b = oracle.compute(x, H, rc, nl=True, lj=(1.0, 0.5), lj_grad=True, sum_d=True,
+                       frame=oracle.wrap(x, H)[2])
+    assert a["count"] == b["count"]
+    for key in ("nl_i", "nl_j", "nl_d", "lj_grad", "virial", "dEdH"):
+        assert np.array_equal(a[key], b[key]), key
+    assert a["lj_energy"] == b["lj_energy"] and a["sum_d"] == b["sum_d"]
+
+
+def test_shifted_frame_gives_the_same_pairs_and_values_to_rounding():
+    """Moving the frame by lattice vectors changes no real distance: the pair
+    set is the same and every value agrees to rounding."""
+    H, x, frame = _framed_case()
+    rc = 4.0
+    a = oracle.compute(x, H, rc, nl=True, lj=(1.0, 0.5), lj_grad=True)
+    b = oracle.compute(x, H, rc, nl=True, lj=(1.0, 0.5), lj_grad=True, frame=frame)
+    assert a["count"] == b["count"] > 1000
+    assert np.array_equal(a["nl_i"], b["nl_i"]) and np.array_equal(a["nl_j"], b["nl_j"])
+    assert np.abs(a["nl_d"] - b["nl_d"]).max() <= 1e-13 * rc
+    assert abs(a["lj_energy"] / b["lj_energy"] - 1) < 1e-12
+    G = np.abs(a["lj_grad"]).max()
+    assert np.abs(a["lj_grad"] - b["lj_grad"]).max() <= 1e-11 * G
+    # dE/dH is taken at fixed Cartesian positions: the frame does not enter
+    assert np.abs(a["dEdH"] - b["dEdH"]).max() <= 1e-11 * np.abs(a["dEdH"]).max()
+
+
+def test_framed_brute_force_and_cell_loops_agree_exactly():
+    """The cell loop derives each pair's frame image from its cell image; the
+    brute-force loop searches the images of the frame positions directly."""
+    H, x, frame = _framed_case(63)
+    rc = 4.0
+    a = oracle.compute(x, H, rc, nl=True, lj=(1.0, 0.5), lj_grad=True, frame=frame,
+                       method=oracle.METHOD_BRUTE)
+    b = oracle.compute(x, H, rc, nl=True, lj=(1.0, 0.5), lj_grad=True, frame=frame,
+                       method=oracle.METHOD_CELLS)
+    assert a["method"] == oracle.METHOD_BRUTE and b["method"] == oracle.METHOD_CELLS
+    assert a["count"] == b["count"]
+    for key in ("nl_i", "nl_j", "nl_d"):
+        assert np.array_equal(a[key], b[key]), key
+    assert abs(a["lj_energy"] / b["lj_energy"] - 1) < 1e-13
+    assert np.abs(a["lj_grad"] - b["lj_grad"]).max() <= 1e-12 * np.abs(a["lj_grad"]).max()
+
+
+# ---------------------------------------------------------------- velocity Verlet
+def _lj_gas(n=216, density=0.5, seed=64, T=1.0):
+    """Reduced LJ units: a jittered simple-cubic start at the given density."""
+    m = round(n ** (1 / 3))
+    side = (n / density) ** (1 / 3)
+    g = W.rng(seed)
+    grid = np.stack(np.meshgrid(*([np.arange(m)] * 3), indexing="ij"), -1).reshape(-1, 3)
+    x = (grid + 0.5 + 0.1 * (g.random(grid.shape) - 0.5)) * (side / m)
+    v = g.normal(0.0, math.sqrt(T), size=x.shape)
+    v -= v.mean(0)
+    return x, v, np.diag([side] * 3)
+
+
+def test_md_free_flight_is_uniform_motion():
+    H = np.diag([50.0, 50.0, 50.0])
+    x = np.array([[5.0, 5.0, 5.0], [30.0, 30.0, 30.0]])
+    v = np.array([[0.3, -0.2, 0.1], [-0.1, 0.05, 0.2]])
+    r = oracle.md_run(x, v, H, 2.5, 1.0, 1.0, 1.0, 0.01, 200)
+    assert np.all(r["count"] == 0)
+    assert np.abs(r["x"] - (x + 200 * 0.01 * v)).max() < 1e-12
+    assert np.array_equal(r["v"], v)
+
+
+def test_md_dimer_oscillates_with_the_harmonic_period():
+    """Small oscillation of an LJ dimer about r_min = 2^(1/6) sigma: the
+    curvature there is 72 eps / r_min^2, so T = 2 pi sqrt(mu / k) with
+    mu = m / 2."""
+    sigma, eps, mass, dt = 1.0, 1.0, 1.0, 0.001
+    rmin = 2 ** (1 / 6) * sigma
+    H = np.diag([20.0, 20.0, 20.0])
+    x = np.array([[10.0, 10.0, 10.0], [10.0 + rmin + 0.002, 10.0, 10.0]])
+    v = np.zeros_like(x)
+    T_exact = 2 * math.pi * math.sqrt((mass / 2) / (72 * eps / rmin ** 2))
+    nsteps = int(2.2 * T_exact / dt)
+    xs = [x[1, 0] - x[0, 0]]
+    xx, vv = x, v
+    for _ in range(nsteps):  # one step at a time to record r(t)
+        r = oracle.md_run(xx, vv, H, 3.0, sigma, eps, mass, dt, 1)
+        xx, vv = r["x"], r["v"]
+        xs.append(xx[1, 0] - xx[0, 0])
+    y = np.array(xs) - rmin
+    # downward zero crossings of r - r_min, linearly interpolated
+    idx = np.where((y[:-1] > 0) & (y[1:] <= 0))[0]
+    t = (idx + y[idx] / (y[idx] - y[idx + 1])) * dt
+    assert len(t) >= 2
+    assert abs((t[1] - t[0]) / T_exact - 1) < 2e-4
+    # momentum stays zero (the pair forces are equal and opposite)
+    assert np.abs(vv.sum(0)).max() < 1e-13
+
+
+def test_md_is_time_reversible():
+    x, v, H = _lj_gas(n=125, density=0.3)
+    a = oracle.md_run(x, v, H, 2.5, 1.0, 1.0, 1.0, 0.002, 100)
+    b = oracle.md_run(a["x"], -a["v"], H, 2.5, 1.0, 1.0, 1.0, 0.002, 100)
+    assert np.abs(b["x"] - x).max() < 1e-8
+    assert np.abs(b["v"] + v).max() < 1e-8
+
+
+def test_md_energy_error_is_second_order_and_momentum_is_kept():
+    """A 27-atom cluster whose every pair stays inside the cutoff (so the
+    truncated potential never jumps): velocity Verlet keeps the total energy
+    with an error of order dt^2."""
+    g = W.rng(65)
+    grid = np.stack(np.meshgrid(*([np.arange(3)] * 3), indexing="ij"), -1).reshape(-1, 3)
+    x = 20.0 + 1.12 * grid + 0.05 * (g.random(grid.shape) - 0.5)
+    v = g.normal(0.0, 0.3, size=x.shape)
+    v -= v.mean(0)
+    H = np.diag([40.0, 40.0, 40.0])
+    errs = []
+    for dt, steps in ((0.004, 250), (0.002, 500)):
+        r = oracle.md_run(x, v, H, 12.0, 1.0, 1.0, 1.0, dt, steps)
+        assert np.all(r["count"] == 27 * 26 // 2)
+        E = r["energy"] + r["ke"]
+        errs.append(np.abs(E - E[0]).max())
+        p = r["v"].sum(0)
+        assert np.abs(p).max() < 1e-12 * np.abs(r["v"]).sum()
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
+def test_md_rescaling_sets_the_kinetic_energy():
+    x, v, H = _lj_gas(n=64, density=0.4)
+    target = 100.0
+    r = oracle.md_run(x, v, H, 2.5, 1.0, 1.0, 1.0, 0.002, 5, rescale_every=5, target_ke=target)
+    ke = 0.5 * np.sum(np.sum(r["v"] * r["v"], axis=1))
+    assert abs(ke / target - 1) < 1e-12
+    assert abs(r["ke"][-1] / target - 1) > 1e-3   # recorded before the rescale
+
+
+def test_md_with_a_skin_follows_the_same_trajectory():
+    """Distances taken in the frame of the last rebuild are the same real
+    distances: pair counts agree exactly and the trajectories to rounding."""
+    x, v, H = _lj_gas(n=216, density=0.6, T=2.0)
+    a = oracle.md_run(x, v, H, 2.5, 1.0, 1.0, 1.0, 0.004, 60)
+    b = oracle.md_run(x, v, H, 2.5, 1.0, 1.0, 1.0, 0.004, 60, skin=0.3)
+    assert np.array_equal(a["count"], b["count"])
+    assert 1 < int(b["rebuilt"].sum()) < 60
+    assert np.abs(a["x"] - b["x"]).max() < 1e-10
+    assert np.abs(a["energy"] / b["energy"] - 1).max() < 1e-11

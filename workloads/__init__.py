@@ -153,3 +153,36 @@ def serve_requests(seed=5, count=10_000, density=0.1, n_lo=1_000, n_hi=200_000,
 
 def request_positions(req):
     return uniform_in_box(req["n"], req["H"], req["pos_seed"])
+
+
+# Neon fluid of the paper's MD comparison (section 4.2): 100 atoms per nm^3,
+# orthorhombic (cubic) periodic box, cutoff 1.2 nm, time step 1 fs, velocity
+# rescaling every 10 steps.  Units: nm, ps, amu, kJ/mol (force kJ/mol/nm, so
+# force / mass is in nm/ps^2).  The paper names CHARMM parameters without
+# giving values; these are common Neon Lennard-Jones values.
+NEON = {"sigma": 0.2749, "epsilon": 0.2960, "mass": 20.1797, "cutoff": 1.2, "dt": 0.001,
+        "density": 100.0, "temperature": 300.0, "rescale_every": 10}
+KB = 0.0083144626  # kJ/mol/K
+
+
+def neon_fluid(n, seed=6, jitter=0.02):
+    """n Neon atoms in a cube at 100 atoms/nm^3: n distinct sites drawn from
+    the smallest simple-cubic lattice with at least n sites, each displaced
+    by up to +-jitter/2 of the lattice spacing, with Maxwell-Boltzmann
+    velocities at 300 K and zero total momentum.  Returns x (n, 3), v (n, 3),
+    H (3, 3) and the parameters."""
+    g = rng(seed)
+    m = int(round(n ** (1.0 / 3.0)))
+    while m ** 3 < n:
+        m += 1
+    side = (n / NEON["density"]) ** (1.0 / 3.0)
+    a = side / m
+    grid = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"),
+                    -1).reshape(-1, 3).astype(np.float64)
+    grid = grid[np.sort(g.choice(m ** 3, size=n, replace=False))]
+    x = (grid + 0.5 + jitter * (g.random((n, 3)) - 0.5)) * a
+    sd = math.sqrt(KB * NEON["temperature"] / NEON["mass"])
+    v = g.normal(0.0, sd, size=(n, 3))
+    v -= v.mean(axis=0)
+    return {"name": f"neon-{n}-rho100-rc1.2", "x": np.ascontiguousarray(x),
+            "v": np.ascontiguousarray(v), "H": np.diag([side] * 3), **NEON}
