@@ -42,7 +42,9 @@
  *  vectors w''_i, the frame position is r''_a = (H_a0*f0 + H_a1*f1) + H_a2*f2
  *  with f_a = s_a - w''_a (no floor).  Displacements, the minimum image and
  *  membership are then the definitions above with r'' in place of r'.  With
- *  w'' equal to the canonical w this is the canonical computation exactly.
+ *  w'' equal to the canonical w this is the canonical computation (except
+ *  for s within one rounding below an integer, where the canonical wrap
+ *  rounds f up to 1 and resets it to 0).
  *  Histogram edges: h = hi/nb, e_k = k*h, E_k = e_k*e_k (k = 0..nb); for a
  *  distance histogram with hi == rc, E_nb = rc2.  A value v goes to the
  *  first bin k (0-based) with v <= E_{k+1} (v = 0 goes to bin 0); values

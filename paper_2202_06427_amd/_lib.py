@@ -72,6 +72,14 @@ class Stats(ctypes.Structure):
     ]
 
 
+class VlistInfo(ctypes.Structure):
+    _fields_ = [
+        ("updates", ctypes.c_int64), ("rebuilds", ctypes.c_int64), ("entries", ctypes.c_int64),
+        ("max_row", ctypes.c_int64), ("row_capacity", ctypes.c_int64), ("skin", ctypes.c_double),
+        ("overflow", ctypes.c_int), ("pad", ctypes.c_int),
+    ]
+
+
 EXPORTS = [
     "clm_context_create", "clm_context_set_stream", "clm_context_destroy", "clm_box_create",
     "clm_box_create_ex",
@@ -80,6 +88,10 @@ EXPORTS = [
     "clm_celllist_info_get", "clm_celllist_destroy", "clm_synchronize", "clm_last_error",
     "clm_status_string", "clm_context_set_timing", "clm_stats_get", "clm_map_batch_workspace_bytes",
     "clm_map_batch",
+    # include/clmap_md.h
+    "clm_md_workspace_bytes", "clm_md_create", "clm_md_kick_drift", "clm_md_kick", "clm_md_destroy",
+    "clm_vlist_workspace_bytes", "clm_vlist_create", "clm_vlist_update", "clm_vlist_lj",
+    "clm_vlist_info_get", "clm_vlist_destroy",
 ]
 
 _lib = None
@@ -120,6 +132,18 @@ def lib():
     L.clm_map_batch_workspace_bytes.argtypes = [c_int, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t)]
     L.clm_map_batch.argtypes = [c_int, ctypes.POINTER(_vp), c_int, ctypes.POINTER(MapParams),
                                 ctypes.POINTER(MapOut), _vp, ctypes.c_size_t]
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    L.clm_md_workspace_bytes.argtypes = [c_i64, szp]
+    L.clm_md_create.argtypes = [_vp, c_int, c_i64, c_d, c_d, _vp, ctypes.c_size_t, pvp]
+    L.clm_md_kick_drift.argtypes = [_vp, _vp, _vp, _vp, c_d]
+    L.clm_md_kick.argtypes = [_vp, _vp, _vp, _vp]
+    L.clm_md_destroy.argtypes = [_vp]
+    L.clm_vlist_workspace_bytes.argtypes = [_vp, c_i64, szp]
+    L.clm_vlist_create.argtypes = [_vp, c_d, c_i64, _vp, ctypes.c_size_t, pvp]
+    L.clm_vlist_update.argtypes = [_vp, _vp]
+    L.clm_vlist_lj.argtypes = [_vp, c_d, c_d, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.clm_vlist_info_get.argtypes = [_vp, ctypes.POINTER(VlistInfo)]
+    L.clm_vlist_destroy.argtypes = [_vp]
     L.clm_last_error.restype = ctypes.c_char_p
     L.clm_status_string.restype = ctypes.c_char_p
     L.clm_status_string.argtypes = [c_int]

@@ -172,6 +172,73 @@ struct FinalArgs {
   unsigned long long* count;
 };
 
+// ---------------------------------------------------------------- molecular dynamics
+constexpr int kMdBlock = 256;  // threads per block of the per-particle / per-row kernels
+constexpr int kMdPart = 8;     // doubles per block partial
+enum : int { MP_E = 0, MP_W = 1 /* 6: xx xy xz yy yz zz */, MP_KE = 7 };
+
+// Device counters of a Verlet list (one per list, in its workspace).
+struct VlFlags {
+  unsigned long long maxd2;     // largest squared displacement of this step (double bits)
+  unsigned long long updates, rebuilds, entries;
+  uint32_t gate;                // 1: the list is rebuilt in this step
+  uint32_t force;               // 1: the next update rebuilds regardless of displacements
+  uint32_t overflow;            // sticky: a row exceeded its capacity at a rebuild
+  uint32_t max_row;             // most partners of one particle at the last rebuild
+};
+
+struct VlRefresh {
+  int n, dim;
+  double H[9], Hinv[9];         // row-major stride 3
+  const double* x;              // caller order
+  const uint32_t* idx;          // sorted slot -> caller index
+  const int4* wrap;             // wrap integers of the last rebuild (sorted)
+  double4* pf;                  // frame positions (sorted)
+  double* xref;                 // positions at the last rebuild (caller order)
+  const uint32_t* gate;
+};
+
+struct VlBuild {
+  int n[3];
+  int l, lx, cap, max_tiles;
+  double rl2;                   // list threshold on the squared distance
+  double tK[27 * 4];            // canonical image shifts H K
+  const Tile* tiles;
+  const uint32_t* ntiles;
+  const uint32_t* off;
+  const double4* r64;
+  uint32_t* list;
+  uint32_t* cnt;
+  VlFlags* fl;
+  const uint32_t* gate;
+};
+
+struct VlForce {
+  int n, cap;
+  double rc2, s2, eps, h;
+  double tK[27 * 4];
+  const uint32_t* list;
+  const uint32_t* cnt;
+  const double4* pf;
+  const uint32_t* idx;
+  double* forces;
+  double* v;                    // fused second half-kick (KICK kernels only)
+  double* part;
+  unsigned long long* pcount;
+};
+
+struct MdFinal {
+  int nb, dim;
+  const double* part;
+  const unsigned long long* pcount;   // NULL: no pair count
+  double eps, mass;
+  double* energy;
+  double* virial;
+  unsigned long long* count;
+  double* ke;                   // caller's copy (may be NULL)
+  double* ke_keep;              // the integrator's copy (NULL: no kinetic energy)
+};
+
 // ---------------------------------------------------------------- launchers
 // Host wrappers (defined next to their kernels); all enqueue on `s`.  The
 // build launchers take an optional device gate: their kernels return at once
@@ -216,6 +283,17 @@ constexpr int kFinalBlocks = 128;  // first-level blocks of the two-level finali
 hipError_t launch_gather_tiles(JobDesc* jobs, int njobs, Tile* tiles, uint32_t* total,
                               hipStream_t s);
 hipError_t launch_finalize_batch(const JobDesc* jobs, const FinalArgs* F, int njobs, hipStream_t s);
+hipError_t launch_md_kick_drift(double* x, double* v, const double* f, int64_t ncomp, double h,
+                                double dt, double target_ke, const double* ke, hipStream_t s);
+hipError_t launch_md_kick(double* v, const double* f, int n, int dim, double h, double* part,
+                          hipStream_t s);
+hipError_t launch_md_finalize(const MdFinal& F, hipStream_t s);
+hipError_t launch_vl_drift(const double* x, const double* xref, int n, int dim,
+                           unsigned long long* maxd2, hipStream_t s);
+hipError_t launch_vl_decide(VlFlags* fl, double lim2, hipStream_t s);
+hipError_t launch_vl_refresh(const VlRefresh& A, hipStream_t s);
+hipError_t launch_vl_build(int dim, const VlBuild& A, hipStream_t s);
+hipError_t launch_vl_lj(int dim, bool kick, bool vir, const VlForce& A, hipStream_t s);
 hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
                              unsigned long long* out, hipStream_t s);
 

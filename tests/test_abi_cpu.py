@@ -1,5 +1,5 @@
 """C-ABI checks that need no GPU: the library loads, exports every function
-include/clmap.h declares, validates its arguments, and sets up box geometry
+include/*.h declares, validates its arguments, and sets up box geometry
 (host FP64) exactly as the canonical definitions say."""
 import ctypes
 import math
@@ -14,14 +14,18 @@ import workloads as W
 from paper_2202_06427_amd import _lib as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "clmap.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:clm_status|const char\*)\s+(clm_\w+)\s*\(", text, re.M)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        names |= set(re.findall(r"^\s*(?:clm_status|const char\*)\s+(clm_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_function():
@@ -194,3 +198,18 @@ def test_null_arguments_are_rejected_not_crashed():
     assert lib.clm_synchronize(None) == 1
     assert lib.clm_box_info_get(None, None) == 1
     assert lib.clm_status_string(4) == b"CLM_E_CAPACITY"
+
+
+def test_md_workspace_sizes_and_validation():
+    lib = L.lib()
+    b = ctypes.c_size_t(0)
+    assert lib.clm_md_workspace_bytes(1000, ctypes.byref(b)) == 0
+    # block partials of ceil(1000/256) blocks (8 doubles each) and one double
+    assert b.value >= 4 * 8 * 8 + 8
+    assert lib.clm_md_workspace_bytes(-1, ctypes.byref(b)) == 1
+    assert lib.clm_md_workspace_bytes(10, None) == 1
+    h = ctypes.c_void_p()
+    assert lib.clm_md_create(None, 3, 10, 1.0, 0.001, None, 0, ctypes.byref(h)) == 1
+    assert lib.clm_vlist_workspace_bytes(None, 100, ctypes.byref(b)) == 1
+    assert lib.clm_vlist_update(None, None) == 1
+    assert lib.clm_vlist_lj(None, 1.0, 1.0, None, None, None, None, None, None, None) == 1
