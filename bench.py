@@ -74,6 +74,10 @@ def parse():
                     help="Poisson arrival rate of the served mix (jobs/s)")
     ap.add_argument("--build-n-large", type=int, default=16_000_000,
                     help="particle count of the second build-bandwidth point (0: skip)")
+    ap.add_argument("--md-steps", type=int, default=200,
+                    help="velocity-Verlet steps per Neon MD case (0: skip the MD section)")
+    ap.add_argument("--md-only", type=int, default=0, metavar="N",
+                    help="run only --steps Verlet-list MD steps of N Neon atoms (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -187,6 +191,62 @@ def build_roofline(clm, W, n, lcell, steps=5):
     return {"n": n, "build_ms": ms, "algorithmic_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
 
 
+def md_cases(steps):
+    """Neon fluid MD (100 atoms/nm^3, rc 1.2 nm, 1 fs, rescaling every 10
+    steps) at 10^4 and 10^5 atoms: the paper's protocol (cell list rebuilt
+    every step, FP32+guard sweep forces) against the Verlet pair list (skin
+    0.1 nm, FP64 forces), timed on the host clock around `steps` steps."""
+    import time
+    import torch
+    import paper_2202_06427_amd.md as md
+    import workloads as W
+    out = {}
+    for n in (10_000, 100_000):
+        w = W.neon_fluid(n, seed=6)
+        target = 0.5 * (3 * n - 3) * W.KB * w["temperature"]
+        row = {}
+        for mode in ("rebuild", "verlet"):
+            kw = dict(cutoff=w["cutoff"], sigma=w["sigma"], epsilon=w["epsilon"], mass=w["mass"],
+                      dt=w["dt"], mode=mode, skin=0.1, rescale_every=10, target_ke=target,
+                      precision="fp32")
+            x = torch.from_numpy(w["x"]).to("cuda:0")
+            v = torch.from_numpy(w["v"]).to("cuda:0")
+            md.run(x, v, w["H"], nsteps=20, **kw)  # warm-up (kernels loaded)
+            x = torch.from_numpy(w["x"]).to("cuda:0")
+            v = torch.from_numpy(w["v"]).to("cuda:0")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = md.run(x, v, w["H"], nsteps=steps, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            pairs = int(r["count"][1:].sum().item())
+            e = {"ms_per_step": 1e3 * dt / steps, "ns_per_day": steps * w["dt"] * 1e-3 / dt * 86400,
+                 "pairs_per_s": pairs / dt}
+            if mode == "verlet":
+                info = r["list"].info()
+                e.update({"skin_nm": 0.1, "rebuilds": info["rebuilds"], "list_entries": info["entries"],
+                          "overflow": info["overflow"]})
+            row[mode] = e
+        row["verlet_speedup"] = row["rebuild"]["ms_per_step"] / row["verlet"]["ms_per_step"]
+        out[w["name"]] = row
+    return out
+
+
+def md_only(n, steps):
+    """Verlet-list MD of n Neon atoms (skin 0.1 nm) for `steps` steps."""
+    import torch
+    import paper_2202_06427_amd.md as md
+    import workloads as W
+    w = W.neon_fluid(n, seed=6)
+    target = 0.5 * (3 * n - 3) * W.KB * w["temperature"]
+    x = torch.from_numpy(w["x"]).to("cuda:0")
+    v = torch.from_numpy(w["v"]).to("cuda:0")
+    r = md.run(x, v, w["H"], cutoff=w["cutoff"], sigma=w["sigma"], epsilon=w["epsilon"], mass=w["mass"],
+               dt=w["dt"], nsteps=steps, mode="verlet", skin=0.1, rescale_every=10, target_ke=target)
+    torch.cuda.synchronize()
+    print(json.dumps({"md_only": w["name"], "steps": steps, **r["list"].info()}), flush=True)
+
+
 def cpu_baseline(cfg, nthreads):
     import oracle
     t0 = time.perf_counter()
@@ -200,6 +260,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.md_only:
+        md_only(args.md_only, args.steps)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (single-GPU workload; no collectives). "
@@ -296,6 +359,10 @@ def main():
         log(f"served mix: {args.serve_requests} requests ...")
         line["served"] = served(args.serve_requests, args.serve_rate)
         log(f"served: {line['served']}")
+    if args.md_steps > 0:
+        log(f"Neon MD: {args.md_steps} steps at 1e4 and 1e5 atoms ...")
+        line["md"] = md_cases(args.md_steps)
+        log(f"md: {line['md']}")
     if not args.no_cpu_baseline:
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
         log(f"cpu baseline: oracle on the full workload with {nth} threads ...")

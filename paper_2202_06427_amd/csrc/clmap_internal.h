@@ -175,6 +175,9 @@ struct FinalArgs {
 // ---------------------------------------------------------------- molecular dynamics
 constexpr int kMdBlock = 256;  // threads per block of the per-particle / per-row kernels
 constexpr int kMdPart = 8;     // doubles per block partial
+constexpr int kDriftBlocks = 512;  // most blocks of the displacement check
+constexpr int kBuildBlocks = 8192; // most blocks of the pair-list build
+constexpr int kBuildWaves = 4;     // waves per block of the pair-list build
 enum : int { MP_E = 0, MP_W = 1 /* 6: xx xy xz yy yz zz */, MP_KE = 7 };
 
 // Device counters of a Verlet list (one per list, in its workspace).
@@ -201,6 +204,8 @@ struct VlRefresh {
 struct VlBuild {
   int n[3];
   int l, lx, cap, max_tiles;
+  int P, lgP;                   // lanes per row of the force kernel (list layout)
+  int split, pad;               // 1: one wave per (tile, neighbour row), else per tile
   double rl2;                   // list threshold on the squared distance
   double tK[27 * 4];            // canonical image shifts H K
   const Tile* tiles;
@@ -288,12 +293,15 @@ hipError_t launch_md_kick_drift(double* x, double* v, const double* f, int64_t n
 hipError_t launch_md_kick(double* v, const double* f, int n, int dim, double h, double* part,
                           hipStream_t s);
 hipError_t launch_md_finalize(const MdFinal& F, hipStream_t s);
-hipError_t launch_vl_drift(const double* x, const double* xref, int n, int dim,
-                           unsigned long long* maxd2, hipStream_t s);
-hipError_t launch_vl_decide(VlFlags* fl, double lim2, hipStream_t s);
+int vl_drift_blocks(int64_t n);
+hipError_t launch_vl_drift(const double* x, const double* xref, int n, int dim, double lim2,
+                           double* bmax, VlFlags* fl, hipStream_t s);
+hipError_t launch_vl_rowstats(uint32_t* cnt, int n, int cap, VlFlags* fl, const uint32_t* gate,
+                              hipStream_t s);
+int vl_rows_per_lane_group(int64_t n);
 hipError_t launch_vl_refresh(const VlRefresh& A, hipStream_t s);
 hipError_t launch_vl_build(int dim, const VlBuild& A, hipStream_t s);
-hipError_t launch_vl_lj(int dim, bool kick, bool vir, const VlForce& A, hipStream_t s);
+hipError_t launch_vl_lj(int dim, bool kick, bool vir, int P, const VlForce& A, hipStream_t s);
 hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
                              unsigned long long* out, hipStream_t s);
 

@@ -24,7 +24,8 @@ struct clm_vlist {
   clm_celllist* cl;
   int dim;
   int64_t n;
-  int64_t cap;
+  int64_t cap;       // row capacity, a multiple of P
+  int P, lgP;        // lanes per row in the force kernel (list layout)
   double rc, rc2;    // interaction cutoff
   double rl2;        // list threshold: (box cutoff)^2 with a relative margin
   double lim2;       // rebuild when a squared displacement exceeds (skin / 2)^2
@@ -33,6 +34,7 @@ struct clm_vlist {
   double4* pf;
   double* xref;
   VlFlags* fl;
+  double* bmax;      // per-block maxima of the displacement check
   double* part;
   unsigned long long* pcount;
 };
@@ -51,6 +53,7 @@ static void md_layout(int64_t n, char* base, size_t* total, clm_md* md) {
 }
 
 static void vl_layout(int64_t n, int64_t cap, char* base, size_t* total, clm_vlist* vl) {
+  // the force kernel runs up to 16 lanes per row: up to 16 n threads of block partials
   Carve c;
   const int64_t slices = (n + kWave - 1) / kWave;
   const size_t o_list = c.take(sizeof(uint32_t) * (size_t)slices * (size_t)cap * kWave);
@@ -58,7 +61,8 @@ static void vl_layout(int64_t n, int64_t cap, char* base, size_t* total, clm_vli
   const size_t o_pf = c.take(sizeof(double4) * (size_t)std::max<int64_t>(n, 1));
   const size_t o_xref = c.take(sizeof(double) * 3 * (size_t)std::max<int64_t>(n, 1));
   const size_t o_fl = c.take(sizeof(VlFlags));
-  const int64_t nb = std::max<int64_t>(md_blocks(n), 1);
+  const size_t o_bmax = c.take(sizeof(double) * kDriftBlocks);
+  const int64_t nb = std::max<int64_t>(md_blocks(16 * n), 1);
   const size_t o_part = c.take(sizeof(double) * kMdPart * (size_t)nb);
   const size_t o_pc = c.take(sizeof(unsigned long long) * (size_t)nb);
   if (base && vl) {
@@ -67,6 +71,7 @@ static void vl_layout(int64_t n, int64_t cap, char* base, size_t* total, clm_vli
     vl->pf = (double4*)(base + o_pf);
     vl->xref = (double*)(base + o_xref);
     vl->fl = (VlFlags*)(base + o_fl);
+    vl->bmax = (double*)(base + o_bmax);
     vl->part = (double*)(base + o_part);
     vl->pcount = (unsigned long long*)(base + o_pc);
   }
@@ -166,7 +171,8 @@ clm_status clm_vlist_workspace_bytes(const clm_celllist* cl, int64_t cap, size_t
   if (s != CLM_OK) return s;
   if (!bytes) return fail(CLM_E_INVALID_ARG, "bytes is NULL");
   if (cap < 1 || cap > (int64_t(1) << 20)) return fail(CLM_E_INVALID_ARG, "row_capacity must be in 1..2^20");
-  vl_layout(cl->nx, cap, nullptr, bytes, nullptr);
+  const int64_t P = vl_rows_per_lane_group(cl->nx);
+  vl_layout(cl->nx, (cap + P - 1) / P * P, nullptr, bytes, nullptr);
   return CLM_OK;
 }
 
@@ -179,6 +185,8 @@ clm_status clm_vlist_create(clm_celllist* cl, double cutoff, int64_t cap, void* 
   const double rl = cl->box.rc;
   if (!(cutoff > 0.0) || !std::isfinite(cutoff) || !(cutoff < rl))
     return fail(CLM_E_BAD_CUTOFF, "cutoff must be in (0, box cutoff %g) (got %g)", rl, cutoff);
+  const int P = vl_rows_per_lane_group(cl->nx);
+  cap = (cap + P - 1) / P * P;
   size_t need = 0;
   vl_layout(cl->nx, cap, nullptr, &need, nullptr);
   s = check_ws(ws, ws_bytes, need);
@@ -189,6 +197,9 @@ clm_status clm_vlist_create(clm_celllist* cl, double cutoff, int64_t cap, void* 
   vl->dim = cl->box.dim;
   vl->n = cl->nx;
   vl->cap = cap;
+  vl->P = P;
+  vl->lgP = 0;
+  while ((1 << vl->lgP) < P) ++vl->lgP;
   vl->rc = cutoff;
   vl->rc2 = cutoff * cutoff;
   // Partners within rl at the rebuild are listed with a relative margin far
@@ -215,17 +226,21 @@ clm_status clm_vlist_update(clm_vlist* vl, const double* x) {
   CLM_HIP(hipSetDevice(cl->ctx->device));
   hipStream_t st = cl->ctx->stream;
   const int n = (int)vl->n;
-  CLM_HIP(launch_vl_drift(x, vl->xref, n, vl->dim, &vl->fl->maxd2, st));
-  CLM_HIP(launch_vl_decide(vl->fl, vl->lim2, st));
+  CLM_HIP(launch_vl_drift(x, vl->xref, n, vl->dim, vl->lim2, vl->bmax, vl->fl, st));
   const uint32_t* gate = &vl->fl->gate;
   clm_status s = celllist_build_gated(cl, x, nullptr, gate);
   if (s != CLM_OK) return s;
+  CLM_HIP(launch_fill_u32(vl->cnt, (size_t)vl->n, 0u, st, gate));
   VlBuild B;
   std::memset(&B, 0, sizeof B);
   for (int d = 0; d < 3; ++d) B.n[d] = cl->box.n[d];
   B.l = cl->box.lcell;
   B.lx = cl->box.lcx;
   B.cap = (int)vl->cap;
+  B.P = vl->P;
+  B.lgP = vl->lgP;
+  // few tiles: spread each tile over its neighbour rows to fill the chip
+  B.split = cl->nx < 400000 ? 1 : 0;
   B.max_tiles = cl->max_tiles;
   B.rl2 = vl->rl2;
   for (int k = 0; k < 27 * 4; ++k) B.tK[k] = cl->box.tK[k];
@@ -238,6 +253,7 @@ clm_status clm_vlist_update(clm_vlist* vl, const double* x) {
   B.fl = vl->fl;
   B.gate = gate;
   CLM_HIP(launch_vl_build(vl->dim, B, st));
+  CLM_HIP(launch_vl_rowstats(vl->cnt, n, (int)vl->cap, vl->fl, gate, st));
   VlRefresh R;
   std::memset(&R, 0, sizeof R);
   R.n = n;
@@ -289,10 +305,10 @@ clm_status clm_vlist_lj(clm_vlist* vl, double sigma, double eps, double* forces,
   A.v = md ? v : nullptr;
   A.part = vl->part;
   A.pcount = vl->pcount;
-  if (vl->n > 0) CLM_HIP(launch_vl_lj(vl->dim, md != nullptr, virial != nullptr, A, st));
+  if (vl->n > 0) CLM_HIP(launch_vl_lj(vl->dim, md != nullptr, virial != nullptr, vl->P, A, st));
   MdFinal F;
   std::memset(&F, 0, sizeof F);
-  F.nb = vl->n > 0 ? (int)md_blocks(vl->n) : 0;
+  F.nb = vl->n > 0 ? (int)md_blocks(vl->n * vl->P) : 0;
   F.dim = vl->dim;
   F.part = vl->part;
   F.pcount = vl->pcount;

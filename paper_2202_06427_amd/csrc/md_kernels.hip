@@ -123,35 +123,35 @@ __global__ void __launch_bounds__(kMdBlock) md_kick_kernel(double* __restrict__ 
   block_partials(acc, 0ull, part, nullptr, blockIdx.x);
 }
 
-// One block: fixed-order sums of nb partials.  energy = 2 eps sum(u) (every
-// pair was seen from both ends), virial = 12 eps sum(f D D), count = pairs / 2,
-// ke = mass / 2 sum |v|^2.
+// One block: fixed-order sums of nb partials (each thread sums rows t,
+// t + 256, ... of all components, then waves and the block combine in a fixed
+// order).  energy = 2 eps sum(u) (every pair was seen from both ends), virial
+// = 12 eps sum(f D D), count = pairs / 2, ke = mass / 2 sum |v|^2.
 __global__ void __launch_bounds__(256) md_finalize_kernel(MdFinal F) {
-  __shared__ double red[256];
-  __shared__ unsigned long long redc[256];
-  double keep[kMdPart];
-  for (int k = 0; k < kMdPart; ++k) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < F.nb; b += 256) s += F.part[(size_t)b * kMdPart + k];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    keep[k] = red[0];
-    __syncthreads();
-  }
+  __shared__ double red[4][kMdPart];
+  __shared__ unsigned long long redc[4];
+  double acc[kMdPart];
+#pragma unroll
+  for (int k = 0; k < kMdPart; ++k) acc[k] = 0.0;
   unsigned long long c = 0;
-  if (F.pcount)
-    for (int b = threadIdx.x; b < F.nb; b += 256) c += F.pcount[b];
-  redc[threadIdx.x] = c;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) redc[threadIdx.x] += redc[threadIdx.x + w];
-    __syncthreads();
+  for (int b = threadIdx.x; b < F.nb; b += 256) {
+#pragma unroll
+    for (int k = 0; k < kMdPart; ++k) acc[k] += F.part[(size_t)b * kMdPart + k];
+    if (F.pcount) c += F.pcount[b];
   }
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kMdPart; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) red[w][k] = v;
+  }
+  c = wave_sum_u64(c);
+  if (lane == 0) redc[w] = c;
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  double keep[kMdPart];
+  for (int k = 0; k < kMdPart; ++k) keep[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  const unsigned long long cnt = redc[0] + redc[1] + redc[2] + redc[3];
   if (F.energy) *F.energy = 2.0 * F.eps * keep[MP_E];
   if (F.virial) {
     const int d = F.dim;
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(256) md_finalize_kernel(MdFinal F) {
     for (int a = 0; a < d; ++a)
       for (int b = 0; b < d; ++b) F.virial[a * d + b] = 12.0 * F.eps * keep[slot[a][b]];
   }
-  if (F.count) *F.count = redc[0] / 2;
+  if (F.count) *F.count = cnt / 2;
   if (F.ke_keep) {
     const double ke = 0.5 * F.mass * keep[MP_KE];
     *F.ke_keep = ke;
@@ -170,33 +170,47 @@ __global__ void __launch_bounds__(256) md_finalize_kernel(MdFinal F) {
 }
 
 // ---------------------------------------------------------------- Verlet list: maintenance
+// Largest squared displacement since the last rebuild: per-block maxima
+// (grid-stride over the particles, at most kDriftBlocks blocks), no atomics.
 __global__ void __launch_bounds__(kMdBlock) vl_drift_kernel(const double* __restrict__ x,
                                                             const double* __restrict__ xref, int n,
-                                                            int dim,
-                                                            unsigned long long* __restrict__ maxd2) {
-  const int i = blockIdx.x * kMdBlock + threadIdx.x;
+                                                            int dim, double* __restrict__ bmax) {
   double m = 0.0;
-  if (i < n) {
+  for (int i = blockIdx.x * kMdBlock + threadIdx.x; i < n; i += gridDim.x * kMdBlock) {
     double q = 0.0;
     for (int a = 0; a < dim; ++a) {
       const double d = x[(size_t)i * dim + a] - xref[(size_t)i * dim + a];
       q = a == 0 ? d * d : q + d * d;
     }
     // a NaN displacement forces a rebuild
-    m = q == q ? q : 1.0e300;
+    m = fmax(m, q == q ? q : 1.0e300);
   }
   for (int d = kWave / 2; d > 0; d >>= 1) m = fmax(m, __shfl_xor(m, d, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0 && m > 0.0)
-    atomicMax(maxd2, (unsigned long long)__double_as_longlong(m));
+  __shared__ double wm[kMdBlock / kWave];
+  if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = wm[0];
+    for (int k = 1; k < kMdBlock / kWave; ++k) b = fmax(b, wm[k]);
+    bmax[blockIdx.x] = b;
+  }
 }
 
-__global__ void vl_decide_kernel(VlFlags* __restrict__ fl, double lim2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double m = __longlong_as_double((long long)fl->maxd2);
-  const bool g = fl->force != 0u || m > lim2;
+// One block: the largest of the block maxima against (skin / 2)^2 decides
+// this step's rebuild; counters.
+__global__ void __launch_bounds__(256) vl_decide_kernel(const double* __restrict__ bmax, int nb,
+                                                        double lim2, VlFlags* __restrict__ fl) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) m = fmax(m, bmax[b]);
+  for (int d = kWave / 2; d > 0; d >>= 1) m = fmax(m, __shfl_xor(m, d, kWave));
+  __shared__ double wm[4];
+  if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double mx = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+  const bool g = fl->force != 0u || mx > lim2;
   fl->gate = g ? 1u : 0u;
   fl->force = 0u;
-  fl->maxd2 = 0ull;
   fl->updates += 1ull;
   if (g) {
     fl->rebuilds += 1ull;
@@ -234,146 +248,282 @@ __global__ void __launch_bounds__(kMdBlock) vl_refresh_kernel(VlRefresh A) {
     for (int a = 0; a < A.dim; ++a) A.xref[(size_t)i * A.dim + a] = r[a];
 }
 
-// One wave per cell-list tile (<= 64 consecutive sorted particles of one
-// cell row): every neighbouring cell of the full shell, every partner within
-// the list cutoff (FP64 on the build's canonical positions), appended to the
-// lane's row as (sorted partner << 5) | image code.  Row s lives in slice
-// s / 64, column s % 64: entry k at list[(s / 64) cap 64 + k 64 + s % 64].
-template <int DIM>
-__global__ void __launch_bounds__(kWave) vl_build_kernel(VlBuild A) {
-  if (*A.gate == 0u) return;
-  const int ntiles = min((int)ldu(A.ntiles), A.max_tiles);
-  const int t = blockIdx.x;
-  if (t >= ntiles) return;
-  const Tile T = ldu(&A.tiles[t]);
-  const int lane = threadIdx.x;
-  const bool active = lane < (int)T.count;
-  const uint32_t i = T.start + (uint32_t)(active ? lane : (int)T.count - 1);
-  double ri[3];
-  {
-    const double4 r = A.r64[i];
-    ri[0] = active ? r.x : 1e100;
-    ri[1] = active ? r.y : 1e100;
-    ri[2] = active ? r.z : 1e100;
-  }
-  uint32_t* row = A.list + (size_t)(i >> 6) * (size_t)A.cap * kWave + (i & 63u);
+// After a rebuild: row lengths (capped at the capacity), overflow flag, the
+// longest row and the number of stored entries.
+__global__ void __launch_bounds__(kMdBlock) vl_rowstats_kernel(uint32_t* __restrict__ cnt, int n,
+                                                               int cap, VlFlags* __restrict__ fl,
+                                                               const uint32_t* __restrict__ gate) {
+  if (*gate == 0u) return;
+  const int s = blockIdx.x * kMdBlock + threadIdx.x;
   uint32_t c = 0;
+  if (s < n) {
+    c = cnt[s];
+    if (c > (uint32_t)cap) {
+      fl->overflow = 1u;
+      cnt[s] = (uint32_t)cap;
+    }
+  }
+  uint32_t cm = c;
+  unsigned long long st = c < (uint32_t)cap ? c : (uint32_t)cap;
+  for (int d = kWave / 2; d > 0; d >>= 1) cm = max(cm, (uint32_t)__shfl_xor((int)cm, d, kWave));
+  st = wave_sum_u64(st);
+  __shared__ uint32_t wm[kMdBlock / kWave];
+  __shared__ unsigned long long ws[kMdBlock / kWave];
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    wm[threadIdx.x / kWave] = cm;
+    ws[threadIdx.x / kWave] = st;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    unsigned long long t = 0;
+    for (int k = 0; k < kMdBlock / kWave; ++k) {
+      m = max(m, wm[k]);
+      t += ws[k];
+    }
+    atomicMax(&fl->max_row, m);
+    atomicAdd(&fl->entries, t);
+  }
+}
+
+// One wave per (cell-list tile, neighbouring cell row): a tile is <= 64
+// consecutive sorted particles of one cell row; blockIdx.y picks one of the
+// (2 l + 1)^2 (3D) or 2 l + 1 (2D) rows of the full shell.  Every partner
+// within the list cutoff (FP64 on the build's canonical positions) is
+// appended to the lane's row as (sorted partner << 5) | image code: the lane
+// counts its partners in the row, reserves space with one atomic add on its
+// row length, and writes them in a second pass (so the order of a row's
+// entries depends on the order in which its waves ran).  Layout (P lanes per
+// row in the force kernel, cap a multiple of P): entry k of row s at
+//   (s / 64) cap 64 + (k / P) 64 P + (s % 64) P + k % P,
+// so that the P lanes of each of 64 / P consecutive rows read 64 consecutive
+// words.
+template <int DIM, bool WRITE>
+__device__ __forceinline__ uint32_t vl_scan_row(const VlBuild& A, const Tile& T, uint32_t i,
+                                                const double* ri, int dz, int dy, uint32_t* row,
+                                                uint32_t c) {
   const int nx = A.n[0], ny = A.n[1], nz = A.n[2];
   const int cy = (int)(T.row % (uint32_t)ny);
   const int cz = DIM == 3 ? (int)(T.row / (uint32_t)ny) : 0;
-  const int l = A.l, lx = A.lx;
-  const int dzlo = DIM == 3 ? -l : 0, dzhi = DIM == 3 ? l : 0;
-  for (int dz = dzlo; dz <= dzhi; ++dz) {
-    for (int dy = -l; dy <= l; ++dy) {
-      int uy = cy + dy, uz = cz + dz, py = 0, pz = 0;
-      if (uy < 0) { uy += ny; py = -1; } else if (uy >= ny) { uy -= ny; py = 1; }
+  const uint32_t lgP = (uint32_t)A.lgP, pm = (uint32_t)A.P - 1u;
+  int uy = cy + dy, uz = cz + dz, py = 0, pz = 0;
+  if (uy < 0) { uy += ny; py = -1; } else if (uy >= ny) { uy -= ny; py = 1; }
+  if (DIM == 3) {
+    if (uz < 0) { uz += nz; pz = -1; } else if (uz >= nz) { uz -= nz; pz = 1; }
+  }
+  const int rowbase = (uy + ny * uz) * nx;
+  uint32_t found = 0;
+  for (int ux = (int)T.cx0 - A.lx; ux <= (int)T.cx1 + A.lx; ++ux) {
+    int uxw = ux, px = 0;
+    if (uxw < 0) { uxw += nx; px = -1; } else if (uxw >= nx) { uxw -= nx; px = 1; }
+    const int cell = rowbase + uxw;
+    const uint32_t jb = ldu(&A.off[cell]), je = ldu(&A.off[cell + 1]);
+    if (jb == je) continue;
+    const int kc = kcode(px, py, pz);
+    const double t0 = A.tK[kc * 4 + 0], t1 = A.tK[kc * 4 + 1], t2 = A.tK[kc * 4 + 2];
+    auto test = [&](const double4& rj, uint32_t j) {
+      const double D0 = (rj.x - ri[0]) + t0;
+      const double D1 = (rj.y - ri[1]) + t1;
+      double d2 = D0 * D0 + D1 * D1;
       if (DIM == 3) {
-        if (uz < 0) { uz += nz; pz = -1; } else if (uz >= nz) { uz -= nz; pz = 1; }
+        const double D2 = (rj.z - ri[2]) + t2;
+        d2 = d2 + D2 * D2;
       }
-      const int rowbase = (uy + ny * uz) * nx;
-      for (int ux = (int)T.cx0 - lx; ux <= (int)T.cx1 + lx; ++ux) {
-        int uxw = ux, px = 0;
-        if (uxw < 0) { uxw += nx; px = -1; } else if (uxw >= nx) { uxw -= nx; px = 1; }
-        const int cell = rowbase + uxw;
-        const uint32_t jb = ldu(&A.off[cell]), je = ldu(&A.off[cell + 1]);
-        if (jb == je) continue;
-        const int kc = kcode(px, py, pz);
-        const double t0 = A.tK[kc * 4 + 0], t1 = A.tK[kc * 4 + 1], t2 = A.tK[kc * 4 + 2];
-        for (uint32_t j = jb; j < je; ++j) {
-          const double4 rj = ldu(&A.r64[j]);
-          const double D0 = (rj.x - ri[0]) + t0;
-          const double D1 = (rj.y - ri[1]) + t1;
-          double d2 = D0 * D0 + D1 * D1;
-          if (DIM == 3) {
-            const double D2 = (rj.z - ri[2]) + t2;
-            d2 = d2 + D2 * D2;
-          }
-          if (d2 <= A.rl2 && j != i) {
-            if (c < (uint32_t)A.cap) row[(size_t)c * kWave] = (j << 5) | (uint32_t)kc;
-            ++c;
-          }
+      if (d2 <= A.rl2 && j != i) {
+        if (WRITE) {
+          const uint32_t k = c + found;
+          if (k < (uint32_t)A.cap)
+            row[(size_t)(k >> lgP) * (kWave << lgP) + (k & pm)] = (j << 5) | (uint32_t)kc;
         }
+        ++found;
       }
+    };
+    // four partner records requested before any is tested
+    uint32_t j = jb;
+    for (; j + 4 <= je; j += 4) {
+      const double4 a0 = ldu(&A.r64[j]), a1 = ldu(&A.r64[j + 1]);
+      const double4 a2 = ldu(&A.r64[j + 2]), a3 = ldu(&A.r64[j + 3]);
+      test(a0, j);
+      test(a1, j + 1);
+      test(a2, j + 2);
+      test(a3, j + 3);
     }
+    for (; j < je; ++j) test(ldu(&A.r64[j]), j);
   }
-  unsigned long long stored = 0;
-  if (active) {
-    A.cnt[i] = c < (uint32_t)A.cap ? c : (uint32_t)A.cap;
-    stored = c < (uint32_t)A.cap ? c : (uint32_t)A.cap;
-    if (c > (uint32_t)A.cap) A.fl->overflow = 1u;
-  }
-  uint32_t cm = active ? c : 0u;
-  for (int d = kWave / 2; d > 0; d >>= 1) cm = max(cm, (uint32_t)__shfl_xor((int)cm, d, kWave));
-  stored = wave_sum_u64(stored);
-  if (lane == 0) {
-    atomicMax(&A.fl->max_row, cm);
-    atomicAdd(&A.fl->entries, stored);
+  return found;
+}
+
+// The grid is bounded (kBuildBlocks): when no rebuild is due the launch
+// costs next to nothing; otherwise each block walks work items with a grid
+// stride.  With A.split a work item is (tile, neighbour row): many waves per
+// tile for lists of few particles, rows filled through atomic reservations
+// (two passes).  Without it a work item is a whole tile: one pass, each
+// lane owns its row and stores its length.
+template <int DIM>
+__global__ void __launch_bounds__(kBuildWaves * kWave) vl_build_kernel(VlBuild A) {
+  if (*A.gate == 0u) return;
+  const int ntiles = min((int)ldu(A.ntiles), A.max_tiles);
+  const int side = 2 * A.l + 1;
+  const int nrow = DIM == 3 ? side * side : side;
+  const int per = A.split ? nrow : 1;
+  const int64_t items = (int64_t)ntiles * per;
+  const int lane = threadIdx.x & (kWave - 1);
+  // the wave index, made visibly wave-uniform so partner records stay scalar loads
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int64_t w0 = (int64_t)blockIdx.x * kBuildWaves + wid;
+  for (int64_t w = w0; w < items; w += (int64_t)gridDim.x * kBuildWaves) {
+    const int t = (int)(w / per), r = (int)(w % per);
+    const Tile T = ldu(&A.tiles[t]);
+    const bool active = lane < (int)T.count;
+    const uint32_t i = T.start + (uint32_t)(active ? lane : (int)T.count - 1);
+    double ri[3];
+    {
+      const double4 p = A.r64[i];
+      ri[0] = active ? p.x : 1e100;
+      ri[1] = active ? p.y : 1e100;
+      ri[2] = active ? p.z : 1e100;
+    }
+    uint32_t* row = A.list + (size_t)(i >> 6) * (size_t)A.cap * kWave + (size_t)(i & 63u) * A.P;
+    if (A.split) {
+      const int dy = r % side - A.l;
+      const int dz = DIM == 3 ? r / side - A.l : 0;
+      const uint32_t found = vl_scan_row<DIM, false>(A, T, i, ri, dz, dy, row, 0);
+      if (active && found != 0) {
+        const uint32_t c = atomicAdd(&A.cnt[i], found);
+        if (c < (uint32_t)A.cap) vl_scan_row<DIM, true>(A, T, i, ri, dz, dy, row, c);
+      }
+    } else {
+      uint32_t c = 0;
+      for (int rr = 0; rr < nrow; ++rr) {
+        const int dy = rr % side - A.l;
+        const int dz = DIM == 3 ? rr / side - A.l : 0;
+        c += vl_scan_row<DIM, true>(A, T, i, ri, dz, dy, row, c);
+      }
+      if (active) A.cnt[i] = c;
+    }
   }
 }
 
 // ---------------------------------------------------------------- Verlet list: forces
-// One thread per row (sorted slot s): canonical FP64 displacement in the
-// frame, membership d2 <= rc2, Lennard-Jones u and f, sums over the row.
-template <int DIM, bool KICK, bool VIR>
+// P lanes per row (sorted slot s), each taking every P-th entry, four entries
+// per iteration with their loads issued first: canonical FP64 displacement
+// in the frame, membership d2 <= rc2, Lennard-Jones u and f.  The P partial
+// sums of a row meet through shuffles; its first lane writes the force (and
+// applies the second half-kick).
+template <int DIM, bool VIR>
+__device__ __forceinline__ void vl_pair(const double4& rs, const double4& rj, const double* tk,
+                                        int kc, double rc2, double s2, double* G, double& E,
+                                        double* W, unsigned long long& npair) {
+  double D[3];
+  D[0] = (rj.x - rs.x) + tk[kc * 4 + 0];
+  D[1] = (rj.y - rs.y) + tk[kc * 4 + 1];
+  double d2 = D[0] * D[0] + D[1] * D[1];
+  if (DIM == 3) {
+    D[2] = (rj.z - rs.z) + tk[kc * 4 + 2];
+    d2 = d2 + D[2] * D[2];
+  } else {
+    D[2] = 0.0;
+  }
+  if (d2 <= rc2) {
+    const double r = rcp64(d2);
+    const double x = s2 * r;
+    const double x3 = x * x * x;
+    E += x3 * x3 - x3;
+    const double f = (2.0 * x3 * x3 - x3) * r;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) G[a] += f * D[a];
+    if constexpr (VIR) {
+      W[0] += f * D[0] * D[0];
+      W[1] += f * D[0] * D[1];
+      W[3] += f * D[1] * D[1];
+      if (DIM == 3) {
+        W[2] += f * D[0] * D[2];
+        W[4] += f * D[1] * D[2];
+        W[5] += f * D[2] * D[2];
+      }
+    }
+    ++npair;
+  }
+}
+
+template <int DIM, bool KICK, bool VIR, int P>
 __global__ void __launch_bounds__(kMdBlock) vl_lj_kernel(VlForce A) {
   __shared__ double tk[27 * 4];
   for (int k = threadIdx.x; k < 27 * 4; k += kMdBlock) tk[k] = A.tK[k];
   __syncthreads();
-  const int nblk = (A.n + kMdBlock - 1) / kMdBlock;
+  constexpr int kRows = kMdBlock / P;  // rows per block
+  const int nblk = (A.n + kRows - 1) / kRows;
   const int b = xcd_block(blockIdx.x, nblk);
-  const int s = b * kMdBlock + threadIdx.x;
+  const int s = b * kRows + (int)threadIdx.x / P;
+  const int q = (int)threadIdx.x % P;
+  double G[3] = {0.0, 0.0, 0.0};
+  double E = 0.0;
+  double W[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  unsigned long long npair = 0;
+  double4 rs = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (s < A.n) {
+    rs = A.pf[s];
+    const int cnt = (int)A.cnt[s];
+    const uint32_t* __restrict__ row =
+        A.list + (size_t)(s >> 6) * (size_t)A.cap * kWave + (size_t)(s & 63) * P + q;
+    constexpr size_t kStep = (size_t)kWave * P;
+    const int T = cnt > q ? (cnt - q + P - 1) / P : 0;
+    const double rc2 = A.rc2, s2 = A.s2;
+    // groups of four entries; the partner positions of the next group are
+    // requested before the current group is evaluated
+    const int ng = T / 4;
+    uint32_t e0[4], e1[4];
+    double4 r0[4];
+    if (ng > 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e0[u] = row[(size_t)u * kStep];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r0[u] = A.pf[e0[u] >> 5];
+    }
+    for (int g = 0; g < ng; ++g) {
+      double4 r1[4];
+      const bool more = g + 1 < ng;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e1[u] = row[(size_t)(4 * (g + 1) + u) * kStep];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r1[u] = A.pf[e1[u] >> 5];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        vl_pair<DIM, VIR>(rs, r0[u], tk, (int)(e0[u] & 31u), rc2, s2, G, E, W, npair);
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          e0[u] = e1[u];
+          r0[u] = r1[u];
+        }
+      }
+    }
+    for (int t = 4 * ng; t < T; ++t) {
+      const uint32_t e = row[(size_t)t * kStep];
+      vl_pair<DIM, VIR>(rs, A.pf[e >> 5], tk, (int)(e & 31u), rc2, s2, G, E, W, npair);
+    }
+  }
+#pragma unroll
+  for (int o = P / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) G[a] += __shfl_xor(G[a], o, kWave);
+    E += __shfl_xor(E, o, kWave);
+    if constexpr (VIR) {
+#pragma unroll
+      for (int w = 0; w < 6; ++w) W[w] += __shfl_xor(W[w], o, kWave);
+    }
+    npair += __shfl_xor(npair, o, kWave);
+  }
   double acc[kMdPart];
 #pragma unroll
   for (int k = 0; k < kMdPart; ++k) acc[k] = 0.0;
-  unsigned long long npair = 0;
-  if (s < A.n) {
-    const double4 rs = A.pf[s];
-    const uint32_t cnt = A.cnt[s];
-    const uint32_t* __restrict__ row = A.list + (size_t)(s >> 6) * (size_t)A.cap * kWave + (s & 63);
-    double G[3] = {0.0, 0.0, 0.0};
-    double E = 0.0;
-    double W[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const double rc2 = A.rc2, s2 = A.s2;
-    uint32_t k = 0;
-    for (; k < cnt; ++k) {
-      const uint32_t e = row[(size_t)k * kWave];
-      const uint32_t j = e >> 5;
-      const int kc = (int)(e & 31u);
-      const double4 rj = A.pf[j];
-      double D[3];
-      D[0] = (rj.x - rs.x) + tk[kc * 4 + 0];
-      D[1] = (rj.y - rs.y) + tk[kc * 4 + 1];
-      double d2 = D[0] * D[0] + D[1] * D[1];
-      if (DIM == 3) {
-        D[2] = (rj.z - rs.z) + tk[kc * 4 + 2];
-        d2 = d2 + D[2] * D[2];
-      } else {
-        D[2] = 0.0;
-      }
-      if (d2 <= rc2) {
-        const double r = rcp64(d2);
-        const double x = s2 * r;
-        const double x3 = x * x * x;
-        E += x3 * x3 - x3;
-        const double f = (2.0 * x3 * x3 - x3) * r;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) G[a] += f * D[a];
-        if constexpr (VIR) {
-          W[0] += f * D[0] * D[0];
-          W[1] += f * D[0] * D[1];
-          W[3] += f * D[1] * D[1];
-          if (DIM == 3) {
-            W[2] += f * D[0] * D[2];
-            W[4] += f * D[1] * D[2];
-            W[5] += f * D[2] * D[2];
-          }
-        }
-        ++npair;
-      }
-    }
+  unsigned long long np = 0;
+  if (s < A.n && q == 0) {
     const uint32_t i = A.idx[s];
     const double m24 = -24.0 * A.eps;
-    double q = 0.0;
+    double qq = 0.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       const double Fa = m24 * G[a];
@@ -381,15 +531,16 @@ __global__ void __launch_bounds__(kMdBlock) vl_lj_kernel(VlForce A) {
       if constexpr (KICK) {
         const double va = A.v[(size_t)i * DIM + a] + A.h * Fa;
         A.v[(size_t)i * DIM + a] = va;
-        q = a == 0 ? va * va : q + va * va;
+        qq = a == 0 ? va * va : qq + va * va;
       }
     }
     acc[MP_E] = E;
 #pragma unroll
     for (int w = 0; w < 6; ++w) acc[MP_W + w] = W[w];
-    acc[MP_KE] = q;
+    acc[MP_KE] = qq;
+    np = npair;
   }
-  block_partials(acc, npair, A.part, A.pcount, b);
+  block_partials(acc, np, A.part, A.pcount, b);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -417,15 +568,24 @@ hipError_t launch_md_finalize(const MdFinal& F, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_vl_drift(const double* x, const double* xref, int n, int dim,
-                           unsigned long long* maxd2, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  vl_drift_kernel<<<blocks_for(n, kMdBlock), kMdBlock, 0, s>>>(x, xref, n, dim, maxd2);
+int vl_drift_blocks(int64_t n) {
+  const int64_t b = (n + kMdBlock - 1) / kMdBlock;
+  return (int)(b < 1 ? 1 : (b > kDriftBlocks ? kDriftBlocks : b));
+}
+
+hipError_t launch_vl_drift(const double* x, const double* xref, int n, int dim, double lim2,
+                           double* bmax, VlFlags* fl, hipStream_t s) {
+  const int nb = vl_drift_blocks(n);
+  vl_drift_kernel<<<nb, kMdBlock, 0, s>>>(x, xref, n, dim, bmax);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  vl_decide_kernel<<<1, 256, 0, s>>>(bmax, nb, lim2, fl);
   return hipGetLastError();
 }
 
-hipError_t launch_vl_decide(VlFlags* fl, double lim2, hipStream_t s) {
-  vl_decide_kernel<<<1, 64, 0, s>>>(fl, lim2);
+hipError_t launch_vl_rowstats(uint32_t* cnt, int n, int cap, VlFlags* fl, const uint32_t* gate,
+                              hipStream_t s) {
+  vl_rowstats_kernel<<<blocks_for(n, kMdBlock), kMdBlock, 0, s>>>(cnt, n, cap, fl, gate);
   return hipGetLastError();
 }
 
@@ -437,23 +597,43 @@ hipError_t launch_vl_refresh(const VlRefresh& A, hipStream_t s) {
 
 hipError_t launch_vl_build(int dim, const VlBuild& A, hipStream_t s) {
   if (A.max_tiles <= 0) return hipSuccess;
+  const int64_t side = 2 * (int64_t)A.l + 1;
+  const int64_t items = (int64_t)A.max_tiles * (A.split ? (dim == 3 ? side * side : side) : 1);
+  const int64_t want = (items + kBuildWaves - 1) / kBuildWaves;
+  const unsigned nb = (unsigned)(want < kBuildBlocks ? want : kBuildBlocks);
   if (dim == 3)
-    vl_build_kernel<3><<<A.max_tiles, kWave, 0, s>>>(A);
+    vl_build_kernel<3><<<nb, kBuildWaves * kWave, 0, s>>>(A);
   else
-    vl_build_kernel<2><<<A.max_tiles, kWave, 0, s>>>(A);
+    vl_build_kernel<2><<<nb, kBuildWaves * kWave, 0, s>>>(A);
   return hipGetLastError();
 }
 
-hipError_t launch_vl_lj(int dim, bool kick, bool vir, const VlForce& A, hipStream_t s) {
-  const unsigned nb = blocks_for(A.n, kMdBlock);
-#define CLM_VL_LJ(D, K, V) vl_lj_kernel<D, K, V><<<nb, kMdBlock, 0, s>>>(A)
-  if (dim == 3) {
-    if (kick) { if (vir) CLM_VL_LJ(3, true, true); else CLM_VL_LJ(3, true, false); }
-    else { if (vir) CLM_VL_LJ(3, false, true); else CLM_VL_LJ(3, false, false); }
-  } else {
-    if (kick) { if (vir) CLM_VL_LJ(2, true, true); else CLM_VL_LJ(2, true, false); }
-    else { if (vir) CLM_VL_LJ(2, false, true); else CLM_VL_LJ(2, false, false); }
+int vl_rows_per_lane_group(int64_t n) {
+  // enough waves to fill the chip several times over: P n / 64 >= 4096
+  int P = 1;
+  while (P < 16 && (int64_t)P * n < (int64_t)4096 * kWave) P *= 2;
+  return P;
+}
+
+hipError_t launch_vl_lj(int dim, bool kick, bool vir, int P, const VlForce& A, hipStream_t s) {
+  const unsigned nb = blocks_for((int64_t)A.n * P, kMdBlock);
+#define CLM_VL_LJ(D, K, V, PP) vl_lj_kernel<D, K, V, PP><<<nb, kMdBlock, 0, s>>>(A)
+#define CLM_VL_P(D, K, V)                        \
+  switch (P) {                                   \
+    case 1: CLM_VL_LJ(D, K, V, 1); break;        \
+    case 2: CLM_VL_LJ(D, K, V, 2); break;        \
+    case 4: CLM_VL_LJ(D, K, V, 4); break;        \
+    case 8: CLM_VL_LJ(D, K, V, 8); break;        \
+    default: CLM_VL_LJ(D, K, V, 16); break;      \
   }
+  if (dim == 3) {
+    if (kick) { if (vir) CLM_VL_P(3, true, true) else CLM_VL_P(3, true, false) }
+    else { if (vir) CLM_VL_P(3, false, true) else CLM_VL_P(3, false, false) }
+  } else {
+    if (kick) { if (vir) CLM_VL_P(2, true, true) else CLM_VL_P(2, true, false) }
+    else { if (vir) CLM_VL_P(2, false, true) else CLM_VL_P(2, false, false) }
+  }
+#undef CLM_VL_P
 #undef CLM_VL_LJ
   return hipGetLastError();
 }

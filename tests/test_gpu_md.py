@@ -72,6 +72,18 @@ def test_vlist_forces_at_a_rebuild(md, lcell):
     _check_against_oracle(x, H, oracle.wrap(x, H)[2], F, E, Wv, C)
 
 
+def test_vlist_forces_at_a_rebuild_large(md):
+    """Above 400k particles the list is built one wave per tile (one pass)."""
+    w = W.neon_fluid(420_000, seed=17)
+    x, H = w["x"], w["H"]
+    xd = T(x)
+    vl = md.VerletList(xd, H, RC, 0.1, lcell=2)
+    vl.update(xd)
+    F, E, Wv, C = _lj_outputs(vl, len(x), 3)
+    assert vl.info()["overflow"] == 0
+    _check_against_oracle(x, H, oracle.wrap(x, H)[2], F, E, Wv, C)
+
+
 def test_vlist_between_rebuilds_and_across_the_box_faces(md):
     """Displacements below half the skin keep the list (no rebuild); the
     distances are taken in the frame of the rebuild, also for particles that
