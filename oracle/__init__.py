@@ -45,6 +45,7 @@ class _Result(ctypes.Structure):
         ("dEdH", ctypes.c_double * 9), ("lj_grad", _dp), ("hist", _u64p),
         ("rel_hist", _u64p), ("rel_sum", _dp), ("nl_i", _i64p), ("nl_j", _i64p),
         ("nl_d", _dp), ("nl_count", ctypes.c_uint64), ("method_used", ctypes.c_int),
+        ("nl_d2", _dp),
     ]
 
 
@@ -217,7 +218,8 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
         nli = np.zeros(max(cap, 1), dtype=np.int64)
         nlj = np.zeros(max(cap, 1), dtype=np.int64)
         nld = np.zeros(max(cap, 1))
-        res.nl_i, res.nl_j, res.nl_d = _p(nli, _i64p), _p(nlj, _i64p), _p(nld)
+        nld2 = np.zeros(max(cap, 1))
+        res.nl_i, res.nl_j, res.nl_d, res.nl_d2 = _p(nli, _i64p), _p(nlj, _i64p), _p(nld), _p(nld2)
     keep.append((vx, vy, fr))
     rc = lib().clmo_compute(dim, _p(H), float(cutoff), _p(x), nx, _p(yy), ny,
                             ctypes.byref(req), ctypes.byref(res))
@@ -241,7 +243,7 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
     if nl:
         m = min(int(res.nl_count), req.nl_capacity)
         out["nl_count"] = int(res.nl_count)
-        out["nl_i"], out["nl_j"], out["nl_d"] = nli[:m], nlj[:m], nld[:m]
+        out["nl_i"], out["nl_j"], out["nl_d"], out["nl_d2"] = nli[:m], nlj[:m], nld[:m], nld2[:m]
     return out
 
 
@@ -343,3 +345,16 @@ def md_run(x, v, H, cutoff, sigma, epsilon, mass, dt, nsteps, *, skin=0.0, resca
     for key, val in rec.items():
         out[key] = np.array(val)
     return out
+
+
+# ---------------------------------------------------------------- k closest pairs
+def kclosest(x, H, cutoff, k, y=None, nthreads=0):
+    """The k pairs with the smallest squared distance among the pairs within
+    the cutoff (paper Code 8: the closest pairs between two sets, merged
+    across threads by a custom reduction), in ascending (d2, i, j) order;
+    fewer than k when fewer pairs are within the cutoff.  Plain definition:
+    every pair within the cutoff, one sort.  Returns (i, j, d2)."""
+    r = compute(x, H, cutoff, y, nl=True, nthreads=nthreads)
+    i, j, d2 = r["nl_i"], r["nl_j"], r["nl_d2"]
+    order = np.lexsort((j, i, d2))[:k]
+    return i[order], j[order], d2[order]

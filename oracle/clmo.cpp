@@ -249,7 +249,7 @@ int bin_of(const std::vector<double>& E, double v) {
 
 struct Pair {
   int64_t i, j;
-  double d;
+  double d, d2;
 };
 
 /* Per-home-cell (or per-particle) partial results. */
@@ -288,7 +288,7 @@ void accumulate(Ctx& C, Partial& P, std::vector<Neumaier>& rel_sum, int tid, int
     double d = std::sqrt(d2);
     if (want & CLMO_W_SUM_D) P.sum_d.add(d);
     if (want & CLMO_W_SUM_INV_D) P.sum_inv_d.add(1.0 / d);
-    if (want & CLMO_W_NL) C.nl_t[tid].push_back(Pair{i, j, d});
+    if (want & CLMO_W_NL) C.nl_t[tid].push_back(Pair{i, j, d, d2});
   }
   if (want & CLMO_W_LJ) {
     double x = (q.sigma * q.sigma) / d2;
@@ -619,6 +619,7 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
       res->nl_i[k] = all[k].i;
       res->nl_j[k] = all[k].j;
       if (res->nl_d) res->nl_d[k] = all[k].d;
+      if (res->nl_d2) res->nl_d2[k] = all[k].d2;
     }
   }
   return CLMO_OK;

@@ -103,6 +103,7 @@ typedef struct clmo_result {
   double* nl_d;            /* may be NULL */
   uint64_t nl_count;       /* true number of pairs (may exceed capacity) */
   int method_used;
+  double* nl_d2;           /* squared distances d2 of the listed pairs (may be NULL) */
 } clmo_result;
 
 /* Box geometry per the definitions above.  widths = perpendicular widths

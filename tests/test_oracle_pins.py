@@ -577,3 +577,36 @@ def test_md_with_a_skin_follows_the_same_trajectory():
     assert 1 < int(b["rebuilt"].sum()) < 60
     assert np.abs(a["x"] - b["x"]).max() < 1e-10
     assert np.abs(a["energy"] / b["energy"] - 1).max() < 1e-11
+
+
+# ---------------------------------------------------------------- k closest pairs (Code 8)
+def test_kclosest_code8_shape_against_exhaustive_enumeration():
+    """Code 8's case: 100 and 1000 uniform points in a unit box, cutoff 0.1,
+    the 5 closest cross pairs; every pair enumerated with all 27 images."""
+    x, y = W.rng(81).random((100, 3)), W.rng(82).random((1000, 3))
+    H = np.eye(3)
+    i, j, d2 = oracle.kclosest(x, H, 0.1, 5, y=y)
+    Ks = np.stack(np.meshgrid(*([np.arange(-1, 2)] * 3), indexing="ij"), -1).reshape(-1, 3).astype(float)
+    D = (y[None, :, None, :] - x[:, None, None, :]) + Ks[None, None, :, :]
+    e2 = ((D[..., 0] * D[..., 0] + D[..., 1] * D[..., 1]) + D[..., 2] * D[..., 2]).min(axis=2)
+    ii, jj = np.nonzero(e2 <= 0.1 * 0.1)
+    order = np.lexsort((jj, ii, e2[ii, jj]))[:5]
+    assert np.array_equal(i, ii[order]) and np.array_equal(j, jj[order])
+    assert np.array_equal(d2, e2[ii[order], jj[order]])
+
+
+def test_kclosest_ties_go_by_index_and_short_lists():
+    """Equal squared distances are ordered by (i, j); with fewer than k pairs
+    in the cutoff every pair is returned."""
+    H = np.diag([8.0, 8.0, 8.0])
+    x = np.array([[4.0, 4.0, 4.0], [1.0, 1.0, 1.0]])
+    off = 0.125 * np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]])
+    y = np.vstack([x[0] + off, [[4.0, 4.0, 4.0 + 0.0625]], x[1] + 2 * off[:2]])
+    i, j, d2 = oracle.kclosest(x, H, 0.3, 4, y=y)
+    assert list(zip(i, j)) == [(0, 6), (0, 0), (0, 1), (0, 2)]
+    assert list(d2) == [0.0625 ** 2, 0.015625, 0.015625, 0.015625]
+    i, j, d2 = oracle.kclosest(x, H, 0.3, 100, y=y)
+    assert len(i) == 9 and list(zip(i[-2:], j[-2:])) == [(1, 7), (1, 8)]
+    # single set: unordered pairs i < j
+    i, j, d2 = oracle.kclosest(y, H, 0.13, 3)
+    assert np.all(i < j) and np.all(np.diff(d2) >= 0)
