@@ -277,6 +277,30 @@ class CellList:
         self._keep_v = (vx, vyy)
         return h, s, c
 
+    def kclosest(self, k, capacity=None):
+        """The k pairs with the smallest distance within the cutoff (paper
+        Code 8), ascending by (d2, i, j): device tensors i, j (int32) and d2
+        (float64) of length min(k, pairs within the cutoff).  Synchronizes."""
+        k = int(k)
+        cap = int(capacity) if capacity is not None else max(8192, 4 * k)
+        nbytes = ctypes.c_size_t(0)
+        L.check(L.lib().clm_kclosest_workspace_bytes(self._h, k, cap, ctypes.byref(nbytes)))
+        raw = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        pad = (-raw.data_ptr()) % 256
+        ws = raw[pad: pad + int(nbytes.value)]
+        i = torch.empty(k, dtype=torch.int32, device=self.device)
+        j = torch.empty(k, dtype=torch.int32, device=self.device)
+        d2 = torch.empty(k, dtype=torch.float64, device=self.device)
+        found = ctypes.c_int64(0)
+        _context(self.device)
+        st = L.lib().clm_kclosest(self._h, k, cap, _ptr(ws), int(nbytes.value), _ptr(i), _ptr(j),
+                                  _ptr(d2), ctypes.byref(found))
+        if st == L.STATUS_CODES["CLM_E_CAPACITY"] and capacity is None:
+            return self.kclosest(k, capacity=int(found.value))
+        L.check(st)
+        m = int(found.value)
+        return i[:m], j[:m], d2[:m]
+
     def neighbor_list(self, capacity=None, distances=True, cutoff=None):
         """Pairs (i, j) within the cutoff (single set: i < j) and their d.
 

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libclmap.so")
 CLM_OK = 0
 STATUS_NAMES = {0: "CLM_OK", 1: "CLM_E_INVALID_ARG", 2: "CLM_E_BAD_BOX", 3: "CLM_E_BAD_CUTOFF",
                 4: "CLM_E_CAPACITY", 5: "CLM_E_WORKSPACE", 6: "CLM_E_DEVICE", 7: "CLM_E_UNSUPPORTED"}
+STATUS_CODES = {v: k for k, v in STATUS_NAMES.items()}
 
 # clm_precision
 CLM_FP64 = 0
@@ -92,6 +93,8 @@ EXPORTS = [
     "clm_md_workspace_bytes", "clm_md_create", "clm_md_kick_drift", "clm_md_kick", "clm_md_destroy",
     "clm_vlist_workspace_bytes", "clm_vlist_create", "clm_vlist_update", "clm_vlist_lj",
     "clm_vlist_info_get", "clm_vlist_destroy",
+    # include/clmap_kclosest.h
+    "clm_kclosest_workspace_bytes", "clm_kclosest",
 ]
 
 _lib = None
@@ -144,6 +147,9 @@ def lib():
     L.clm_vlist_lj.argtypes = [_vp, c_d, c_d, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.clm_vlist_info_get.argtypes = [_vp, ctypes.POINTER(VlistInfo)]
     L.clm_vlist_destroy.argtypes = [_vp]
+    L.clm_kclosest_workspace_bytes.argtypes = [_vp, c_i64, c_i64, szp]
+    L.clm_kclosest.argtypes = [_vp, c_i64, c_i64, _vp, ctypes.c_size_t, _vp, _vp, _vp,
+                               ctypes.POINTER(c_i64)]
     L.clm_last_error.restype = ctypes.c_char_p
     L.clm_status_string.restype = ctypes.c_char_p
     L.clm_status_string.argtypes = [c_int]

@@ -244,6 +244,27 @@ struct MdFinal {
   double* ke_keep;              // the integrator's copy (NULL: no kinetic energy)
 };
 
+// ---------------------------------------------------------------- k closest pairs
+struct KcRecord {            // a candidate pair: canonical d2 (bits), caller indices
+  unsigned long long key;
+  uint32_t i, j;
+};
+static_assert(sizeof(KcRecord) == 16, "record is 16 bytes");
+constexpr int kKcLdsRecords = 2048;  // records sorted in LDS by one block
+constexpr int kKcLdsThreads = 1024;
+
+struct KcKeys {
+  int dim, cross, cap, npow2;
+  double tK[27 * 4];
+  const int32_t* pairs;                 // candidate pairs (caller indices)
+  const unsigned long long* count;      // number of candidates (device)
+  const double4* r64_x;
+  const double4* r64_y;
+  const uint32_t* inv_x;
+  const uint32_t* inv_y;
+  KcRecord* rec;
+};
+
 // ---------------------------------------------------------------- launchers
 // Host wrappers (defined next to their kernels); all enqueue on `s`.  The
 // build launchers take an optional device gate: their kernels return at once
@@ -302,6 +323,11 @@ int vl_rows_per_lane_group(int64_t n);
 hipError_t launch_vl_refresh(const VlRefresh& A, hipStream_t s);
 hipError_t launch_vl_build(int dim, const VlBuild& A, hipStream_t s);
 hipError_t launch_vl_lj(int dim, bool kick, bool vir, int P, const VlForce& A, hipStream_t s);
+hipError_t launch_kc_inverse(const uint32_t* idx, int n, uint32_t* inv, hipStream_t s);
+hipError_t launch_kc_keys(const KcKeys& A, hipStream_t s);
+hipError_t launch_kc_sort(KcRecord* rec, int n, hipStream_t s);
+hipError_t launch_kc_output(const KcRecord* rec, int k, int found, int32_t* io, int32_t* jo, double* d2o,
+                            hipStream_t s);
 hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
                              unsigned long long* out, hipStream_t s);
 
