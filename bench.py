@@ -76,6 +76,7 @@ def parse():
                     help="particle count of the second build-bandwidth point (0: skip)")
     ap.add_argument("--md-steps", type=int, default=200,
                     help="velocity-Verlet steps per Neon MD case (0: skip the MD section)")
+    ap.add_argument("--kclosest", type=int, default=1, help="0: skip the k-closest-pairs section")
     ap.add_argument("--md-only", type=int, default=0, metavar="N",
                     help="run only --steps Verlet-list MD steps of N Neon atoms (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -232,6 +233,36 @@ def md_cases(steps):
     return out
 
 
+def kclosest_cases(reps=5):
+    """k closest cross pairs (Code 8) on the cross-set workload (5000 blob
+    particles against 5*10^5 uniform ones, box 170, cutoff 5), FP32+guard
+    cell list: milliseconds per query (cell list built once)."""
+    import time
+    import torch
+    import paper_2202_06427_amd as clm
+    import workloads as W
+    cfg = W.config3()
+    x = torch.from_numpy(cfg["x"]).to("cuda:0")
+    y = torch.from_numpy(cfg["y"]).to("cuda:0")
+    cl = clm.CellList(x, clm.Box(cfg["H"], cfg["cutoff"], 2), y=y, precision="fp32")
+    pairs = int(cl.count().item())
+    out = {"workload": cfg["name"], "pairs_within_cutoff": pairs}
+    for k in (5, 1000):
+        cl.kclosest(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            i, j, d2 = cl.kclosest(k)
+        torch.cuda.synchronize()
+        out[f"k{k}_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cl.count()
+    torch.cuda.synchronize()
+    out["one_count_sweep_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+    return out
+
+
 def md_only(n, steps):
     """Verlet-list MD of n Neon atoms (skin 0.1 nm) for `steps` steps."""
     import torch
@@ -363,6 +394,10 @@ def main():
         log(f"Neon MD: {args.md_steps} steps at 1e4 and 1e5 atoms ...")
         line["md"] = md_cases(args.md_steps)
         log(f"md: {line['md']}")
+    if args.kclosest:
+        log("k closest pairs ...")
+        line["kclosest"] = kclosest_cases()
+        log(f"kclosest: {line['kclosest']}")
     if not args.no_cpu_baseline:
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
         log(f"cpu baseline: oracle on the full workload with {nth} threads ...")
