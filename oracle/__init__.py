@@ -358,3 +358,24 @@ def kclosest(x, H, cutoff, k, y=None, nthreads=0):
     i, j, d2 = r["nl_i"], r["nl_j"], r["nl_d2"]
     order = np.lexsort((j, i, d2))[:k]
     return i[order], j[order], d2[order]
+
+
+# ---------------------------------------------------------------- non-periodic neighbour list
+def nonperiodic_box(x, cutoff, y=None):
+    """The bounding box of the paper's non-periodic neighbour list (section
+    4.1: a box from the extrema of the points, large enough that no periodic
+    image comes within the cutoff): orthorhombic, side (max - min) + 1.000001
+    cutoff along each axis over both sets.  Every image of a displacement is
+    then farther than the cutoff, so the canonical periodic pair set is the
+    set of Euclidean distances <= cutoff."""
+    pts = _f64(x) if y is None else np.vstack([_f64(x), _f64(y)])
+    lo, hi = pts.min(axis=0), pts.max(axis=0)
+    return np.diag((hi - lo) + 1.000001 * float(cutoff))
+
+
+def neighbor_list_nonperiodic(x, cutoff, y=None, nthreads=0):
+    """Pairs within the cutoff without periodic boundaries (paper section 4.1):
+    the canonical pair set in ``nonperiodic_box``.  Returns the ``compute``
+    dict (nl_i, nl_j, nl_d, nl_d2, count)."""
+    H = nonperiodic_box(x, cutoff, y)
+    return compute(x, H, cutoff, y, nl=True, nthreads=nthreads)

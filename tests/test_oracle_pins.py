@@ -610,3 +610,33 @@ def test_kclosest_ties_go_by_index_and_short_lists():
     # single set: unordered pairs i < j
     i, j, d2 = oracle.kclosest(y, H, 0.13, 3)
     assert np.all(i < j) and np.all(np.diff(d2) >= 0)
+
+
+# ---------------------------------------------------------------- non-periodic neighbour list (section 4.1)
+@pytest.mark.parametrize("offset", [0.0, -37.5, 1000.0])
+def test_nonperiodic_list_is_the_euclidean_pair_set(offset):
+    """Two disjoint sets at water-like density (100 per nm^3, cutoff 1.2 nm):
+    the bounding-box computation equals a plain Euclidean enumeration with
+    no images, wherever the cloud sits."""
+    g = W.rng(91)
+    y = offset + 2.5 * g.random((2500, 3))          # 100 per nm^3 in a 2.5 nm cube
+    x = offset + 0.6 + 1.3 * g.random((220, 3))     # a smaller set inside it
+    r = oracle.neighbor_list_nonperiodic(x, 1.2, y=y)
+    D = y[None, :, :] - x[:, None, :]
+    e2 = (D[..., 0] * D[..., 0] + D[..., 1] * D[..., 1]) + D[..., 2] * D[..., 2]
+    ii, jj = np.nonzero(e2 <= 1.2 * 1.2)
+    assert r["count"] == len(ii) > 10000
+    assert np.array_equal(r["nl_i"], ii) and np.array_equal(r["nl_j"], jj)
+    assert np.abs(r["nl_d2"] - e2[ii, jj]).max() <= 1e-13 * (1.0 + abs(offset))
+    # single set: i < j, the same on the Euclidean side
+    r1 = oracle.neighbor_list_nonperiodic(x, 1.2)
+    D1 = x[None, :, :] - x[:, None, :]
+    f2 = (D1[..., 0] * D1[..., 0] + D1[..., 1] * D1[..., 1]) + D1[..., 2] * D1[..., 2]
+    a, b = np.nonzero(np.triu(f2 <= 1.2 * 1.2, k=1))
+    assert np.array_equal(r1["nl_i"], a) and np.array_equal(r1["nl_j"], b)
+
+
+def test_nonperiodic_box_sides():
+    x = np.array([[0.0, -1.0, 2.0], [3.0, 4.0, 2.5]])
+    H = oracle.nonperiodic_box(x, 1.0)
+    assert np.allclose(np.diag(H), [3.0 + 1.000001, 5.0 + 1.000001, 0.5 + 1.000001], rtol=0, atol=1e-15)
