@@ -170,7 +170,23 @@ clm_status clm_box_create(int dim, const double* H, double cutoff, int lcell, cl
  * row axis packs more particles into each work tile of whole cells. */
 clm_status clm_box_create_ex(int dim, const double* H, double cutoff, int lcell, int lcell_x,
                              clm_box** out);
-/* Triclinic box from lengths (a, b, c) and angles in degrees (alpha =
+/* Bounding box of a NON-periodic computation (paper section 4.1: the
+ * extrema of the points set a box large enough to avoid periodic
+ * interactions within the cutoff): orthorhombic, side (hi[a] - lo[a]) +
+ * 1.000001 * cutoff along each axis a, with lo/hi the coordinate extrema over
+ * every set (clm_extrema).  Every periodic image of a displacement between
+ * points inside [lo, hi] is then farther than the cutoff, so the canonical
+ * pair set of this box is the set of pairs whose Euclidean distance is
+ * <= cutoff.  Errors: CLM_E_BAD_BOX (non-finite or lo > hi), as clm_box_create. */
+clm_status clm_box_nonperiodic(int dim, const double* lo, const double* hi, double cutoff, int lcell,
+                               clm_box** out);
+/* Coordinate extrema of n >= 1 points (n x dim FP64, device): lo[a] = min,
+ * hi[a] = max over the points (host arrays of dim doubles).  Synchronizes
+ * the context's stream.  Workspace: clm_extrema_workspace_bytes. */
+clm_status clm_extrema_workspace_bytes(int64_t n, size_t* bytes);
+clm_status clm_extrema(clm_context* ctx, int dim, const double* x_dev, int64_t n, void* workspace_dev,
+                       size_t workspace_bytes, double* lo, double* hi);
+/* Triclinic box from lengths (a, b, c) and angles in degrees (alpha =/* Triclinic box from lengths (a, b, c) and angles in degrees (alpha =
  * angle(b,c), beta = angle(a,c), gamma = angle(a,b)); a along x, b in xy. */
 clm_status clm_box_from_lengths_angles(const double* lengths, const double* angles_deg,
                                        double cutoff, int lcell, clm_box** out);

@@ -16,7 +16,8 @@ import torch
 from . import _lib as L
 from ._lib import ClmError
 
-__all__ = ["Box", "CellList", "LJEnergy", "lj_energy", "ClmError"]
+__all__ = ["Box", "CellList", "LJEnergy", "lj_energy", "ClmError", "extrema",
+           "neighbor_list_nonperiodic"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -90,6 +91,25 @@ class Box:
         b._h = h
         info = b.info()
         b.dim = 3
+        b.H = np.array(info["H"])
+        b.cutoff = float(cutoff)
+        b.lcell_requested = int(lcell)
+        return b
+
+    @classmethod
+    def nonperiodic(cls, lo, hi, cutoff, lcell=2):
+        """Bounding box of a non-periodic computation (paper section 4.1):
+        side (hi - lo) + 1.000001 cutoff per axis, so that no periodic image
+        comes within the cutoff."""
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        h = ctypes.c_void_p()
+        L.check(L.lib().clm_box_nonperiodic(len(lo), lo.ctypes.data_as(_dp), hi.ctypes.data_as(_dp),
+                                            float(cutoff), int(lcell), ctypes.byref(h)))
+        b = cls.__new__(cls)
+        b._h = h
+        info = b.info()
+        b.dim = info["dim"]
         b.H = np.array(info["H"])
         b.cutoff = float(cutoff)
         b.lcell_requested = int(lcell)
@@ -317,6 +337,45 @@ class CellList:
             if n <= cap:
                 return pairs[:n], (dist[:n] if distances else None)
             cap = n
+
+
+# ---------------------------------------------------------------- non-periodic neighbour list
+def extrema(x):
+    """Per-axis minima and maxima of device coordinates (n, dim), computed by
+    the library's reduction kernels (synchronizes)."""
+    x = _as_coords(x, x.shape[1] if x.ndim == 2 else -1, "x")
+    n, dim = x.shape
+    nbytes = ctypes.c_size_t(0)
+    L.check(L.lib().clm_extrema_workspace_bytes(n, ctypes.byref(nbytes)))
+    raw = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=x.device)
+    pad = (-raw.data_ptr()) % 256
+    lo, hi = np.zeros(dim), np.zeros(dim)
+    L.check(L.lib().clm_extrema(_context(x.device), dim, _ptr(x), n, ctypes.c_void_p(raw.data_ptr() + pad),
+                                int(nbytes.value), lo.ctypes.data_as(_dp), hi.ctypes.data_as(_dp)))
+    return lo, hi
+
+
+def neighbor_list_nonperiodic(x, cutoff, y=None, lcell=2, precision="fp32", distances=True,
+                              capacity=None):
+    """Pairs within the cutoff without periodic boundaries (paper section 4.1):
+    the extrema of the points set a bounding box large enough that no periodic
+    image comes within the cutoff (``Box.nonperiodic``), then the cell list
+    of one set (or of x and y) and the neighbour-list map.  Returns the pairs
+    (int32, (m, 2); single set i < j) and, with ``distances``, d (float64)."""
+    lo, hi = extrema(x)
+    if y is not None:
+        lo2, hi2 = extrema(y)
+        lo, hi = np.minimum(lo, lo2), np.maximum(hi, hi2)
+    box = Box.nonperiodic(lo, hi, cutoff, lcell)
+    cl = CellList(x, box, y=y, precision=precision)
+    if capacity is None:
+        # ideal-gas estimate over the bounding box of the partner set
+        vol = float(np.prod(np.maximum(hi - lo, 1e-300)))
+        ball = 4.0 / 3.0 * np.pi * cutoff ** 3 if box.dim == 3 else np.pi * cutoff ** 2
+        partners = (cl.ny if y is not None else cl.nx) / vol * ball
+        pairs = cl.nx * partners * (1.0 if y is not None else 0.5)
+        capacity = int(1.25 * min(pairs, cl.nx * max(cl.ny, cl.nx))) + 1024
+    return cl.neighbor_list(capacity=capacity, distances=distances)
 
 
 # ---------------------------------------------------------------- autograd

@@ -88,7 +88,7 @@ EXPORTS = [
     "clm_celllist_workspace_bytes", "clm_celllist_create", "clm_celllist_build", "clm_map",
     "clm_celllist_info_get", "clm_celllist_destroy", "clm_synchronize", "clm_last_error",
     "clm_status_string", "clm_context_set_timing", "clm_stats_get", "clm_map_batch_workspace_bytes",
-    "clm_map_batch",
+    "clm_map_batch", "clm_box_nonperiodic", "clm_extrema_workspace_bytes", "clm_extrema",
     # include/clmap_md.h
     "clm_md_workspace_bytes", "clm_md_create", "clm_md_kick_drift", "clm_md_kick", "clm_md_destroy",
     "clm_vlist_workspace_bytes", "clm_vlist_create", "clm_vlist_update", "clm_vlist_lj",
@@ -147,6 +147,9 @@ def lib():
     L.clm_vlist_lj.argtypes = [_vp, c_d, c_d, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.clm_vlist_info_get.argtypes = [_vp, ctypes.POINTER(VlistInfo)]
     L.clm_vlist_destroy.argtypes = [_vp]
+    L.clm_box_nonperiodic.argtypes = [c_int, _dp, _dp, c_d, c_int, pvp]
+    L.clm_extrema_workspace_bytes.argtypes = [c_i64, szp]
+    L.clm_extrema.argtypes = [_vp, c_int, _vp, c_i64, _vp, ctypes.c_size_t, _dp, _dp]
     L.clm_kclosest_workspace_bytes.argtypes = [_vp, c_i64, c_i64, szp]
     L.clm_kclosest.argtypes = [_vp, c_i64, c_i64, _vp, ctypes.c_size_t, _vp, _vp, _vp,
                                ctypes.POINTER(c_i64)]

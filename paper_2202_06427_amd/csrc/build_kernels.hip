@@ -334,6 +334,50 @@ __global__ void __launch_bounds__(256) gather_vel_kernel(const double* __restric
   if ((threadIdx.x & (kWave - 1)) == 0 && m > 0.0f) atomicMax(vmax_bits, __float_as_uint(m));
 }
 
+// ---------------------------------------------------------------- extrema
+// Per-block minima and maxima of each coordinate (grid stride, at most
+// kExtremaBlocks blocks), then one block combines them: the bounding box of
+// a non-periodic computation (paper section 4.1).
+__global__ void __launch_bounds__(256) extrema_kernel(const double* __restrict__ x, int64_t n, int dim,
+                                                      double* __restrict__ part) {
+  const double inf = __longlong_as_double(0x7ff0000000000000ll);
+  double lo[3] = {inf, inf, inf}, hi[3] = {-inf, -inf, -inf};
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    for (int a = 0; a < dim; ++a) {
+      const double v = x[i * dim + a];
+      lo[a] = fmin(lo[a], v);
+      hi[a] = fmax(hi[a], v);
+    }
+  __shared__ double red[4][6];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int a = 0; a < 3; ++a) {
+    double l = lo[a], h = hi[a];
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      l = fmin(l, __shfl_xor(l, d, kWave));
+      h = fmax(h, __shfl_xor(h, d, kWave));
+    }
+    if (lane == 0) {
+      red[w][a] = l;
+      red[w][3 + a] = h;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double v = red[0][threadIdx.x];
+    for (int q = 1; q < 4; ++q) v = threadIdx.x < 3 ? fmin(v, red[q][threadIdx.x]) : fmax(v, red[q][threadIdx.x]);
+    part[blockIdx.x * 6 + threadIdx.x] = v;
+  }
+}
+
+__global__ void __launch_bounds__(64) extrema_final_kernel(const double* __restrict__ part, int nb,
+                                                           double* __restrict__ out) {
+  if (threadIdx.x >= 6) return;
+  double v = part[threadIdx.x];
+  for (int b = 1; b < nb; ++b)
+    v = threadIdx.x < 3 ? fmin(v, part[b * 6 + threadIdx.x]) : fmax(v, part[b * 6 + threadIdx.x]);
+  out[threadIdx.x] = v;
+}
+
 // ---------------------------------------------------------------- launchers
 static inline unsigned grid_for(size_t n, int block) {
   size_t g = (n + block - 1) / block;
@@ -395,6 +439,20 @@ hipError_t launch_tiles(const uint32_t* off, const TileGeom& g, uint32_t* row_ti
   hipError_t e = launch_scan(row_tiles, g.nrows, scan_scratch, row_off, s, gate);
   if (e != hipSuccess) return e;
   tiles_emit_kernel<<<nb, 256, 0, s>>>(off, g, row_off, tiles, gate);
+  return hipGetLastError();
+}
+
+int extrema_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > kExtremaBlocks ? kExtremaBlocks : b));
+}
+
+hipError_t launch_extrema(const double* x, int64_t n, int dim, double* part, double* out, hipStream_t s) {
+  const int nb = extrema_blocks(n);
+  extrema_kernel<<<nb, 256, 0, s>>>(x, n, dim, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  extrema_final_kernel<<<1, 64, 0, s>>>(part, nb, out);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -422,6 +423,51 @@ clm_status clm_box_from_lengths_angles(const double* len, const double* deg, dou
     H[r * 3 + 2] = c[r];
   }
   return clm_box_create(3, H, cutoff, lcell, out);
+}
+
+clm_status clm_box_nonperiodic(int dim, const double* lo, const double* hi, double cutoff, int lcell,
+                               clm_box** out) {
+  if (dim != 2 && dim != 3) return fail(CLM_E_BAD_BOX, "dim must be 2 or 3 (got %d)", dim);
+  if (!lo || !hi || !out) return fail(CLM_E_INVALID_ARG, "lo, hi or out is NULL");
+  if (!(cutoff > 0.0) || !std::isfinite(cutoff))
+    return fail(CLM_E_BAD_CUTOFF, "cutoff must be finite and > 0");
+  double H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < dim; ++a) {
+    if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(lo[a] <= hi[a]))
+      return fail(CLM_E_BAD_BOX, "extrema must be finite with lo <= hi (axis %d)", a);
+    // every periodic image of a displacement is then farther than the cutoff
+    H[a * dim + a] = (hi[a] - lo[a]) + 1.000001 * cutoff;
+  }
+  return clm_box_create(dim, H, cutoff, lcell, out);
+}
+
+clm_status clm_extrema_workspace_bytes(int64_t n, size_t* bytes) {
+  if (!bytes) return fail(CLM_E_INVALID_ARG, "bytes is NULL");
+  if (n < 1) return fail(CLM_E_INVALID_ARG, "n must be >= 1");
+  *bytes = sizeof(double) * (6 * (size_t)kExtremaBlocks + 8);
+  return CLM_OK;
+}
+
+clm_status clm_extrema(clm_context* ctx, int dim, const double* x, int64_t n, void* ws, size_t ws_bytes,
+                       double* lo, double* hi) {
+  if (!ctx || !x || !lo || !hi) return fail(CLM_E_INVALID_ARG, "an argument is NULL");
+  if (dim != 2 && dim != 3) return fail(CLM_E_INVALID_ARG, "dim must be 2 or 3");
+  if (n < 1) return fail(CLM_E_INVALID_ARG, "n must be >= 1");
+  const size_t need = sizeof(double) * (6 * (size_t)kExtremaBlocks + 8);
+  if (!ws || ws_bytes < need) return fail(CLM_E_WORKSPACE, "workspace needs %zu bytes", need);
+  if (((uintptr_t)ws & 255u) != 0) return fail(CLM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  CLM_HIP(hipSetDevice(ctx->device));
+  double* part = (double*)ws;
+  double* res = part + 6 * kExtremaBlocks;
+  CLM_HIP(launch_extrema(x, n, dim, part, res, ctx->stream));
+  double h[6];
+  CLM_HIP(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+  CLM_HIP(hipStreamSynchronize(ctx->stream));
+  for (int a = 0; a < dim; ++a) {
+    lo[a] = h[a];
+    hi[a] = h[3 + a];
+  }
+  return CLM_OK;
 }
 
 clm_status clm_box_info_get(const clm_box* B, clm_box_info* o) {

@@ -286,6 +286,10 @@ hipError_t launch_scatter(const double* x, int n, const BuildGeom& g, const uint
 hipError_t launch_tiles(const uint32_t* off, const TileGeom& g, uint32_t* row_tiles,
                         uint32_t* row_off, uint32_t* scan_scratch, Tile* tiles, hipStream_t s,
                         const uint32_t* gate = nullptr);
+constexpr int kExtremaBlocks = 512;
+int extrema_blocks(int64_t n);
+// lo (3) and hi (3) of the coordinates into out[0..5]; part: kExtremaBlocks * 6 doubles
+hipError_t launch_extrema(const double* x, int64_t n, int dim, double* part, double* out, hipStream_t s);
 hipError_t launch_gather_vel(const double* v, int dim, const uint32_t* idx, int n, float4* v32,
                              unsigned int* vmax_bits, hipStream_t s);
 hipError_t launch_set_job(const JobDesc& jd, JobDesc* dst, hipStream_t s);

@@ -186,3 +186,18 @@ def neon_fluid(n, seed=6, jitter=0.02):
     v -= v.mean(axis=0)
     return {"name": f"neon-{n}-rho100-rc1.2", "x": np.ascontiguousarray(x),
             "v": np.ascontiguousarray(v), "H": np.diag([side] * 3), **NEON}
+
+
+def e1_sets(n_small, n_large=1_000_000, seed=9, density=100.0):
+    """The neighbour-list benchmark of the paper's section 4.1: two disjoint
+    sets at 100 particles per nm^3 (cutoff 1.2 nm) without periodic
+    boundaries: n_large points uniform in a cube of side (n_large /
+    density)^(1/3) nm and n_small points uniform in a cube of side
+    (n_small / density)^(1/3) nm centred in it."""
+    g = rng(seed)
+    big = (n_large / density) ** (1.0 / 3.0)
+    small = (n_small / density) ** (1.0 / 3.0)
+    y = big * g.random((n_large, 3))
+    x = 0.5 * (big - small) + small * g.random((n_small, 3))
+    return {"name": f"e1-{n_small}-vs-{n_large}-rho100-rc1.2-nonperiodic", "x": x, "y": y,
+            "cutoff": 1.2}
