@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--md-steps", type=int, default=200,
                     help="velocity-Verlet steps per Neon MD case (0: skip the MD section)")
     ap.add_argument("--kclosest", type=int, default=1, help="0: skip the k-closest-pairs section")
+    ap.add_argument("--nonperiodic", type=int, default=1, help="0: skip the non-periodic list section")
     ap.add_argument("--md-only", type=int, default=0, metavar="N",
                     help="run only --steps Verlet-list MD steps of N Neon atoms (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -263,6 +264,31 @@ def kclosest_cases(reps=5):
     return out
 
 
+def nonperiodic_cases(reps=5):
+    """The neighbour-list benchmark of section 4.1: pairs within 1.2 nm
+    between a set of 10..10^5 particles and one of 10^6 (100 per nm^3, no
+    periodic boundaries).  Whole call (extrema, bounding box, cell lists of
+    both sets, list with distances), FP32+guard, host clock."""
+    import time
+    import torch
+    import paper_2202_06427_amd as clm
+    import workloads as W
+    out = {}
+    for n_small in (10, 100, 1000, 10_000, 100_000):
+        w = W.e1_sets(n_small)
+        x = torch.from_numpy(w["x"]).to("cuda:0")
+        y = torch.from_numpy(w["y"]).to("cuda:0")
+        pairs, _ = clm.neighbor_list_nonperiodic(x, w["cutoff"], y=y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pairs, _ = clm.neighbor_list_nonperiodic(x, w["cutoff"], y=y)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[str(n_small)] = {"ms": 1e3 * dt, "pairs": int(pairs.shape[0]), "pairs_per_s": pairs.shape[0] / dt}
+    return {"workload": "e1 sets vs 10^6 (section 4.1), rc 1.2, 100/nm^3, non-periodic", "points": out}
+
+
 def md_only(n, steps):
     """Verlet-list MD of n Neon atoms (skin 0.1 nm) for `steps` steps."""
     import torch
@@ -398,6 +424,10 @@ def main():
         log("k closest pairs ...")
         line["kclosest"] = kclosest_cases()
         log(f"kclosest: {line['kclosest']}")
+    if args.nonperiodic:
+        log("non-periodic neighbour lists ...")
+        line["nonperiodic_nl"] = nonperiodic_cases()
+        log(f"nonperiodic: {line['nonperiodic_nl']}")
     if not args.no_cpu_baseline:
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
         log(f"cpu baseline: oracle on the full workload with {nth} threads ...")
