@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 W_COUNT, W_SUM_D, W_SUM_INV_D, W_LJ, W_HIST_DIST, W_HIST_REL, W_NL = 1, 2, 4, 8, 16, 32, 64
+W_SUM_W_INV_D, W_HIST_DIST_VEL = 128, 256
 METHOD_AUTO, METHOD_BRUTE, METHOD_CELLS = -1, 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -34,7 +35,8 @@ class _Request(ctypes.Structure):
         ("hist_nbins", ctypes.c_int), ("hist_hi", ctypes.c_double),
         ("rel_nbins", ctypes.c_int), ("rel_hi", ctypes.c_double),
         ("vel_x", _dp), ("vel_y", _dp), ("nl_capacity", ctypes.c_int64),
-        ("frame_x", _i64p),
+        ("frame_x", _i64p), ("weights_x", _dp), ("weights_y", _dp),
+        ("dv_nbins", ctypes.c_int), ("dv_hi", ctypes.c_double),
     ]
 
 
@@ -45,7 +47,7 @@ class _Result(ctypes.Structure):
         ("dEdH", ctypes.c_double * 9), ("lj_grad", _dp), ("hist", _u64p),
         ("rel_hist", _u64p), ("rel_sum", _dp), ("nl_i", _i64p), ("nl_j", _i64p),
         ("nl_d", _dp), ("nl_count", ctypes.c_uint64), ("method_used", ctypes.c_int),
-        ("nl_d2", _dp),
+        ("nl_d2", _dp), ("sum_w_inv_d", ctypes.c_double), ("dv_hist", _u64p), ("dv_sum", _dp),
     ]
 
 
@@ -140,14 +142,17 @@ def pair_d2(xi, xj, H, reach):
 
 def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, lj=None,
             lj_grad=False, hist=None, rel_hist=None, vel_x=None, vel_y=None, nl=False,
-            nl_capacity=None, method=METHOD_AUTO, nthreads=0, frame=None):
+            nl_capacity=None, method=METHOD_AUTO, nthreads=0, frame=None, weights=None,
+            dist_vel_hist=None):
     """Run the oracle; returns a dict of the requested outputs.
 
     lj = (sigma, epsilon); hist = (nbins, hi); rel_hist = (nbins, hi) with
     vel_x (and vel_y for a cross set).  Neighbour-list indices are 0-based,
     sorted by (i, j); single set has i < j.  frame: (nx, dim) integers that
     replace the canonical wrap integers (positions kept in the wrap of an
-    earlier step; single set only).
+    earlier step; single set only).  weights = (w_x, w_y or None): the sum
+    of w_i w_j / d (Code 5).  dist_vel_hist = (nbins, hi) with vel_x (and
+    vel_y): pairs per distance bin and the per-bin sum of |v_j - v_i| (Code 10).
     """
     x = _f64(x)
     H = _f64(H)
@@ -181,6 +186,23 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
             req.vel_y = _p(vy)
     if nl:
         want |= W_NL
+    wx = wy = None
+    if weights is not None:
+        want |= W_SUM_W_INV_D
+        wx = _f64(weights[0])
+        req.weights_x = _p(wx)
+        if yy is not None:
+            wy = _f64(weights[1])
+            req.weights_y = _p(wy)
+    if dist_vel_hist is not None:
+        want |= W_HIST_DIST_VEL
+        req.dv_nbins, req.dv_hi = int(dist_vel_hist[0]), float(dist_vel_hist[1])
+        if vx is None:
+            vx = _f64(vel_x)
+            req.vel_x = _p(vx)
+            if yy is not None:
+                vy = _f64(vel_y)
+                req.vel_y = _p(vy)
     req.want = want
     req.method = method
     req.nthreads = nthreads
@@ -220,7 +242,13 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
         nld = np.zeros(max(cap, 1))
         nld2 = np.zeros(max(cap, 1))
         res.nl_i, res.nl_j, res.nl_d, res.nl_d2 = _p(nli, _i64p), _p(nlj, _i64p), _p(nld), _p(nld2)
-    keep.append((vx, vy, fr))
+    dvh = dvs = None
+    if dist_vel_hist is not None:
+        dvh = np.zeros(req.dv_nbins + 1, dtype=np.uint64)
+        dvs = np.zeros(req.dv_nbins)
+        res.dv_hist = _p(dvh, _u64p)
+        res.dv_sum = _p(dvs)
+    keep.append((vx, vy, fr, wx, wy))
     rc = lib().clmo_compute(dim, _p(H), float(cutoff), _p(x), nx, _p(yy), ny,
                             ctypes.byref(req), ctypes.byref(res))
     _check(rc, "compute")
@@ -235,6 +263,11 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
         out["dEdH"] = np.array(res.dEdH[: dim * dim]).reshape(dim, dim)
         if grad is not None:
             out["lj_grad"] = grad
+    if weights is not None:
+        out["sum_w_inv_d"] = res.sum_w_inv_d
+    if dist_vel_hist is not None:
+        out["dv_hist"] = dvh
+        out["dv_sum"] = dvs
     if hist is not None:
         out["hist"] = h
     if rel_hist is not None:

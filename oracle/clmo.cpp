@@ -255,7 +255,7 @@ struct Pair {
 /* Per-home-cell (or per-particle) partial results. */
 struct Partial {
   uint64_t count = 0;
-  Neumaier sum_d, sum_inv_d, lj;
+  Neumaier sum_d, sum_inv_d, lj, sum_w;
   Neumaier vir[9], dEdH[9];
 };
 
@@ -272,7 +272,9 @@ struct Ctx {
   const double* vy = nullptr;
   std::vector<double> Ehist, Erel;
   /* per-thread integer and list outputs (order-independent or sorted) */
-  std::vector<std::vector<uint64_t>> hist_t, rel_t;
+  std::vector<std::vector<uint64_t>> hist_t, rel_t, dv_t;
+  std::vector<double> Edv;
+  int nrel = 0;                         /* per-unit sums: [0, nrel) relative speed, then distance bins */
   std::vector<std::vector<Pair>> nl_t;
 };
 
@@ -289,6 +291,12 @@ void accumulate(Ctx& C, Partial& P, std::vector<Neumaier>& rel_sum, int tid, int
     if (want & CLMO_W_SUM_D) P.sum_d.add(d);
     if (want & CLMO_W_SUM_INV_D) P.sum_inv_d.add(1.0 / d);
     if (want & CLMO_W_NL) C.nl_t[tid].push_back(Pair{i, j, d, d2});
+  }
+  if (want & CLMO_W_SUM_W_INV_D) {
+    /* Code 5, second example: m_i m_j / d */
+    const double wi = q.weights_x[i];
+    const double wj = C.cross ? q.weights_y[j] : q.weights_x[j];
+    P.sum_w.add((wi * wj) / std::sqrt(d2));
   }
   if (want & CLMO_W_LJ) {
     double x = (q.sigma * q.sigma) / d2;
@@ -317,6 +325,18 @@ void accumulate(Ctx& C, Partial& P, std::vector<Neumaier>& rel_sum, int tid, int
     int b = bin_of(C.Erel, qq);
     C.rel_t[tid][b] += 1;
     if (b < q.rel_nbins) rel_sum[b].add(std::sqrt(qq));
+  }
+  if (want & CLMO_W_HIST_DIST_VEL) {
+    /* Code 10: pairs binned by distance, |v_j - v_i| summed per bin */
+    const double* vi = &C.vx[i * dim];
+    const double* vj = C.cross ? &C.vy[j * dim] : &C.vx[j * dim];
+    double dv[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < dim; ++a) dv[a] = vj[a] - vi[a];
+    double qq = dv[0] * dv[0] + dv[1] * dv[1];
+    if (dim == 3) qq = qq + dv[2] * dv[2];
+    int b = bin_of(C.Edv, d2);
+    C.dv_t[tid][b] += 1;
+    if (b < q.dv_nbins) rel_sum[C.nrel + b].add(std::sqrt(qq));
   }
 }
 
@@ -417,6 +437,11 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
   const int want = req->want;
   if ((want & CLMO_W_LJ) && res->lj_grad && cross) return CLMO_EINVAL;
   if (req->frame_x && cross) return CLMO_EINVAL;
+  if ((want & CLMO_W_SUM_W_INV_D) && (!req->weights_x || (cross && !req->weights_y))) return CLMO_EINVAL;
+  if ((want & CLMO_W_HIST_DIST_VEL) &&
+      (req->dv_nbins < 1 || !(req->dv_hi > 0) || !res->dv_hist || !res->dv_sum || !req->vel_x ||
+       (cross && !req->vel_y)))
+    return CLMO_EINVAL;
   if ((want & CLMO_W_HIST_DIST) && (req->hist_nbins < 1 || !(req->hist_hi > 0) || !res->hist))
     return CLMO_EINVAL;
   if ((want & CLMO_W_HIST_REL) &&
@@ -460,6 +485,8 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
   if (want & CLMO_W_HIST_DIST)
     C.Ehist = edges(req->hist_nbins, req->hist_hi, req->hist_hi == cutoff, B.rc2);
   if (want & CLMO_W_HIST_REL) C.Erel = edges(req->rel_nbins, req->rel_hi, false, 0.0);
+  if (want & CLMO_W_HIST_DIST_VEL) C.Edv = edges(req->dv_nbins, req->dv_hi, req->dv_hi == cutoff, B.rc2);
+  C.dv_t.assign(nthreads, std::vector<uint64_t>((want & CLMO_W_HIST_DIST_VEL) ? req->dv_nbins + 1 : 0, 0));
   C.hist_t.assign(nthreads, std::vector<uint64_t>((want & CLMO_W_HIST_DIST) ? req->hist_nbins + 1 : 0, 0));
   C.rel_t.assign(nthreads, std::vector<uint64_t>((want & CLMO_W_HIST_REL) ? req->rel_nbins + 1 : 0, 0));
   C.nl_t.assign(nthreads, std::vector<Pair>());
@@ -467,7 +494,9 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
   const double* yw = cross ? C.yw.data() : C.xw.data();
   const double* fy = cross ? C.fy.data() : C.fx.data();
   const int64_t nyy = C.ny;
-  const int nrel = (want & CLMO_W_HIST_REL) ? req->rel_nbins : 0;
+  C.nrel = (want & CLMO_W_HIST_REL) ? req->rel_nbins : 0;
+  const int ndv = (want & CLMO_W_HIST_DIST_VEL) ? req->dv_nbins : 0;
+  const int nrel = C.nrel + ndv;  /* per-unit FP64 sums of both histograms */
   double* grad = ((want & CLMO_W_LJ) && !cross) ? res->lj_grad : nullptr;
   if (grad) std::memset(grad, 0, sizeof(double) * nx * dim);
 
@@ -569,13 +598,14 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
 
   /* fixed-order combination */
   uint64_t count = 0;
-  Neumaier sd, sid, lj, vir[9], dh[9];
+  Neumaier sd, sid, lj, sw, vir[9], dh[9];
   std::vector<Neumaier> rs(nrel);
   for (size_t u = 0; u < partial.size(); ++u) {
     const Partial& P = partial[u];
     count += P.count;
     sd.add(P.sum_d.value());
     sid.add(P.sum_inv_d.value());
+    sw.add(P.sum_w.value());
     lj.add(P.lj.value());
     for (int k = 0; k < 9; ++k) {
       vir[k].add(P.vir[k].value());
@@ -586,6 +616,7 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
   res->count = count;
   res->sum_d = sd.value();
   res->sum_inv_d = sid.value();
+  res->sum_w_inv_d = sw.value();
   res->lj_energy = lj.value();
   for (int k = 0; k < 9; ++k) {
     res->virial[k] = vir[k].value();
@@ -604,7 +635,15 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
       for (int t = 0; t < nthreads; ++t) s += C.rel_t[t][b];
       res->rel_hist[b] = s;
     }
-    for (int b = 0; b < nrel; ++b) res->rel_sum[b] = rs[b].value();
+    for (int b = 0; b < C.nrel; ++b) res->rel_sum[b] = rs[b].value();
+  }
+  if (want & CLMO_W_HIST_DIST_VEL) {
+    for (int b = 0; b <= req->dv_nbins; ++b) {
+      uint64_t s = 0;
+      for (int t = 0; t < nthreads; ++t) s += C.dv_t[t][b];
+      res->dv_hist[b] = s;
+    }
+    for (int b = 0; b < ndv; ++b) res->dv_sum[b] = rs[C.nrel + b].value();
   }
   res->nl_count = 0;
   if (want & CLMO_W_NL) {

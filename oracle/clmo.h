@@ -70,6 +70,8 @@ extern "C" {
 #define CLMO_W_HIST_DIST 16  /* distance histogram */
 #define CLMO_W_HIST_REL 32   /* relative-speed histogram (+ per-bin sums) */
 #define CLMO_W_NL 64         /* neighbour list (sorted) */
+#define CLMO_W_SUM_W_INV_D 128    /* sum of w_i w_j / d (Code 5, masses) */
+#define CLMO_W_HIST_DIST_VEL 256  /* distance histogram with per-bin sum of |v_j - v_i| (Code 10) */
 
 #define CLMO_METHOD_AUTO (-1)
 #define CLMO_METHOD_BRUTE 0
@@ -86,6 +88,9 @@ typedef struct clmo_request {
   const double* vel_y;            /* ny*dim velocities of the cross set */
   int64_t nl_capacity;            /* entries available in nl_i/nl_j/nl_d */
   const int64_t* frame_x;         /* nx*dim frame integers w'' (single set), or NULL */
+  const double* weights_x;        /* nx weights (SUM_W_INV_D) */
+  const double* weights_y;        /* ny weights of the cross set */
+  int dv_nbins; double dv_hi;     /* HIST_DIST_VEL: distance bins on (0, dv_hi], velocities vel_x/y */
 } clmo_request;
 
 typedef struct clmo_result {
@@ -104,6 +109,9 @@ typedef struct clmo_result {
   uint64_t nl_count;       /* true number of pairs (may exceed capacity) */
   int method_used;
   double* nl_d2;           /* squared distances d2 of the listed pairs (may be NULL) */
+  double sum_w_inv_d;      /* sum of w_i w_j / d */
+  uint64_t* dv_hist;       /* caller-owned dv_nbins+1: pairs per distance bin (last = overflow) */
+  double* dv_sum;          /* caller-owned dv_nbins: per distance bin, sum of |v_j - v_i| */
 } clmo_result;
 
 /* Box geometry per the definitions above.  widths = perpendicular widths

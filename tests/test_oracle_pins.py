@@ -640,3 +640,52 @@ def test_nonperiodic_box_sides():
     x = np.array([[0.0, -1.0, 2.0], [3.0, 4.0, 2.5]])
     H = oracle.nonperiodic_box(x, 1.0)
     assert np.allclose(np.diag(H), [3.0 + 1.000001, 5.0 + 1.000001, 0.5 + 1.000001], rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- weighted maps (Code 5 masses, Code 10)
+def test_weighted_inverse_distance_sum():
+    """Code 5's second example, sum of m_i m_j / d: unit weights give the sum
+    of 1/d bit for bit, a constant weight c gives c^2 times it, and a small
+    case matches an exhaustive enumeration over the 27 images."""
+    H = BOXES["tric3"]
+    x = W.uniform_in_box(1500, H, 95)
+    rc = 4.0
+    r1 = oracle.compute(x, H, rc, sum_inv_d=True, weights=(np.ones(len(x)), None))
+    assert r1["sum_w_inv_d"] == r1["sum_inv_d"]
+    r3 = oracle.compute(x, H, rc, weights=(np.full(len(x), 3.0), None))
+    assert abs(r3["sum_w_inv_d"] / (9.0 * r1["sum_inv_d"]) - 1) < 1e-14
+    # exhaustive, cross set in an orthorhombic box
+    Ho = BOXES["ortho3"]
+    xa, ya = W.uniform_in_box(60, Ho, 96), W.uniform_in_box(300, Ho, 97)
+    wa, wb = W.rng(98).random(60), W.rng(99).random(300)
+    r = oracle.compute(xa, Ho, 6.0, ya, weights=(wa, wb))
+    s = 0.0
+    for i in range(60):
+        for j in range(300):
+            d2 = exhaustive_d2(xa[i], ya[j], Ho, kmax=1)
+            if d2 <= 36.0:
+                s += wa[i] * wb[j] / math.sqrt(d2)
+    assert abs(r["sum_w_inv_d"] / s - 1) < 1e-12
+
+
+def test_distance_binned_relative_speed():
+    """Code 10: pairs binned by distance with |v_j - v_i| summed per bin.  The
+    counts are the plain distance histogram's; the sums match an exhaustive
+    enumeration; equal velocities give zero sums."""
+    H = BOXES["cube3"]
+    x = W.uniform_in_box(500, H, 100)
+    v = W.rng(101).normal(size=x.shape)
+    rc = 5.0
+    r = oracle.compute(x, H, rc, hist=(10, rc), dist_vel_hist=(10, rc), vel_x=v)
+    assert np.array_equal(r["dv_hist"], r["hist"])
+    sums = np.zeros(10)
+    h = rc / 10
+    for i in range(len(x)):
+        for j in range(i + 1, len(x)):
+            d2 = exhaustive_d2(x[i], x[j], H, kmax=1)
+            if d2 <= rc * rc:
+                b = min(int(math.ceil(math.sqrt(d2) / h)) - 1, 9) if d2 > 0 else 0
+                sums[b] += np.linalg.norm(v[j] - v[i])
+    assert np.allclose(r["dv_sum"], sums, rtol=1e-12, atol=0)
+    r0 = oracle.compute(x, H, rc, dist_vel_hist=(10, rc), vel_x=np.ones_like(x))
+    assert np.all(r0["dv_sum"] == 0.0)
