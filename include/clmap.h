@@ -84,7 +84,11 @@ typedef enum clm_map_kind {
   CLM_MAP_LJ_ADJOINT = 5,     /* g * dE/dr and g * dE/dH for an upstream g (differentiation, section 3.3) */
   CLM_MAP_HIST_DIST = 6,      /* histogram of d on (0, hi], right-closed bins (Code 10's rule) */
   CLM_MAP_HIST_RELSPEED = 7,  /* histogram of |v_j - v_i| on (0, hi] + per-bin sums (Code 10) */
-  CLM_MAP_NEIGHBOR_LIST = 8   /* compacted list of pairs (i, j[, d]) (section 4.1) */
+  CLM_MAP_NEIGHBOR_LIST = 8,  /* compacted list of pairs (i, j[, d]) (section 4.1) */
+  CLM_MAP_SUM_W_INV_D = 9,    /* sum of w_i w_j / d with per-particle weights (Code 5, masses) */
+  CLM_MAP_HIST_DIST_VEL = 10  /* histogram of d on (0, hi] (Code 10's bins) with the per-bin sum
+                                 of |v_j - v_i| in hist_sums_dev: the mean relative speed
+                                 per distance bin is sums / counts (Code 10) */
 } clm_map_kind;
 
 typedef struct clm_context clm_context;
@@ -131,14 +135,17 @@ typedef struct clm_map_params {
   const double* upstream_dev;   /* LJ_ADJOINT: device pointer to the upstream gradient g (1 double) */
   int nbins;                    /* HIST_*: number of bins (1..1000) */
   double hist_hi;               /* HIST_*: upper edge of the last bin */
-  const double* vel_x_dev;      /* HIST_RELSPEED: velocities of x, n_x*dim FP64 */
-  const double* vel_y_dev;      /* HIST_RELSPEED, cross set: velocities of y */
+  const double* vel_x_dev;      /* HIST_RELSPEED, HIST_DIST_VEL: velocities of x, n_x*dim FP64 */
+  const double* vel_y_dev;      /* the same, cross set: velocities of y */
   int want_sums;                /* HIST_RELSPEED: per-bin FP64 sum of |v_j - v_i| */
   int64_t capacity;             /* NEIGHBOR_LIST: pair slots available in pairs_dev */
   int with_distances;           /* NEIGHBOR_LIST: also write d (FP64) */
   double cutoff;                /* every kind: membership cutoff of this map, 0 < cutoff <=
                                    the box cutoff (0: the box cutoff).  The cell grid stays
                                    the box's; pairs are those with min-image d <= cutoff. */
+  const double* weights_x_dev;  /* SUM_W_INV_D: n_x FP64 weights (caller order); the map copies
+                                   them into the cell list's sorted records */
+  const double* weights_y_dev;  /* SUM_W_INV_D, cross set: n_y weights */
 } clm_map_params;
 
 typedef struct clm_map_out {
@@ -147,7 +154,7 @@ typedef struct clm_map_out {
   double* virial_dev;      /* LJ_EF with want_virial: dim*dim FP64 */
   double* grad_box_dev;    /* LJ_EF: dE/dH, LJ_ADJOINT: g*dE/dH (fixed Cartesian r); dim*dim */
   uint64_t* hist_dev;      /* HIST_*: nbins+1 counts, the last slot counts values above hist_hi */
-  double* hist_sums_dev;   /* HIST_RELSPEED with want_sums: nbins FP64 */
+  double* hist_sums_dev;   /* HIST_RELSPEED with want_sums, HIST_DIST_VEL: nbins FP64 */
   int32_t* pairs_dev;      /* NEIGHBOR_LIST: capacity x 2 (i, j); single set i < j;
                               cross set i indexes x and j indexes y; order unspecified */
   double* dist_dev;        /* NEIGHBOR_LIST with with_distances: capacity FP64 */

@@ -240,6 +240,42 @@ class CellList:
                   L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
         return e, c
 
+    def sum_w_inv_d(self, w, wy=None, cutoff=None):
+        """Sum of w_i w_j / d over the pairs (paper Code 5, with masses as the
+        weights); w (and wy for a cross set) are per-particle device tensors."""
+        w = w.detach().to(device=self.device, dtype=torch.float64).reshape(-1).contiguous()
+        if w.shape[0] != self.nx:
+            raise ValueError("w must have one weight per particle of x")
+        wyy = None
+        if self.cross:
+            if wy is None:
+                raise ValueError("a cross set needs wy")
+            wyy = wy.detach().to(device=self.device, dtype=torch.float64).reshape(-1).contiguous()
+            if wyy.shape[0] != self.ny:
+                raise ValueError("wy must have one weight per particle of y")
+        e, c = self._scalars()
+        P = L.MapParams(cutoff=_rc(cutoff), weights_x_dev=_ptr(w), weights_y_dev=_ptr(wyy))
+        self._map("sum_w_inv_d", P, L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
+        self._keep_w = (w, wyy)
+        return e, c
+
+    def dist_vel_histogram(self, v, nbins, hi=None, vy=None, cutoff=None):
+        """Pairs per distance bin on (0, hi] and, per bin, the sum of
+        |v_j - v_i| (paper Code 10: the mean pairwise speed as a function of
+        distance is sums / counts).  Returns (counts with the overflow slot,
+        sums, pair count)."""
+        rc = self.box.cutoff if cutoff is None else float(cutoff)
+        hi = rc if hi is None else float(hi)
+        vx = _as_coords(v, self.dim, "v")
+        vyy = _as_coords(vy, self.dim, "vy") if self.cross else None
+        h = torch.empty(nbins + 1, dtype=torch.int64, device=self.device)
+        sums = torch.empty(nbins, dtype=torch.float64, device=self.device)
+        _, c = self._scalars()
+        P = L.MapParams(nbins=nbins, hist_hi=hi, vel_x_dev=_ptr(vx), vel_y_dev=_ptr(vyy), cutoff=_rc(cutoff))
+        self._map("hist_dist_vel", P, L.MapOut(hist_dev=_ptr(h), hist_sums_dev=_ptr(sums), count_dev=_ptr(c)))
+        self._keep_v = (vx, vyy)
+        return h, sums, c
+
     def lj_energy(self, sigma, epsilon, near_factor=1.0, cutoff=None):
         """Lennard-Jones energy 4 eps ((s/d)^12 - (s/d)^6) (paper Code 6)."""
         e, c = self._scalars()

@@ -22,7 +22,7 @@ CLM_FP32_GUARD = 1
 # clm_map_kind
 MAP_KINDS = {
     "count": 0, "sum_d": 1, "sum_inv_d": 2, "lj_e": 3, "lj_ef": 4, "lj_adjoint": 5,
-    "hist_dist": 6, "hist_relspeed": 7, "neighbor_list": 8,
+    "hist_dist": 6, "hist_relspeed": 7, "neighbor_list": 8, "sum_w_inv_d": 9, "hist_dist_vel": 10,
 }
 
 _vp = ctypes.c_void_p
@@ -54,7 +54,7 @@ class MapParams(ctypes.Structure):
         ("want_virial", ctypes.c_int), ("upstream_dev", _vp), ("nbins", ctypes.c_int),
         ("hist_hi", ctypes.c_double), ("vel_x_dev", _vp), ("vel_y_dev", _vp),
         ("want_sums", ctypes.c_int), ("capacity", ctypes.c_int64), ("with_distances", ctypes.c_int),
-        ("cutoff", ctypes.c_double),
+        ("cutoff", ctypes.c_double), ("weights_x_dev", _vp), ("weights_y_dev", _vp),
     ]
 
 

@@ -334,6 +334,19 @@ __global__ void __launch_bounds__(256) gather_vel_kernel(const double* __restric
   if ((threadIdx.x & (kWave - 1)) == 0 && m > 0.0f) atomicMax(vmax_bits, __float_as_uint(m));
 }
 
+// Weights of a weighted map into the unused 4th components of the sorted
+// records (FP32 for the FP32 sweep, FP64 for the FP64 sweep and re-tests).
+__global__ void __launch_bounds__(256) gather_weights_kernel(const double* __restrict__ w,
+                                                             const uint32_t* __restrict__ idx, int n,
+                                                             float4* __restrict__ pos,
+                                                             double4* __restrict__ r64) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  const double v = w[idx[s]];
+  pos[s].w = (float)v;
+  r64[s].w = v;
+}
+
 // ---------------------------------------------------------------- extrema
 // Per-block minima and maxima of each coordinate (grid stride, at most
 // kExtremaBlocks blocks), then one block combines them: the bounding box of
@@ -453,6 +466,13 @@ hipError_t launch_extrema(const double* x, int64_t n, int dim, double* part, dou
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   extrema_final_kernel<<<1, 64, 0, s>>>(part, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_weights(const double* w, const uint32_t* idx, int n, float4* pos, double4* r64,
+                                 hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  gather_weights_kernel<<<(n + 255) / 256, 256, 0, s>>>(w, idx, n, pos, r64);
   return hipGetLastError();
 }
 

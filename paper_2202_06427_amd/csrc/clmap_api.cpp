@@ -616,6 +616,8 @@ static int internal_kind(clm_map_kind k) {
     case CLM_MAP_HIST_DIST: return K_HIST_DIST;
     case CLM_MAP_HIST_RELSPEED: return K_HIST_REL;
     case CLM_MAP_NEIGHBOR_LIST: return K_NL;
+    case CLM_MAP_SUM_W_INV_D: return K_SUM_W;
+    case CLM_MAP_HIST_DIST_VEL: return K_HIST_DV;
   }
   return -1;
 }
@@ -680,15 +682,23 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     return fail(CLM_E_INVALID_ARG, "params->upstream_dev is required for LJ_ADJOINT");
   if (ljf && P->want_virial && !O->virial_dev)
     return fail(CLM_E_INVALID_ARG, "want_virial needs out->virial_dev");
-  if ((kind == CLM_MAP_SUM_D || kind == CLM_MAP_SUM_INV_D || lj) && !O->energy_dev)
+  if ((kind == CLM_MAP_SUM_D || kind == CLM_MAP_SUM_INV_D || kind == CLM_MAP_SUM_W_INV_D || lj) &&
+      !O->energy_dev)
     return fail(CLM_E_INVALID_ARG, "out->energy_dev is required");
-  const bool hist = k == K_HIST_DIST || k == K_HIST_REL;
+  if (k == K_SUM_W && (!P->weights_x_dev || (cl->cross && !P->weights_y_dev)))
+    return fail(CLM_E_INVALID_ARG, "SUM_W_INV_D needs weights_x_dev (and weights_y_dev for a cross set)");
+  const bool hist = k == K_HIST_DIST || k == K_HIST_REL || k == K_HIST_DV;
   if (hist) {
     if (P->nbins < 1 || P->nbins > kMaxBins)
       return fail(CLM_E_INVALID_ARG, "nbins must be in 1..%d", kMaxBins);
     if (!(P->hist_hi > 0.0) || !std::isfinite(P->hist_hi))
       return fail(CLM_E_INVALID_ARG, "hist_hi must be finite and > 0");
     if (!O->hist_dev) return fail(CLM_E_INVALID_ARG, "out->hist_dev is required");
+  }
+  if (k == K_HIST_DV) {
+    if (!P->vel_x_dev || (cl->cross && !P->vel_y_dev))
+      return fail(CLM_E_INVALID_ARG, "HIST_DIST_VEL needs velocities");
+    if (!O->hist_sums_dev) return fail(CLM_E_INVALID_ARG, "HIST_DIST_VEL needs hist_sums_dev");
   }
   if (k == K_HIST_REL) {
     if (!P->vel_x_dev || (cl->cross && !P->vel_y_dev))
@@ -738,7 +748,7 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     jd.inv_h = (float)((double)P->nbins / P->hist_hi);
     jd.hist = (unsigned long long*)O->hist_dev;
     jd.hist_sums = O->hist_sums_dev;
-    jd.want_sums = (k == K_HIST_REL && P->want_sums) ? 1 : 0;
+    jd.want_sums = ((k == K_HIST_REL && P->want_sums) || k == K_HIST_DV) ? 1 : 0;
     jd.vel64_x = P->vel_x_dev;
     jd.vel64_y = cl->cross ? P->vel_y_dev : P->vel_x_dev;
   }
@@ -749,7 +759,7 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     jd.capacity = P->capacity;
   }
   if (hist) {
-    const int force_last = (k == K_HIST_DIST && P->hist_hi == rcm) ? 1 : 0;
+    const int force_last = ((k == K_HIST_DIST || k == K_HIST_DV) && P->hist_hi == rcm) ? 1 : 0;
     CLM_HIP(launch_hist_edges(cl->E64, cl->E32, P->nbins, P->hist_hi, force_last, jd.rc2, st));
     CLM_HIP(launch_fill_u64((unsigned long long*)O->hist_dev, (size_t)P->nbins + 1, 0ull, st));
     if (jd.want_sums) CLM_HIP(launch_fill_f64(O->hist_sums_dev, (size_t)P->nbins, 0.0, st));
@@ -760,6 +770,16 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     if (cl->cross)
       CLM_HIP(launch_gather_vel(P->vel_y_dev, dim, cl->Y.idx, (int)cl->ny, cl->Y.vel32, cl->vmax_bits, st));
     CLM_HIP(launch_relspeed_band(cl->vmax_bits, P->hist_hi, dim, cl->bandq, st));
+  }
+  if (k == K_HIST_DV) {
+    CLM_HIP(launch_gather_vel(P->vel_x_dev, dim, cl->X.idx, (int)cl->nx, cl->X.vel32, cl->vmax_bits, st));
+    if (cl->cross)
+      CLM_HIP(launch_gather_vel(P->vel_y_dev, dim, cl->Y.idx, (int)cl->ny, cl->Y.vel32, cl->vmax_bits, st));
+  }
+  if (k == K_SUM_W) {
+    CLM_HIP(launch_gather_weights(P->weights_x_dev, cl->X.idx, (int)cl->nx, cl->X.pos, cl->X.r64, st));
+    if (cl->cross)
+      CLM_HIP(launch_gather_weights(P->weights_y_dev, cl->Y.idx, (int)cl->ny, cl->Y.pos, cl->Y.r64, st));
   }
   if (k == K_NL) CLM_HIP(launch_fill_u64(cl->nl_counter, 1, 0ull, st));
   CLM_HIP(launch_fill_u64(cl->guard, 2, 0ull, st));
@@ -822,7 +842,7 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
     F.nparts = nblocks;
     F.nparts_dev = nullptr;
   } else {
-    const bool hist = k_launch == K_HIST_DIST || k_launch == K_HIST_REL;
+    const bool hist = k_launch == K_HIST_DIST || k_launch == K_HIST_REL || k_launch == K_HIST_DV;
     CLM_HIP(launch_sweep(B.dim, cl->prec == CLM_FP32_GUARD, k_launch, cl->job_dev, cl->tiles,
                          &cl->row_off[cl->nrows], cl->max_tiles, hist ? P->nbins : 0, st));
     F.nparts = cl->max_tiles;
@@ -873,7 +893,8 @@ clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
     if (cls[k]->ctx != ctx) return fail(CLM_E_INVALID_ARG, "all cell lists must share one context");
     if (cls[k]->box.dim != dim || cls[k]->prec != prec)
       return fail(CLM_E_INVALID_ARG, "all cell lists of a batch need the same dim and precision");
-    if ((kind == CLM_MAP_HIST_DIST || kind == CLM_MAP_HIST_RELSPEED) && P[k].nbins != P[0].nbins)
+    if ((kind == CLM_MAP_HIST_DIST || kind == CLM_MAP_HIST_RELSPEED || kind == CLM_MAP_HIST_DIST_VEL) &&
+        P[k].nbins != P[0].nbins)
       return fail(CLM_E_INVALID_ARG, "all histograms of a batch need the same nbins");
   }
   size_t need = 0, o_jobs, o_fin, o_tiles, o_total;

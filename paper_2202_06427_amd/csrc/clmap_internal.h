@@ -38,7 +38,9 @@ enum : int {
 
 enum Kind : int {
   K_COUNT = 0, K_SUM_D = 1, K_SUM_INV_D = 2, K_LJ_E = 3, K_LJ_F = 4, K_LJ_FV = 5,
-  K_HIST_DIST = 6, K_HIST_REL = 7, K_NL = 8
+  K_HIST_DIST = 6, K_HIST_REL = 7, K_NL = 8,
+  K_SUM_W = 9,     // sum of w_i w_j / d (weights in the 4th component of pos / r64)
+  K_HIST_DV = 10   // distance histogram with per-bin sums of |v_j - v_i|
 };
 
 struct Tile {
@@ -124,7 +126,7 @@ __host__ __device__ inline size_t sweep_lds_queue_bytes(int kind, bool fp32) {
 }
 __host__ __device__ inline size_t sweep_lds_per_wave(int kind, int nbins, bool fp32) {
   size_t b = sweep_lds_queue_bytes(kind, fp32);
-  if (kind == K_HIST_DIST || kind == K_HIST_REL)
+  if (kind == K_HIST_DIST || kind == K_HIST_REL || kind == K_HIST_DV)
     b += (size_t)(nbins + 1) * 4 + 8 + (size_t)nbins * 8 + (size_t)(nbins + 1) * 4;
   else if (kind == K_NL)
     b += (size_t)kNLStage * 16 + 16;
@@ -292,6 +294,10 @@ int extrema_blocks(int64_t n);
 hipError_t launch_extrema(const double* x, int64_t n, int dim, double* part, double* out, hipStream_t s);
 hipError_t launch_gather_vel(const double* v, int dim, const uint32_t* idx, int n, float4* v32,
                              unsigned int* vmax_bits, hipStream_t s);
+// Per-particle weights of a weighted map into the sorted records: pos[s].w =
+// (float) w[idx[s]], r64[s].w = w[idx[s]].
+hipError_t launch_gather_weights(const double* w, const uint32_t* idx, int n, float4* pos, double4* r64,
+                                 hipStream_t s);
 hipError_t launch_set_job(const JobDesc& jd, JobDesc* dst, hipStream_t s);
 hipError_t launch_hist_edges(double* E64, float* E32, int nbins, double hi, int force_last,
                              double rc2, hipStream_t s);

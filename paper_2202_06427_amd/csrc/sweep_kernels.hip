@@ -123,10 +123,13 @@ struct Sweep {
   static constexpr bool kLJF = KIND == K_LJ_F || KIND == K_LJ_FV;
   static constexpr bool kVir = KIND == K_LJ_FV;
   static constexpr bool kLJ = KIND == K_LJ_E || kLJF;
-  static constexpr bool kHist = KIND == K_HIST_DIST || KIND == K_HIST_REL;
+  static constexpr bool kDV = KIND == K_HIST_DV;
+  static constexpr bool kHist = KIND == K_HIST_DIST || KIND == K_HIST_REL || kDV;
   static constexpr bool kRel = KIND == K_HIST_REL;
+  static constexpr bool kVel = kRel || kDV;
+  static constexpr bool kW = KIND == K_SUM_W;
   static constexpr bool kNL = KIND == K_NL;
-  static constexpr bool kSum = KIND == K_SUM_D || KIND == K_SUM_INV_D || kLJ;
+  static constexpr bool kSum = KIND == K_SUM_D || KIND == K_SUM_INV_D || kW || kLJ;
 
   // ---- uniform job constants
   const JobDesc* J;
@@ -162,6 +165,7 @@ struct Sweep {
   double ri[3];
   float vi[3];
   double vi64[3];
+  double wi64, wj64;   // weights of the lane's particle and of the candidate (FP64 form)
   double accE;
   double G[3];
   double S[3];       // FP64 form, per visited cell: sum of f_s D (folded into G and B)
@@ -201,10 +205,12 @@ struct Sweep {
       inv_h64 = (double)nbins / ldu(&J->hist_hi);
       E64 = ldu(&J->E64);
     }
-    if constexpr (kRel) {
-      want_sums = ldu(&J->want_sums);
+    if constexpr (kVel) {
       VJ = cross ? ldu(&J->vel32_y) : ldu(&J->vel32_x);
       VJ64 = cross ? ldu(&J->vel64_y) : ldu(&J->vel64_x);
+    }
+    if constexpr (kRel) {
+      want_sums = ldu(&J->want_sums);
       bandh = (float)ldu(ldu(&J->bandq));
     }
     if constexpr (kNL) with_dist = ldu(&J->with_dist);
@@ -277,11 +283,23 @@ struct Sweep {
     nl_emit(a, b, d, g);
   }
 
+  // |v_j - v_i| in FP64 for partner jo (caller index) and the velocity vo of
+  // the particle on the other end (the oracle's operation order)
+  __device__ __forceinline__ double speed64(uint32_t jo, const double* vo) const {
+    double dv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) dv[a] = VJ64[(size_t)jo * DIM + a] - vo[a];
+    double qq = dv[0] * dv[0] + dv[1] * dv[1];
+    if (DIM == 3) qq = qq + dv[2] * dv[2];
+    return sqrt(qq);
+  }
+
   // ---------------- FP64 epilogue for one member pair (canonical d2, D)
   __device__ __forceinline__ void pair64(double d2, const double* D, uint32_t j, bool count_it) {
     if (count_it) cnt_lane += 1;
     if constexpr (KIND == K_SUM_D) accE += sqrt(d2);
     if constexpr (KIND == K_SUM_INV_D) accE += 1.0 / sqrt(d2);
+    if constexpr (kW) accE += (wi64 * wj64) / sqrt(d2);
     if constexpr (kLJ) {
       const double r = rcp64(d2);
       double x = s2 * r;
@@ -309,6 +327,11 @@ struct Sweep {
     if constexpr (KIND == K_HIST_DIST) {
       int k = bin64(E64, nbins, inv_h64, d2);
       atomicAdd(&L.hist[k], 1u);
+    }
+    if constexpr (kDV) {
+      const int k = bin64(E64, nbins, inv_h64, d2);
+      atomicAdd(&L.hist[k], 1u);
+      if (k < nbins) atomicAdd(&L.hsum[k], speed64(ldu(&IDXJ[j]), vi64));
     }
     if constexpr (kRel) {
       uint32_t jo = ldu(&IDXJ[j]);
@@ -365,6 +388,7 @@ struct Sweep {
     if (count_it) cnt_lane += 1;
     if constexpr (KIND == K_SUM_D) accE += sqrt(d2);
     if constexpr (KIND == K_SUM_INV_D) accE += 1.0 / sqrt(d2);
+    if constexpr (kW) accE += (rI.w * rJ.w) / sqrt(d2);
     if constexpr (kLJ) {
       const double r = rcp64(d2);
       const double x = s2 * r;
@@ -395,6 +419,18 @@ struct Sweep {
       }
     }
     if constexpr (KIND == K_HIST_DIST) atomicAdd(&L.hist[bin64(E64, nbins, inv_h64, d2)], 1u);
+    if constexpr (kDV) {
+      const int k = bin64(E64, nbins, inv_h64, d2);
+      atomicAdd(&L.hist[k], 1u);
+      if (k < nbins) {
+        const uint32_t io = ldu(&J->idx_x)[iL];
+        const double* v64 = ldu(&J->vel64_x);
+        double vo[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) vo[a] = v64[(size_t)io * DIM + a];
+        atomicAdd(&L.hsum[k], speed64(IDXJ[j], vo));
+      }
+    }
     if constexpr (kRel) {
       const uint32_t io = ldu(&J->idx_x)[iL];
       const double* v64 = ldu(&J->vel64_x);
@@ -463,9 +499,9 @@ struct Sweep {
     const bool in = __builtin_amdgcn_inverse_ballot_w64(in_m);
     bool spec = false;  // per-lane extra reasons (histogram edges)
     cnt_wave += (unsigned long long)__popcll(in_m);
-    if constexpr (KIND == K_SUM_D || KIND == K_SUM_INV_D) {
+    if constexpr (KIND == K_SUM_D || KIND == K_SUM_INV_D || kW) {
       const float r = __builtin_amdgcn_rsqf(d2);
-      const float term = KIND == K_SUM_D ? d2 * r : r;
+      const float term = KIND == K_SUM_D ? d2 * r : (kW ? pj.w * r : r);
       visE += in ? term : 0.0f;
     } else if constexpr (kLJ) {
       // near2f < lo32: near pairs are members, evaluated in FP64
@@ -510,6 +546,14 @@ struct Sweep {
         if (certain) {
           atomicAdd(&L.hist[k], 1u);
           if (kRel && want_sums && k < nbins) atomicAdd(&L.hsum[k], (double)__builtin_sqrtf(v));
+          if (kDV && k < nbins) {
+            const float4 vj = ldu(&VJ[j]);
+            const float ex = vj.x - vi[0], ey = vj.y - vi[1];
+            const float ez = DIM == 3 ? vj.z - vi[2] : 0.0f;
+            const float qq = DIM == 3 ? __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex))
+                                      : __builtin_fmaf(ey, ey, ex * ex);
+            atomicAdd(&L.hsum[k], (double)__builtin_sqrtf(qq));
+          }
         } else {
           spec = true;
         }
@@ -522,6 +566,7 @@ struct Sweep {
   }
 
   __device__ __forceinline__ void cand64(uint32_t j, const double4& rj, unsigned long long okm) {
+    if constexpr (kW) wj64 = rj.w;
     double D[3];
     D[0] = (rj.x - ri[0]) + t[0];
     D[1] = (rj.y - ri[1]) + t[1];
@@ -589,7 +634,7 @@ struct Sweep {
         loop32<false>(jb, je, 0, visE, g32, w32, kc);
       else
         loop32<true>(jb, je, mode, visE, g32, w32, kc);
-      if constexpr (kSum) accE += kLJF ? 0.5 * (double)visE : (double)visE;
+      if constexpr (kSum) accE += kLJF ? 0.5 * (double)visE : (kW ? wi64 * (double)visE : (double)visE);
       if constexpr (kLJF) {
         double ga[3];
 #pragma unroll
@@ -636,8 +681,9 @@ struct Sweep {
       ri[0] = active ? r.x : 1e100;
       ri[1] = active ? r.y : 1e100;
       ri[2] = active ? r.z : 1e100;
+      if constexpr (kW) wi64 = active ? r.w : 0.0;
     }
-    if constexpr (kRel) {
+    if constexpr (kVel) {
       const float4 v = ldu(&J->vel32_x)[i];
       vi[0] = v.x; vi[1] = v.y; vi[2] = v.z;
       const double* v64 = ldu(&J->vel64_x);
@@ -782,7 +828,7 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
                                                        const Tile* __restrict__ tiles,
                                                        const uint32_t* __restrict__ ntiles_dev) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr bool kHist = KIND == K_HIST_DIST || KIND == K_HIST_REL;
+  constexpr bool kHist = KIND == K_HIST_DIST || KIND == K_HIST_REL || KIND == K_HIST_DV;
   constexpr bool kNL = KIND == K_NL;
   const int lane = (int)__lane_id();
   const int wid = uniform((int)(threadIdx.x / kWave));
@@ -845,7 +891,7 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
     for (int k = lane; k <= nb; k += kWave) {
       const uint32_t c = S.L.hist[k];
       if (c) atomicAdd(&hist[k], (unsigned long long)c);
-      if (KIND == K_HIST_REL && S.want_sums && k < nb) {
+      if (((KIND == K_HIST_REL && S.want_sums) || KIND == K_HIST_DV) && k < nb) {
         const double sm = S.L.hsum[k];
         if (sm != 0.0) atomicAdd(&hsums[k], sm);
       }
@@ -916,7 +962,7 @@ __global__ void __launch_bounds__(64) brute_kernel(const JobDesc* __restrict__ j
     const double4 r = J.r64_x[i];
     const double ri[3] = {r.x, r.y, r.z};
     double vi[3] = {0, 0, 0};
-    if (A.kind == K_HIST_REL)
+    if (A.kind == K_HIST_REL || A.kind == K_HIST_DV)
       for (int a = 0; a < dim; ++a) vi[a] = J.vel64_x[(size_t)io * dim + a];
     const double4* __restrict__ R = A.cross ? J.r64_y : J.r64_x;
     const uint32_t* __restrict__ IX = A.cross ? J.idx_y : J.idx_x;
@@ -935,6 +981,21 @@ __global__ void __launch_bounds__(64) brute_kernel(const JobDesc* __restrict__ j
       switch (A.kind) {
         case K_SUM_D: accE += sqrt(d2); break;
         case K_SUM_INV_D: accE += 1.0 / sqrt(d2); break;
+        case K_SUM_W: accE += (r.w * rr.w) / sqrt(d2); break;
+        case K_HIST_DV: {
+          const int k = bin64(J.E64, J.nbins, (double)J.nbins / J.hist_hi, d2);
+          atomicAdd(&J.hist[k], 1ull);
+          if (k < J.nbins) {
+            const uint32_t jo = IX[j];
+            const double* vv = A.cross ? J.vel64_y : J.vel64_x;
+            double dv[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a) dv[a] = vv[(size_t)jo * dim + a] - vi[a];
+            double qq = dv[0] * dv[0] + dv[1] * dv[1];
+            if (dim == 3) qq = qq + dv[2] * dv[2];
+            atomicAdd(&J.hist_sums[k], sqrt(qq));
+          }
+          break;
+        }
         case K_LJ_E: case K_LJ_F: {
           const double r = rcp64(d2);
           double x = J.s2 * r, x3 = x * x * x;
@@ -1290,6 +1351,8 @@ static hipError_t sweep_dispatch(int kind, dim3 grid, size_t lds, const JobDesc*
     case K_LJ_FV: sweep_kernel<DIM, FP32, K_LJ_FV><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
     case K_HIST_DIST: sweep_kernel<DIM, FP32, K_HIST_DIST><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
     case K_HIST_REL: sweep_kernel<DIM, FP32, K_HIST_REL><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_SUM_W: sweep_kernel<DIM, FP32, K_SUM_W><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_HIST_DV: sweep_kernel<DIM, FP32, K_HIST_DV><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
     case K_NL: sweep_kernel<DIM, FP32, K_NL><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
     default: return hipErrorInvalidValue;
   }
