@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--md-steps", type=int, default=200,
                     help="velocity-Verlet steps per Neon MD case (0: skip the MD section)")
     ap.add_argument("--kclosest", type=int, default=1, help="0: skip the k-closest-pairs section")
+    ap.add_argument("--weighted", type=int, default=1, help="0: skip the weighted-map section")
     ap.add_argument("--nonperiodic", type=int, default=1, help="0: skip the non-periodic list section")
     ap.add_argument("--md-only", type=int, default=0, metavar="N",
                     help="run only --steps Verlet-list MD steps of N Neon atoms (profiling)")
@@ -289,6 +290,48 @@ def nonperiodic_cases(reps=5):
     return {"workload": "e1 sets vs 10^6 (section 4.1), rc 1.2, 100/nm^3, non-periodic", "points": out}
 
 
+def weighted_cases(reps=5):
+    """The weighted maps: sum of m_i m_j / d (Code 5) on the 10^6-particle
+    triclinic workload next to the plain sum of 1/d, and Code 10's
+    distance-binned mean relative speed (10 bins) on the 2D clustered
+    workload (2*10^6 points); FP32+guard, host clock around `reps` maps."""
+    import time
+    import torch
+    import paper_2202_06427_amd as clm
+    import workloads as W
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = f()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) / reps
+
+    out = {}
+    cfg = W.config2()
+    x = torch.from_numpy(cfg["x"]).to("cuda:0")
+    cl = clm.CellList(x, clm.Box(cfg["H"], cfg["cutoff"], 2), precision="fp32")
+    m = torch.from_numpy(W.rng(7).random(x.shape[0]) + 0.5).to("cuda:0")
+    (e, c), dtw = timed(lambda: cl.sum_w_inv_d(m))
+    (_, _), dtu = timed(lambda: cl.sum_inv_d())
+    pairs = int(c.item())
+    out["sum_w_inv_d"] = {"workload": cfg["name"] if "name" in cfg else "uniform-1e6-triclinic-rc12",
+                          "ms": 1e3 * dtw, "pairs_per_s": pairs / dtw, "unweighted_ms": 1e3 * dtu}
+    del cl
+    cfg4 = W.config4()
+    x4 = torch.from_numpy(cfg4["x"]).to("cuda:0")
+    v4 = torch.from_numpy(cfg4["v"]).to("cuda:0")
+    cl4 = clm.CellList(x4, clm.Box(cfg4["H"], cfg4["cutoff"], 2), precision="fp32")
+    (h, sums, c4), dtv = timed(lambda: cl4.dist_vel_histogram(v4, 10))
+    pairs4 = int(c4.item())
+    out["dist_vel_hist"] = {"workload": cfg4["name"] if "name" in cfg4 else "2d-clustered-2e6",
+                            "bins": 10, "ms": 1e3 * dtv, "pairs_per_s": pairs4 / dtv,
+                            "mean_speed_first_bins": (sums[:3] / h[:3].to(torch.float64)).tolist()}
+    return out
+
+
 def md_only(n, steps):
     """Verlet-list MD of n Neon atoms (skin 0.1 nm) for `steps` steps."""
     import torch
@@ -420,6 +463,10 @@ def main():
         log(f"Neon MD: {args.md_steps} steps at 1e4 and 1e5 atoms ...")
         line["md"] = md_cases(args.md_steps)
         log(f"md: {line['md']}")
+    if args.weighted:
+        log("weighted maps ...")
+        line["weighted_maps"] = weighted_cases()
+        log(f"weighted: {line['weighted_maps']}")
     if args.kclosest:
         log("k closest pairs ...")
         line["kclosest"] = kclosest_cases()
