@@ -132,6 +132,16 @@ def test_vlist_row_overflow_is_reported(md):
     assert info["overflow"] == 1 and info["max_row"] > 16
 
 
+def _counts_close(got, ref):
+    """A trajectory driven by FP32 forces is another rounding of the same
+    dynamics (positions agree to ~1e-10 nm), so a pair within that distance
+    of the cutoff may be counted on one side only: per-step pair counts agree
+    to 2 pairs on at most a few steps.  (For given positions the pair set is
+    exact: the per-configuration parity tests.)"""
+    diff = np.abs(got.astype(np.int64) - ref.astype(np.int64))
+    assert diff.max() <= 2 and np.count_nonzero(diff) <= 3, diff
+
+
 def _md_case(n=6000, seed=15):
     w = W.neon_fluid(n, seed=seed)
     ndof = 3 * n - 3
@@ -175,7 +185,7 @@ def test_md_rebuild_mode_fp32_guard(md):
     out = md.run(x, v, w["H"], cutoff=RC, sigma=SIG, epsilon=EPS, mass=w["mass"], dt=w["dt"],
                  nsteps=nsteps, mode="rebuild", rescale_every=10, target_ke=target, precision="fp32")
     torch.cuda.synchronize()
-    assert np.array_equal(out["count"].cpu().numpy(), ref["count"])
+    _counts_close(out["count"].cpu().numpy(), ref["count"])
     E = out["energy"].cpu().numpy()
     assert np.abs(E - ref["energy"]).max() <= 1e-6 * np.abs(ref["energy"]).max()
     assert np.abs(x.cpu().numpy() - ref["x"]).max() < 1e-9
