@@ -81,6 +81,12 @@ def parse():
     ap.add_argument("--nonperiodic", type=int, default=1, help="0: skip the non-periodic list section")
     ap.add_argument("--md-only", type=int, default=0, metavar="N",
                     help="run only --steps Verlet-list MD steps of N Neon atoms (profiling)")
+    ap.add_argument("--calibrate", type=int, default=1,
+                    help="0: skip the measured device rates (FMA loops, copy kernel)")
+    ap.add_argument("--step-samples", type=int, default=20,
+                    help="individually timed steps for the median / min step time (0: skip)")
+    ap.add_argument("--section", choices=["kclosest", "nonperiodic", "weighted"], default=None,
+                    help="run only this section and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -101,7 +107,7 @@ def copy_calibration(mib, reps=4):
                       "copy_calibration_bytes_written_per_copy": n * 4, "copies": reps}), flush=True)
 
 
-def time_steps(clm, cl, xt, steps, warmup, sigma, eps):
+def time_steps(clm, cl, xt, steps, warmup, sigma, eps, samples=0):
     import torch
     for _ in range(warmup):
         cl.build(xt)
@@ -121,7 +127,20 @@ def time_steps(clm, cl, xt, steps, warmup, sigma, eps):
     wall = time.perf_counter() - t0
     st = clm.stats(reset=True)
     clm.set_timing(False)
+    per_step = []
+    for _ in range(samples):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cl.build(xt)
+        cl.lj_forces(sigma, eps)
+        e1.record()
+        e1.synchronize()
+        per_step.append(e0.elapsed_time(e1))
+    per_step.sort()
     return {
+        "step_ms_median": per_step[len(per_step) // 2] if per_step else None,
+        "step_ms_min": per_step[0] if per_step else None,
         "ms_per_step": ev0.elapsed_time(ev1) / steps,
         "wall_ms_per_step": 1e3 * wall / steps,
         "sweep_ms": st["sweep_ms"] / max(st["sweeps"], 1),
@@ -347,6 +366,37 @@ def md_only(n, steps):
     print(json.dumps({"md_only": w["name"], "steps": steps, **r["list"].info()}), flush=True)
 
 
+def measured_peaks(clm):
+    """Device rates measured by the library's microbenchmarks (FMA chains
+    without packed FP32, FP64 FMA chains, a 1 GiB device copy)."""
+    out = {}
+    for kind, key in (("fma_f32", "valu_fp32_tflops"), ("fma_f64", "valu_fp64_tflops"),
+                      ("copy", "copy_GBs")):
+        ms, work, rate = clm.calibrate(kind, nbytes=1 << 30, reps=10)
+        out[key] = rate
+        out[key.rsplit("_", 1)[0] + "_ms"] = ms
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def per_core_sample(W):
+    """The headline density (10^6 particles per 215.4-box) in a box of half
+    the lattice-vector lengths: 125,000 particles, the same angles, cutoff and
+    LJ parameters, for the oracle on one thread."""
+    H = 0.5 * W.triclinic_h(W.CFG2_LENGTHS, W.CFG2_ANGLES)
+    x = W.rng(2).random((125_000, 3)) @ H.T
+    return {"x": x, "H": H, "cutoff": 12.0, "sigma": 3.4, "epsilon": 0.238}
+
+
 def cpu_baseline(cfg, nthreads):
     import oracle
     t0 = time.perf_counter()
@@ -363,6 +413,10 @@ def main():
         return
     if args.md_only:
         md_only(args.md_only, args.steps)
+        return
+    if args.section:
+        f = {"kclosest": kclosest_cases, "nonperiodic": nonperiodic_cases, "weighted": weighted_cases}
+        print(json.dumps({"section": args.section, **f[args.section]()}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (single-GPU workload; no collectives). "
@@ -383,7 +437,7 @@ def main():
     res = {}
     for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
         cl = clm.CellList(xt, box, precision=prec)
-        r = time_steps(clm, cl, xt, args.steps, args.warmup, sigma, eps)
+        r = time_steps(clm, cl, xt, args.steps, args.warmup, sigma, eps, args.step_samples)
         info = cl.info()  # after the timed steps: re-evaluation counts of the last map
         r["info"] = info
         res[prec] = r
@@ -443,6 +497,15 @@ def main():
     if args.build_n_large > 0:
         log(f"build-only timing at n={args.build_n_large} ...")
         line["build_roofline"]["points"].append(build_roofline(clm, W, args.build_n_large, args.lcell))
+    line["step_ms_median"] = main_r["step_ms_median"]
+    line["step_ms_min"] = main_r["step_ms_min"]
+    if args.calibrate:
+        log("measured device rates (FMA chains, copy) ...")
+        mp = measured_peaks(clm)
+        line["measured_peaks"] = mp
+        line["roofline"]["frac_of_measured_peak"] = achieved / mp["valu_fp32_tflops"]
+        line["build_roofline"]["frac_of_measured_copy"] = b1["algorithmic_GBs"] / mp["copy_GBs"]
+        log(f"measured: {mp}")
     if "fp64" in res:
         r64 = res["fp64"]
         line["fp64"] = {
@@ -452,7 +515,14 @@ def main():
             "build_ms": r64["build_ms"],
             "pairs": r64["count"],
             "energy": r64["energy"],
+            "step_ms_median": r64["step_ms_median"],
+            "step_ms_min": r64["step_ms_min"],
         }
+        a64 = flops / (r64["sweep_ms"] * 1e-3) / 1e12
+        line["fp64"]["roofline"] = {"bound": "alu", "achieved": a64, "peak": VALU_FP64_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": a64 / VALU_FP64_TFLOPS}
+        if "measured_peaks" in line:
+            line["fp64"]["roofline"]["frac_of_measured_peak"] = a64 / line["measured_peaks"]["valu_fp64_tflops"]
         line["fp32_over_fp64"] = value / line["fp64"]["value"]
         line["energy_rel_diff_fp32_fp64"] = abs(main_r["energy"] - r64["energy"]) / abs(r64["energy"])
     if args.serve_requests > 0:
@@ -488,7 +558,15 @@ def main():
             "pairs": r["count"],
             "pairs_match_gpu": r["count"] == pairs,
             "energy_rel_err_fp32": abs(main_r["energy"] - r["lj_energy"]) / abs(r["lj_energy"]),
+            "cpu_model": cpu_model(),
         }
+        log("cpu baseline: oracle on one thread (per-core figure) ...")
+        pc = per_core_sample(W)
+        r1, dt1 = cpu_baseline(pc, 1)
+        line["cpu_baseline"]["per_core"] = {
+            "value": r1["count"] / dt1, "unit": "pairs/s", "threads": 1,
+            "sample": f"125,000 particles at the headline density (box of half the lengths), {dt1:.1f} s",
+            "pairs": r1["count"]}
     print(json.dumps(line), flush=True)
 
 

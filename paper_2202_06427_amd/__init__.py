@@ -17,7 +17,7 @@ from . import _lib as L
 from ._lib import ClmError
 
 __all__ = ["Box", "CellList", "LJEnergy", "lj_energy", "ClmError", "extrema",
-           "neighbor_list_nonperiodic"]
+           "neighbor_list_nonperiodic", "calibrate"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -373,6 +373,32 @@ class CellList:
             if n <= cap:
                 return pairs[:n], (dist[:n] if distances else None)
             cap = n
+
+
+# ---------------------------------------------------------------- device rates
+def calibrate(kind, nbytes=1 << 30, reps=10, device="cuda:0"):
+    """Measured device rate of a microbenchmark (include/clmap_calib.h):
+    ``"fma_f32"`` / ``"fma_f64"`` (vector FMA chains) or ``"copy"`` (a
+    device copy of ``nbytes``).  Returns (ms per launch, work per launch,
+    rate) with the rate in TFLOP/s for FMA and GB/s (read + written) for the
+    copy.  Synchronizes."""
+    k = L.CALIB_KINDS[kind]
+    dev = torch.device(device)
+    need = ctypes.c_size_t(0)
+    L.check(L.lib().clm_calibrate_scratch_bytes(k, ctypes.byref(need)))
+    if kind == "copy":
+        nbytes = int(nbytes) // 16 * 16
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        src.fill_(1)
+        dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    else:
+        src, nbytes = None, int(need.value)
+        dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    ms, work = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    L.check(L.lib().clm_calibrate(_context(dev), k, _ptr(src), _ptr(dst), nbytes, int(reps),
+                                  ctypes.byref(ms), ctypes.byref(work)))
+    rate = work.value / (ms.value * 1e-3) / (1e9 if kind == "copy" else 1e12)
+    return ms.value, work.value, rate
 
 
 # ---------------------------------------------------------------- non-periodic neighbour list

@@ -95,7 +95,11 @@ EXPORTS = [
     "clm_vlist_info_get", "clm_vlist_destroy",
     # include/clmap_kclosest.h
     "clm_kclosest_workspace_bytes", "clm_kclosest",
+    # include/clmap_calib.h
+    "clm_calibrate_scratch_bytes", "clm_calibrate",
 ]
+
+CALIB_KINDS = {"fma_f32": 0, "fma_f64": 1, "copy": 2}
 
 _lib = None
 
@@ -153,6 +157,8 @@ def lib():
     L.clm_kclosest_workspace_bytes.argtypes = [_vp, c_i64, c_i64, szp]
     L.clm_kclosest.argtypes = [_vp, c_i64, c_i64, _vp, ctypes.c_size_t, _vp, _vp, _vp,
                                ctypes.POINTER(c_i64)]
+    L.clm_calibrate_scratch_bytes.argtypes = [c_int, szp]
+    L.clm_calibrate.argtypes = [_vp, c_int, _vp, _vp, ctypes.c_size_t, c_int, _dp, _dp]
     L.clm_last_error.restype = ctypes.c_char_p
     L.clm_status_string.restype = ctypes.c_char_p
     L.clm_status_string.argtypes = [c_int]

@@ -341,4 +341,16 @@ hipError_t launch_kc_output(const KcRecord* rec, int k, int found, int32_t* io, 
 hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
                              unsigned long long* out, hipStream_t s);
 
+// ---------------------------------------------------------------- calibration
+// Microbenchmarks of the device's attainable FMA rate and copy bandwidth.
+constexpr int kCalibThreads = 256;
+constexpr int kCalibBlocks = 4096;      // 16 blocks per CU
+constexpr int kCalibChains = 8;         // independent FMA chains per thread
+constexpr int kCalibCopyBlocks = 8192;
+// FMA chains of FP32 (fp64 = 0) or FP64; out holds kCalibBlocks * kCalibThreads values.
+hipError_t launch_calib_fma(int fp64, void* out, int iters, hipStream_t s);
+// dst[0..n16) = src[0..n16) in 16-byte vectors.
+hipError_t launch_calib_copy(const void* src, void* dst, int64_t n16, hipStream_t s);
+
+
 }  // namespace clm

@@ -213,3 +213,18 @@ def test_md_workspace_sizes_and_validation():
     assert lib.clm_vlist_workspace_bytes(None, 100, ctypes.byref(b)) == 1
     assert lib.clm_vlist_update(None, None) == 1
     assert lib.clm_vlist_lj(None, 1.0, 1.0, None, None, None, None, None, None, None) == 1
+
+
+def test_calibration_arguments():
+    """The device-rate microbenchmarks (include/clmap_calib.h): scratch sizes
+    and argument validation before any device call."""
+    lib = L.lib()
+    nb = ctypes.c_size_t(0)
+    assert lib.clm_calibrate_scratch_bytes(0, ctypes.byref(nb)) == 0 and nb.value == 4096 * 256 * 4
+    assert lib.clm_calibrate_scratch_bytes(1, ctypes.byref(nb)) == 0 and nb.value == 4096 * 256 * 8
+    assert lib.clm_calibrate_scratch_bytes(2, ctypes.byref(nb)) == 0 and nb.value == 0
+    assert lib.clm_calibrate_scratch_bytes(3, ctypes.byref(nb)) == L.STATUS_CODES["CLM_E_INVALID_ARG"]
+    assert lib.clm_calibrate_scratch_bytes(0, None) == L.STATUS_CODES["CLM_E_INVALID_ARG"]
+    ms, work = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    assert lib.clm_calibrate(None, 0, None, None, 0, 1, ctypes.byref(ms), ctypes.byref(work)) \
+        == L.STATUS_CODES["CLM_E_INVALID_ARG"]
