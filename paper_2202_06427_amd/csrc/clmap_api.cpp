@@ -843,10 +843,12 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
     F.nparts_dev = nullptr;
   } else {
     const bool hist = k_launch == K_HIST_DIST || k_launch == K_HIST_REL || k_launch == K_HIST_DV;
+    const int split = sweep_split_rows(k_launch, B.dim, B.lcell, jd.full_shell || cl->cross);
     CLM_HIP(launch_sweep(B.dim, cl->prec == CLM_FP32_GUARD, k_launch, cl->job_dev, cl->tiles,
-                         &cl->row_off[cl->nrows], cl->max_tiles, hist ? P->nbins : 0, st));
+                         &cl->row_off[cl->nrows], cl->max_tiles, hist ? P->nbins : 0, st, split));
     F.nparts = cl->max_tiles;
     F.nparts_dev = &cl->row_off[cl->nrows];
+    F.split_rows = split;
   }
   s = ts.stop();
   if (s != CLM_OK) return s;

@@ -160,9 +160,36 @@ struct BruteArgs {
   double reach;   // min(rc, half the sum of lattice-vector lengths) (1 + 1e-6)
 };
 
+// ---------------------------------------------------------------- row split
+// When a sweep has few tiles (small or sparse sets, cross sets with a small
+// x), the neighbour rows of a tile are spread over G waves: work item
+// tile * G + g visits the rows r (counted in visiting order) with r % G == g
+// and owns partial slot tile * G + g.  G is derived on the device from the
+// tile count, identically by the sweep and by the finalize.
+constexpr int kSplitTarget = 16384;  // work items aimed at (about 4 per SIMD slot)
+__host__ __device__ inline int sweep_split(int ntiles, int cap, int rows) {
+  if (rows <= 1 || ntiles <= 0) return 1;
+  int g = kSplitTarget / ntiles;
+  g = g < rows ? g : rows;
+  const int c = cap / ntiles;
+  g = g < c ? g : c;
+  return g > 1 ? g : 1;
+}
+
+// Rows a tile of a single-job sweep visits, or 1 when its rows must stay in
+// one wave: maps with per-particle outputs (LJ forces, the adjoint) write
+// each particle's result from the wave that holds it.
+inline int sweep_split_rows(int kind, int dim, int lcell, bool full) {
+  if (kind == K_LJ_F || kind == K_LJ_FV) return 1;
+  const int side = 2 * lcell + 1;
+  const int rows = dim == 3 ? side * side : side;
+  return full ? rows : (rows + 1) / 2;
+}
+
 struct FinalArgs {
   int nparts;                      // used when nparts_dev is NULL
   const uint32_t* nparts_dev;      // device count of partials (tiles)
+  int split_rows;                  // > 1: the sweep split rows (partials = tiles * G)
   int kind, dim, want_virial;
   int halve_count;                 // full-shell sweep: every pair was counted from both ends
   double eps;
@@ -303,8 +330,12 @@ hipError_t launch_hist_edges(double* E64, float* E32, int nbins, double hi, int 
                              double rc2, hipStream_t s);
 hipError_t launch_relspeed_band(const unsigned int* vmax_bits, double hi, int dim, double* bandq,
                                 hipStream_t s);
+// split_rows: rows a tile visits when its rows may be spread over waves
+// (sweep_split), 1 to keep one wave per tile (maps with per-particle outputs,
+// batches).
 hipError_t launch_sweep(int dim, bool fp32, int kind, const JobDesc* jobs, const Tile* tiles,
-                        const uint32_t* ntiles_dev, int max_tiles, int nbins, hipStream_t s);
+                        const uint32_t* ntiles_dev, int max_tiles, int nbins, hipStream_t s,
+                        int split_rows = 1);
 // Brute-force path: j chunks per 64 particles (enough waves to fill the chip
 // for a few thousand particles); partial rows = ceil(n_x / 64) * chunks.
 __host__ __device__ inline int brute_chunks(int64_t ny) {

@@ -127,6 +127,9 @@ struct Sweep {
   static constexpr bool kHist = KIND == K_HIST_DIST || KIND == K_HIST_REL || kDV;
   static constexpr bool kRel = KIND == K_HIST_REL;
   static constexpr bool kVel = kRel || kDV;
+  // rows may be spread over waves unless each particle's output is written
+  // by the wave that holds it
+  static constexpr bool kRowSplit = !(KIND == K_LJ_F || KIND == K_LJ_FV);
   static constexpr bool kW = KIND == K_SUM_W;
   static constexpr bool kNL = KIND == K_NL;
   static constexpr bool kSum = KIND == K_SUM_D || KIND == K_SUM_INV_D || kW || kLJ;
@@ -667,7 +670,9 @@ struct Sweep {
   }
 
   // ---------------- one tile
-  __device__ __forceinline__ void run(const Tile& T, int tile_id) {
+  // Rows r (in visiting order) with r % ngrp == grp; partial slot
+  // tile * ngrp + grp.
+  __device__ __forceinline__ void run(const Tile& T, int tile_id, int grp, int ngrp) {
     const int cy = (int)(T.row % (uint32_t)ny);
     const int cz = DIM == 3 ? (int)(T.row / (uint32_t)ny) : 0;
     const int count = T.count;
@@ -711,9 +716,14 @@ struct Sweep {
     }
 
     const int dzlo = DIM == 3 ? -l : 0, dzhi = DIM == 3 ? l : 0;
+    int r = -1, next = grp;  // rows grp, grp + ngrp, ... (split maps)
     for (int dz = dzlo; dz <= dzhi; ++dz) {
       for (int dy = -l; dy <= l; ++dy) {
         if (!full && (dz < 0 || (dz == 0 && dy < 0))) continue;
+        if constexpr (kRowSplit) {
+          if (++r != next) continue;
+          next += ngrp;
+        }
         const bool home = !full && dz == 0 && dy == 0;
         const int uy = cy + dy, uz = cz + dz;
         int uyw = uy, uzw = uz, py = 0, pz = 0;
@@ -731,29 +741,45 @@ struct Sweep {
 #pragma unroll
           for (int a = 0; a < DIM; ++a) Orow[a] = ldu(&J->Hn[a * 3 + 1]) * u1 + ldu(&J->Hn[a * 3 + 2]) * u2;
         }
-        for (int ux = xlo; ux <= xhi; ++ux) {
-          int uxw = ux, px = 0;
-          if (uxw < 0) { uxw += nx; px = -1; } else if (uxw >= nx) { uxw -= nx; px = 1; }
-          const int c = rowbase + uxw;
-          const uint32_t jb = ldu(&OFF[c]), je = ldu(&OFF[c + 1]);
-          if (jb == je) continue;
-          p[0] = px; p[1] = py; p[2] = pz;
-          const int kc = kcode(px, py, pz);
-          t[0] = ldu(&J->tK[kc * 4 + 0]);
-          t[1] = ldu(&J->tK[kc * 4 + 1]);
-          t[2] = ldu(&J->tK[kc * 4 + 2]);
-          if constexpr (FP32) {
-            // origin of the visited cell (unwrapped index u), FP64
-            const double u0 = (double)ux;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-              const double O = Orow[a] + Hn0[a] * u0;
-              q[a] = active ? (float)(ri[a] - O) : 1e18f;
+        // The row's cells in chunks of up to 64: lane L loads the offsets of
+        // cell cs + L (one vector load per chunk instead of a dependent
+        // scalar load per cell), empty cells drop out of a ballot mask.
+        for (int cs = xlo; cs <= xhi; cs += kWave) {
+          uint32_t jbv = 0u, jev = 0u;
+          {
+            const int ux = cs + lane;
+            if (ux <= xhi) {
+              const int uxw = ux < 0 ? ux + nx : (ux >= nx ? ux - nx : ux);
+              jbv = OFF[rowbase + uxw];
+              jev = OFF[rowbase + uxw + 1];
             }
-            if (DIM == 2) q[2] = 0.0f;
           }
-          const bool own = !cross && dz == 0 && dy == 0 && px == 0 && ux >= cx0 && ux <= cx1;
-          visit(jb, je, (home && px == 0) ? 1 : ((full && own) ? 2 : 0));
+          unsigned long long cells = __builtin_amdgcn_ballot_w64(jev != jbv);
+          while (cells) {
+            const int L = (int)__builtin_ctzll(cells);
+            cells &= cells - 1ull;
+            const int ux = cs + L;
+            const int px = ux < 0 ? -1 : (ux >= nx ? 1 : 0);
+            const uint32_t jb = (uint32_t)__builtin_amdgcn_readlane((int)jbv, L);
+            const uint32_t je = (uint32_t)__builtin_amdgcn_readlane((int)jev, L);
+            p[0] = px; p[1] = py; p[2] = pz;
+            const int kc = kcode(px, py, pz);
+            t[0] = ldu(&J->tK[kc * 4 + 0]);
+            t[1] = ldu(&J->tK[kc * 4 + 1]);
+            t[2] = ldu(&J->tK[kc * 4 + 2]);
+            if constexpr (FP32) {
+              // origin of the visited cell (unwrapped index u), FP64
+              const double u0 = (double)ux;
+#pragma unroll
+              for (int a = 0; a < DIM; ++a) {
+                const double O = Orow[a] + Hn0[a] * u0;
+                q[a] = active ? (float)(ri[a] - O) : 1e18f;
+              }
+              if (DIM == 2) q[2] = 0.0f;
+            }
+            const bool own = !cross && dz == 0 && dy == 0 && px == 0 && ux >= cx0 && ux <= cx1;
+            visit(jb, je, (home && px == 0) ? 1 : ((full && own) ? 2 : 0));
+          }
         }
       }
     }
@@ -786,7 +812,7 @@ struct Sweep {
     }
     if constexpr (kNL) nl_flush();
     const unsigned long long cnt = cnt_wave + wave_sum_u64(cnt_lane);
-    const int local = tile_id - ldu(&J->tile_begin);  // this job's tile index
+    const int local = (tile_id - ldu(&J->tile_begin)) * ngrp + grp;  // this job's partial slot
     double* Pp = ldu(&J->partials) + (size_t)local * kPartialD;
     // every lane may hold queued FP64 contributions of other lanes' particles:
     // reduce over all lanes (inactive lanes contribute nothing of their own)
@@ -826,7 +852,8 @@ struct Sweep {
 template <int DIM, bool FP32, int KIND>
 __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict__ jobs,
                                                        const Tile* __restrict__ tiles,
-                                                       const uint32_t* __restrict__ ntiles_dev) {
+                                                       const uint32_t* __restrict__ ntiles_dev,
+                                                       int split_rows) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr bool kHist = KIND == K_HIST_DIST || KIND == K_HIST_REL || KIND == K_HIST_DV;
   constexpr bool kNL = KIND == K_NL;
@@ -834,12 +861,18 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
   const int wid = uniform((int)(threadIdx.x / kWave));
   // the tile count is produced on the device; never trust it past the array
   constexpr int kWpb = kSweepWaves;
-  const int ntiles = min((int)ldu(ntiles_dev), (int)(gridDim.x * kWpb));
+  const int cap = (int)(gridDim.x * kWpb);
+  const int ntiles = min((int)ldu(ntiles_dev), cap);
+  // G waves per tile when the tiles are few (G * ntiles <= cap); maps with
+  // per-particle outputs keep one wave per tile (compiled out)
+  constexpr bool kSplit = Sweep<DIM, FP32, KIND>::kRowSplit;
+  const int G = kSplit ? sweep_split(ntiles, cap, split_rows) : 1;
+  const int nitems = ntiles * G;
   // The grid is sized by an upper bound on the tile count; only the first
   // nblk blocks have work.  Blocks are dispatched to the 8 XCDs round-robin,
   // so block b (b < nblk) runs on XCD b % 8: give each XCD a contiguous
   // range of tiles (neighbouring cells share their rows in that XCD's L2).
-  const int nblk = (ntiles + kWpb - 1) / kWpb;
+  const int nblk = (nitems + kWpb - 1) / kWpb;
   int b = blockIdx.x;
   if (b >= nblk) return;
   if (nblk >= 8) {
@@ -847,8 +880,9 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
     const int xcd = b % 8, k = b / 8;
     b = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
   }
-  const int tile_id = uniform(b * kWpb + wid);
-  if (tile_id >= ntiles) return;
+  const int item = uniform(b * kWpb + wid);
+  if (item >= nitems) return;
+  const int tile_id = kSplit ? item / G : item, grp = kSplit ? item - tile_id * G : 0;
   const Tile T = ldu(&tiles[tile_id]);
 
   Sweep<DIM, FP32, KIND> S;
@@ -881,7 +915,7 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   }
-  S.run(T, tile_id);
+  S.run(T, tile_id, grp, G);
   if constexpr (kHist) {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1107,7 +1141,8 @@ __global__ void __launch_bounds__(256) finalize1_kernel(const JobDesc* __restric
   __shared__ double red[256];
   __shared__ unsigned long long redc[256];
   const int tid = threadIdx.x;
-  const int nparts = F.nparts_dev ? min((int)*F.nparts_dev, F.nparts) : F.nparts;
+  int nparts = F.nparts_dev ? min((int)*F.nparts_dev, F.nparts) : F.nparts;
+  if (F.nparts_dev) nparts *= sweep_split(nparts, F.nparts, F.split_rows);
   const int chunk = (nparts + gridDim.x - 1) / gridDim.x;
   const int lo = blockIdx.x * chunk, hi = min(nparts, lo + chunk);
   unsigned long long c = 0;
@@ -1341,35 +1376,37 @@ hipError_t launch_finalize_batch(const JobDesc* jobs, const FinalArgs* F, int nj
 
 template <int DIM, bool FP32>
 static hipError_t sweep_dispatch(int kind, dim3 grid, size_t lds, const JobDesc* jobs,
-                                 const Tile* tiles, const uint32_t* nt, hipStream_t s) {
+                                 const Tile* tiles, const uint32_t* nt, int split, hipStream_t s) {
   switch (kind) {
-    case K_COUNT: sweep_kernel<DIM, FP32, K_COUNT><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_SUM_D: sweep_kernel<DIM, FP32, K_SUM_D><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_SUM_INV_D: sweep_kernel<DIM, FP32, K_SUM_INV_D><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_LJ_E: sweep_kernel<DIM, FP32, K_LJ_E><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_LJ_F: sweep_kernel<DIM, FP32, K_LJ_F><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_LJ_FV: sweep_kernel<DIM, FP32, K_LJ_FV><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_HIST_DIST: sweep_kernel<DIM, FP32, K_HIST_DIST><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_HIST_REL: sweep_kernel<DIM, FP32, K_HIST_REL><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_SUM_W: sweep_kernel<DIM, FP32, K_SUM_W><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_HIST_DV: sweep_kernel<DIM, FP32, K_HIST_DV><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
-    case K_NL: sweep_kernel<DIM, FP32, K_NL><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt); break;
+    case K_COUNT: sweep_kernel<DIM, FP32, K_COUNT><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_SUM_D: sweep_kernel<DIM, FP32, K_SUM_D><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_SUM_INV_D: sweep_kernel<DIM, FP32, K_SUM_INV_D><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_LJ_E: sweep_kernel<DIM, FP32, K_LJ_E><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_LJ_F: sweep_kernel<DIM, FP32, K_LJ_F><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_LJ_FV: sweep_kernel<DIM, FP32, K_LJ_FV><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_HIST_DIST: sweep_kernel<DIM, FP32, K_HIST_DIST><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_HIST_REL: sweep_kernel<DIM, FP32, K_HIST_REL><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_SUM_W: sweep_kernel<DIM, FP32, K_SUM_W><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_HIST_DV: sweep_kernel<DIM, FP32, K_HIST_DV><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
+    case K_NL: sweep_kernel<DIM, FP32, K_NL><<<grid, kSweepWaves * kWave, lds, s>>>(jobs, tiles, nt, split); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_sweep(int dim, bool fp32, int kind, const JobDesc* jobs, const Tile* tiles,
-                        const uint32_t* ntiles_dev, int max_tiles, int nbins, hipStream_t s) {
+                        const uint32_t* ntiles_dev, int max_tiles, int nbins, hipStream_t s,
+                        int split_rows) {
   if (max_tiles <= 0) return hipSuccess;
+  const int split = split_rows;
   const int waves = kSweepWaves;
   dim3 grid((max_tiles + waves - 1) / waves);
   size_t lds = sweep_lds_per_wave(kind, nbins, fp32) * waves;
   if (dim == 3)
-    return fp32 ? sweep_dispatch<3, true>(kind, grid, lds, jobs, tiles, ntiles_dev, s)
-                : sweep_dispatch<3, false>(kind, grid, lds, jobs, tiles, ntiles_dev, s);
-  return fp32 ? sweep_dispatch<2, true>(kind, grid, lds, jobs, tiles, ntiles_dev, s)
-              : sweep_dispatch<2, false>(kind, grid, lds, jobs, tiles, ntiles_dev, s);
+    return fp32 ? sweep_dispatch<3, true>(kind, grid, lds, jobs, tiles, ntiles_dev, split, s)
+                : sweep_dispatch<3, false>(kind, grid, lds, jobs, tiles, ntiles_dev, split, s);
+  return fp32 ? sweep_dispatch<2, true>(kind, grid, lds, jobs, tiles, ntiles_dev, split, s)
+              : sweep_dispatch<2, false>(kind, grid, lds, jobs, tiles, ntiles_dev, split, s);
 }
 
 hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, double* FB, int* nparts_out,
