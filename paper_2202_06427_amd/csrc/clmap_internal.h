@@ -115,8 +115,8 @@ struct JobDesc {
 // Dynamic LDS bytes per wave of the sweep.  The FP32 form keeps a ring
 // queue of candidates to re-evaluate in FP64 (kQueueCap entries of 8 bytes)
 // and, for LJ forces, per-lane FP64 force accumulators fed by that queue.
-// Histogram kinds add a private histogram (nbins+1 u32), per-bin FP64 sums
-// and the FP32 edge table; the neighbour list adds a staging area.
+// Histogram kinds add private histograms (nbins+1 u32 each) and per-bin FP64
+// sums; the neighbour list adds a staging area.
 constexpr int kQueueCap = 512;  // power of two
 __host__ __device__ inline size_t sweep_lds_queue_bytes(int kind, bool fp32) {
   if (!fp32) return 0;
@@ -124,11 +124,29 @@ __host__ __device__ inline size_t sweep_lds_queue_bytes(int kind, bool fp32) {
   if (kind == K_LJ_F || kind == K_LJ_FV) b += (size_t)kWave * 3 * 8;
   return b;
 }
+// Copies of a wave's private histogram: lane l adds to copy l % C (copies
+// of nbins+1 counters, then copies of nbins sums, one after the other), so
+// fewer lanes of one LDS atomic meet at one address.  C
+// is the largest power of two up to 64 whose counters (and per-bin FP64
+// sums) fit in kHistPrivBytes.
+constexpr size_t kHistPrivBytes = 2048;
+constexpr int kHistMaxCopies = 16;
+// FP32 bin edges read from a per-wave LDS table (true) or formed in registers
+constexpr bool kHistEdgeTable = false;
+__host__ __device__ constexpr bool hist_has_sums(int kind) { return kind == K_HIST_REL || kind == K_HIST_DV; }
+__host__ __device__ inline int hist_copies(int kind, int nbins) {
+  const size_t per = (size_t)(nbins + 1) * 4 + (hist_has_sums(kind) ? (size_t)nbins * 8 : 0);
+  int c = 1;
+  while (c < kHistMaxCopies && (size_t)(2 * c) * per <= kHistPrivBytes) c *= 2;
+  return c;
+}
 __host__ __device__ inline size_t sweep_lds_per_wave(int kind, int nbins, bool fp32) {
   size_t b = sweep_lds_queue_bytes(kind, fp32);
-  if (kind == K_HIST_DIST || kind == K_HIST_REL || kind == K_HIST_DV)
-    b += (size_t)(nbins + 1) * 4 + 8 + (size_t)nbins * 8 + (size_t)(nbins + 1) * 4;
-  else if (kind == K_NL)
+  if (kind == K_HIST_DIST || kind == K_HIST_REL || kind == K_HIST_DV) {
+    const size_t C = (size_t)hist_copies(kind, nbins);
+    b += C * (size_t)(nbins + 1) * 4 + 8 + (hist_has_sums(kind) ? C * (size_t)nbins * 8 : 0);
+    if (kHistEdgeTable) b += (size_t)(nbins + 1) * 4;
+  } else if (kind == K_NL)
     b += (size_t)kNLStage * 16 + 16;
   return (b + 15) & ~(size_t)15;
 }

@@ -73,21 +73,28 @@ __device__ __forceinline__ int bin64(const double* __restrict__ E, int nb, doubl
   return m == 0 ? 0 : m - 1;
 }
 
-// FP32 bin with certainty flag: the bin is certain when v is farther than
-// band from both edges of the bin chosen against the FP32 table.  Et is the
-// FP32 edge table in LDS; band covers the FP32 error of v and of Et.
-__device__ __forceinline__ int bin32(const float* __restrict__ Et, int nb, float inv_h, float v,
+// FP32 bin with certainty flag.  The edges are formed in FP32, E_m =
+// (m h)^2 for m < nb and E_nb = elast (the canonical last edge rounded to
+// FP32): each is within 5 units of 2^-24 (relative) of the canonical FP64
+// edge.  The bin is certain when v is farther than band from both of its
+// edges; band covers the FP32 error of v plus 8 * 2^-24 * elast.
+__device__ __forceinline__ float edge32(const float* Et, int m, int nb, float h, float elast) {
+  if constexpr (kHistEdgeTable) return Et[m];
+  const float e = (float)m * h;
+  return m >= nb ? elast : e * e;
+}
+__device__ __forceinline__ int bin32(const float* Et, int nb, float h, float inv_h, float elast, float v,
                                      float band, bool* certain) {
-  float sq = __builtin_sqrtf(v);
+  const float sq = __builtin_sqrtf(v);
   int k = (int)ceilf(sq * inv_h) - 1;
   k = k < 0 ? 0 : (k > nb ? nb : k);
-  if (k < nb && v <= Et[k] && k > 0) --k;
-  else if (k < nb && v > Et[k + 1]) ++k;
+  if (k < nb && k > 0 && v <= edge32(Et, k, nb, h, elast)) --k;
+  else if (k < nb && v > edge32(Et, k + 1, nb, h, elast)) ++k;
   if (k >= nb) {
-    *certain = (v - Et[nb]) > band;
+    *certain = (v - elast) > band;
     return nb;
   }
-  float lo = Et[k], hi = Et[k + 1];
+  const float lo = edge32(Et, k, nb, h, elast), hi = edge32(Et, k + 1, nb, h, elast);
   *certain = (k == 0 ? true : (v - lo) > band) && (hi - v) > band && v > lo && v <= hi;
   return k;
 }
@@ -107,9 +114,9 @@ __device__ __forceinline__ T ldu(const T* p) {
 
 // ---------------------------------------------------------------- per-wave LDS
 struct WaveLds {
-  uint32_t* hist;     // nbins+1
-  double* hsum;       // nbins
-  float* E32;         // nbins+1
+  uint32_t* hist;     // copies x (nbins+1)
+  double* hsum;       // copies x nbins
+  float* E32;         // nbins+1 (when the FP32 edges come from a table)
   uint32_t* nl_ij;    // kNLStage*2
   double* nl_d;       // kNLStage
   int* nl_fill;       // 1
@@ -144,6 +151,10 @@ struct Sweep {
   double s2, inv_s2;
   int nbins;
   float inv_h;
+  float h32, elast;  // FP32 bin width and last edge
+  int hC;            // histogram copies
+  uint32_t* hist_l;  // this lane's copy: counters (nbins+1)
+  double* hsum_l;    // and sums (nbins)
   double inv_h64;
   float bandh;       // histogram edge band (FP32)
   int want_sums, with_dist;
@@ -207,6 +218,9 @@ struct Sweep {
       inv_h = ldu(&J->inv_h);
       inv_h64 = (double)nbins / ldu(&J->hist_hi);
       E64 = ldu(&J->E64);
+      h32 = (float)(ldu(&J->hist_hi) / (double)nbins);
+      elast = ldu(&ldu(&J->E32)[nbins]);
+      hC = hist_copies(KIND, nbins);
     }
     if constexpr (kVel) {
       VJ = cross ? ldu(&J->vel32_y) : ldu(&J->vel32_x);
@@ -216,6 +230,7 @@ struct Sweep {
       want_sums = ldu(&J->want_sums);
       bandh = (float)ldu(ldu(&J->bandq));
     }
+    if constexpr (kHist) bandh += 4.77e-7f * elast;  // 8 * 2^-24 * elast: the FP32 edges
     if constexpr (kNL) with_dist = ldu(&J->with_dist);
     P = cross ? ldu(&J->pos_y) : ldu(&J->pos_x);
     R = cross ? ldu(&J->r64_y) : ldu(&J->r64_x);
@@ -329,12 +344,12 @@ struct Sweep {
     }
     if constexpr (KIND == K_HIST_DIST) {
       int k = bin64(E64, nbins, inv_h64, d2);
-      atomicAdd(&L.hist[k], 1u);
+      hist_add(k);
     }
     if constexpr (kDV) {
       const int k = bin64(E64, nbins, inv_h64, d2);
-      atomicAdd(&L.hist[k], 1u);
-      if (k < nbins) atomicAdd(&L.hsum[k], speed64(ldu(&IDXJ[j]), vi64));
+      hist_add(k);
+      if (k < nbins) hsum_add(k, speed64(ldu(&IDXJ[j]), vi64));
     }
     if constexpr (kRel) {
       uint32_t jo = ldu(&IDXJ[j]);
@@ -344,11 +359,15 @@ struct Sweep {
       double qq = dv[0] * dv[0] + dv[1] * dv[1];
       if (DIM == 3) qq = qq + dv[2] * dv[2];
       int k = bin64(E64, nbins, inv_h64, qq);
-      atomicAdd(&L.hist[k], 1u);
-      if (want_sums && k < nbins) atomicAdd(&L.hsum[k], sqrt(qq));
+      hist_add(k);
+      if (want_sums && k < nbins) hsum_add(k, sqrt(qq));
     }
     if constexpr (kNL) nl_one(j, sqrt(d2));
   }
+
+  // ---------------- private histogram (this lane's copy)
+  __device__ __forceinline__ void hist_add(int k) { atomicAdd(&hist_l[k], 1u); }
+  __device__ __forceinline__ void hsum_add(int k, double v) { atomicAdd(&hsum_l[k], v); }
 
   // ---------------- FP64 re-evaluation queue (FP32 form)
   // Append this iteration's special lanes (uniform control flow).
@@ -421,17 +440,17 @@ struct Sweep {
         }
       }
     }
-    if constexpr (KIND == K_HIST_DIST) atomicAdd(&L.hist[bin64(E64, nbins, inv_h64, d2)], 1u);
+    if constexpr (KIND == K_HIST_DIST) hist_add(bin64(E64, nbins, inv_h64, d2));
     if constexpr (kDV) {
       const int k = bin64(E64, nbins, inv_h64, d2);
-      atomicAdd(&L.hist[k], 1u);
+      hist_add(k);
       if (k < nbins) {
         const uint32_t io = ldu(&J->idx_x)[iL];
         const double* v64 = ldu(&J->vel64_x);
         double vo[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < DIM; ++a) vo[a] = v64[(size_t)io * DIM + a];
-        atomicAdd(&L.hsum[k], speed64(IDXJ[j], vo));
+        hsum_add(k, speed64(IDXJ[j], vo));
       }
     }
     if constexpr (kRel) {
@@ -444,8 +463,8 @@ struct Sweep {
       double qq = dv[0] * dv[0] + dv[1] * dv[1];
       if (DIM == 3) qq = qq + dv[2] * dv[2];
       const int k = bin64(E64, nbins, inv_h64, qq);
-      atomicAdd(&L.hist[k], 1u);
-      if (want_sums && k < nbins) atomicAdd(&L.hsum[k], sqrt(qq));
+      hist_add(k);
+      if (want_sums && k < nbins) hsum_add(k, sqrt(qq));
     }
     if constexpr (kNL) {
       uint32_t a = ldu(&J->idx_x)[iL], b = IDXJ[j];
@@ -545,17 +564,17 @@ struct Sweep {
       }
       if (in) {
         bool certain;
-        const int k = bin32(L.E32, nbins, inv_h, v, bandh, &certain);
+        const int k = bin32(L.E32, nbins, h32, inv_h, elast, v, bandh, &certain);
         if (certain) {
-          atomicAdd(&L.hist[k], 1u);
-          if (kRel && want_sums && k < nbins) atomicAdd(&L.hsum[k], (double)__builtin_sqrtf(v));
+          hist_add(k);
+          if (kRel && want_sums && k < nbins) hsum_add(k, (double)__builtin_sqrtf(v));
           if (kDV && k < nbins) {
             const float4 vj = ldu(&VJ[j]);
             const float ex = vj.x - vi[0], ey = vj.y - vi[1];
             const float ez = DIM == 3 ? vj.z - vi[2] : 0.0f;
             const float qq = DIM == 3 ? __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex))
                                       : __builtin_fmaf(ey, ey, ex * ex);
-            atomicAdd(&L.hsum[k], (double)__builtin_sqrtf(qq));
+            hsum_add(k, (double)__builtin_sqrtf(qq));
           }
         } else {
           spec = true;
@@ -897,14 +916,20 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
     }
     base += sweep_lds_queue_bytes(KIND, FP32);
     if constexpr (kHist) {
+      const int C = S.hC;
       S.L.hist = (uint32_t*)base;
-      S.L.hsum = (double*)(((uintptr_t)(base + (size_t)(nb + 1) * 4) + 7) & ~(uintptr_t)7);
-      S.L.E32 = (float*)((unsigned char*)S.L.hsum + (size_t)nb * 8);
-      const float* E32g = ldu(&S.J->E32);
-      for (int k = lane; k <= nb; k += kWave) {
-        S.L.hist[k] = 0u;
-        S.L.E32[k] = E32g[k];
-        if (k < nb) S.L.hsum[k] = 0.0;
+      S.L.hsum = (double*)(((uintptr_t)(base + (size_t)C * (nb + 1) * 4) + 7) & ~(uintptr_t)7);
+      for (int k = lane; k < C * (nb + 1); k += kWave) S.L.hist[k] = 0u;
+      if constexpr (hist_has_sums(KIND))
+        for (int k = lane; k < C * nb; k += kWave) S.L.hsum[k] = 0.0;
+      // copy q of the counters at q * (nb + 1), of the sums at q * nb
+      const int q = lane & (C - 1);
+      S.hist_l = S.L.hist + q * (nb + 1);
+      S.hsum_l = S.L.hsum + q * nb;
+      if constexpr (kHistEdgeTable) {
+        S.L.E32 = (float*)(S.L.hsum + (hist_has_sums(KIND) ? (size_t)C * nb : 0));
+        const float* E32g = ldu(&S.J->E32);
+        for (int k = lane; k <= nb; k += kWave) S.L.E32[k] = E32g[k];
       }
     } else if constexpr (kNL) {
       S.L.nl_ij = (uint32_t*)base;
@@ -922,11 +947,14 @@ __global__ void __launch_bounds__(kBlock) sweep_kernel(const JobDesc* __restrict
     const int nb = S.nbins;
     unsigned long long* hist = ldu(&S.J->hist);
     double* hsums = ldu(&S.J->hist_sums);
-    for (int k = lane; k <= nb; k += kWave) {
-      const uint32_t c = S.L.hist[k];
+    const int C = S.hC;
+    for (int k = lane; k <= nb; k += kWave) {  // copies summed in a fixed order
+      uint32_t c = 0u;
+      for (int q = 0; q < C; ++q) c += S.L.hist[q * (nb + 1) + k];
       if (c) atomicAdd(&hist[k], (unsigned long long)c);
       if (((KIND == K_HIST_REL && S.want_sums) || KIND == K_HIST_DV) && k < nb) {
-        const double sm = S.L.hsum[k];
+        double sm = 0.0;
+        for (int q = 0; q < C; ++q) sm += S.L.hsum[q * nb + k];
         if (sm != 0.0) atomicAdd(&hsums[k], sm);
       }
     }
