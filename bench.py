@@ -215,7 +215,7 @@ def build_roofline(clm, W, n, lcell, steps=5):
 
 def md_cases(steps):
     """Neon fluid MD (100 atoms/nm^3, rc 1.2 nm, 1 fs, rescaling every 10
-    steps) at 10^4 and 10^5 atoms: the paper's protocol (cell list rebuilt
+    steps) at 10^4, 10^5 and 10^6 atoms: the paper's protocol (cell list rebuilt
     every step, FP32+guard sweep forces) against the Verlet pair list (skin
     0.1 nm, FP64 forces), timed on the host clock around `steps` steps."""
     import time
@@ -223,7 +223,7 @@ def md_cases(steps):
     import paper_2202_06427_amd.md as md
     import workloads as W
     out = {}
-    for n in (10_000, 100_000):
+    for n in (10_000, 100_000, 1_000_000):
         w = W.neon_fluid(n, seed=6)
         target = 0.5 * (3 * n - 3) * W.KB * w["temperature"]
         row = {}
@@ -530,7 +530,7 @@ def main():
         line["served"] = served(args.serve_requests, args.serve_rate)
         log(f"served: {line['served']}")
     if args.md_steps > 0:
-        log(f"Neon MD: {args.md_steps} steps at 1e4 and 1e5 atoms ...")
+        log(f"Neon MD: {args.md_steps} steps at 1e4, 1e5 and 1e6 atoms ...")
         line["md"] = md_cases(args.md_steps)
         log(f"md: {line['md']}")
     if args.weighted:

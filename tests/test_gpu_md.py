@@ -84,6 +84,27 @@ def test_vlist_forces_at_a_rebuild_large(md):
     _check_against_oracle(x, H, oracle.wrap(x, H)[2], F, E, Wv, C)
 
 
+def test_vlist_forces_at_a_rebuild_1e6(md):
+    """The benchmark's largest Neon case (10^6 atoms, skin 0.1 nm): per-tile
+    build, 4 lanes per row.  Pair count exact, energy and virial 1e-12; forces
+    per particle within 1e-10 of the largest reference force (the list path
+    is FP64 throughout)."""
+    w = W.neon_fluid(1_000_000, seed=6)
+    x, H = w["x"], w["H"]
+    xd = T(x)
+    vl = md.VerletList(xd, H, RC, 0.1, lcell=2)
+    vl.update(xd)
+    F, E, Wv, C = _lj_outputs(vl, len(x), 3)
+    info = vl.info()
+    assert info["overflow"] == 0 and info["rebuilds"] == 1
+    ref = oracle.compute(x, H, RC, lj=(SIG, EPS), lj_grad=True, frame=oracle.wrap(x, H)[2])
+    assert C == ref["count"]
+    assert abs(E - ref["lj_energy"]) <= 1e-12 * abs(ref["lj_energy"])
+    Fr = -ref["lj_grad"]
+    assert np.abs(F - Fr).max() <= 1e-10 * np.abs(Fr).max()
+    assert np.abs(Wv - ref["virial"]).max() <= 1e-11 * np.abs(ref["virial"]).max()
+
+
 def test_vlist_between_rebuilds_and_across_the_box_faces(md):
     """Displacements below half the skin keep the list (no rebuild); the
     distances are taken in the frame of the rebuild, also for particles that
