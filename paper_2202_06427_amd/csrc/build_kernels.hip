@@ -382,13 +382,25 @@ __global__ void __launch_bounds__(256) extrema_kernel(const double* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(64) extrema_final_kernel(const double* __restrict__ part, int nb,
-                                                           double* __restrict__ out) {
-  if (threadIdx.x >= 6) return;
-  double v = part[threadIdx.x];
-  for (int b = 1; b < nb; ++b)
-    v = threadIdx.x < 3 ? fmin(v, part[b * 6 + threadIdx.x]) : fmax(v, part[b * 6 + threadIdx.x]);
-  out[threadIdx.x] = v;
+// One block: thread t takes the partials t, t + 256, ... (independent loads),
+// then a tree in LDS (minimum and maximum are exact in any order).
+__global__ void __launch_bounds__(256) extrema_final_kernel(const double* __restrict__ part, int nb,
+                                                            double* __restrict__ out) {
+  const double inf = __longlong_as_double(0x7ff0000000000000ll);
+  const int t = threadIdx.x;
+  double v[6] = {inf, inf, inf, -inf, -inf, -inf};
+  for (int b = t; b < nb; b += 256)
+    for (int a = 0; a < 6; ++a) v[a] = a < 3 ? fmin(v[a], part[b * 6 + a]) : fmax(v[a], part[b * 6 + a]);
+  __shared__ double red[6][256];
+  for (int a = 0; a < 6; ++a) red[a][t] = v[a];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st)
+      for (int a = 0; a < 6; ++a)
+        red[a][t] = a < 3 ? fmin(red[a][t], red[a][t + st]) : fmax(red[a][t], red[a][t + st]);
+    __syncthreads();
+  }
+  if (t < 6) out[t] = red[t][0];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -465,7 +477,7 @@ hipError_t launch_extrema(const double* x, int64_t n, int dim, double* part, dou
   extrema_kernel<<<nb, 256, 0, s>>>(x, n, dim, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  extrema_final_kernel<<<1, 64, 0, s>>>(part, nb, out);
+  extrema_final_kernel<<<1, 256, 0, s>>>(part, nb, out);
   return hipGetLastError();
 }
 
