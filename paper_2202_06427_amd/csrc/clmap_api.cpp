@@ -265,6 +265,7 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
   size_t o_job = c.take(sizeof(JobDesc));
   size_t o_part = c.take(sizeof(double) * kPartialD * parts);
   size_t o_pc = c.take(sizeof(unsigned long long) * parts);
+  size_t o_nlo = c.take(sizeof(unsigned long long) * parts);
   size_t o_E64 = c.take(sizeof(double) * (kMaxBins + 1));
   size_t o_E32 = c.take(sizeof(float) * (kMaxBins + 1));
   size_t o_bq = c.take(sizeof(double) * 2);
@@ -283,6 +284,7 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
     cl->job_dev = (JobDesc*)(base + o_job);
     cl->partials = (double*)(base + o_part);
     cl->pcount = (unsigned long long*)(base + o_pc);
+    cl->nl_off = (unsigned long long*)(base + o_nlo);
     cl->E64 = (double*)(base + o_E64);
     cl->E32 = (float*)(base + o_E32);
     cl->bandq = (double*)(base + o_bq);
@@ -812,6 +814,10 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
   if (s != CLM_OK) return s;
   const clm_box& B = cl->box;
   hipStream_t st = cl->ctx->stream;
+  // neighbour lists: a counting sweep gives every work item its output
+  // offset, so the list sweep writes without a shared counter
+  const bool nl_two_pass = k_launch == K_NL && !B.small;
+  if (nl_two_pass) jd.nl_offsets = cl->nl_off;
   CLM_HIP(launch_set_job(jd, cl->job_dev, st));
   Timed ts(cl->ctx, &cl->ctx->sweep_ev);
   s = ts.start();
@@ -844,6 +850,12 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
   } else {
     const bool hist = k_launch == K_HIST_DIST || k_launch == K_HIST_REL || k_launch == K_HIST_DV;
     const int split = sweep_split_rows(k_launch, B.dim, B.lcell, jd.full_shell || cl->cross);
+    if (nl_two_pass) {
+      CLM_HIP(launch_sweep(B.dim, cl->prec == CLM_FP32_GUARD, K_COUNT, cl->job_dev, cl->tiles,
+                           &cl->row_off[cl->nrows], cl->max_tiles, 0, st, split));
+      CLM_HIP(launch_nl_offsets(cl->pcount, &cl->row_off[cl->nrows], cl->max_tiles, split, cl->nl_off, st));
+      CLM_HIP(launch_fill_u64(cl->guard, 2, 0ull, st));  // count the list pass's re-tests only
+    }
     CLM_HIP(launch_sweep(B.dim, cl->prec == CLM_FP32_GUARD, k_launch, cl->job_dev, cl->tiles,
                          &cl->row_off[cl->nrows], cl->max_tiles, hist ? P->nbins : 0, st, split));
     F.nparts = cl->max_tiles;

@@ -103,6 +103,9 @@ struct JobDesc {
   int32_t* pairs;
   double* dist;
   unsigned long long* nl_counter;
+  // output offset of each work item (tile * G + g) from a counting pass, or
+  // NULL: items then reserve output slots from nl_counter
+  const unsigned long long* nl_offsets;
   long long capacity;
   int tile_begin, tile_end;  // this job's tiles in the launched tile list
   // the job's own tile list (built by its cell list)
@@ -348,6 +351,10 @@ hipError_t launch_hist_edges(double* E64, float* E32, int nbins, double hi, int 
                              double rc2, hipStream_t s);
 hipError_t launch_relspeed_band(const unsigned int* vmax_bits, double hi, int dim, double* bandq,
                                 hipStream_t s);
+// Exclusive prefix sums of the per-item pair counts of a counting sweep
+// (pcount, tiles * G items with G from sweep_split) into offsets.
+hipError_t launch_nl_offsets(const unsigned long long* pcount, const uint32_t* ntiles_dev, int max_tiles,
+                             int split_rows, unsigned long long* offsets, hipStream_t s);
 // split_rows: rows a tile visits when its rows may be spread over waves
 // (sweep_split), 1 to keep one wave per tile (maps with per-particle outputs,
 // batches).

@@ -142,6 +142,7 @@ struct clm_celllist {
   JobDesc* job_dev;
   double* partials;
   unsigned long long* pcount;
+  unsigned long long* nl_off;  // neighbour lists: per-item output offsets
   int max_parts;
   double* E64;
   float* E32;

@@ -187,6 +187,10 @@ struct Sweep {
   double B[9];
   unsigned long long cnt_wave, cnt_lane;
   uint32_t qband, qnear;   // FP64 re-evaluations done by this lane (summed per tile)
+  bool qe;                 // neighbour list: this lane's queued entry is a member (qa, qb, qd)
+  uint32_t qa, qb;
+  double qd;
+  unsigned long long nl_base;  // neighbour list: next output slot of this work item
   // ---- visit
   float q[3];
   double t[3];
@@ -253,8 +257,13 @@ struct Sweep {
     n = n > kNLStage ? kNLStage : n;
     if (n > 0) {
       unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(ldu(&J->nl_counter), (unsigned long long)n);
-      base = __shfl(base, 0, kWave);
+      if (ldu(&J->nl_offsets)) {  // this work item's slots follow its offset
+        base = nl_base;
+        nl_base += (unsigned long long)n;
+      } else {
+        if (lane == 0) base = atomicAdd(ldu(&J->nl_counter), (unsigned long long)n);
+        base = __shfl(base, 0, kWave);
+      }
       for (int s = lane; s < n; s += kWave) nl_emit(L.nl_ij[2 * s], L.nl_ij[2 * s + 1], L.nl_d[s], base + s);
     }
     __builtin_amdgcn_wave_barrier();
@@ -273,6 +282,14 @@ struct Sweep {
   // certain members of one iteration (same j for every lane)
   __device__ __forceinline__ void nl_stage_wave(unsigned long long m, uint32_t j, double d) {
     if (m == 0) return;
+    uint32_t a = 0u, b = 0u;
+    if (__builtin_amdgcn_inverse_ballot_w64(m)) nl_pair(j, &a, &b);
+    nl_stage_lanes(m, a, b, d);
+  }
+
+  // the lanes of m stage their pair (a, b, d); called by the whole wave
+  __device__ __forceinline__ void nl_stage_lanes(unsigned long long m, uint32_t a, uint32_t b, double d) {
+    if (m == 0) return;
     const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
     int cnt = __popcll(m);
     int base = uniform(*(volatile int*)L.nl_fill);
@@ -282,8 +299,6 @@ struct Sweep {
     }
     if (in) {
       int slot = base + lane_rank(m);
-      uint32_t a, b;
-      nl_pair(j, &a, &b);
       L.nl_ij[2 * slot] = a;
       L.nl_ij[2 * slot + 1] = b;
       L.nl_d[slot] = d;
@@ -466,11 +481,13 @@ struct Sweep {
       hist_add(k);
       if (want_sums && k < nbins) hsum_add(k, sqrt(qq));
     }
-    if constexpr (kNL) {
+    if constexpr (kNL) {  // staged by the whole wave after this batch (drain)
       uint32_t a = ldu(&J->idx_x)[iL], b = IDXJ[j];
       if (!cross && a > b) { uint32_t tmp = a; a = b; b = tmp; }
-      const unsigned long long g = atomicAdd(ldu(&J->nl_counter), 1ull);
-      nl_emit(a, b, sqrt(d2), g);
+      qe = true;
+      qa = a;
+      qb = b;
+      qd = sqrt(d2);
     }
   }
 
@@ -480,6 +497,7 @@ struct Sweep {
     const uint32_t tl = (uint32_t)uniform((int)qtail);
     while (tl - h >= (uint32_t)kWave || (all && tl != h)) {
       const uint32_t nb = min(tl - h, (uint32_t)kWave);
+      if constexpr (kNL) qe = false;
       if ((uint32_t)lane < nb) {
         const uint2 e = Q[(h + (uint32_t)lane) & (uint32_t)(kQueueCap - 1)];
         const uint32_t b = (e.y >> 16) & 1u;  // band entries carry count_it
@@ -487,6 +505,7 @@ struct Sweep {
         qnear += 1u - b;
         process(e);
       }
+      if constexpr (kNL) nl_stage_lanes(__builtin_amdgcn_ballot_w64(qe), qa, qb, qd);
       h = (uint32_t)uniform((int)(h + nb));
     }
     qhead = h;
@@ -726,6 +745,11 @@ struct Sweep {
     qband = 0;
     qnear = 0;
     tstart = T.start;
+    const int local = (tile_id - ldu(&J->tile_begin)) * ngrp + grp;  // this job's partial slot
+    if constexpr (kNL) {
+      const unsigned long long* no = ldu(&J->nl_offsets);
+      nl_base = no ? ldu(&no[local]) : 0ull;
+    }
     qhead = 0;
     qtail = 0;
     if constexpr (FP32 && kLJF) {
@@ -831,7 +855,6 @@ struct Sweep {
     }
     if constexpr (kNL) nl_flush();
     const unsigned long long cnt = cnt_wave + wave_sum_u64(cnt_lane);
-    const int local = (tile_id - ldu(&J->tile_begin)) * ngrp + grp;  // this job's partial slot
     double* Pp = ldu(&J->partials) + (size_t)local * kPartialD;
     // every lane may hold queued FP64 contributions of other lanes' particles:
     // reduce over all lanes (inactive lanes contribute nothing of their own)
@@ -1390,7 +1413,43 @@ __global__ void __launch_bounds__(256) finalize_batch_kernel(const JobDesc* __re
   }
 }
 
+// ---------------------------------------------------------------- neighbour-list offsets
+// One block: exclusive prefix sums of the n = tiles * G per-item pair counts
+// of a counting sweep; thread t scans a contiguous chunk.
+__global__ void __launch_bounds__(1024) nl_offsets_kernel(const unsigned long long* __restrict__ pcount,
+                                                          const uint32_t* __restrict__ ntiles_dev, int cap,
+                                                          int split_rows, unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[1024];
+  const int nt = min((int)*ntiles_dev, cap);
+  const int n = nt * sweep_split(nt, cap, split_rows);
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  unsigned long long s = 0;
+  for (int k = lo; k < hi; ++k) s += pcount[k];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan of the chunk sums
+    const unsigned long long v = t >= d ? part[t - d] : 0ull;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  unsigned long long run = part[t] - s;
+  for (int k = lo; k < hi; ++k) {
+    out[k] = run;
+    run += pcount[k];
+  }
+}
+
 // ---------------------------------------------------------------- launchers
+hipError_t launch_nl_offsets(const unsigned long long* pcount, const uint32_t* ntiles_dev, int max_tiles,
+                             int split_rows, unsigned long long* offsets, hipStream_t s) {
+  if (max_tiles <= 0) return hipSuccess;
+  nl_offsets_kernel<<<1, 1024, 0, s>>>(pcount, ntiles_dev, max_tiles, split_rows, offsets);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_tiles(JobDesc* jobs, int njobs, Tile* tiles, uint32_t* total,
                                hipStream_t s) {
   gather_tiles_kernel<<<njobs, 256, 0, s>>>(jobs, njobs, tiles, total);
