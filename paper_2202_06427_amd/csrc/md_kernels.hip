@@ -298,10 +298,21 @@ __global__ void __launch_bounds__(kMdBlock) vl_rowstats_kernel(uint32_t* __restr
 //   (s / 64) cap 64 + (k / P) 64 P + (s % 64) P + k % P,
 // so that the P lanes of each of 64 / P consecutive rows read 64 consecutive
 // words.
-template <int DIM, bool WRITE>
+// Stores the WC entries of a chunk (WC = P: one row's P consecutive words).
+template <int WC>
+__device__ __forceinline__ void vl_store_chunk(uint32_t* p, const uint32_t* buf) {
+#pragma unroll
+  for (int q = 0; q < WC / 4; ++q)
+    reinterpret_cast<uint4*>(p)[q] = make_uint4(buf[4 * q], buf[4 * q + 1], buf[4 * q + 2], buf[4 * q + 3]);
+}
+
+// WC > 0 (= P, 4..16): entries are gathered in buf, one chunk of P
+// consecutive words of the row, and stored a chunk at a time (16-byte
+// stores instead of 4-byte ones); the caller stores the last partial chunk.
+template <int DIM, bool WRITE, int WC>
 __device__ __forceinline__ uint32_t vl_scan_row(const VlBuild& A, const Tile& T, uint32_t i,
                                                 const double* ri, int dz, int dy, uint32_t* row,
-                                                uint32_t c) {
+                                                uint32_t c, uint32_t* buf) {
   const int nx = A.n[0], ny = A.n[1], nz = A.n[2];
   const int cy = (int)(T.row % (uint32_t)ny);
   const int cz = DIM == 3 ? (int)(T.row / (uint32_t)ny) : 0;
@@ -332,8 +343,15 @@ __device__ __forceinline__ uint32_t vl_scan_row(const VlBuild& A, const Tile& T,
       if (d2 <= A.rl2 && j != i) {
         if (WRITE) {
           const uint32_t k = c + found;
-          if (k < (uint32_t)A.cap)
-            row[(size_t)(k >> lgP) * (kWave << lgP) + (k & pm)] = (j << 5) | (uint32_t)kc;
+          const uint32_t e = (j << 5) | (uint32_t)kc;
+          if constexpr (WC > 0) {
+#pragma unroll
+            for (int q = 0; q < WC; ++q) buf[q] = (k & (uint32_t)(WC - 1)) == (uint32_t)q ? e : buf[q];
+            if ((k & (uint32_t)(WC - 1)) == (uint32_t)(WC - 1) && k < (uint32_t)A.cap)
+              vl_store_chunk<WC>(row + (size_t)(k >> lgP) * (kWave << lgP), buf);
+          } else if (k < (uint32_t)A.cap) {
+            row[(size_t)(k >> lgP) * (kWave << lgP) + (k & pm)] = e;
+          }
         }
         ++found;
       }
@@ -359,7 +377,7 @@ __device__ __forceinline__ uint32_t vl_scan_row(const VlBuild& A, const Tile& T,
 // tile for lists of few particles, rows filled through atomic reservations
 // (two passes).  Without it a work item is a whole tile: one pass, each
 // lane owns its row and stores its length.
-template <int DIM>
+template <int DIM, int WC>
 __global__ void __launch_bounds__(kBuildWaves * kWave) vl_build_kernel(VlBuild A) {
   if (*A.gate == 0u) return;
   const int ntiles = min((int)ldu(A.ntiles), A.max_tiles);
@@ -387,17 +405,25 @@ __global__ void __launch_bounds__(kBuildWaves * kWave) vl_build_kernel(VlBuild A
     if (A.split) {
       const int dy = r % side - A.l;
       const int dz = DIM == 3 ? r / side - A.l : 0;
-      const uint32_t found = vl_scan_row<DIM, false>(A, T, i, ri, dz, dy, row, 0);
+      const uint32_t found = vl_scan_row<DIM, false, 0>(A, T, i, ri, dz, dy, row, 0, nullptr);
       if (active && found != 0) {
         const uint32_t c = atomicAdd(&A.cnt[i], found);
-        if (c < (uint32_t)A.cap) vl_scan_row<DIM, true>(A, T, i, ri, dz, dy, row, c);
+        if (c < (uint32_t)A.cap) vl_scan_row<DIM, true, 0>(A, T, i, ri, dz, dy, row, c, nullptr);
       }
     } else {
       uint32_t c = 0;
+      uint32_t buf[WC > 0 ? WC : 1];
+#pragma unroll
+      for (int q = 0; q < (WC > 0 ? WC : 1); ++q) buf[q] = 0u;
       for (int rr = 0; rr < nrow; ++rr) {
         const int dy = rr % side - A.l;
         const int dz = DIM == 3 ? rr / side - A.l : 0;
-        c += vl_scan_row<DIM, true>(A, T, i, ri, dz, dy, row, c);
+        c += vl_scan_row<DIM, true, WC>(A, T, i, ri, dz, dy, row, c, buf);
+      }
+      if constexpr (WC > 0) {  // the last, partial chunk (its unused words are never read)
+        const uint32_t k0 = c & ~(uint32_t)(WC - 1);
+        if ((c & (uint32_t)(WC - 1)) != 0u && k0 < (uint32_t)A.cap)
+          vl_store_chunk<WC>(row + (size_t)(k0 >> (uint32_t)A.lgP) * (kWave << A.lgP), buf);
       }
       if (active) A.cnt[i] = c;
     }
@@ -601,10 +627,21 @@ hipError_t launch_vl_build(int dim, const VlBuild& A, hipStream_t s) {
   const int64_t items = (int64_t)A.max_tiles * (A.split ? (dim == 3 ? side * side : side) : 1);
   const int64_t want = (items + kBuildWaves - 1) / kBuildWaves;
   const unsigned nb = (unsigned)(want < kBuildBlocks ? want : kBuildBlocks);
-  if (dim == 3)
-    vl_build_kernel<3><<<nb, kBuildWaves * kWave, 0, s>>>(A);
-  else
-    vl_build_kernel<2><<<nb, kBuildWaves * kWave, 0, s>>>(A);
+  // one pass per tile: entries stored a row chunk (P words) at a time
+  const int wc = !A.split && (A.P == 4 || A.P == 8 || A.P == 16) ? A.P : 0;
+#define CLM_VL_BUILD(D)                                                     \
+  switch (wc) {                                                             \
+    case 4: vl_build_kernel<D, 4><<<nb, kBuildWaves * kWave, 0, s>>>(A); break;   \
+    case 8: vl_build_kernel<D, 8><<<nb, kBuildWaves * kWave, 0, s>>>(A); break;   \
+    case 16: vl_build_kernel<D, 16><<<nb, kBuildWaves * kWave, 0, s>>>(A); break; \
+    default: vl_build_kernel<D, 0><<<nb, kBuildWaves * kWave, 0, s>>>(A); break;  \
+  }
+  if (dim == 3) {
+    CLM_VL_BUILD(3)
+  } else {
+    CLM_VL_BUILD(2)
+  }
+#undef CLM_VL_BUILD
   return hipGetLastError();
 }
 
