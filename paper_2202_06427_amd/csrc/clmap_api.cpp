@@ -807,6 +807,13 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
 
 clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
                    const clm_map_out* O) {
+  return map_one(cl, kind, P, O, true);
+}
+
+}  // extern "C"
+
+clm_status map_one(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P, const clm_map_out* O,
+                   bool nl_two_pass_ok) {
   JobDesc jd;
   FinalArgs F;
   int k_launch = 0;
@@ -816,7 +823,7 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
   hipStream_t st = cl->ctx->stream;
   // neighbour lists: a counting sweep gives every work item its output
   // offset, so the list sweep writes without a shared counter
-  const bool nl_two_pass = k_launch == K_NL && !B.small;
+  const bool nl_two_pass = nl_two_pass_ok && k_launch == K_NL && !B.small;
   if (nl_two_pass) jd.nl_offsets = cl->nl_off;
   CLM_HIP(launch_set_job(jd, cl->job_dev, st));
   Timed ts(cl->ctx, &cl->ctx->sweep_ev);
@@ -867,6 +874,8 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
   CLM_HIP(launch_finalize(cl->job_dev, F, cl->fin_scratch, cl->fin_count, st));
   return CLM_OK;
 }
+
+extern "C" {
 
 // ---------------------------------------------------------------- batched maps
 static size_t batch_layout(int njobs, int64_t tiles, size_t* o_jobs, size_t* o_fin, size_t* o_tiles,

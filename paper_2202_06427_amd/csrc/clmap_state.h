@@ -169,6 +169,13 @@ inline BuildGeom geom_of(const clm_box& B) {
   return g;
 }
 
+// clm_map; a neighbour list is written in two passes (a counting sweep gives
+// every work item its output offset) unless nl_two_pass_ok is false, when the
+// work items reserve output slots from one shared counter (cheaper for short
+// lists, where the counter is not contended).
+clm_status map_one(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P, const clm_map_out* O,
+                   bool nl_two_pass_ok);
+
 // Cell-list build whose kernels all return at once when `gate` (device
 // uint32) reads 0; gate == NULL builds unconditionally.
 clm_status celllist_build_gated(clm_celllist* cl, const double* x, const double* y,

@@ -161,7 +161,9 @@ clm_status clm_kclosest(clm_celllist* cl, int64_t k, int64_t cap, void* ws, size
     std::memset(&O, 0, sizeof O);
     O.pairs_dev = pairs;
     O.count_dev = ncount;
-    s = clm_map(cl, CLM_MAP_NEIGHBOR_LIST, &P, &O);
+    // up to 2^20 candidates the shared output counter is not contended: one
+    // sweep instead of a counting sweep and the list sweep
+    s = map_one(cl, CLM_MAP_NEIGHBOR_LIST, &P, &O, C > (uint64_t(1) << 20));
     if (s != CLM_OK) return s;
     uint64_t got = 0;
     s = fetch(ctx, &got, ncount, sizeof got);
