@@ -156,7 +156,13 @@ typedef struct clm_map_out {
   uint64_t* hist_dev;      /* HIST_*: nbins+1 counts, the last slot counts values above hist_hi */
   double* hist_sums_dev;   /* HIST_RELSPEED with want_sums, HIST_DIST_VEL: nbins FP64 */
   int32_t* pairs_dev;      /* NEIGHBOR_LIST: capacity x 2 (i, j); single set i < j;
-                              cross set i indexes x and j indexes y; order unspecified */
+                              cross set i indexes x and j indexes y.  Order: clm_map on
+                              a cell list with at least 2*lcell+1 cells per axis writes
+                              the pairs in an order fixed by the built cell list (a
+                              counting sweep first gives every work item its output
+                              offset), so repeated calls give the same list, also in
+                              clm_map_batch; small boxes take slots from a shared
+                              counter (order unspecified). */
   double* dist_dev;        /* NEIGHBOR_LIST with with_distances: capacity FP64 */
   uint64_t* count_dev;     /* [1] REQUIRED for every kind: number of pairs in the set.
                               NEIGHBOR_LIST: if *count_dev > capacity only the first

@@ -932,8 +932,10 @@ clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
   uint32_t* total_dev = (uint32_t*)(base + o_total);
   std::vector<JobDesc> jds;
   std::vector<FinalArgs> fas;
+  std::vector<clm_celllist*> bcl;  // the batched (not small-box) jobs' cell lists
   jds.reserve(njobs);
   fas.reserve(njobs);
+  bcl.reserve(njobs);
   int k_launch = -1, nbins = 0;
   for (int k = 0; k < njobs; ++k) {
     if (cls[k]->box.small) {  // brute-force minimum image: a job of its own
@@ -950,6 +952,8 @@ clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
       return fail(CLM_E_INVALID_ARG, "all jobs of a batch must launch the same map (virial flags differ)");
     k_launch = kl;
     nbins = jd.nbins;
+    if (kl == K_NL) jd.nl_offsets = cls[k]->nl_off;  // two passes, as in clm_map
+    bcl.push_back(cls[k]);
     jd.own_tiles = cls[k]->tiles;
     jd.own_ntiles = &cls[k]->row_off[cls[k]->nrows];
     jd.own_max_tiles = cls[k]->max_tiles;
@@ -970,6 +974,14 @@ clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
   Timed ts(ctx, &ctx->sweep_ev);
   clm_status s = ts.start();
   if (s != CLM_OK) return s;
+  if (k_launch == K_NL) {  // counting sweep, then each job's per-tile output offsets
+    CLM_HIP(launch_sweep(dim, prec == CLM_FP32_GUARD, K_COUNT, jobs_dev, tiles_dev, total_dev,
+                         (int)std::min<int64_t>(maxt, INT32_MAX), 0, st));
+    for (clm_celllist* c : bcl) {
+      CLM_HIP(launch_nl_offsets(c->pcount, &c->row_off[c->nrows], c->max_tiles, 1, c->nl_off, st));
+      CLM_HIP(launch_fill_u64(c->guard, 2, 0ull, st));
+    }
+  }
   CLM_HIP(launch_sweep(dim, prec == CLM_FP32_GUARD, k_launch, jobs_dev, tiles_dev, total_dev,
                        (int)std::min<int64_t>(maxt, INT32_MAX), nbins, st));
   s = ts.stop();

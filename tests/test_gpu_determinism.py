@@ -1,6 +1,7 @@
 """Repeated maps over the same cell list give bitwise-identical results: the
 per-tile (or per tile and row group) partials are reduced in a fixed order,
-and forces are written by the wave that holds the particle.  Checked where
+forces are written by the wave that holds the particle, and neighbour lists
+are written at offsets from a counting pass (same pairs in the same order).  Checked where
 the rows of a tile are spread over several waves (few tiles: small sets,
 cross sets) and where they are not (10^5 particles), in both precisions.
 Per-bin FP64 sums of the speed histograms are merged with device atomics and
@@ -43,6 +44,9 @@ def _maps(cl, v):
     out["hist128"] = h.cpu().numpy().copy()
     hd = cl.dist_vel_histogram(v, 10)
     out["dv_counts"] = hd[0].cpu().numpy().copy()
+    pairs, dist = cl.neighbor_list()  # two-pass list: the order is fixed too
+    out["nl_pairs"] = pairs.cpu().numpy().copy()
+    out["nl_dist"] = dist.cpu().numpy().copy()
     return out
 
 
