@@ -1189,73 +1189,80 @@ __global__ void __launch_bounds__(256) finalize1_kernel(const JobDesc* __restric
                                                         double* __restrict__ scratch,
                                                         unsigned long long* __restrict__ scount) {
   const JobDesc& J = jobs[0];
-  __shared__ double red[256];
-  __shared__ unsigned long long redc[256];
-  const int tid = threadIdx.x;
+  __shared__ double red[4][kPartialD];
+  __shared__ unsigned long long redc[4];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   int nparts = F.nparts_dev ? min((int)*F.nparts_dev, F.nparts) : F.nparts;
   if (F.nparts_dev) nparts *= sweep_split(nparts, F.nparts, F.split_rows);
   const int chunk = (nparts + gridDim.x - 1) / gridDim.x;
   const int lo = blockIdx.x * chunk, hi = min(nparts, lo + chunk);
-  unsigned long long c = 0;
-  for (int k = lo + tid; k < hi; k += 256) c += J.pcount[k];
-  redc[tid] = c;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (tid < st) redc[tid] += redc[tid + st];
-    __syncthreads();
-  }
-  if (tid == 0) scount[blockIdx.x] = redc[0];
   const int nslots = final_slots(F.kind);
-  for (int slot = 0; slot < nslots; ++slot) {
-    double v = 0.0;
-    for (int k = lo + tid; k < hi; k += 256) v += J.partials[(size_t)k * kPartialD + slot];
-    red[tid] = v;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    if (tid == 0) scratch[(size_t)blockIdx.x * kPartialD + slot] = red[0];
-    __syncthreads();
+  // every slot at once: thread sums, then a shuffle tree per wave, then the
+  // four waves in order
+  unsigned long long c = 0;
+  double v[kPartialD];
+#pragma unroll
+  for (int q = 0; q < kPartialD; ++q) v[q] = 0.0;
+  for (int k = lo + tid; k < hi; k += 256) {
+    c += J.pcount[k];
+#pragma unroll
+    for (int q = 0; q < kPartialD; ++q)
+      if (q < nslots) v[q] += J.partials[(size_t)k * kPartialD + q];
   }
+  c = wave_sum_u64(c);
+  if (lane == 0) redc[w] = c;
+#pragma unroll
+  for (int q = 0; q < kPartialD; ++q) {
+    if (q < nslots) {
+      const double t = wave_sum_d(v[q]);
+      if (lane == 0) red[w][q] = t;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) scount[blockIdx.x] = ((redc[0] + redc[1]) + redc[2]) + redc[3];
+  if (tid < nslots) scratch[(size_t)blockIdx.x * kPartialD + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
 }
 
+// One block of kFinalBlocks threads: the block results in a fixed order
+// (shuffle trees, then the waves in order); thread q writes output slot q.
 __global__ void __launch_bounds__(kFinalBlocks) finalize2_kernel(FinalArgs F,
                                                                  const double* __restrict__ scratch,
                                                                  const unsigned long long* __restrict__ scount) {
-  __shared__ double red[kFinalBlocks];
-  __shared__ unsigned long long redc[kFinalBlocks];
-  const int tid = threadIdx.x;
-  redc[tid] = scount[tid];
-  __syncthreads();
-  for (int st = kFinalBlocks / 2; st > 0; st >>= 1) {
-    if (tid < st) redc[tid] += redc[tid + st];
-    __syncthreads();
-  }
-  if (tid == 0 && F.count) *F.count = F.halve_count ? redc[0] / 2 : redc[0];
+  constexpr int kW = kFinalBlocks / kWave;
+  __shared__ double red[kW][kPartialD];
+  __shared__ unsigned long long redc[kW];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int nslots = final_slots(F.kind);
-  for (int slot = 0; slot < nslots; ++slot) {
-    red[tid] = scratch[(size_t)tid * kPartialD + slot];
-    __syncthreads();
-    for (int st = kFinalBlocks / 2; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
-      __syncthreads();
+  const unsigned long long c = wave_sum_u64(scount[tid]);
+  if (lane == 0) redc[w] = c;
+#pragma unroll
+  for (int q = 0; q < kPartialD; ++q) {
+    if (q < nslots) {
+      const double t = wave_sum_d(scratch[(size_t)tid * kPartialD + q]);
+      if (lane == 0) red[w][q] = t;
     }
-    if (tid == 0) {
-      const double tot = red[0];
-      if (slot == P_SUM && F.energy) {
-        const bool lj = F.kind == K_LJ_E || F.kind == K_LJ_F || F.kind == K_LJ_FV;
-        *F.energy = (lj ? 4.0 * F.eps : 1.0) * tot;
-      } else if (slot >= P_VIR && slot < P_VIR + 9 && F.virial && F.want_virial) {
-        const int k = slot - P_VIR, a = k / 3, b = k % 3;
-        if (a < F.dim && b < F.dim) F.virial[a * F.dim + b] = 24.0 * F.eps * tot;
-      } else if (slot >= P_BOX && slot < P_BOX + 9 && F.grad_box) {
-        const int k = slot - P_BOX, a = k / 3, b = k % 3;
-        const double g = F.upstream ? *F.upstream : F.box_mult;
-        if (a < F.dim && b < F.dim) F.grad_box[a * F.dim + b] = -24.0 * F.eps * g * tot;
-      }
+  }
+  __syncthreads();
+  if (tid == 0 && F.count) {
+    unsigned long long n = 0;
+    for (int k = 0; k < kW; ++k) n += redc[k];
+    *F.count = F.halve_count ? n / 2 : n;
+  }
+  if (tid < nslots) {
+    const int slot = tid;
+    double tot = 0.0;
+    for (int k = 0; k < kW; ++k) tot += red[k][slot];
+    if (slot == P_SUM && F.energy) {
+      const bool lj = F.kind == K_LJ_E || F.kind == K_LJ_F || F.kind == K_LJ_FV;
+      *F.energy = (lj ? 4.0 * F.eps : 1.0) * tot;
+    } else if (slot >= P_VIR && slot < P_VIR + 9 && F.virial && F.want_virial) {
+      const int k = slot - P_VIR, a = k / 3, b = k % 3;
+      if (a < F.dim && b < F.dim) F.virial[a * F.dim + b] = 24.0 * F.eps * tot;
+    } else if (slot >= P_BOX && slot < P_BOX + 9 && F.grad_box) {
+      const int k = slot - P_BOX, a = k / 3, b = k % 3;
+      const double g = F.upstream ? *F.upstream : F.box_mult;
+      if (a < F.dim && b < F.dim) F.grad_box[a * F.dim + b] = -24.0 * F.eps * g * tot;
     }
-    __syncthreads();
   }
 }
 
