@@ -388,6 +388,8 @@ def calibrate(kind, nbytes=1 << 30, reps=10, device="cuda:0"):
     L.check(L.lib().clm_calibrate_scratch_bytes(k, ctypes.byref(need)))
     if kind == "copy":
         nbytes = int(nbytes) // 16 * 16
+        if nbytes < 16:
+            raise ValueError("copy calibration needs at least 16 bytes")
         src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         src.fill_(1)
         dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
