@@ -226,66 +226,89 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const uint32_t
 }
 
 // ---------------------------------------------------------------- tiles
-// One thread per cell row (cy, cz): greedy tiles of consecutive sorted
+// One wave per cell row (cy, cz): greedy tiles of consecutive sorted
 // particles, whole cells only, <= 64 particles and <= smax cells; a cell with
-// more than 64 particles is split into chunks of 64.
+// more than 64 particles is split into chunks of 64.  The lanes load the
+// row's cell offsets (64 cells per load); the greedy walk then runs on
+// wave-uniform values read from the lanes, so a row costs one load round
+// trip per 64 cells instead of one per cell.
+constexpr int kTileRowsPerBlock = 256 / kWave;
+
 template <bool EMIT>
 __device__ uint32_t walk_row(const uint32_t* __restrict__ off, const TileGeom& g, int row,
-                             Tile* __restrict__ tiles, uint32_t t0) {
+                             Tile* __restrict__ tiles, uint32_t t0, int lane) {
   const int nx = g.n[0];
   const uint32_t* o = off + (size_t)row * nx;
   uint32_t nt = 0;
-  int cx = 0;
-  while (cx < nx) {
-    uint32_t a = o[cx], b = o[cx + 1];
-    uint32_t cnt = b - a;
-    if (cnt == 0) { ++cx; continue; }
-    if (cnt > (uint32_t)kTileMax) {
-      for (uint32_t s = a; s < b; s += kTileMax) {
-        if (EMIT && t0 + nt < g.max_tiles) {
-          uint32_t c = b - s < (uint32_t)kTileMax ? b - s : (uint32_t)kTileMax;
-          tiles[t0 + nt] = Tile{s, (uint32_t)row, (uint16_t)c, (uint16_t)cx, (uint16_t)cx, (uint16_t)g.job};
-        }
-        ++nt;
-      }
-      ++cx;
-      continue;
-    }
-    const int c0 = cx;
-    int last = cx;
-    uint32_t tcount = cnt;
-    ++cx;
-    while (cx < nx && cx - c0 < g.smax) {
-      uint32_t c2 = o[cx + 1] - o[cx];
-      if (c2 == 0) { ++cx; continue; }
-      if (tcount + c2 > (uint32_t)kTileMax) break;
-      tcount += c2;
-      last = cx;
-      ++cx;
-    }
-    if (EMIT && t0 + nt < g.max_tiles)
-      tiles[t0 + nt] = Tile{a, (uint32_t)row, (uint16_t)tcount, (uint16_t)c0, (uint16_t)last, (uint16_t)g.job};
+  bool open = false;  // a tile of cells c0..last (tcount particles from a0) is open
+  int c0 = 0, last = 0;
+  uint32_t a0 = 0, tcount = 0;
+  auto emit = [&](uint32_t start, uint32_t count, int first, int lastc) {
+    if (EMIT && lane == 0 && t0 + nt < g.max_tiles)
+      tiles[t0 + nt] = Tile{start, (uint32_t)row, (uint16_t)count, (uint16_t)first, (uint16_t)lastc,
+                            (uint16_t)g.job};
     ++nt;
-    cx = last + 1;
+  };
+  for (int cs = 0; cs < nx; cs += kWave) {
+    uint32_t av = 0u, bv = 0u;
+    if (cs + lane < nx) {
+      av = o[cs + lane];
+      bv = o[cs + lane + 1];
+    }
+    const int nch = nx - cs < kWave ? nx - cs : kWave;
+    for (int L = 0; L < nch; ++L) {
+      const int cx = cs + L;
+      const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)av, L);
+      const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)bv, L) - a;
+      if (open) {
+        // the open tile ends at smax cells, or before a cell that does not fit
+        if (cx - c0 >= g.smax || (cnt != 0u && tcount + cnt > (uint32_t)kTileMax)) {
+          emit(a0, tcount, c0, last);
+          open = false;
+        } else {
+          if (cnt != 0u) {
+            tcount += cnt;
+            last = cx;
+          }
+          continue;
+        }
+      }
+      if (cnt == 0u) continue;
+      if (cnt > (uint32_t)kTileMax) {  // a heavy cell: chunks of 64
+        for (uint32_t s = a; s < a + cnt; s += kTileMax) {
+          const uint32_t c = a + cnt - s < (uint32_t)kTileMax ? a + cnt - s : (uint32_t)kTileMax;
+          emit(s, c, cx, cx);
+        }
+        continue;
+      }
+      open = true;
+      c0 = cx;
+      last = cx;
+      a0 = a;
+      tcount = cnt;
+    }
   }
+  if (open) emit(a0, tcount, c0, last);
   return nt;
 }
 
 __global__ void __launch_bounds__(256) tiles_count_kernel(const uint32_t* __restrict__ off, TileGeom g,
                                                           uint32_t* __restrict__ row_tiles,
                                                           const uint32_t* __restrict__ gate) {
-  int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int row = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kTileRowsPerBlock + threadIdx.x / kWave));
   if (row >= g.nrows || gate_closed(gate)) return;
-  row_tiles[row] = walk_row<false>(off, g, row, nullptr, 0);
+  const uint32_t nt = walk_row<false>(off, g, row, nullptr, 0, lane);
+  if (lane == 0) row_tiles[row] = nt;
 }
-
 __global__ void __launch_bounds__(256) tiles_emit_kernel(const uint32_t* __restrict__ off, TileGeom g,
                                                          const uint32_t* __restrict__ row_off,
                                                          Tile* __restrict__ tiles,
                                                          const uint32_t* __restrict__ gate) {
-  int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int row = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kTileRowsPerBlock + threadIdx.x / kWave));
   if (row >= g.nrows || gate_closed(gate)) return;
-  walk_row<true>(off, g, row, tiles, row_off[row]);
+  walk_row<true>(off, g, row, tiles, row_off[row], lane);
 }
 
 // ---------------------------------------------------------------- small helpers
@@ -459,7 +482,7 @@ hipError_t launch_scatter(const double* x, int n, const BuildGeom& g, const uint
 hipError_t launch_tiles(const uint32_t* off, const TileGeom& g, uint32_t* row_tiles,
                         uint32_t* row_off, uint32_t* scan_scratch, Tile* tiles, hipStream_t s,
                         const uint32_t* gate) {
-  const int nb = (g.nrows + 255) / 256;
+  const int nb = (g.nrows + kTileRowsPerBlock - 1) / kTileRowsPerBlock;
   tiles_count_kernel<<<nb, 256, 0, s>>>(off, g, row_tiles, gate);
   hipError_t e = launch_scan(row_tiles, g.nrows, scan_scratch, row_off, s, gate);
   if (e != hipSuccess) return e;
