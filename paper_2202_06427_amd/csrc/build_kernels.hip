@@ -6,7 +6,7 @@
 //   bin      one thread per particle: canonical FP64 wrap into the primary
 //            cell, fractional cell index, rank = atomicAdd(count[cell])
 //   scan     exclusive prefix of the counts -> cell offsets
-//   tiles    one thread per cell row: greedy work units of <= 64 particles
+//   tiles    one wave per cell row: greedy work units of <= 64 particles
 //   scatter  one thread per particle: FP32 cell-local offset, FP64 wrapped
 //            position, original index and wrap integers at offset+rank
 // Every kernel is HBM- or latency-bound; nothing here is a dense contraction.

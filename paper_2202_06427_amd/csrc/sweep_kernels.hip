@@ -14,7 +14,11 @@
 // Half shell (single set, symmetric maps): neighbour cells with offset
 // (dz, dy) > 0 lexicographically, plus the home row where j > i in sorted
 // order (the sorted order follows the cells along x).  Full shell (LJ
-// forces as a gather, cross sets): every neighbour cell.
+// forces as a gather, cross sets): every neighbour cell.  A neighbour row's
+// cell offsets are loaded once, one cell per lane; with few tiles the rows
+// of a tile are spread over several waves (sweep_split), each with its own
+// partial slot.  Neighbour lists take their output offsets from a counting
+// sweep over the same work items (or slots from a shared counter).
 //
 // Precision forms:
 //  FP64 (canonical): D = (r'_j - r'_i) + H K, d2 = (Dx^2 + Dy^2) + Dz^2 with
@@ -25,7 +29,8 @@
 //   (the band, computed on the host) classifies each candidate as certainly
 //   in, certainly out, or uncertain; uncertain candidates (and histogram
 //   values within the band of a bin edge, and LJ pairs closer than the near
-//   threshold) are recomputed in canonical FP64 inline.
+//   threshold) are queued per wave in LDS and recomputed in canonical FP64,
+//   64 at a time.
 #include "clmap_internal.h"
 
 namespace clm {
