@@ -57,7 +57,9 @@ def build(verbose=False, jobs=None):
     with cf.ThreadPoolExecutor(max_workers=jobs or min(4, len(procs))) as ex:
         list(ex.map(lambda c: _run(c, verbose), procs))
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950"] + objs + ["-o", tmp], verbose)
+    # export only the C-ABI (clm_*), see csrc/libclmap.map
+    exports = "-Wl,--version-script=" + os.path.join(CSRC, "libclmap.map")
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", exports] + objs + ["-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 
