@@ -689,3 +689,115 @@ def test_distance_binned_relative_speed():
     assert np.allclose(r["dv_sum"], sums, rtol=1e-12, atol=0)
     r0 = oracle.compute(x, H, rc, dist_vel_hist=(10, rc), vel_x=np.ones_like(x))
     assert np.all(r0["dv_sum"] == 0.0)
+
+
+# ---------------------------------------------------------------- per-particle LJ and neighbours of one particle
+
+def _numpy_min_images(x, i, H):
+    """For every j: the image K (raw coordinates) minimising |x_j - x_i + H K|
+    and that squared distance, by an exhaustive numpy search of K0 + {-2..2}^dim
+    around K0 = -round(H^-1 (x_j - x_i)) (independent of the oracle's search)."""
+    dim = H.shape[0]
+    Hi = np.linalg.inv(H)
+    dr = x - x[i]
+    K0 = -np.rint(dr @ Hi.T)
+    rng = np.arange(-2, 3)
+    off = np.stack(np.meshgrid(*([rng] * dim), indexing="ij"), -1).reshape(-1, dim)
+    Ks = K0[:, None, :] + off[None, :, :]                      # (n, 5^dim, dim)
+    D = dr[:, None, :] + Ks @ H.T
+    d2 = (D * D).sum(-1)
+    k = d2.argmin(1)
+    return d2[np.arange(len(x)), k], Ks[np.arange(len(x)), k].astype(np.int64)
+
+
+def _lj_pair(d2, s, e):
+    """u(d) = 4 eps (x^6 - x^3), x = s^2/d^2 (paper Code 6), and
+    f_s = 24 eps (2 x^6 - x^3) / d^2, the factor of D in dE/dr_i."""
+    x = s * s / d2
+    x3 = x ** 3
+    return 4 * e * (x3 * x3 - x3), 24 * e * (2 * x3 * x3 - x3) / d2
+
+
+SAMPLE_CASES = [("tric3", 500, 6.5, 0.0), ("skew3", 500, 6.0, 0.0), ("tric2", 400, 7.0, 0.0),
+                ("tric3", 500, 6.5, 1.0)]
+
+
+@pytest.mark.parametrize("name,n,rc,far", SAMPLE_CASES)
+def test_lj_sample_against_numpy_enumeration_and_compute(name, n, rc, far):
+    """E_i and dE/dr_i of lj_sample (Code 6 energy, its exact gradient) against
+    (a) a numpy enumeration of each sampled particle's pairs with the
+    exhaustively searched nearest image, (b) the gradient rows of compute()
+    for the same particles, and (c) sum_i E_i = 2E over all particles."""
+    H = BOXES[name]
+    dim = H.shape[0]
+    s, e = 3.0, 0.238
+    x = _lattice(H, 8 if dim == 3 else 20, 171 + n)[:n]
+    if far:  # far from the origin: raw coordinates many boxes away
+        x = x + np.array([1000, -700, 300][:dim]) @ H.T
+    full = oracle.compute(x, H, rc, lj=(s, e), lj_grad=True)
+    sample = np.array([0, 7, 101, n // 2, n - 1])
+    Ei, Gi = oracle.lj_sample(x, H, rc, sample, s, e)
+    for k, i in enumerate(sample):
+        d2, K = _numpy_min_images(x, i, H)
+        m = (d2 <= rc * rc) & (np.arange(n) != i)
+        D = (x[m] - x[i]) + K[m] @ H.T
+        u, fs = _lj_pair((D * D).sum(1), s, e)
+        assert math.isclose(Ei[k], u.sum(), rel_tol=1e-11, abs_tol=1e-12)
+        gref = (fs[:, None] * D).sum(0)
+        scale = np.abs(fs[:, None] * D).sum()
+        assert np.abs(Gi[k] - gref).max() <= 1e-11 * scale
+        assert np.abs(Gi[k] - full["lj_grad"][i]).max() <= 1e-12 * scale
+    Eall, _ = oracle.lj_sample(x, H, rc, np.arange(n), s, e)
+    assert math.isclose(Eall.sum(), 2 * full["lj_energy"], rel_tol=1e-12)
+
+
+def test_lj_sample_sign_against_a_two_particle_closed_form():
+    """Two particles on the x axis at distance d: E_0 = u(d) and dE/dr_0 =
+    -u'(d) e_x (pulling 0 towards 1 lowers E beyond the minimum)."""
+    H = np.diag([30.0, 30.0, 30.0])
+    s, e = 3.4, 0.238
+    for d in (3.2, 3.4 * 2 ** (1 / 6), 5.0):
+        x = np.array([[10.0, 10.0, 10.0], [10.0 + d, 10.0, 10.0]])
+        E, G = oracle.lj_sample(x, H, 8.0, np.array([0, 1]), s, e)
+        u = 4 * e * ((s / d) ** 12 - (s / d) ** 6)
+        du = 4 * e * (-12 * s ** 12 / d ** 13 + 6 * s ** 6 / d ** 7)
+        assert math.isclose(E[0], u, rel_tol=1e-13, abs_tol=1e-15)
+        assert math.isclose(G[0, 0], -du, rel_tol=1e-12, abs_tol=1e-14)
+        assert math.isclose(G[1, 0], du, rel_tol=1e-12, abs_tol=1e-14)
+        assert np.abs(G[:, 1:]).max() == 0.0
+
+
+@pytest.mark.parametrize("name,n,rc,far", SAMPLE_CASES)
+def test_neighbors_of_against_numpy_enumeration_and_the_list(name, n, rc, far):
+    """neighbors_of(i): the j with nearest-image distance <= rc and the raw
+    image K with x_j - x_i + H K the nearest displacement; against a numpy
+    exhaustive search (set and K exactly) and against the neighbour list of
+    compute() (the pairs containing i, and their distances to rounding)."""
+    H = BOXES[name]
+    dim = H.shape[0]
+    x = W.uniform_in_box(n, H, 181 + n)
+    # every particle displaced by its own lattice vector (different wrap
+    # integers per particle), and far from the origin for `far`
+    x = x + W.rng(191 + n).integers(-3, 4, size=(n, dim)) @ H.T
+    if far:
+        x = x + np.array([1000, -700, 300][:dim]) @ H.T
+    nl = oracle.compute(x, H, rc, nl=True)
+    pairs_i, pairs_j, pairs_d = nl["nl_i"], nl["nl_j"], nl["nl_d"]
+    for i in (0, 3, n // 3, n - 1):
+        js, Ks = oracle.neighbors_of(x, H, rc, i)
+        d2, Kref = _numpy_min_images(x, i, H)
+        # pairs within 1e-9 rc^2 of the cutoff would be decided by rounding
+        assert not np.any((np.abs(d2 - rc * rc) < 1e-9 * rc * rc) & (np.arange(n) != i))
+        want = np.nonzero((d2 <= rc * rc) & (np.arange(n) != i))[0]
+        assert np.array_equal(np.sort(js), want)
+        order = np.argsort(js)
+        assert np.array_equal(Ks[order], Kref[want])
+        # the list's pairs containing i, with i's partner and distance
+        sel = (pairs_i == i) | (pairs_j == i)
+        other = np.where(pairs_i[sel] == i, pairs_j[sel], pairs_i[sel])
+        assert np.array_equal(np.sort(other), want)
+        D = (x[js] - x[i]) + Ks @ H.T
+        dd = np.sqrt((D * D).sum(1))
+        ref_d = dict(zip(other.tolist(), pairs_d[sel].tolist()))
+        for j, dj in zip(js.tolist(), dd.tolist()):
+            assert math.isclose(dj, ref_d[j], rel_tol=1e-9, abs_tol=1e-9 * (1 + 1e3 * far))
