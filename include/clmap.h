@@ -199,7 +199,7 @@ clm_status clm_box_nonperiodic(int dim, const double* lo, const double* hi, doub
 clm_status clm_extrema_workspace_bytes(int64_t n, size_t* bytes);
 clm_status clm_extrema(clm_context* ctx, int dim, const double* x_dev, int64_t n, void* workspace_dev,
                        size_t workspace_bytes, double* lo, double* hi);
-/* Triclinic box from lengths (a, b, c) and angles in degrees (alpha =/* Triclinic box from lengths (a, b, c) and angles in degrees (alpha =
+/* Triclinic box from lengths (a, b, c) and angles in degrees (alpha =
  * angle(b,c), beta = angle(a,c), gamma = angle(a,b)); a along x, b in xy. */
 clm_status clm_box_from_lengths_angles(const double* lengths, const double* angles_deg,
                                        double cutoff, int lcell, clm_box** out);
@@ -234,6 +234,26 @@ clm_status clm_map_batch_workspace_bytes(int njobs, clm_celllist* const* cls, si
 clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
                          const clm_map_params* params, const clm_map_out* outs, void* workspace_dev,
                          size_t workspace_bytes);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bin and
+ * map in one call with no workspace argument and no allocation.  The cell
+ * list is placed in a static device array of the library (its size from
+ * clm_map_static_max_bytes: 64 MiB, held on every device the library runs
+ * on until the process ends).  Arguments as clm_celllist_create +
+ * clm_celllist_build + clm_map with x_dev / y_dev (n_x*dim and n_y*dim FP64,
+ * y_dev NULL and n_y = 0 for a single set); results, order of neighbour
+ * lists included, equal theirs.  Asynchronous on the context's stream; the
+ * inputs may be freed once the call's work has run.  Errors: as those calls,
+ * plus CLM_E_CAPACITY (synchronously, before any launch) when the cell list
+ * needs more than the static array (clm_celllist_workspace_bytes).  Every
+ * call on one device shares that device's array: calls that overlap on one
+ * device (different streams or host threads) race.  Timing events
+ * (clm_context_set_timing) are not recorded for these calls. */
+clm_status clm_map_static_max_bytes(size_t* bytes);
+clm_status clm_map_static(clm_context* ctx, const clm_box* box, const double* x_dev, int64_t n_x,
+                          const double* y_dev, int64_t n_y, clm_precision precision,
+                          clm_map_kind kind, const clm_map_params* params, const clm_map_out* out);
 
 /* Host-side counters of the last build (synchronizes the stream). */
 clm_status clm_celllist_info_get(clm_celllist* cl, clm_celllist_info* out);

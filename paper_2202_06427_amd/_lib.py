@@ -89,6 +89,7 @@ EXPORTS = [
     "clm_celllist_info_get", "clm_celllist_destroy", "clm_synchronize", "clm_last_error",
     "clm_status_string", "clm_context_set_timing", "clm_stats_get", "clm_map_batch_workspace_bytes",
     "clm_map_batch", "clm_box_nonperiodic", "clm_extrema_workspace_bytes", "clm_extrema",
+    "clm_map_static_max_bytes", "clm_map_static",
     # include/clmap_md.h
     "clm_md_workspace_bytes", "clm_md_create", "clm_md_kick_drift", "clm_md_kick", "clm_md_destroy",
     "clm_vlist_workspace_bytes", "clm_vlist_create", "clm_vlist_update", "clm_vlist_lj",
@@ -140,6 +141,9 @@ def lib():
     L.clm_map_batch.argtypes = [c_int, ctypes.POINTER(_vp), c_int, ctypes.POINTER(MapParams),
                                 ctypes.POINTER(MapOut), _vp, ctypes.c_size_t]
     szp = ctypes.POINTER(ctypes.c_size_t)
+    L.clm_map_static_max_bytes.argtypes = [szp]
+    L.clm_map_static.argtypes = [_vp, _vp, _vp, c_i64, _vp, c_i64, c_int, c_int,
+                                 ctypes.POINTER(MapParams), ctypes.POINTER(MapOut)]
     L.clm_md_workspace_bytes.argtypes = [c_i64, szp]
     L.clm_md_create.argtypes = [_vp, c_int, c_i64, c_d, c_d, _vp, ctypes.c_size_t, pvp]
     L.clm_md_kick_drift.argtypes = [_vp, _vp, _vp, _vp, c_d]

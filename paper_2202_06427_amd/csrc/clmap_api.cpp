@@ -530,14 +530,30 @@ clm_status clm_celllist_create(clm_context* ctx, const clm_box* box, int64_t n_x
   if (!ctx || !out) return fail(CLM_E_INVALID_ARG, "NULL argument");
   clm_status s = check_sizes(box, n_x, n_y, precision);
   if (s != CLM_OK) return s;
+  auto* cl = new (std::nothrow) clm_celllist;
+  if (!cl) return fail(CLM_E_INVALID_ARG, "out of host memory");
+  s = celllist_init(cl, ctx, box, n_x, n_y, precision, ws, ws_bytes);
+  if (s != CLM_OK) {
+    delete cl;
+    return s;
+  }
+  *out = cl;
+  return CLM_OK;
+}
+
+}  // extern "C"
+
+clm_status celllist_init(clm_celllist* cl, clm_context* ctx, const clm_box* box, int64_t n_x,
+                         int64_t n_y, clm_precision precision, void* ws, size_t ws_bytes) {
+  if (!ctx || !cl) return fail(CLM_E_INVALID_ARG, "NULL argument");
+  clm_status s = check_sizes(box, n_x, n_y, precision);
+  if (s != CLM_OK) return s;
   size_t need = 0;
   clm_celllist_workspace_bytes(box, n_x, n_y, precision, &need);
   if (!ws) return fail(CLM_E_WORKSPACE, "workspace is NULL");
   if (((uintptr_t)ws & 255) != 0) return fail(CLM_E_WORKSPACE, "workspace must be 256-byte aligned");
   if (ws_bytes < need)
     return fail(CLM_E_WORKSPACE, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
-  auto* cl = new (std::nothrow) clm_celllist;
-  if (!cl) return fail(CLM_E_INVALID_ARG, "out of host memory");
   std::memset(cl, 0, sizeof *cl);
   cl->ctx = ctx;
   cl->box = *box;
@@ -550,11 +566,8 @@ clm_status clm_celllist_create(clm_context* ctx, const clm_box* box, int64_t n_x
   size_t tot = 0;
   layout(cl, (char*)ws, &tot);
   if (!cl->cross) cl->Y = cl->X;
-  *out = cl;
   return CLM_OK;
 }
-
-}  // extern "C"
 
 static clm_status build_set(clm_celllist* cl, const double* x, int64_t n, SetBufs& S,
                             const uint32_t* gate) {
@@ -575,7 +588,7 @@ clm_status celllist_build_gated(clm_celllist* cl, const double* x, const double*
   if (cl->cross && cl->ny > 0 && !y) return fail(CLM_E_INVALID_ARG, "y is NULL for a cross set");
   if (!cl->cross && y) return fail(CLM_E_INVALID_ARG, "y given but the cell list has n_y = 0");
   CLM_HIP(hipSetDevice(cl->ctx->device));
-  Timed tb(cl->ctx, &cl->ctx->build_ev);
+  Timed tb(cl->untimed ? nullptr : cl->ctx, &cl->ctx->build_ev);
   clm_status s = tb.start();
   if (s != CLM_OK) return s;
   s = build_set(cl, x, cl->nx, cl->X, gate);
@@ -826,7 +839,7 @@ clm_status map_one(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
   const bool nl_two_pass = nl_two_pass_ok && k_launch == K_NL && !B.small;
   if (nl_two_pass) jd.nl_offsets = cl->nl_off;
   CLM_HIP(launch_set_job(jd, cl->job_dev, st));
-  Timed ts(cl->ctx, &cl->ctx->sweep_ev);
+  Timed ts(cl->untimed ? nullptr : cl->ctx, &cl->ctx->sweep_ev);
   s = ts.start();
   if (s != CLM_OK) return s;
   if (B.small) {

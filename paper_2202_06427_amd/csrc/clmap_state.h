@@ -68,7 +68,7 @@ struct Timed {
   bool on = false;
   Timed(clm_context* ctx, std::vector<EventPair>* d) : c(ctx), dst(d) {}
   clm_status start() {
-    if (!c->timing || dst->size() >= 4096) return CLM_OK;
+    if (!c || !c->timing || dst->size() >= 4096) return CLM_OK;
     clm_status s = take_events(c, &ev);
     if (s != CLM_OK) return s;
     CLM_HIP(hipEventRecord(ev.a, c->stream));
@@ -155,6 +155,7 @@ struct clm_celllist {
   unsigned long long* fin_count;
   double* brute_fb;       // small boxes: per-chunk LJ force rows
   int built;
+  int untimed;            // never record timing events (no runtime objects created)
 };
 
 // ---------------------------------------------------------------- shared helpers
@@ -175,6 +176,11 @@ inline BuildGeom geom_of(const clm_box& B) {
 // lists, where the counter is not contended).
 clm_status map_one(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P, const clm_map_out* O,
                    bool nl_two_pass_ok);
+
+// Fills a caller-provided cell-list handle over workspace `ws` (the body of
+// clm_celllist_create without the host allocation of the handle).
+clm_status celllist_init(clm_celllist* cl, clm_context* ctx, const clm_box* box, int64_t n_x,
+                         int64_t n_y, clm_precision precision, void* ws, size_t ws_bytes);
 
 // Cell-list build whose kernels all return at once when `gate` (device
 // uint32) reads 0; gate == NULL builds unconditionally.
