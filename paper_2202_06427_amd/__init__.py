@@ -283,27 +283,49 @@ class CellList:
         self._map("lj_e", P, L.MapOut(energy_dev=_ptr(e), count_dev=_ptr(c)))
         return e, c
 
-    def lj_forces(self, sigma, epsilon, near_factor=1.0, virial=False, cutoff=None):
-        """Energy, forces (-dE/dr, paper Code 7), dE/dH and optionally the virial."""
+    def _half_scratch(self, kind, half):
+        """(pointer, bytes) of the map scratch that selects the half-shell LJ
+        force sweep (every pair once), or (None, 0) when half is False or the
+        sweep does not apply to this cell list."""
+        if not half:
+            return None, 0
+        nbytes = ctypes.c_size_t(0)
+        L.check(L.lib().clm_map_scratch_bytes(self._h, L.MAP_KINDS[kind], ctypes.byref(nbytes)))
+        need = int(nbytes.value)
+        if need == 0:
+            return None, 0
+        buf = getattr(self, "_scratch", None)
+        if buf is None or buf[1] < need:
+            raw = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            self._scratch = (raw, need)
+        raw = self._scratch[0]
+        return ctypes.c_void_p(raw.data_ptr() + (-raw.data_ptr()) % 256), need
+
+    def lj_forces(self, sigma, epsilon, near_factor=1.0, virial=False, cutoff=None, half=True):
+        """Energy, forces (-dE/dr, paper Code 7), dE/dH and optionally the virial.
+        half: FP32 form only -- evaluate every pair once (half-shell sweep with
+        map scratch) instead of from both ends (full-shell gather)."""
         e, c = self._scalars()
         f = torch.empty((self.nx, self.dim), dtype=torch.float64, device=self.device)
         gb = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device)
         w = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device) if virial else None
+        sp, sb = self._half_scratch("lj_ef", half)
         P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, want_virial=int(virial),
-                        cutoff=_rc(cutoff))
+                        cutoff=_rc(cutoff), scratch_dev=sp, scratch_bytes=sb)
         o = L.MapOut(energy_dev=_ptr(e), forces_dev=_ptr(f), grad_box_dev=_ptr(gb),
                      virial_dev=_ptr(w), count_dev=_ptr(c))
         self._map("lj_ef", P, o)
         return {"energy": e, "forces": f, "grad_box": gb, "virial": w, "count": c}
 
-    def lj_adjoint(self, sigma, epsilon, upstream, near_factor=1.0, cutoff=None):
+    def lj_adjoint(self, sigma, epsilon, upstream, near_factor=1.0, cutoff=None, half=True):
         """g dE/dr and g dE/dH for an upstream gradient g (device float64[1])."""
         e, c = self._scalars()
         up = upstream.detach().to(device=self.device, dtype=torch.float64).reshape(1).contiguous()
         gx = torch.empty((self.nx, self.dim), dtype=torch.float64, device=self.device)
         gb = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device)
+        sp, sb = self._half_scratch("lj_adjoint", half)
         P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, upstream_dev=_ptr(up),
-                        cutoff=_rc(cutoff))
+                        cutoff=_rc(cutoff), scratch_dev=sp, scratch_bytes=sb)
         o = L.MapOut(energy_dev=_ptr(e), forces_dev=_ptr(gx), grad_box_dev=_ptr(gb), count_dev=_ptr(c))
         self._map("lj_adjoint", P, o)
         self._keep_up = up

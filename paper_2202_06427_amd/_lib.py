@@ -55,6 +55,7 @@ class MapParams(ctypes.Structure):
         ("hist_hi", ctypes.c_double), ("vel_x_dev", _vp), ("vel_y_dev", _vp),
         ("want_sums", ctypes.c_int), ("capacity", ctypes.c_int64), ("with_distances", ctypes.c_int),
         ("cutoff", ctypes.c_double), ("weights_x_dev", _vp), ("weights_y_dev", _vp),
+        ("scratch_dev", _vp), ("scratch_bytes", ctypes.c_size_t),
     ]
 
 
@@ -89,7 +90,7 @@ EXPORTS = [
     "clm_celllist_info_get", "clm_celllist_destroy", "clm_synchronize", "clm_last_error",
     "clm_status_string", "clm_context_set_timing", "clm_stats_get", "clm_map_batch_workspace_bytes",
     "clm_map_batch", "clm_box_nonperiodic", "clm_extrema_workspace_bytes", "clm_extrema",
-    "clm_map_static_max_bytes", "clm_map_static",
+    "clm_map_static_max_bytes", "clm_map_static", "clm_map_scratch_bytes",
     # include/clmap_md.h
     "clm_md_workspace_bytes", "clm_md_create", "clm_md_kick_drift", "clm_md_kick", "clm_md_destroy",
     "clm_vlist_workspace_bytes", "clm_vlist_create", "clm_vlist_update", "clm_vlist_lj",
@@ -142,6 +143,7 @@ def lib():
                                 ctypes.POINTER(MapOut), _vp, ctypes.c_size_t]
     szp = ctypes.POINTER(ctypes.c_size_t)
     L.clm_map_static_max_bytes.argtypes = [szp]
+    L.clm_map_scratch_bytes.argtypes = [_vp, c_int, szp]
     L.clm_map_static.argtypes = [_vp, _vp, _vp, c_i64, _vp, c_i64, c_int, c_int,
                                  ctypes.POINTER(MapParams), ctypes.POINTER(MapOut)]
     L.clm_md_workspace_bytes.argtypes = [c_i64, szp]

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libclmap.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["build_kernels.hip", "sweep_kernels.hip", "md_kernels.hip", "kclosest_kernels.hip",
+SOURCES = ["build_kernels.hip", "sweep_kernels.hip", "sweep_half.hip", "md_kernels.hip", "kclosest_kernels.hip",
            "calib_kernels.hip", "static_map.hip",
            "clmap_api.cpp", "md_api.cpp", "kclosest_api.cpp", "calib_api.cpp"]
 

@@ -76,7 +76,13 @@ static constexpr int64_t kMaxCells = int64_t(1) << 24;
 // |D| <= 1.01 rc (a farther one has d2_32 > rc^2 whatever the rounding), so
 // |d2_32 - d2| <= 2 (1.01 rc) |E| + |E|^2 + 4 u (1.02 rc^2) for the FMA chain
 // of three roundings.  The band is twice that bound.
-static void map_band(const clm_box& B, double rc, double* band, float* lo32, float* hi32) {
+// M scales the cell extent per fractional axis: the j coordinates of the
+// half-shell LJ sweep are offsets from a particle of the same row piece, at
+// most M_b cells apart along axis b (C_a = sum_b |H_ab| M_b / n_b), and the
+// i coordinates from the same origin are at most |D_a| + C_a, which the same
+// bound covers.
+static void map_band(const clm_box& B, double rc, double* band, float* lo32, float* hi32,
+                     const double* M = nullptr) {
   const int dim = B.dim;
   const double rc2 = rc * rc;
   const double u = std::ldexp(1.0, -24);
@@ -84,7 +90,7 @@ static void map_band(const clm_box& B, double rc, double* band, float* lo32, flo
   for (int a = 0; a < dim; ++a) {
     double C = 0.0, Hs = 0.0;
     for (int b = 0; b < dim; ++b) {
-      C += std::fabs(B.H[a * 3 + b]) / (double)B.n[b];
+      C += std::fabs(B.H[a * 3 + b]) / (double)B.n[b] * (M ? M[b] : 1.0);
       Hs += std::fabs(B.H[a * 3 + b]);
     }
     double e64 = 64.0 * std::ldexp(1.0, -53) * (4.0 * Hs + 4.0 * rc);
@@ -742,6 +748,13 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     jd.rc2 = rcm * rcm;
     map_band(B, rcm, &jd.band, &jd.lo32, &jd.hi32);
   }
+  if (ljf) {  // half-shell LJ sweep: thresholds per tile span
+    for (int sp = 0; sp <= kMaxSpan; ++sp) {
+      const double M[3] = {(double)(std::max(sp, 1) + 2 * B.lcx), 1.0, 1.0};
+      double bd;
+      map_band(B, rcm, &bd, &jd.half_lo[sp], &jd.half_hi[sp], M);
+    }
+  }
   const int k_launch = (ljf && P->want_virial) ? K_LJ_FV : k;
   jd.kind = k_launch;
   jd.full_shell = ljf ? 1 : 0;
@@ -823,6 +836,38 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
   return map_one(cl, kind, P, O, true);
 }
 
+// ---------------------------------------------------------------- half-shell LJ scratch
+static bool half_applies(const clm_celllist* cl, int k) {
+  return k == K_LJ_F && cl->prec == CLM_FP32_GUARD && !cl->box.small && !cl->cross && cl->nx > 0;
+}
+
+struct HalfLayout {
+  int NR, nitems, ngather;
+  size_t npad, o_part, o_parts, o_pc, total;
+};
+
+static HalfLayout half_layout(const clm_celllist* cl) {
+  HalfLayout L;
+  L.NR = half_rows(cl->box.dim, cl->box.lcell);
+  L.nitems = cl->nrows * L.NR;
+  L.ngather = (int)((cl->nx + 255) / 256);
+  L.npad = (size_t)((cl->nx + 63) / 64) * 64;
+  Carve c;
+  L.o_part = c.take(sizeof(float) * 2 * (size_t)L.NR * 3 * L.npad);
+  L.o_parts = c.take(sizeof(double) * kPartialD * (size_t)(L.nitems + L.ngather));
+  L.o_pc = c.take(sizeof(unsigned long long) * (size_t)(L.nitems + L.ngather));
+  L.total = c.off;
+  return L;
+}
+
+clm_status clm_map_scratch_bytes(const clm_celllist* cl, clm_map_kind kind, size_t* bytes) {
+  if (!cl || !bytes) return fail(CLM_E_INVALID_ARG, "NULL argument");
+  const int k = internal_kind(kind);
+  if (k < 0) return fail(CLM_E_INVALID_ARG, "unknown map kind %d", (int)kind);
+  *bytes = half_applies(cl, k) ? half_layout(cl).total : 0;
+  return CLM_OK;
+}
+
 }  // extern "C"
 
 clm_status map_one(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P, const clm_map_out* O,
@@ -834,6 +879,41 @@ clm_status map_one(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
   if (s != CLM_OK) return s;
   const clm_box& B = cl->box;
   hipStream_t st = cl->ctx->stream;
+  if (half_applies(cl, internal_kind(kind)) && P->scratch_dev) {
+    // half-shell LJ sweep: every pair once, force planes in the map scratch
+    const HalfLayout HL = half_layout(cl);
+    if (((uintptr_t)P->scratch_dev & 255) != 0)
+      return fail(CLM_E_WORKSPACE, "map scratch must be 256-byte aligned");
+    if (P->scratch_bytes < HL.total)
+      return fail(CLM_E_WORKSPACE, "map scratch too small: %zu bytes given, %zu needed", P->scratch_bytes,
+                  HL.total);
+    char* base = (char*)P->scratch_dev;
+    HalfArgs A;
+    A.part = (float*)(base + HL.o_part);
+    A.npad = HL.npad;
+    A.partials = (double*)(base + HL.o_parts);
+    A.pcount = (unsigned long long*)(base + HL.o_pc);
+    A.row_off = cl->row_off;
+    A.tiles = cl->tiles;
+    A.max_tiles = cl->max_tiles;
+    A.nitems = HL.nitems;
+    A.NR = HL.NR;
+    jd.partials = A.partials;  // the finalize reads the item and gather partials
+    jd.pcount = A.pcount;
+    CLM_HIP(launch_set_job(jd, cl->job_dev, st));
+    Timed ts(cl->untimed ? nullptr : cl->ctx, &cl->ctx->sweep_ev);
+    s = ts.start();
+    if (s != CLM_OK) return s;
+    CLM_HIP(launch_half_lj(B.dim, k_launch == K_LJ_FV, cl->job_dev, A, (int)cl->nx, st));
+    s = ts.stop();
+    if (s != CLM_OK) return s;
+    F.nparts = HL.nitems + HL.ngather;
+    F.nparts_dev = nullptr;
+    F.split_rows = 0;
+    F.halve_count = 0;
+    CLM_HIP(launch_finalize(cl->job_dev, F, cl->fin_scratch, cl->fin_count, st));
+    return CLM_OK;
+  }
   // neighbour lists: a counting sweep gives every work item its output
   // offset, so the list sweep writes without a shared counter
   const bool nl_two_pass = nl_two_pass_ok && k_launch == K_NL && !B.small;

@@ -113,6 +113,9 @@ struct JobDesc {
   const uint32_t* own_ntiles;  // device count
   int own_max_tiles;
   int pad3;
+  // half-shell LJ sweep: FP32 membership thresholds per tile span (1..kMaxSpan
+  // cells along x), coordinates relative to the tile's first cell origin
+  float half_lo[kMaxSpan + 1], half_hi[kMaxSpan + 1];
 };
 
 // Dynamic LDS bytes per wave of the sweep.  The FP32 form keeps a ring
@@ -206,6 +209,23 @@ inline int sweep_split_rows(int kind, int dim, int lcell, bool full) {
   const int rows = dim == 3 ? side * side : side;
   return full ? rows : (rows + 1) / 2;
 }
+
+// Half-shell LJ force sweep (sweep_half.hip): one wave per (cell row,
+// half-shell row offset) item; FP32 force planes indexed by sorted slot,
+// 2 NR planes of 3 components (stride npad floats): plane 2 rho holds the
+// i-side sums of offset rho, plane 2 rho + 1 the j-side sums.
+struct HalfArgs {
+  float* part;
+  size_t npad;
+  double* partials;            // nitems + gather blocks, kPartialD each
+  unsigned long long* pcount;  // nitems + gather blocks
+  const uint32_t* row_off;     // tiles of row h: [row_off[h], row_off[h + 1])
+  const Tile* tiles;
+  int max_tiles;               // entries of tiles
+  int nitems, NR;
+};
+// Half-shell row offsets including the home row: 2 l^2 + 2 l + 1 in 3D, l + 1 in 2D.
+__host__ __device__ inline int half_rows(int dim, int l) { return dim == 3 ? 2 * l * l + 2 * l + 1 : l + 1; }
 
 struct FinalArgs {
   int nparts;                      // used when nparts_dev is NULL
@@ -369,6 +389,8 @@ __host__ __device__ inline int brute_chunks(int64_t ny) {
 }
 hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, double* FB, int* nparts_out,
                         hipStream_t s);
+hipError_t launch_half_lj(int dim, bool virial, const JobDesc* jobs, const HalfArgs& A, int n,
+                          hipStream_t s);
 hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, double* scratch,
                            unsigned long long* scratch_count, hipStream_t s);
 constexpr int kFinalBlocks = 128;  // first-level blocks of the two-level finalize

@@ -17,36 +17,11 @@
 // All are HBM- or latency-bound except vl_lj, whose bound is the FP64 VALU
 // work per listed partner and the gathers of partner positions.
 #include "clmap_internal.h"
+#include "device_util.h"
 
 namespace clm {
 
 namespace {
-
-template <typename T>
-__device__ __forceinline__ T ldu(const T* p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return *(const __attribute__((address_space(4))) T*)(p);
-#else
-  return *p;
-#endif
-}
-
-// 1/v to FP64 accuracy: hardware reciprocal estimate and one Newton step.
-__device__ __forceinline__ double rcp64(double v) {
-  double r = __builtin_amdgcn_rcp(v);
-  const double e = __builtin_fma(-v, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
-}
 
 // Block of kMdBlock threads: sums of kMdPart doubles and one count into
 // part[b * kMdPart + k] and pcount[b] (fixed order: waves, then wave 0..3).
@@ -58,7 +33,7 @@ __device__ __forceinline__ void block_partials(const double* acc, unsigned long 
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
   for (int k = 0; k < kMdPart; ++k) {
-    const double s = wave_sum(acc[k]);
+    const double s = wave_sum_d(acc[k]);
     if (lane == 0) red[w][k] = s;
   }
   const unsigned long long c = wave_sum_u64(cnt);
@@ -142,7 +117,7 @@ __global__ void __launch_bounds__(256) md_finalize_kernel(MdFinal F) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
   for (int k = 0; k < kMdPart; ++k) {
-    const double v = wave_sum(acc[k]);
+    const double v = wave_sum_d(acc[k]);
     if (lane == 0) red[w][k] = v;
   }
   c = wave_sum_u64(c);

@@ -1,0 +1,595 @@
+// sweep_half.hip -- Lennard-Jones energy + forces (+ box gradient, virial)
+// over the half shell in the FP32 + FP64-guard form: every unordered pair is
+// evaluated once (paper section 2.8: a cell and half of its neighbour cells),
+// both particles' force sums are kept, and no atomics decide the summation
+// order (repeated maps give bitwise-identical results).
+//
+// Work item: (home cell row h, half-shell row offset rho).  A row is the run
+// of cells (0..nx-1, cy, cz); rho = 0 is the home row itself (pairs j > i in
+// sorted order, cells forward along x), rho > 0 the neighbour rows with
+// (dz, dy) > (0, 0).  One wavefront runs one item: for each tile of row h
+// (<= 64 consecutive sorted particles, one per lane) it streams the tile's
+// reach in row r = h + offset(rho) as blocks of 64 particles, one per lane.
+//
+// A block is a 64 x 64 set of pairs, visited in 64 steps: in step (phase g,
+// k) lane l pairs its i with the j that a DPP row rotation by k brings from
+// the lane group (l/16 + g) mod 4.  The rotation is folded into the
+// subtractions (v_sub_f32 with a DPP source), and the j-side force term goes
+// back through the inverse rotation folded into an add, so a step is about
+// 27 VALU instructions for 64 pairs.  Between phases the j data rotate by 16
+// lanes (ds_bpermute); after the 4th phase they are back in place.
+//
+// Force sums: per lane, the i-side FP32 sum of a block (64 steps) is folded
+// into FP64; the j-side FP32 block sum is added (FP64 arithmetic, one FP32
+// rounding) into a FP32 plane slot owned by this item alone:
+//     plane 2 rho     : i-side sums of item (row(i), rho)
+//     plane 2 rho + 1 : j-side sums of item (row(j) - offset(rho), rho)
+// Both are indexed by sorted index, so every slot has exactly one writer; a
+// gather kernel sums the 2 NR planes of each particle in FP64 in a fixed
+// order.
+//
+// FP32 coordinates: relative to an origin O per block (the position of the
+// block's middle particle, shifted by the piece's image t), x = fl32(r' + t
+// - O) and x_i = fl32(r'_i - O), computed in FP64.  |x_j,a| <= C_a, the
+// extent of the visited piece of the row (at most span + 2 lx cells along x,
+// one cell across), and |x_i,a| <= |D_a| + C_a, so |D32_a - D_a| <=
+// u (2 C_a + 2 |D_a|) + FP64 roundings.  The membership band comes from that
+// bound per tile span (host table).  Pairs within the band of rc^2, and pairs
+// closer than the near threshold, are queued per wave and evaluated in
+// canonical FP64.
+#include "clmap_internal.h"
+#include "device_util.h"
+
+namespace clm {
+
+namespace {
+
+constexpr int kHQCap = 512;  // per-wave queue of FP64 re-evaluations (power of two, >= 63 + 4 * 64)
+
+template <int K>
+__device__ __forceinline__ float row_ror(float v) {  // lane p reads lane (p - K) mod 16 of its row
+  if constexpr (K == 0) {
+    return v;
+  } else {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + K, 0xF, 0xF, true));
+  }
+}
+template <int K>
+__device__ __forceinline__ int row_ror_i(int v) {
+  if constexpr (K == 0) {
+    return v;
+  } else {
+    return __builtin_amdgcn_mov_dpp(v, 0x120 + K, 0xF, 0xF, true);
+  }
+}
+// inverse of row_ror<K>
+template <int K>
+__device__ __forceinline__ float row_back(float v) {
+  if constexpr (K == 0) {
+    return v;
+  } else {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + (16 - K),
+                                                                0xF, 0xF, true));
+  }
+}
+
+// (dy, dz) of half-shell row offset rho: 0 -> home row; then (0, 1..l);
+// then dz = 1..l with dy = -l..l.  2D: dz = 0, dy = 0..l.
+__device__ __forceinline__ void row_offset(int dim, int l, int rho, int* dy, int* dz) {
+  if (rho == 0) {
+    *dy = 0;
+    *dz = 0;
+    return;
+  }
+  if (rho <= l) {
+    *dy = rho;
+    *dz = 0;
+    return;
+  }
+  const int q = rho - l - 1;  // 3D only
+  (void)dim;
+  *dz = 1 + q / (2 * l + 1);
+  *dy = q % (2 * l + 1) - l;
+}
+
+template <int DIM, bool VIR>
+struct Half {
+  const JobDesc* J;
+  int lane;
+  // uniform
+  int l, lx, nx, ny, nz;
+  double rc2, s2, inv_s2;
+  float s2f, near2f;
+  float lo, hi;
+  // per lane (i side, fixed for a tile; xi is relative to the block origin)
+  double ri[3];
+  bool active;
+  float xi[3];
+  double Fi[3];
+  // per lane accumulators of the item
+  double E64;
+  double B[9];
+  double W[6];
+  uint32_t qband, qnear;
+  unsigned long long cnt;  // wave-uniform
+  // per block
+  float xj[3];
+  float acc[3];
+  int mid;                 // j-block lane whose data this lane holds
+  float e32;
+  float fi32[3];
+  float w32[6];
+  // queue (LDS)
+  uint32_t* Q;
+  double* GA;   // [64][3] FP64 i-side sums of queued pairs
+  double* GJ;   // [64][3] FP64 sums of f D (i -> j) of queued pairs, by j-block lane
+  uint32_t qhead, qtail;
+  uint32_t tstart, b0;
+  int kc;
+  int pp[3];
+
+  // ---------------------------------------------------------------- FP64 queue
+  // Canonical FP64 evaluation of one queued pair (i lane il, j-block lane jm).
+  __device__ __forceinline__ void process(uint32_t e, bool* in_out) {
+    const int il = (int)(e & 63u), jm = (int)((e >> 6) & 63u);
+    const double4 rI = J->r64_x[tstart + (uint32_t)il];
+    const double4 rJ = J->r64_x[b0 + (uint32_t)jm];
+    const double* tk = &J->tK[kc * 4];
+    double D[3];
+    D[0] = (rJ.x - rI.x) + tk[0];
+    D[1] = (rJ.y - rI.y) + tk[1];
+    double d2 = D[0] * D[0] + D[1] * D[1];
+    if (DIM == 3) {
+      D[2] = (rJ.z - rI.z) + tk[2];
+      d2 = d2 + D[2] * D[2];
+    } else {
+      D[2] = 0.0;
+    }
+    *in_out = d2 <= rc2;
+    if (!(d2 <= rc2)) return;
+    const double r = rcp64(d2);
+    const double x = s2 * r;
+    const double x3 = x * x * x;
+    const double u = x3 * x3 - x3;
+    const double f = (2.0 * x3 * x3 - x3) * r;
+    E64 += u;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      atomicAdd(&GA[il * 3 + a], f * D[a]);
+      atomicAdd(&GJ[jm * 3 + a], f * D[a]);
+    }
+    // (the image term f D p^T of the box gradient is added with the block's
+    // j-side sums, which include GJ)
+    if constexpr (VIR) {
+      W[0] += f * D[0] * D[0];
+      W[1] += f * D[0] * D[1];
+      W[3] += f * D[1] * D[1];
+      if (DIM == 3) {
+        W[2] += f * D[0] * D[2];
+        W[4] += f * D[1] * D[2];
+        W[5] += f * D[2] * D[2];
+      }
+    }
+  }
+
+  __device__ __forceinline__ void drain(bool all) {
+    uint32_t h = (uint32_t)uniform((int)qhead);
+    const uint32_t tl = (uint32_t)uniform((int)qtail);
+    while (tl - h >= (uint32_t)kWave || (all && tl != h)) {
+      const uint32_t nb = min(tl - h, (uint32_t)kWave);
+      bool band_in = false;
+      if ((uint32_t)lane < nb) {
+        const uint32_t e = Q[(h + (uint32_t)lane) & (uint32_t)(kHQCap - 1)];
+        bool in = false;
+        process(e, &in);
+        const bool band = (e >> 31) != 0u;
+        qband += band ? 1u : 0u;
+        qnear += band ? 0u : 1u;
+        band_in = band && in;
+      }
+      cnt += (unsigned long long)__popcll(__builtin_amdgcn_ballot_w64(band_in));
+      h = (uint32_t)uniform((int)(h + nb));
+    }
+    qhead = h;
+  }
+
+  // ---------------------------------------------------------------- one step
+  template <int K, bool SELF>
+  __device__ __forceinline__ void step() {
+    const float dx = row_ror<K>(xj[0]) - xi[0];
+    const float dy = row_ror<K>(xj[1]) - xi[1];
+    const float dz = DIM == 3 ? row_ror<K>(xj[2]) - xi[2] : 0.0f;
+    const float d2 = DIM == 3 ? __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))
+                              : __builtin_fmaf(dy, dy, dx * dx);
+    unsigned long long okm = ~0ull;
+    int mj = 0;
+    if constexpr (SELF) {
+      mj = row_ror_i<K>(mid);
+      okm = __builtin_amdgcn_ballot_w64(mj > lane);
+    }
+    const unsigned long long mlo = __builtin_amdgcn_ballot_w64(d2 <= lo) & okm;
+    const unsigned long long mhi = __builtin_amdgcn_ballot_w64(d2 <= hi) & okm;
+    const unsigned long long mnr = __builtin_amdgcn_ballot_w64(d2 < near2f) & okm;
+    cnt += (unsigned long long)__popcll(mlo);
+    const bool fast = __builtin_amdgcn_inverse_ballot_w64(mlo & ~mnr);
+    const float x = fast ? s2f * __builtin_amdgcn_rcpf(d2) : 0.0f;
+    const float x3 = x * x * x;
+    const float u = __builtin_fmaf(x3, x3, -x3);
+    e32 += u;
+    const float f = __builtin_fmaf(2.0f, u, x3) * x;
+    const float tx = f * dx, ty = f * dy, tz = f * dz;
+    fi32[0] += tx;
+    fi32[1] += ty;
+    acc[0] += row_back<K>(tx);
+    acc[1] += row_back<K>(ty);
+    if (DIM == 3) {
+      fi32[2] += tz;
+      acc[2] += row_back<K>(tz);
+    }
+    if constexpr (VIR) {
+      w32[0] = __builtin_fmaf(tx, dx, w32[0]);
+      w32[1] = __builtin_fmaf(tx, dy, w32[1]);
+      w32[3] = __builtin_fmaf(ty, dy, w32[3]);
+      if (DIM == 3) {
+        w32[2] = __builtin_fmaf(tx, dz, w32[2]);
+        w32[4] = __builtin_fmaf(ty, dz, w32[4]);
+        w32[5] = __builtin_fmaf(tz, dz, w32[5]);
+      }
+    }
+    // keep the accumulator updates in this step (an empty asm that reads and
+    // redefines them): left free, the scheduler defers them past later steps
+    // and spills the pending terms
+    asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(fi32[0]), "+v"(fi32[1]),
+                 "+v"(fi32[2]), "+v"(e32));
+    if constexpr (VIR)
+      asm volatile("" : "+v"(w32[0]), "+v"(w32[1]), "+v"(w32[2]), "+v"(w32[3]), "+v"(w32[4]),
+                   "+v"(w32[5]));
+    const unsigned long long band = mhi & ~mlo;
+    const unsigned long long spec = band | mnr;
+    if (spec) {
+      if constexpr (!SELF) mj = row_ror_i<K>(mid);
+      const uint32_t t0 = (uint32_t)uniform((int)qtail);
+      if (__builtin_amdgcn_inverse_ballot_w64(spec)) {
+        const uint32_t slot = (t0 + (uint32_t)lane_rank(spec)) & (uint32_t)(kHQCap - 1);
+        const bool b = __builtin_amdgcn_inverse_ballot_w64(band);
+        Q[slot] = (uint32_t)lane | ((uint32_t)mj << 6) | (b ? 0x80000000u : 0u);
+      }
+      qtail = (uint32_t)uniform((int)(t0 + (uint32_t)__popcll(spec)));
+    }
+  }
+
+  // 16 steps; the queue is drained (64 entries at a time) after every 4
+  // steps, so it never holds more than 63 + 4 * 64 entries
+  template <bool SELF>
+  __device__ __forceinline__ void phase() {
+    step<0, SELF>(); step<1, SELF>(); step<2, SELF>(); step<3, SELF>();
+    if (qtail - qhead >= (uint32_t)kWave) drain(false);
+    step<4, SELF>(); step<5, SELF>(); step<6, SELF>(); step<7, SELF>();
+    if (qtail - qhead >= (uint32_t)kWave) drain(false);
+    step<8, SELF>(); step<9, SELF>(); step<10, SELF>(); step<11, SELF>();
+    if (qtail - qhead >= (uint32_t)kWave) drain(false);
+    step<12, SELF>(); step<13, SELF>(); step<14, SELF>(); step<15, SELF>();
+    if (qtail - qhead >= (uint32_t)kWave) drain(false);
+  }
+
+  // rotate the j data by one lane group (lane L takes lane L + 16)
+  __device__ __forceinline__ void rotate(bool pos) {
+    const int src = ((lane + 16) & 63) << 2;
+    if (pos) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+        xj[a] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, xj[a])));
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      acc[a] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, acc[a])));
+    mid = __builtin_amdgcn_ds_bpermute(src, mid);
+  }
+
+  // One block: j = b0 + lane for lanes with j < je.  part_j: this item's
+  // j-side plane (3 components, stride npad).
+  template <bool SELF>
+  __device__ __forceinline__ void block(uint32_t je, const double* t, float* part_j, size_t npad) {
+    const uint32_t j = b0 + (uint32_t)lane;
+    const bool jv = j < je;
+    {
+      // block origin: the middle particle of the block (shifted by t), so
+      // the FP32 offsets of the block are small and those of the lanes are
+      // at most their distance to the block plus its extent
+      const uint32_t jm = b0 + (min(je - b0, (uint32_t)kWave) - 1u) / 2u;
+      const double4 rm = ldu(&J->r64_x[jm]);
+      const double O[3] = {rm.x + t[0], rm.y + t[1], rm.z + t[2]};
+      xi[0] = active ? (float)(ri[0] - O[0]) : 1e18f;
+      xi[1] = active ? (float)(ri[1] - O[1]) : 1e18f;
+      xi[2] = DIM == 3 ? (active ? (float)(ri[2] - O[2]) : 1e18f) : 0.0f;
+      double4 r = jv ? J->r64_x[j] : make_double4(0.0, 0.0, 0.0, 0.0);
+      xj[0] = jv ? (float)((r.x + t[0]) - O[0]) : -1e18f;
+      xj[1] = jv ? (float)((r.y + t[1]) - O[1]) : -1e18f;
+      xj[2] = DIM == 3 ? (jv ? (float)((r.z + t[2]) - O[2]) : -1e18f) : 0.0f;
+    }
+    float jold[3] = {0.0f, 0.0f, 0.0f};
+    if (jv) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) jold[a] = part_j[(size_t)a * npad + j];
+    }
+    mid = lane;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      acc[a] = 0.0f;
+      fi32[a] = 0.0f;
+      GJ[lane * 3 + a] = 0.0;
+    }
+    e32 = 0.0f;
+    if constexpr (VIR) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w32[k] = 0.0f;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int g = 0; g < 4; ++g) {
+      phase<SELF>();
+      rotate(g < 3);  // after the 4th phase only acc and mid (back in place)
+    }
+    drain(true);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // fold the block into FP64
+    E64 += (double)e32;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) Fi[a] += (double)fi32[a] * inv_s2;
+    if constexpr (VIR) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) W[k] += (double)w32[k] * inv_s2;
+    }
+    const bool img = (pp[0] | pp[1] | pp[2]) != 0;
+    if (jv) {
+      double S[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        S[a] = (double)acc[a] * inv_s2 + GJ[lane * 3 + a];
+        part_j[(size_t)a * npad + j] = (float)((double)jold[a] - S[a]);
+      }
+      if (img) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int b = 0; b < DIM; ++b) B[a * 3 + b] += S[a] * (double)pp[b];
+      }
+    }
+  }
+};
+
+}  // namespace
+
+template <int DIM, bool VIR>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
+  __shared__ uint32_t sQ[kHQCap];
+  __shared__ double sGA[kWave * 3];
+  __shared__ double sGJ[kWave * 3];
+  const int lane = (int)__lane_id();
+  const int nitems = A.nitems;
+  int b = blockIdx.x;
+  if (b >= nitems) return;
+  if (nitems >= 8) {  // each XCD takes a contiguous range of items (neighbouring rows share L2)
+    const int per = nitems / 8, rem = nitems % 8;
+    const int xcd = b % 8, k = b / 8;
+    b = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
+  }
+  const int item = uniform(b);
+  const int NR = A.NR;
+  const int h = item / NR, rho = item - (item / NR) * NR;
+  const JobDesc* J = &jobs[0];
+
+  Half<DIM, VIR> S;
+  S.J = J;
+  S.lane = lane;
+  S.Q = sQ;
+  S.GA = sGA;
+  S.GJ = sGJ;
+  S.l = ldu(&J->lcell);
+  S.lx = ldu(&J->lcell_x);
+  S.nx = ldu(&J->n[0]);
+  S.ny = ldu(&J->n[1]);
+  S.nz = ldu(&J->n[2]);
+  S.rc2 = ldu(&J->rc2);
+  S.s2 = ldu(&J->s2);
+  S.inv_s2 = 1.0 / S.s2;
+  S.s2f = ldu(&J->s2f);
+  S.near2f = ldu(&J->near2f);
+  S.E64 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) S.B[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) S.W[k] = 0.0;
+  S.qband = 0;
+  S.qnear = 0;
+  S.cnt = 0;
+  S.qhead = 0;
+  S.qtail = 0;
+
+  const int nx = S.nx, ny = S.ny, nz = S.nz, l = S.l, lx = S.lx;
+  const int cy = h % ny, cz = DIM == 3 ? h / ny : 0;
+  int dy, dz;
+  row_offset(DIM, l, rho, &dy, &dz);
+  int uy = cy + dy, uz = cz + dz, py = 0, pz = 0;
+  if (uy >= ny) { uy -= ny; py = 1; } else if (uy < 0) { uy += ny; py = -1; }
+  if (DIM == 3) {
+    if (uz >= nz) { uz -= nz; pz = 1; }
+  }
+  const uint32_t* off = ldu(&J->off_x);
+  const int rbase = (uy + ny * uz) * nx;
+  const size_t npad = A.npad;
+  float* part_i = A.part + (size_t)(2 * rho) * 3 * npad;
+  float* part_j = A.part + (size_t)(2 * rho + 1) * 3 * npad;
+  {  // this item owns the j-side plane over row r: clear it
+    const uint32_t r0 = ldu(&off[rbase]), r1 = ldu(&off[rbase + nx]);
+    for (uint32_t j = r0 + (uint32_t)lane; j < r1; j += kWave) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) part_j[(size_t)a * npad + j] = 0.0f;
+    }
+  }
+  const uint32_t* row_off = A.row_off;
+  const int t0 = (int)ldu(&row_off[h]), t1 = min((int)ldu(&row_off[h + 1]), A.max_tiles);
+  const Tile* tiles = A.tiles;
+  for (int ti = t0; ti < t1; ++ti) {
+    // the previous tile's plane updates are visible to every lane
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const Tile T = ldu(&tiles[ti]);
+    const int count = T.count;
+    const int cx0 = T.cx0, cx1 = T.cx1;
+    const bool active = lane < count;
+    S.tstart = T.start;
+    const uint32_t i = T.start + (uint32_t)(active ? lane : count - 1);
+    const int span = cx1 - cx0 + 1;
+    S.lo = ldu(&J->half_lo[span]);
+    S.hi = ldu(&J->half_hi[span]);
+    {
+      const double4 r = J->r64_x[i];
+      S.ri[0] = r.x;
+      S.ri[1] = r.y;
+      S.ri[2] = r.z;
+      S.active = active;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      S.Fi[a] = 0.0;
+      sGA[lane * 3 + a] = 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // pieces of the visited cell range [xlo, xhi] of row r: px = -1, 0, +1
+    const int xlo = rho == 0 ? cx0 : cx0 - lx, xhi = cx1 + lx;
+    for (int px = -1; px <= 1; ++px) {
+      int a0 = xlo, a1 = xhi;
+      if (px < 0) { a1 = min(a1, -1); }
+      else if (px == 0) { a0 = max(a0, 0); a1 = min(a1, nx - 1); }
+      else { a0 = max(a0, nx); }
+      if (a0 > a1) continue;
+      const int c0 = a0 - px * nx, c1 = a1 - px * nx;  // wrapped cell indices
+      uint32_t jb = ldu(&off[rbase + c0]);
+      const uint32_t je = ldu(&off[rbase + c1 + 1]);
+      const bool home = rho == 0 && px == 0;
+      if (home) jb = T.start;  // pairs j > i: from the tile's first particle on
+      if (jb >= je) continue;
+      S.pp[0] = px;
+      S.pp[1] = py;
+      S.pp[2] = pz;
+      S.kc = kcode(px, py, pz);
+      const double t[3] = {ldu(&J->tK[S.kc * 4 + 0]), ldu(&J->tK[S.kc * 4 + 1]), ldu(&J->tK[S.kc * 4 + 2])};
+      for (uint32_t bb = jb; bb < je; bb += kWave) {
+        S.b0 = bb;
+        if (home && bb == jb)
+          S.template block<true>(je, t, part_j, npad);
+        else
+          S.template block<false>(je, t, part_j, npad);
+      }
+    }
+    // the tile's i-side sums (plane 2 rho, one writer per particle)
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) S.Fi[a] += sGA[lane * 3 + a];
+    if (active) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) part_i[(size_t)a * npad + i] = (float)S.Fi[a];
+    }
+  }
+
+  // ---- item partials
+  const unsigned long long cnt = S.cnt;
+  const double e = wave_sum_d(S.E64);
+  double* Pp = A.partials + (size_t)item * kPartialD;
+  if (lane == 0) {
+    A.pcount[item] = cnt;
+    Pp[P_SUM] = e;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double bsum = wave_sum_d(S.B[k]);
+    if (lane == 0) Pp[P_BOX + k] = bsum;
+  }
+  {
+    constexpr int map[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+    double ws[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ws[k] = VIR ? wave_sum_d(S.W[k]) : 0.0;
+    if (lane == 0) {
+#pragma unroll
+      for (int m = 0; m < 9; ++m) Pp[P_VIR + m] = ws[map[m]];
+    }
+  }
+  const unsigned long long gb = wave_sum_u64(S.qband), gn = wave_sum_u64(S.qnear);
+  if (lane == 0 && (gb | gn)) {
+    unsigned long long* g = ldu(&J->guard);
+    atomicAdd(&g[0], gb);
+    atomicAdd(&g[1], gn);
+  }
+}
+
+// Sum of the 2 NR planes of each particle (fixed order), forces in original
+// order, and the wrap term of the box gradient, sum over particles of
+// G_p w_p^T (block partials after the item partials).
+template <int DIM>
+__global__ void __launch_bounds__(256) half_gather_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A,
+                                                          int n) {
+  const JobDesc& J = jobs[0];
+  __shared__ double red[4][9];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int p = blockIdx.x * 256 + tid;
+  double G[3] = {0.0, 0.0, 0.0};
+  double Bl[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (p < n) {
+    const size_t npad = A.npad;
+    for (int q = 0; q < 2 * A.NR; ++q) {
+      const float* pl = A.part + (size_t)q * 3 * npad;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) G[a] += (double)pl[(size_t)a * npad + p];
+    }
+    const double mult = J.upstream ? *J.upstream : J.scale;
+    const double sc = mult * 24.0 * J.eps;
+    const uint32_t io = J.idx_x[p];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) J.forces[(size_t)io * DIM + a] = sc * G[a];
+    const int4 wv = J.wrap_x[p];
+    const int wa[3] = {wv.x, wv.y, wv.z};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) Bl[a * 3 + b] = G[a] * (double)wa[b];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double s = wave_sum_d(Bl[k]);
+    if (lane == 0) red[w][k] = s;
+  }
+  __syncthreads();
+  const size_t slot = (size_t)A.nitems + blockIdx.x;
+  if (tid < kPartialD) {
+    double v = 0.0;
+    if (tid >= P_BOX && tid < P_BOX + 9) {
+      const int k = tid - P_BOX;
+      v = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
+    A.partials[slot * kPartialD + tid] = v;
+  }
+  if (tid == 0) A.pcount[slot] = 0ull;
+}
+
+hipError_t launch_half_lj(int dim, bool virial, const JobDesc* jobs, const HalfArgs& A, int n,
+                          hipStream_t s) {
+  if (A.nitems > 0) {
+    if (dim == 3)
+      virial ? half_lj_kernel<3, true><<<A.nitems, 64, 0, s>>>(jobs, A)
+             : half_lj_kernel<3, false><<<A.nitems, 64, 0, s>>>(jobs, A);
+    else
+      virial ? half_lj_kernel<2, true><<<A.nitems, 64, 0, s>>>(jobs, A)
+             : half_lj_kernel<2, false><<<A.nitems, 64, 0, s>>>(jobs, A);
+  }
+  const int nb = (n + 255) / 256;
+  if (nb > 0) {
+    if (dim == 3)
+      half_gather_kernel<3><<<nb, 256, 0, s>>>(jobs, A, n);
+    else
+      half_gather_kernel<2><<<nb, 256, 0, s>>>(jobs, A, n);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace clm

@@ -32,37 +32,9 @@
 //   threshold) are queued per wave in LDS and recomputed in canonical FP64,
 //   64 at a time.
 #include "clmap_internal.h"
+#include "device_util.h"
 
 namespace clm {
-
-// ---------------------------------------------------------------- wave helpers
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
-}
-
-__device__ __forceinline__ int lane_rank(unsigned long long mask) {
-  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// 1/v for the FP64 pair terms: the hardware reciprocal refined by one Newton
-// step (error ~1 ulp; one reciprocal serves both s^2/d^2 and f = (...)/d^2
-// instead of two IEEE divisions).  Membership never depends on it.
-__device__ __forceinline__ double rcp64(double v) {
-  double r = __builtin_amdgcn_rcp(v);
-  const double e = __builtin_fma(-v, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
 
 // ---------------------------------------------------------------- histogram bins
 // Canonical bin of v against E64[0..nb] (first k with v <= E_{k+1}; v = 0 ->
@@ -102,19 +74,6 @@ __device__ __forceinline__ int bin32(const float* Et, int nb, float h, float inv
   const float lo = edge32(Et, k, nb, h, elast), hi = edge32(Et, k + 1, nb, h, elast);
   *certain = (k == 0 ? true : (v - lo) > band) && (hi - v) > band && v > lo && v <= hi;
   return k;
-}
-
-// ---------------------------------------------------------------- uniform loads
-// A load through the constant address space with a wave-uniform address is
-// emitted as a scalar (SMEM) load into SGPRs.
-// (The host compilation pass never runs device code; it only needs a body.)
-template <typename T>
-__device__ __forceinline__ T ldu(const T* p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return *(const __attribute__((address_space(4))) T*)(p);
-#else
-  return *p;
-#endif
 }
 
 // ---------------------------------------------------------------- per-wave LDS

@@ -1,0 +1,171 @@
+"""GPU parity of the half-shell Lennard-Jones force sweep (FP32 + FP64 guard;
+every pair evaluated once, both particles' force sums kept in FP32 planes
+with one writer per slot, summed per particle in FP64) against the oracle and
+against the full-shell gather, through the C-ABI.
+
+Tolerances as for every FP32+guard map: energy 1e-6 relative, per-particle
+force error 1e-5 relative to the sum of the pair-force magnitudes on that
+particle, box gradient and virial 1e-5 of their largest entry; pair counts
+exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def clm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2202_06427_amd as clm
+    return clm
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _lattice(H, n, seed, jitter=0.3):
+    dim = H.shape[0]
+    m = int(round(n ** (1.0 / dim)))
+    grid = np.stack(np.meshgrid(*([np.arange(m)] * dim), indexing="ij"), -1).reshape(-1, dim)
+    s = (grid + 0.5 + jitter * (W.rng(seed).random(grid.shape) - 0.5)) / m
+    return s @ H.T
+
+
+def _force_scale(ref, n, sigma, eps):
+    d = ref["nl_d"]
+    xx = (sigma / d) ** 2
+    x3 = xx ** 3
+    fmag = np.abs(24.0 * eps * (2 * x3 * x3 - x3) / d)
+    s = np.zeros(n)
+    np.add.at(s, ref["nl_i"], fmag)
+    np.add.at(s, ref["nl_j"], fmag)
+    return s
+
+
+def _check(out, ref, x, sigma, eps, virial=True):
+    n = len(x)
+    assert int(out["count"].item()) == ref["count"]
+    assert abs(out["energy"].item() - ref["lj_energy"]) <= 1e-6 * abs(ref["lj_energy"])
+    scale = _force_scale(ref, n, sigma, eps)
+    err = np.linalg.norm(out["forces"].cpu().numpy() + ref["lj_grad"], axis=1) / np.maximum(scale, 1e-300)
+    assert err.max() <= 1e-5, err.max()
+    gb = out["grad_box"].cpu().numpy()
+    assert np.abs(gb - ref["dEdH"]).max() <= 1e-5 * np.abs(ref["dEdH"]).max()
+    if virial:
+        assert np.abs(out["virial"].cpu().numpy() - ref["virial"]).max() <= 1e-5 * np.abs(ref["virial"]).max()
+
+
+BOXES = {
+    "cube3": (np.diag([30.0, 30.0, 30.0]), 5.0),
+    "tric3": (W.triclinic_h((32.0, 30.0, 31.0), (80.0, 95.0, 100.0)), 4.0),
+    "skew3": (W.triclinic_h((30.0, 29.0, 33.0), (70.0, 110.0, 75.0)), 4.0),
+    "sq2": (np.diag([60.0, 60.0]), 3.0),
+    "tric2": (np.array([[55.0, -12.0], [0.0, 50.0]]), 3.2),
+}
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+@pytest.mark.parametrize("lcell,lcell_x", [(1, None), (2, None), (3, None), (2, 3)])
+def test_half_shell_lattice_against_oracle(clm, name, lcell, lcell_x):
+    H, rc = BOXES[name]
+    dim = H.shape[0]
+    x = _lattice(H, 6000 if dim == 3 else 5000, 11) + H @ np.array([3, -2, 5][:dim])
+    sigma, eps = 1.1, 0.3
+    ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
+    cl = clm.CellList(T(x), clm.Box(H, rc, lcell, lcell_x), precision="fp32")
+    assert cl._half_scratch("lj_ef", True)[1] > 0, "the half-shell sweep applies here"
+    print(f"case {name} lcell={lcell} lcell_x={lcell_x}", flush=True)
+    _check(cl.lj_forces(sigma, eps, virial=True, half=True), ref, x, sigma, eps)
+    _check(cl.lj_forces(sigma, eps, virial=False, half=True), ref, x, sigma, eps, virial=False)
+
+
+@pytest.mark.parametrize("name", ["tric3", "cube3", "tric2"])
+def test_half_shell_uniform_random_near_pairs(clm, name):
+    """Uniform random points: pairs far inside sigma (FP64 near-pair path,
+    forces into both particles' planes) dominate E."""
+    H, rc = BOXES[name]
+    x = W.uniform_in_box(6000, H, 21)
+    sigma, eps = 3.4 if H.shape[0] == 3 else 1.0, 0.238
+    ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
+    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp32")
+    out = cl.lj_forces(sigma, eps, virial=True, half=True)
+    _check(out, ref, x, sigma, eps)
+    info = cl.info()
+    assert info["near_evaluations"] > 0
+
+
+def test_half_shell_heavy_cell_tiles(clm):
+    """900 particles in one cell (tiles that split a cell, so the home row's
+    first block starts inside a cell) among uniform ones."""
+    H = np.diag([40.0, 40.0, 40.0])
+    g = W.rng(3)
+    x = np.concatenate([20.0 + 0.8 * g.random((900, 3)), W.uniform_in_box(3000, H, 4)])
+    sigma, eps = 0.2, 0.01
+    ref = oracle.compute(x, H, 3.0, lj=(sigma, eps), lj_grad=True, nl=True)
+    cl = clm.CellList(T(x), clm.Box(H, 3.0, 2), precision="fp32")
+    _check(cl.lj_forces(sigma, eps, virial=True, half=True), ref, x, sigma, eps)
+
+
+def test_half_shell_map_cutoff_and_adjoint(clm):
+    H, rc = BOXES["tric3"]
+    x = _lattice(H, 6000, 12)
+    sigma, eps = 1.1, 0.3
+    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp32")
+    rm = 0.7 * rc
+    ref = oracle.compute(x, H, rm, lj=(sigma, eps), lj_grad=True, nl=True)
+    _check(cl.lj_forces(sigma, eps, virial=True, cutoff=rm, half=True), ref, x, sigma, eps)
+    g = torch.tensor([2.5], dtype=torch.float64, device="cuda:0")
+    ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
+    gx, gb, e = cl.lj_adjoint(sigma, eps, g, half=True)
+    scale = _force_scale(ref, len(x), sigma, eps)
+    err = np.linalg.norm(gx.cpu().numpy() - 2.5 * ref["lj_grad"], axis=1) / np.maximum(2.5 * scale, 1e-300)
+    assert err.max() <= 1e-5
+    assert np.abs(gb.cpu().numpy() - 2.5 * ref["dEdH"]).max() <= 1e-5 * 2.5 * np.abs(ref["dEdH"]).max()
+
+
+def test_half_shell_equals_full_shell_and_repeats_bitwise(clm):
+    H, rc = BOXES["skew3"]
+    x = W.uniform_in_box(8000, H, 31)
+    sigma, eps = 2.0, 0.2
+    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp32")
+    a = cl.lj_forces(sigma, eps, virial=True, half=True)
+    b = cl.lj_forces(sigma, eps, virial=True, half=True)
+    for k in ("energy", "forces", "grad_box", "virial", "count"):
+        assert a[k].cpu().numpy().tobytes() == b[k].cpu().numpy().tobytes(), k
+    f = cl.lj_forces(sigma, eps, virial=True, half=False)
+    assert int(f["count"].item()) == int(a["count"].item())
+    ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
+    _check(a, ref, x, sigma, eps)
+    _check(f, ref, x, sigma, eps)
+
+
+def test_half_shell_scratch_errors(clm):
+    import ctypes
+    L = clm._lib
+    H, rc = BOXES["cube3"]
+    x = _lattice(H, 3000, 13)
+    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp32")
+    sp, need = cl._half_scratch("lj_ef", True)
+    e = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    c = torch.full((1,), -1, dtype=torch.int64, device="cuda:0")
+    f = torch.empty((len(x), 3), dtype=torch.float64, device="cuda:0")
+    P = L.MapParams(sigma=1.0, epsilon=0.1, scratch_dev=sp, scratch_bytes=need - 1)
+    o = L.MapOut(energy_dev=ctypes.c_void_p(e.data_ptr()), forces_dev=ctypes.c_void_p(f.data_ptr()),
+                 count_dev=ctypes.c_void_p(c.data_ptr()))
+    st = L.lib().clm_map(cl._h, L.MAP_KINDS["lj_ef"], ctypes.byref(P), ctypes.byref(o))
+    assert st == L.STATUS_CODES["CLM_E_WORKSPACE"]
+    P.scratch_dev = ctypes.c_void_p(sp.value + 8)
+    P.scratch_bytes = need
+    st = L.lib().clm_map(cl._h, L.MAP_KINDS["lj_ef"], ctypes.byref(P), ctypes.byref(o))
+    assert st == L.STATUS_CODES["CLM_E_WORKSPACE"]
+    torch.cuda.synchronize()
+    assert int(c.item()) == -1
+    # where the sweep does not apply (FP64 form) the scratch is 0 bytes
+    cl64 = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp64")
+    assert cl64._half_scratch("lj_ef", True) == (None, 0)
