@@ -76,10 +76,10 @@ static constexpr int64_t kMaxCells = int64_t(1) << 24;
 // |D| <= 1.01 rc (a farther one has d2_32 > rc^2 whatever the rounding), so
 // |d2_32 - d2| <= 2 (1.01 rc) |E| + |E|^2 + 4 u (1.02 rc^2) for the FMA chain
 // of three roundings.  The band is twice that bound.
-// M scales the cell extent per fractional axis: the j coordinates of the
-// half-shell LJ sweep are offsets from a particle of the same row piece, at
-// most M_b cells apart along axis b (C_a = sum_b |H_ab| M_b / n_b), and the
-// i coordinates from the same origin are at most |D_a| + C_a, which the same
+// M scales the cell extent per fractional axis: the i coordinates of the
+// half-shell LJ sweep are offsets from the centre of the tile's bounding box,
+// within M_b cells along axis b (C_a = sum_b |H_ab| M_b / n_b), and the j
+// coordinates from the same origin are at most |D_a| + C_a, which the same
 // bound covers.
 static void map_band(const clm_box& B, double rc, double* band, float* lo32, float* hi32,
                      const double* M = nullptr) {
@@ -748,12 +748,18 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     jd.rc2 = rcm * rcm;
     map_band(B, rcm, &jd.band, &jd.lo32, &jd.hi32);
   }
-  if (ljf) {  // half-shell LJ sweep: thresholds per tile span
+  if (ljf) {  // half-shell LJ sweep: thresholds per tile span, in units of sigma^2
+    const double s2 = P->sigma * P->sigma;
     for (int sp = 0; sp <= kMaxSpan; ++sp) {
-      const double M[3] = {(double)(std::max(sp, 1) + 2 * B.lcx), 1.0, 1.0};
+      const double M[3] = {(double)std::max(sp, 1), 1.0, 1.0};
       double bd;
-      map_band(B, rcm, &bd, &jd.half_lo[sp], &jd.half_hi[sp], M);
+      float lo, hi;
+      map_band(B, rcm, &bd, &lo, &hi, M);
+      jd.half_lo[sp] = round_down_f((rcm * rcm - bd) / s2);
+      jd.half_hi[sp] = round_up_f((rcm * rcm + bd) / s2);
     }
+    const double nf = P->near_factor > 0.0 ? P->near_factor : 1.0;
+    jd.half_near2 = round_up_f(nf * nf);
   }
   const int k_launch = (ljf && P->want_virial) ? K_LJ_FV : k;
   jd.kind = k_launch;

@@ -113,9 +113,11 @@ struct JobDesc {
   const uint32_t* own_ntiles;  // device count
   int own_max_tiles;
   int pad3;
-  // half-shell LJ sweep: FP32 membership thresholds per tile span (1..kMaxSpan
-  // cells along x), coordinates relative to the tile's first cell origin
+  // half-shell LJ sweep (coordinates in units of sigma): FP32 membership
+  // thresholds on d^2 / sigma^2 per tile span (1..kMaxSpan cells along x) and
+  // the near threshold near_factor^2
   float half_lo[kMaxSpan + 1], half_hi[kMaxSpan + 1];
+  float half_near2, pad4;
 };
 
 // Dynamic LDS bytes per wave of the sweep.  The FP32 form keeps a ring

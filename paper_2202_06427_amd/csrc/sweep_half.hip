@@ -8,35 +8,43 @@
 // of cells (0..nx-1, cy, cz); rho = 0 is the home row itself (pairs j > i in
 // sorted order, cells forward along x), rho > 0 the neighbour rows with
 // (dz, dy) > (0, 0).  One wavefront runs one item: for each tile of row h
-// (<= 64 consecutive sorted particles, one per lane) it streams the tile's
-// reach in row r = h + offset(rho) as blocks of 64 particles, one per lane.
+// (<= 64 consecutive sorted particles, one per lane) it scans the tile's
+// reach in row r = h + offset(rho) (one to three pieces of consecutive
+// cells, with their periodic images) and keeps the particles whose distance
+// to the tile's bounding box is within the cutoff (the paper's section 2.8
+// pruning of candidates by their position, applied to the whole tile).  The
+// kept candidates are packed, in order, into blocks of 64 (the last one of
+// 16, 32 or 64).
 //
-// A block is a 64 x 64 set of pairs, visited in 64 steps: in step (phase g,
-// k) lane l pairs its i with the j that a DPP row rotation by k brings from
-// the lane group (l/16 + g) mod 4.  The rotation is folded into the
-// subtractions (v_sub_f32 with a DPP source), and the j-side force term goes
-// back through the inverse rotation folded into an add, so a step is about
-// 27 VALU instructions for 64 pairs.  Between phases the j data rotate by 16
-// lanes (ds_bpermute); after the 4th phase they are back in place.
+// A block is a 64 x JW set of pairs visited in JW steps: the JW candidates
+// sit in the lanes (JW < 64: 64 / JW copies), and in step (phase g, k) lane
+// l pairs its i with the candidate that a DPP row rotation by k brings from
+// its 16-lane row (the candidates rotate by 16 lanes inside each JW-lane
+// group between phases).  The rotation is folded into the subtractions
+// (v_sub_f32 with a DPP source) and the candidate-side force term goes back
+// through the inverse rotation folded into an add: a step is 26 VALU
+// instructions (one of them a quarter-rate reciprocal) for 64 pairs.
+// Coordinates are in units of sigma, so x = sigma^2 / d^2 is one reciprocal.
 //
-// Force sums: per lane, the i-side FP32 sum of a block (64 steps) is folded
-// into FP64; the j-side FP32 block sum is added (FP64 arithmetic, one FP32
-// rounding) into a FP32 plane slot owned by this item alone:
+// Force sums: per lane, the i-side FP32 sum of a block is folded into FP64;
+// the candidate-side FP32 sum of a block (the copies added) is added (FP64
+// arithmetic, one FP32 rounding) into a FP32 plane slot owned by this item
+// alone:
 //     plane 2 rho     : i-side sums of item (row(i), rho)
 //     plane 2 rho + 1 : j-side sums of item (row(j) - offset(rho), rho)
 // Both are indexed by sorted index, so every slot has exactly one writer; a
 // gather kernel sums the 2 NR planes of each particle in FP64 in a fixed
 // order.
 //
-// FP32 coordinates: relative to an origin O per block (the position of the
-// block's middle particle, shifted by the piece's image t), x = fl32(r' + t
-// - O) and x_i = fl32(r'_i - O), computed in FP64.  |x_j,a| <= C_a, the
-// extent of the visited piece of the row (at most span + 2 lx cells along x,
-// one cell across), and |x_i,a| <= |D_a| + C_a, so |D32_a - D_a| <=
-// u (2 C_a + 2 |D_a|) + FP64 roundings.  The membership band comes from that
-// bound per tile span (host table).  Pairs within the band of rc^2, and pairs
-// closer than the near threshold, are queued per wave and evaluated in
-// canonical FP64.
+// FP32 coordinates: relative to the centre O of the tile's bounding box,
+// x_i = fl32((r'_i - O) / sigma) and x_j = fl32((r'_j + t - O) / sigma),
+// computed in FP64.  |x_i,a| <= C_a, half the tile's extent (at most span
+// cells along x, one cell across), and |x_j,a| <= C_a + |D_a|, so
+// |D32_a - D_a| <= u (2 C_a + 2 |D_a|) + FP64 roundings (in sigma units):
+// the steep pairs (|D| near sigma) keep small errors when the tile is
+// compact.  The membership band comes from that bound per tile span (host
+// table).  Pairs within the band of rc^2, and pairs closer than the near
+// threshold, are queued per wave and evaluated in canonical FP64.
 #include "clmap_internal.h"
 #include "device_util.h"
 
@@ -44,7 +52,9 @@ namespace clm {
 
 namespace {
 
-constexpr int kHQCap = 512;  // per-wave queue of FP64 re-evaluations (power of two, >= 63 + 4 * 64)
+constexpr int kHQCap = 512;   // FP64 re-evaluation queue (power of two, >= 63 + 4 * 64)
+constexpr int kHLCap = 128;   // packed candidate list (power of two, >= 63 + 64)
+constexpr uint32_t kCenter = 13u;  // image code of K = (0, 0, 0)
 
 template <int K>
 __device__ __forceinline__ float row_ror(float v) {  // lane p reads lane (p - K) mod 16 of its row
@@ -74,9 +84,24 @@ __device__ __forceinline__ float row_back(float v) {
   }
 }
 
+__device__ __forceinline__ float shfl_f(float v, int src_byte) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src_byte, __builtin_bit_cast(int, v)));
+}
+
+__device__ __forceinline__ double wave_min_d(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v = fmin(v, __shfl_xor(v, d, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  return v;
+}
+
 // (dy, dz) of half-shell row offset rho: 0 -> home row; then (0, 1..l);
 // then dz = 1..l with dy = -l..l.  2D: dz = 0, dy = 0..l.
-__device__ __forceinline__ void row_offset(int dim, int l, int rho, int* dy, int* dz) {
+__device__ __forceinline__ void row_offset(int l, int rho, int* dy, int* dz) {
   if (rho == 0) {
     *dy = 0;
     *dz = 0;
@@ -88,7 +113,6 @@ __device__ __forceinline__ void row_offset(int dim, int l, int rho, int* dy, int
     return;
   }
   const int q = rho - l - 1;  // 3D only
-  (void)dim;
   *dz = 1 + q / (2 * l + 1);
   *dy = q % (2 * l + 1) - l;
 }
@@ -98,14 +122,12 @@ struct Half {
   const JobDesc* J;
   int lane;
   // uniform
-  int l, lx, nx, ny, nz;
-  double rc2, s2, inv_s2;
-  float s2f, near2f;
-  float lo, hi;
-  // per lane (i side, fixed for a tile; xi is relative to the block origin)
-  double ri[3];
-  bool active;
-  float xi[3];
+  double rc2, s2, inv_sig;
+  float near2f;            // (near_factor)^2: sigma units
+  float lo, hi;            // membership thresholds on d^2 / sigma^2
+  // per lane (i side, fixed for a tile)
+  double O[3];             // origin of the FP32 coordinates: centre of the tile's bounding box
+  float xi[3];             // relative to O, sigma units
   double Fi[3];
   // per lane accumulators of the item
   double E64;
@@ -116,26 +138,29 @@ struct Half {
   // per block
   float xj[3];
   float acc[3];
-  int mid;                 // j-block lane whose data this lane holds
+  int key;                 // home row: candidate's sorted index (pairs only j > i), else INT_MAX
   float e32;
   float fi32[3];
   float w32[6];
-  // queue (LDS)
-  uint32_t* Q;
-  double* GA;   // [64][3] FP64 i-side sums of queued pairs
-  double* GJ;   // [64][3] FP64 sums of f D (i -> j) of queued pairs, by j-block lane
+  // LDS
+  uint32_t* Q;             // queue of FP64 re-evaluations: i lane | candidate << 6 | band << 31
+  double* GA;              // [64][3] FP64 i-side sums of queued pairs
+  double* GJ;              // [64][3] FP64 sums of f D (i -> j) of queued pairs, by candidate
+  uint2* LST;              // packed candidates (sorted index, image code)
   uint32_t qhead, qtail;
-  uint32_t tstart, b0;
-  int kc;
-  int pp[3];
+  uint32_t lhead, ltail;
+  uint32_t tstart;
+  uint32_t bbase;          // list position of the block's first candidate
 
   // ---------------------------------------------------------------- FP64 queue
-  // Canonical FP64 evaluation of one queued pair (i lane il, j-block lane jm).
+  // Canonical FP64 evaluation of one queued pair (i lane il, candidate jm of
+  // the current block).
   __device__ __forceinline__ void process(uint32_t e, bool* in_out) {
     const int il = (int)(e & 63u), jm = (int)((e >> 6) & 63u);
+    const uint2 c = LST[(bbase + (uint32_t)jm) & (uint32_t)(kHLCap - 1)];
     const double4 rI = J->r64_x[tstart + (uint32_t)il];
-    const double4 rJ = J->r64_x[b0 + (uint32_t)jm];
-    const double* tk = &J->tK[kc * 4];
+    const double4 rJ = J->r64_x[c.x];
+    const double* tk = &J->tK[c.y * 4];
     double D[3];
     D[0] = (rJ.x - rI.x) + tk[0];
     D[1] = (rJ.y - rI.y) + tk[1];
@@ -160,7 +185,7 @@ struct Half {
       atomicAdd(&GJ[jm * 3 + a], f * D[a]);
     }
     // (the image term f D p^T of the box gradient is added with the block's
-    // j-side sums, which include GJ)
+    // candidate-side sums, which include GJ)
     if constexpr (VIR) {
       W[0] += f * D[0] * D[0];
       W[1] += f * D[0] * D[1];
@@ -195,25 +220,22 @@ struct Half {
   }
 
   // ---------------------------------------------------------------- one step
-  template <int K, bool SELF>
-  __device__ __forceinline__ void step() {
+  // JW: candidates of the block; lane L holds candidate (mrot of L) mod JW.
+  template <int K, bool SELF, int JW>
+  __device__ __forceinline__ void step(int mrot) {
     const float dx = row_ror<K>(xj[0]) - xi[0];
     const float dy = row_ror<K>(xj[1]) - xi[1];
     const float dz = DIM == 3 ? row_ror<K>(xj[2]) - xi[2] : 0.0f;
     const float d2 = DIM == 3 ? __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))
                               : __builtin_fmaf(dy, dy, dx * dx);
     unsigned long long okm = ~0ull;
-    int mj = 0;
-    if constexpr (SELF) {
-      mj = row_ror_i<K>(mid);
-      okm = __builtin_amdgcn_ballot_w64(mj > lane);
-    }
+    if constexpr (SELF) okm = __builtin_amdgcn_ballot_w64(row_ror_i<K>(key) > (int)(tstart + (uint32_t)lane));
     const unsigned long long mlo = __builtin_amdgcn_ballot_w64(d2 <= lo) & okm;
     const unsigned long long mhi = __builtin_amdgcn_ballot_w64(d2 <= hi) & okm;
     const unsigned long long mnr = __builtin_amdgcn_ballot_w64(d2 < near2f) & okm;
     cnt += (unsigned long long)__popcll(mlo);
     const bool fast = __builtin_amdgcn_inverse_ballot_w64(mlo & ~mnr);
-    const float x = fast ? s2f * __builtin_amdgcn_rcpf(d2) : 0.0f;
+    const float x = fast ? __builtin_amdgcn_rcpf(d2) : 0.0f;  // sigma^2 / d^2
     const float x3 = x * x * x;
     const float u = __builtin_fmaf(x3, x3, -x3);
     e32 += u;
@@ -248,7 +270,7 @@ struct Half {
     const unsigned long long band = mhi & ~mlo;
     const unsigned long long spec = band | mnr;
     if (spec) {
-      if constexpr (!SELF) mj = row_ror_i<K>(mid);
+      const int mj = row_ror_i<K>(mrot) & (JW - 1);
       const uint32_t t0 = (uint32_t)uniform((int)qtail);
       if (__builtin_amdgcn_inverse_ballot_w64(spec)) {
         const uint32_t slot = (t0 + (uint32_t)lane_rank(spec)) & (uint32_t)(kHQCap - 1);
@@ -261,64 +283,47 @@ struct Half {
 
   // 16 steps; the queue is drained (64 entries at a time) after every 4
   // steps, so it never holds more than 63 + 4 * 64 entries
-  template <bool SELF>
-  __device__ __forceinline__ void phase() {
-    step<0, SELF>(); step<1, SELF>(); step<2, SELF>(); step<3, SELF>();
+  template <bool SELF, int JW>
+  __device__ __forceinline__ void phase(int mrot) {
+    step<0, SELF, JW>(mrot); step<1, SELF, JW>(mrot); step<2, SELF, JW>(mrot); step<3, SELF, JW>(mrot);
     if (qtail - qhead >= (uint32_t)kWave) drain(false);
-    step<4, SELF>(); step<5, SELF>(); step<6, SELF>(); step<7, SELF>();
+    step<4, SELF, JW>(mrot); step<5, SELF, JW>(mrot); step<6, SELF, JW>(mrot); step<7, SELF, JW>(mrot);
     if (qtail - qhead >= (uint32_t)kWave) drain(false);
-    step<8, SELF>(); step<9, SELF>(); step<10, SELF>(); step<11, SELF>();
+    step<8, SELF, JW>(mrot); step<9, SELF, JW>(mrot); step<10, SELF, JW>(mrot); step<11, SELF, JW>(mrot);
     if (qtail - qhead >= (uint32_t)kWave) drain(false);
-    step<12, SELF>(); step<13, SELF>(); step<14, SELF>(); step<15, SELF>();
+    step<12, SELF, JW>(mrot); step<13, SELF, JW>(mrot); step<14, SELF, JW>(mrot); step<15, SELF, JW>(mrot);
     if (qtail - qhead >= (uint32_t)kWave) drain(false);
   }
 
-  // rotate the j data by one lane group (lane L takes lane L + 16)
-  __device__ __forceinline__ void rotate(bool pos) {
-    const int src = ((lane + 16) & 63) << 2;
-    if (pos) {
-#pragma unroll
-      for (int a = 0; a < DIM; ++a)
-        xj[a] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, xj[a])));
-    }
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-      acc[a] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, acc[a])));
-    mid = __builtin_amdgcn_ds_bpermute(src, mid);
-  }
-
-  // One block: j = b0 + lane for lanes with j < je.  part_j: this item's
-  // j-side plane (3 components, stride npad).
-  template <bool SELF>
-  __device__ __forceinline__ void block(uint32_t je, const double* t, float* part_j, size_t npad) {
-    const uint32_t j = b0 + (uint32_t)lane;
-    const bool jv = j < je;
+  // One block of the nb (1..JW) candidates at list positions bbase..;
+  // part_j: this item's j-side plane (3 components, stride npad).
+  template <bool SELF, int JW>
+  __device__ __forceinline__ void block(uint32_t nb, float* part_j, size_t npad) {
+    const int m = lane & (JW - 1);
+    const bool jv = (uint32_t)m < nb;
+    const uint2 c = jv ? LST[(bbase + (uint32_t)m) & (uint32_t)(kHLCap - 1)] : make_uint2(0u, kCenter);
+    const double* tK = J->tK;
     {
-      // block origin: the middle particle of the block (shifted by t), so
-      // the FP32 offsets of the block are small and those of the lanes are
-      // at most their distance to the block plus its extent
-      const uint32_t jm = b0 + (min(je - b0, (uint32_t)kWave) - 1u) / 2u;
-      const double4 rm = ldu(&J->r64_x[jm]);
-      const double O[3] = {rm.x + t[0], rm.y + t[1], rm.z + t[2]};
-      xi[0] = active ? (float)(ri[0] - O[0]) : 1e18f;
-      xi[1] = active ? (float)(ri[1] - O[1]) : 1e18f;
-      xi[2] = DIM == 3 ? (active ? (float)(ri[2] - O[2]) : 1e18f) : 0.0f;
-      double4 r = jv ? J->r64_x[j] : make_double4(0.0, 0.0, 0.0, 0.0);
-      xj[0] = jv ? (float)((r.x + t[0]) - O[0]) : -1e18f;
-      xj[1] = jv ? (float)((r.y + t[1]) - O[1]) : -1e18f;
-      xj[2] = DIM == 3 ? (jv ? (float)((r.z + t[2]) - O[2]) : -1e18f) : 0.0f;
+      const double4 r = jv ? J->r64_x[c.x] : make_double4(0.0, 0.0, 0.0, 0.0);
+      const double* t = &tK[c.y * 4];
+      xj[0] = jv ? (float)(((r.x + t[0]) - O[0]) * inv_sig) : -1e18f;
+      xj[1] = jv ? (float)(((r.y + t[1]) - O[1]) * inv_sig) : -1e18f;
+      xj[2] = DIM == 3 ? (jv ? (float)(((r.z + t[2]) - O[2]) * inv_sig) : -1e18f) : 0.0f;
     }
+    if constexpr (SELF) key = (jv && c.y == kCenter) ? (int)c.x : 0x7fffffff;
     float jold[3] = {0.0f, 0.0f, 0.0f};
-    if (jv) {
+    if (jv && lane < JW) {
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) jold[a] = part_j[(size_t)a * npad + j];
+      for (int a = 0; a < DIM; ++a) jold[a] = part_j[(size_t)a * npad + c.x];
     }
-    mid = lane;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       acc[a] = 0.0f;
       fi32[a] = 0.0f;
-      GJ[lane * 3 + a] = 0.0;
+    }
+    if (lane < JW) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) GJ[lane * 3 + a] = 0.0;
     }
     e32 = 0.0f;
     if constexpr (VIR) {
@@ -326,44 +331,191 @@ struct Half {
       for (int k = 0; k < 6; ++k) w32[k] = 0.0f;
     }
     __builtin_amdgcn_wave_barrier();
-    for (int g = 0; g < 4; ++g) {
-      phase<SELF>();
-      rotate(g < 3);  // after the 4th phase only acc and mid (back in place)
+    // phases: the candidates rotate by 16 lanes inside each JW-lane group
+    int mrot = lane;
+    const int src = ((lane & ~(JW - 1)) | ((lane + 16) & (JW - 1))) << 2;
+#pragma unroll
+    for (int g = 0; g < JW / 16; ++g) {
+      phase<SELF, JW>(mrot);
+      if constexpr (JW > 16) {
+        if (g + 1 < JW / 16) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) xj[a] = shfl_f(xj[a], src);
+          if constexpr (SELF) key = __builtin_amdgcn_ds_bpermute(src, key);
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) acc[a] = shfl_f(acc[a], src);  // back in place after the last
+        mrot = __builtin_amdgcn_ds_bpermute(src, mrot);
+      }
+    }
+    // the 64 / JW copies of each candidate's sums
+    if constexpr (JW <= 32) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) acc[a] += shfl_f(acc[a], (lane ^ 32) << 2);
+    }
+    if constexpr (JW <= 16) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) acc[a] += shfl_f(acc[a], (lane ^ 16) << 2);
     }
     drain(true);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    // fold the block into FP64
+    // fold the block into FP64 (sigma units: forces times 1/sigma, virial as is)
     E64 += (double)e32;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) Fi[a] += (double)fi32[a] * inv_s2;
+    for (int a = 0; a < DIM; ++a) Fi[a] += (double)fi32[a] * inv_sig;
     if constexpr (VIR) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) W[k] += (double)w32[k] * inv_s2;
+      for (int k = 0; k < 6; ++k) W[k] += (double)w32[k];
     }
-    const bool img = (pp[0] | pp[1] | pp[2]) != 0;
-    if (jv) {
+    if (jv && lane < JW) {
       double S[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        S[a] = (double)acc[a] * inv_s2 + GJ[lane * 3 + a];
-        part_j[(size_t)a * npad + j] = (float)((double)jold[a] - S[a]);
+        S[a] = (double)acc[a] * inv_sig + GJ[lane * 3 + a];
+        part_j[(size_t)a * npad + c.x] = (float)((double)jold[a] - S[a]);
       }
-      if (img) {
+      if (c.y != kCenter) {  // a periodic image: the box-gradient term S p^T
+        const int p[3] = {(int)(c.y % 3u) - 1, (int)((c.y / 3u) % 3u) - 1, (int)(c.y / 9u) - 1};
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
 #pragma unroll
-          for (int b = 0; b < DIM; ++b) B[a * 3 + b] += S[a] * (double)pp[b];
+          for (int b = 0; b < DIM; ++b) B[a * 3 + b] += S[a] * (double)p[b];
       }
     }
   }
+
+  template <bool SELF>
+  __device__ __forceinline__ void run_full(float* part_j, size_t npad) {
+    while (ltail - lhead >= (uint32_t)kWave) {
+      bbase = lhead;
+      block<SELF, 64>(64u, part_j, npad);
+      lhead += (uint32_t)kWave;
+    }
+  }
+
+  template <bool SELF>
+  __device__ __forceinline__ void run_tail(float* part_j, size_t npad) {
+    const uint32_t r = ltail - lhead;
+    if (r == 0u) return;
+    bbase = lhead;
+    if (r > 32u)
+      block<SELF, 64>(r, part_j, npad);
+    else if (r > 16u)
+      block<SELF, 32>(r, part_j, npad);
+    else
+      block<SELF, 16>(r, part_j, npad);
+    lhead = ltail;
+  }
 };
+
+template <int DIM, bool VIR, bool SELF>
+__device__ __forceinline__ void run_tiles(Half<DIM, VIR>& S, const HalfArgs& A, int h, int py, int pz,
+                                          int rbase, float* part_i, float* part_j) {
+  const JobDesc* J = S.J;
+  const int lane = S.lane;
+  const int nx = ldu(&J->n[0]), lx = ldu(&J->lcell_x);
+  const uint32_t* off = ldu(&J->off_x);
+  const size_t npad = A.npad;
+  const uint32_t* row_off = A.row_off;
+  const int t0 = (int)ldu(&row_off[h]), t1 = min((int)ldu(&row_off[h + 1]), A.max_tiles);
+  const Tile* tiles = A.tiles;
+  // pruning threshold: above the cutoff by far more than the FP64 rounding
+  // of the bounding-box distance
+  const double rcut2 = S.rc2 * (1.0 + 1e-9);
+  for (int ti = t0; ti < t1; ++ti) {
+    // the previous tile's plane updates are visible to every lane
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const Tile T = ldu(&tiles[ti]);
+    const int count = T.count;
+    const int cx0 = T.cx0, cx1 = T.cx1;
+    const bool active = lane < count;
+    S.tstart = T.start;
+    const uint32_t i = T.start + (uint32_t)(active ? lane : count - 1);
+    const int span = cx1 - cx0 + 1;
+    S.lo = ldu(&J->half_lo[span]);
+    S.hi = ldu(&J->half_hi[span]);
+    double bl[3] = {0.0, 0.0, 0.0}, bh[3] = {0.0, 0.0, 0.0};
+    {
+      const double4 r = J->r64_x[i];
+      const double ri[3] = {r.x, r.y, r.z};
+      // the tile's bounding box (inactive lanes repeat the last particle);
+      // its centre is the origin of the FP32 coordinates
+#pragma unroll
+      for (int a = 0; a < 3; ++a) S.O[a] = 0.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        bl[a] = wave_min_d(ri[a]);
+        bh[a] = wave_max_d(ri[a]);
+        S.O[a] = 0.5 * (bl[a] + bh[a]);
+      }
+      S.xi[0] = active ? (float)((ri[0] - S.O[0]) * S.inv_sig) : 1e18f;
+      S.xi[1] = active ? (float)((ri[1] - S.O[1]) * S.inv_sig) : 1e18f;
+      S.xi[2] = DIM == 3 ? (active ? (float)((ri[2] - S.O[2]) * S.inv_sig) : 1e18f) : 0.0f;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      S.Fi[a] = 0.0;
+      S.GA[lane * 3 + a] = 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    S.lhead = 0;
+    S.ltail = 0;
+    // pieces of the visited cell range [xlo, xhi] of row r: px = -1, 0, +1
+    const int xlo = SELF ? cx0 : cx0 - lx, xhi = cx1 + lx;
+    for (int px = -1; px <= 1; ++px) {
+      int a0 = xlo, a1 = xhi;
+      if (px < 0) { a1 = min(a1, -1); }
+      else if (px == 0) { a0 = max(a0, 0); a1 = min(a1, nx - 1); }
+      else { a0 = max(a0, nx); }
+      if (a0 > a1) continue;
+      const int c0 = a0 - px * nx, c1 = a1 - px * nx;  // wrapped cell indices
+      uint32_t jb = ldu(&off[rbase + c0]);
+      const uint32_t je = ldu(&off[rbase + c1 + 1]);
+      if (SELF && px == 0) jb = T.start;  // pairs j > i: from the tile's first particle on
+      const int kc = kcode(px, py, pz);
+      const double t[3] = {ldu(&J->tK[kc * 4 + 0]), ldu(&J->tK[kc * 4 + 1]), ldu(&J->tK[kc * 4 + 2])};
+      for (uint32_t cb = jb; cb < je; cb += kWave) {
+        // keep the candidates within the cutoff of the tile's bounding box
+        const uint32_t j = cb + (uint32_t)lane;
+        bool keep = false;
+        if (j < je) {
+          const double4 r = J->r64_x[j];
+          const double q[3] = {r.x + t[0], r.y + t[1], r.z + t[2]};
+          double dd = 0.0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            const double e = fmax(0.0, fmax(bl[a] - q[a], q[a] - bh[a]));
+            dd += e * e;
+          }
+          keep = dd <= rcut2;
+        }
+        const unsigned long long km = __builtin_amdgcn_ballot_w64(keep);
+        if (keep)
+          S.LST[(S.ltail + (uint32_t)lane_rank(km)) & (uint32_t)(kHLCap - 1)] = make_uint2(j, (uint32_t)kc);
+        S.ltail += (uint32_t)__popcll(km);
+        __builtin_amdgcn_wave_barrier();
+        S.template run_full<SELF>(part_j, npad);
+      }
+    }
+    S.template run_tail<SELF>(part_j, npad);
+    // the tile's i-side sums (plane 2 rho, one writer per particle)
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) S.Fi[a] += S.GA[lane * 3 + a];
+    if (active) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) part_i[(size_t)a * npad + i] = (float)S.Fi[a];
+    }
+  }
+}
 
 }  // namespace
 
 template <int DIM, bool VIR>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   __shared__ uint32_t sQ[kHQCap];
+  __shared__ uint2 sL[kHLCap];
   __shared__ double sGA[kWave * 3];
   __shared__ double sGJ[kWave * 3];
   const int lane = (int)__lane_id();
@@ -384,18 +536,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ha
   S.J = J;
   S.lane = lane;
   S.Q = sQ;
+  S.LST = sL;
   S.GA = sGA;
   S.GJ = sGJ;
-  S.l = ldu(&J->lcell);
-  S.lx = ldu(&J->lcell_x);
-  S.nx = ldu(&J->n[0]);
-  S.ny = ldu(&J->n[1]);
-  S.nz = ldu(&J->n[2]);
   S.rc2 = ldu(&J->rc2);
   S.s2 = ldu(&J->s2);
-  S.inv_s2 = 1.0 / S.s2;
-  S.s2f = ldu(&J->s2f);
-  S.near2f = ldu(&J->near2f);
+  S.inv_sig = 1.0 / sqrt(S.s2);
+  S.near2f = ldu(&J->half_near2);
   S.E64 = 0.0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) S.B[k] = 0.0;
@@ -406,11 +553,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ha
   S.cnt = 0;
   S.qhead = 0;
   S.qtail = 0;
+  S.key = 0x7fffffff;
 
-  const int nx = S.nx, ny = S.ny, nz = S.nz, l = S.l, lx = S.lx;
+  const int nx = ldu(&J->n[0]), ny = ldu(&J->n[1]), nz = ldu(&J->n[2]), l = ldu(&J->lcell);
   const int cy = h % ny, cz = DIM == 3 ? h / ny : 0;
   int dy, dz;
-  row_offset(DIM, l, rho, &dy, &dz);
+  row_offset(l, rho, &dy, &dz);
   int uy = cy + dy, uz = cz + dz, py = 0, pz = 0;
   if (uy >= ny) { uy -= ny; py = 1; } else if (uy < 0) { uy += ny; py = -1; }
   if (DIM == 3) {
@@ -428,69 +576,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ha
       for (int a = 0; a < DIM; ++a) part_j[(size_t)a * npad + j] = 0.0f;
     }
   }
-  const uint32_t* row_off = A.row_off;
-  const int t0 = (int)ldu(&row_off[h]), t1 = min((int)ldu(&row_off[h + 1]), A.max_tiles);
-  const Tile* tiles = A.tiles;
-  for (int ti = t0; ti < t1; ++ti) {
-    // the previous tile's plane updates are visible to every lane
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    const Tile T = ldu(&tiles[ti]);
-    const int count = T.count;
-    const int cx0 = T.cx0, cx1 = T.cx1;
-    const bool active = lane < count;
-    S.tstart = T.start;
-    const uint32_t i = T.start + (uint32_t)(active ? lane : count - 1);
-    const int span = cx1 - cx0 + 1;
-    S.lo = ldu(&J->half_lo[span]);
-    S.hi = ldu(&J->half_hi[span]);
-    {
-      const double4 r = J->r64_x[i];
-      S.ri[0] = r.x;
-      S.ri[1] = r.y;
-      S.ri[2] = r.z;
-      S.active = active;
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      S.Fi[a] = 0.0;
-      sGA[lane * 3 + a] = 0.0;
-    }
-    __builtin_amdgcn_wave_barrier();
-    // pieces of the visited cell range [xlo, xhi] of row r: px = -1, 0, +1
-    const int xlo = rho == 0 ? cx0 : cx0 - lx, xhi = cx1 + lx;
-    for (int px = -1; px <= 1; ++px) {
-      int a0 = xlo, a1 = xhi;
-      if (px < 0) { a1 = min(a1, -1); }
-      else if (px == 0) { a0 = max(a0, 0); a1 = min(a1, nx - 1); }
-      else { a0 = max(a0, nx); }
-      if (a0 > a1) continue;
-      const int c0 = a0 - px * nx, c1 = a1 - px * nx;  // wrapped cell indices
-      uint32_t jb = ldu(&off[rbase + c0]);
-      const uint32_t je = ldu(&off[rbase + c1 + 1]);
-      const bool home = rho == 0 && px == 0;
-      if (home) jb = T.start;  // pairs j > i: from the tile's first particle on
-      if (jb >= je) continue;
-      S.pp[0] = px;
-      S.pp[1] = py;
-      S.pp[2] = pz;
-      S.kc = kcode(px, py, pz);
-      const double t[3] = {ldu(&J->tK[S.kc * 4 + 0]), ldu(&J->tK[S.kc * 4 + 1]), ldu(&J->tK[S.kc * 4 + 2])};
-      for (uint32_t bb = jb; bb < je; bb += kWave) {
-        S.b0 = bb;
-        if (home && bb == jb)
-          S.template block<true>(je, t, part_j, npad);
-        else
-          S.template block<false>(je, t, part_j, npad);
-      }
-    }
-    // the tile's i-side sums (plane 2 rho, one writer per particle)
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) S.Fi[a] += sGA[lane * 3 + a];
-    if (active) {
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) part_i[(size_t)a * npad + i] = (float)S.Fi[a];
-    }
-  }
+  if (rho == 0)
+    run_tiles<DIM, VIR, true>(S, A, h, py, pz, rbase, part_i, part_j);
+  else
+    run_tiles<DIM, VIR, false>(S, A, h, py, pz, rbase, part_i, part_j);
 
   // ---- item partials
   const unsigned long long cnt = S.cnt;
