@@ -157,6 +157,10 @@ typedef struct clm_map_params {
                                    too small or misaligned is CLM_E_WORKSPACE; other kinds and
                                    forms ignore it. */
   size_t scratch_bytes;
+  int no_prune;                 /* half-shell force sweep: 1 keeps every candidate of the visited
+                                   cells (no pruning by the distance to the tile's bounding box;
+                                   same results, for comparison) */
+  int pad_params;
 } clm_map_params;
 
 typedef struct clm_map_out {

@@ -301,17 +301,20 @@ class CellList:
         raw = self._scratch[0]
         return ctypes.c_void_p(raw.data_ptr() + (-raw.data_ptr()) % 256), need
 
-    def lj_forces(self, sigma, epsilon, near_factor=1.0, virial=False, cutoff=None, half=True):
+    def lj_forces(self, sigma, epsilon, near_factor=1.0, virial=False, cutoff=None, half=True,
+                  prune=True):
         """Energy, forces (-dE/dr, paper Code 7), dE/dH and optionally the virial.
         half: FP32 form only -- evaluate every pair once (half-shell sweep with
-        map scratch) instead of from both ends (full-shell gather)."""
+        map scratch) instead of from both ends (full-shell gather); prune:
+        that sweep skips candidates farther than the cutoff from the tile's
+        bounding box (same results)."""
         e, c = self._scalars()
         f = torch.empty((self.nx, self.dim), dtype=torch.float64, device=self.device)
         gb = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device)
         w = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device) if virial else None
         sp, sb = self._half_scratch("lj_ef", half)
         P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, want_virial=int(virial),
-                        cutoff=_rc(cutoff), scratch_dev=sp, scratch_bytes=sb)
+                        cutoff=_rc(cutoff), scratch_dev=sp, scratch_bytes=sb, no_prune=int(not prune))
         o = L.MapOut(energy_dev=_ptr(e), forces_dev=_ptr(f), grad_box_dev=_ptr(gb),
                      virial_dev=_ptr(w), count_dev=_ptr(c))
         self._map("lj_ef", P, o)

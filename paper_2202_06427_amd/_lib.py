@@ -56,6 +56,7 @@ class MapParams(ctypes.Structure):
         ("want_sums", ctypes.c_int), ("capacity", ctypes.c_int64), ("with_distances", ctypes.c_int),
         ("cutoff", ctypes.c_double), ("weights_x_dev", _vp), ("weights_y_dev", _vp),
         ("scratch_dev", _vp), ("scratch_bytes", ctypes.c_size_t),
+        ("no_prune", ctypes.c_int), ("pad_params", ctypes.c_int),
     ]
 
 

@@ -760,6 +760,7 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     }
     const double nf = P->near_factor > 0.0 ? P->near_factor : 1.0;
     jd.half_near2 = round_up_f(nf * nf);
+    jd.half_noprune = P->no_prune ? 1 : 0;
   }
   const int k_launch = (ljf && P->want_virial) ? K_LJ_FV : k;
   jd.kind = k_launch;
@@ -910,9 +911,10 @@ clm_status map_one(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
     Timed ts(cl->untimed ? nullptr : cl->ctx, &cl->ctx->sweep_ev);
     s = ts.start();
     if (s != CLM_OK) return s;
-    CLM_HIP(launch_half_lj(B.dim, k_launch == K_LJ_FV, cl->job_dev, A, (int)cl->nx, st));
+    CLM_HIP(launch_half_lj(B.dim, k_launch == K_LJ_FV, cl->job_dev, A, st));
     s = ts.stop();
     if (s != CLM_OK) return s;
+    CLM_HIP(launch_half_gather(B.dim, cl->job_dev, A, (int)cl->nx, st));
     F.nparts = HL.nitems + HL.ngather;
     F.nparts_dev = nullptr;
     F.split_rows = 0;

@@ -117,7 +117,8 @@ struct JobDesc {
   // thresholds on d^2 / sigma^2 per tile span (1..kMaxSpan cells along x) and
   // the near threshold near_factor^2
   float half_lo[kMaxSpan + 1], half_hi[kMaxSpan + 1];
-  float half_near2, pad4;
+  float half_near2;
+  int half_noprune;          // 1: keep every candidate (no bounding-box pruning)
 };
 
 // Dynamic LDS bytes per wave of the sweep.  The FP32 form keeps a ring
@@ -391,8 +392,8 @@ __host__ __device__ inline int brute_chunks(int64_t ny) {
 }
 hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, double* FB, int* nparts_out,
                         hipStream_t s);
-hipError_t launch_half_lj(int dim, bool virial, const JobDesc* jobs, const HalfArgs& A, int n,
-                          hipStream_t s);
+hipError_t launch_half_lj(int dim, bool virial, const JobDesc* jobs, const HalfArgs& A, hipStream_t s);
+hipError_t launch_half_gather(int dim, const JobDesc* jobs, const HalfArgs& A, int n, hipStream_t s);
 hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, double* scratch,
                            unsigned long long* scratch_count, hipStream_t s);
 constexpr int kFinalBlocks = 128;  // first-level blocks of the two-level finalize

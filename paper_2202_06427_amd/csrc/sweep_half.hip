@@ -208,7 +208,7 @@ struct Half {
         const uint32_t e = Q[(h + (uint32_t)lane) & (uint32_t)(kHQCap - 1)];
         bool in = false;
         process(e, &in);
-        const bool band = (e >> 31) != 0u;
+        const bool band = (e >> 31) != 0u;  // above lo in FP32: FP64 decides and counts
         qband += band ? 1u : 0u;
         qnear += band ? 0u : 1u;
         band_in = band && in;
@@ -220,9 +220,9 @@ struct Half {
   }
 
   // ---------------------------------------------------------------- one step
-  // JW: candidates of the block; lane L holds candidate (mrot of L) mod JW.
+  // jtag: (candidate held by this lane) << 6.
   template <int K, bool SELF, int JW>
-  __device__ __forceinline__ void step(int mrot) {
+  __device__ __forceinline__ void step(int jtag) {
     const float dx = row_ror<K>(xj[0]) - xi[0];
     const float dy = row_ror<K>(xj[1]) - xi[1];
     const float dz = DIM == 3 ? row_ror<K>(xj[2]) - xi[2] : 0.0f;
@@ -270,12 +270,17 @@ struct Half {
     const unsigned long long band = mhi & ~mlo;
     const unsigned long long spec = band | mnr;
     if (spec) {
-      const int mj = row_ror_i<K>(mrot) & (JW - 1);
+      // entry: i lane | candidate << 6 | band << 31 (jtag rotates with the
+      // candidates; the DPP read happens with every lane active: a source
+      // lane outside exec would read as 0)
+      const uint32_t jt = (uint32_t)row_ror_i<K>(jtag);
       const uint32_t t0 = (uint32_t)uniform((int)qtail);
       if (__builtin_amdgcn_inverse_ballot_w64(spec)) {
-        const uint32_t slot = (t0 + (uint32_t)lane_rank(spec)) & (uint32_t)(kHQCap - 1);
-        const bool b = __builtin_amdgcn_inverse_ballot_w64(band);
-        Q[slot] = (uint32_t)lane | ((uint32_t)mj << 6) | (b ? 0x80000000u : 0u);
+        const uint32_t slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(spec >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)spec, t0));
+        const uint32_t me = __builtin_amdgcn_inverse_ballot_w64(band) ? ((uint32_t)lane | 0x80000000u)
+                                                                      : (uint32_t)lane;
+        Q[slot & (uint32_t)(kHQCap - 1)] = jt | me;
       }
       qtail = (uint32_t)uniform((int)(t0 + (uint32_t)__popcll(spec)));
     }
@@ -284,14 +289,14 @@ struct Half {
   // 16 steps; the queue is drained (64 entries at a time) after every 4
   // steps, so it never holds more than 63 + 4 * 64 entries
   template <bool SELF, int JW>
-  __device__ __forceinline__ void phase(int mrot) {
-    step<0, SELF, JW>(mrot); step<1, SELF, JW>(mrot); step<2, SELF, JW>(mrot); step<3, SELF, JW>(mrot);
+  __device__ __forceinline__ void phase(int jtag) {
+    step<0, SELF, JW>(jtag); step<1, SELF, JW>(jtag); step<2, SELF, JW>(jtag); step<3, SELF, JW>(jtag);
     if (qtail - qhead >= (uint32_t)kWave) drain(false);
-    step<4, SELF, JW>(mrot); step<5, SELF, JW>(mrot); step<6, SELF, JW>(mrot); step<7, SELF, JW>(mrot);
+    step<4, SELF, JW>(jtag); step<5, SELF, JW>(jtag); step<6, SELF, JW>(jtag); step<7, SELF, JW>(jtag);
     if (qtail - qhead >= (uint32_t)kWave) drain(false);
-    step<8, SELF, JW>(mrot); step<9, SELF, JW>(mrot); step<10, SELF, JW>(mrot); step<11, SELF, JW>(mrot);
+    step<8, SELF, JW>(jtag); step<9, SELF, JW>(jtag); step<10, SELF, JW>(jtag); step<11, SELF, JW>(jtag);
     if (qtail - qhead >= (uint32_t)kWave) drain(false);
-    step<12, SELF, JW>(mrot); step<13, SELF, JW>(mrot); step<14, SELF, JW>(mrot); step<15, SELF, JW>(mrot);
+    step<12, SELF, JW>(jtag); step<13, SELF, JW>(jtag); step<14, SELF, JW>(jtag); step<15, SELF, JW>(jtag);
     if (qtail - qhead >= (uint32_t)kWave) drain(false);
   }
 
@@ -332,11 +337,11 @@ struct Half {
     }
     __builtin_amdgcn_wave_barrier();
     // phases: the candidates rotate by 16 lanes inside each JW-lane group
-    int mrot = lane;
+    int jtag = (lane & (JW - 1)) << 6;
     const int src = ((lane & ~(JW - 1)) | ((lane + 16) & (JW - 1))) << 2;
 #pragma unroll
     for (int g = 0; g < JW / 16; ++g) {
-      phase<SELF, JW>(mrot);
+      phase<SELF, JW>(jtag);
       if constexpr (JW > 16) {
         if (g + 1 < JW / 16) {
 #pragma unroll
@@ -345,7 +350,7 @@ struct Half {
         }
 #pragma unroll
         for (int a = 0; a < DIM; ++a) acc[a] = shfl_f(acc[a], src);  // back in place after the last
-        mrot = __builtin_amdgcn_ds_bpermute(src, mrot);
+        jtag = __builtin_amdgcn_ds_bpermute(src, jtag);
       }
     }
     // the 64 / JW copies of each candidate's sums
@@ -422,7 +427,7 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR>& S, const HalfArgs& A, 
   const Tile* tiles = A.tiles;
   // pruning threshold: above the cutoff by far more than the FP64 rounding
   // of the bounding-box distance
-  const double rcut2 = S.rc2 * (1.0 + 1e-9);
+  const double rcut2 = ldu(&J->half_noprune) ? __builtin_inf() : S.rc2 * (1.0 + 1e-9);
   for (int ti = t0; ti < t1; ++ti) {
     // the previous tile's plane updates are visible to every lane
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -661,8 +666,7 @@ __global__ void __launch_bounds__(256) half_gather_kernel(const JobDesc* __restr
   if (tid == 0) A.pcount[slot] = 0ull;
 }
 
-hipError_t launch_half_lj(int dim, bool virial, const JobDesc* jobs, const HalfArgs& A, int n,
-                          hipStream_t s) {
+hipError_t launch_half_lj(int dim, bool virial, const JobDesc* jobs, const HalfArgs& A, hipStream_t s) {
   if (A.nitems > 0) {
     if (dim == 3)
       virial ? half_lj_kernel<3, true><<<A.nitems, 64, 0, s>>>(jobs, A)
@@ -671,6 +675,10 @@ hipError_t launch_half_lj(int dim, bool virial, const JobDesc* jobs, const HalfA
       virial ? half_lj_kernel<2, true><<<A.nitems, 64, 0, s>>>(jobs, A)
              : half_lj_kernel<2, false><<<A.nitems, 64, 0, s>>>(jobs, A);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_half_gather(int dim, const JobDesc* jobs, const HalfArgs& A, int n, hipStream_t s) {
   const int nb = (n + 255) / 256;
   if (nb > 0) {
     if (dim == 3)

@@ -72,7 +72,8 @@ BOXES = {
 
 @pytest.mark.parametrize("name", list(BOXES))
 @pytest.mark.parametrize("lcell,lcell_x", [(1, None), (2, None), (3, None), (2, 3)])
-def test_half_shell_lattice_against_oracle(clm, name, lcell, lcell_x):
+@pytest.mark.parametrize("prune", [True, False])
+def test_half_shell_lattice_against_oracle(clm, name, lcell, lcell_x, prune):
     H, rc = BOXES[name]
     dim = H.shape[0]
     x = _lattice(H, 6000 if dim == 3 else 5000, 11) + H @ np.array([3, -2, 5][:dim])
@@ -80,13 +81,14 @@ def test_half_shell_lattice_against_oracle(clm, name, lcell, lcell_x):
     ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
     cl = clm.CellList(T(x), clm.Box(H, rc, lcell, lcell_x), precision="fp32")
     assert cl._half_scratch("lj_ef", True)[1] > 0, "the half-shell sweep applies here"
-    print(f"case {name} lcell={lcell} lcell_x={lcell_x}", flush=True)
-    _check(cl.lj_forces(sigma, eps, virial=True, half=True), ref, x, sigma, eps)
-    _check(cl.lj_forces(sigma, eps, virial=False, half=True), ref, x, sigma, eps, virial=False)
+    print(f"case {name} lcell={lcell} lcell_x={lcell_x} prune={prune}", flush=True)
+    _check(cl.lj_forces(sigma, eps, virial=True, half=True, prune=prune), ref, x, sigma, eps)
+    _check(cl.lj_forces(sigma, eps, virial=False, half=True, prune=prune), ref, x, sigma, eps, virial=False)
 
 
 @pytest.mark.parametrize("name", ["tric3", "cube3", "tric2"])
-def test_half_shell_uniform_random_near_pairs(clm, name):
+@pytest.mark.parametrize("prune", [True, False])
+def test_half_shell_uniform_random_near_pairs(clm, name, prune):
     """Uniform random points: pairs far inside sigma (FP64 near-pair path,
     forces into both particles' planes) dominate E."""
     H, rc = BOXES[name]
@@ -94,7 +96,7 @@ def test_half_shell_uniform_random_near_pairs(clm, name):
     sigma, eps = 3.4 if H.shape[0] == 3 else 1.0, 0.238
     ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
     cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp32")
-    out = cl.lj_forces(sigma, eps, virial=True, half=True)
+    out = cl.lj_forces(sigma, eps, virial=True, half=True, prune=prune)
     _check(out, ref, x, sigma, eps)
     info = cl.info()
     assert info["near_evaluations"] > 0
