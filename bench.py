@@ -4,10 +4,11 @@ Workload (the headline configuration): 1,000,000 uniform-random particles in
 a triclinic periodic box (lengths 215.4, angles 80/95/100 degrees), cutoff
 12, Lennard-Jones energy + forces (sigma 3.4, epsilon 0.238) through the
 adjoint sweep.  One step = one pass of the whole hot path over the resident
-positions: bin (wrap, cell index, prefix scan, tiles, scatter) + the
-full-shell LJ sweep with fused energy/force/box-gradient reduction +
-finalize.  The FP32+guard form is the headline value; the plain FP64 form is
-reported beside it.
+positions: bin (wrap, cell index, prefix scan, tiles, scatter) + the LJ
+sweep with fused energy/force/box-gradient reduction (FP32+guard: the
+half-shell sweep, every pair once; plain FP64: the full-shell gather) +
+per-particle force gather + finalize.  The FP32+guard form is the headline
+value; the plain FP64 form is reported beside it.
 
 Prints ONE JSON line (see the repository's benchmark contract).
 """
@@ -33,8 +34,8 @@ FLOPS_PER_LJ_PAIR = 20         # 1 reciprocal + ~19 flops: energy + force on bot
 BUILD_BYTES_PER_PARTICLE = 44  # 24 read + 16 (FP32 record) + 4 (index) written, 3D
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_lj_forces_uniform1e6_hbm_traffic.md")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_2202_06427_amd", "csrc", "sweep_kernels.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_half_lj_forces_uniform1e6_hbm_traffic.md")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2202_06427_amd", "csrc", "sweep_half.hip")
 
 
 def measured_traffic():
@@ -47,7 +48,7 @@ def measured_traffic():
     except OSError:
         return None
     fields = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith(("-", "|", "`")))
-    if fields.get("sweep_kernels.hip sha256 prefix", "").strip() != sha:
+    if fields.get("sweep_half.hip sha256 prefix", "").strip() != sha:
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
@@ -69,9 +70,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--serve-rate", type=float, default=1000.0,
-                    help="Poisson arrival rate of the served mix (jobs/s)")
+    ap.add_argument("--serve-requests", type=int, default=10_000)
+    ap.add_argument("--serve-fracs", type=str, default="0.5,0.8,0.95",
+                    help="Poisson arrival rates of the served mix as fractions of the measured "
+                         "closed-loop capacity")
     ap.add_argument("--build-n-large", type=int, default=16_000_000,
                     help="particle count of the second build-bandwidth point (0: skip)")
     ap.add_argument("--md-steps", type=int, default=200,
@@ -150,9 +152,12 @@ def time_steps(clm, cl, xt, steps, warmup, sigma, eps, samples=0):
     }
 
 
-def served(n_requests, rate, seed=5):
+def served(n_requests, fracs, seed=5, budget=8 << 30):
     """Served mix: closed-loop capacity (every job available at once), then
-    Poisson arrivals at a fixed rate (jobs/s) with p50/p99 latency."""
+    Poisson arrivals at each fraction of that capacity, with p50/p99
+    latency (arrival -> results complete on the device).  Results other than
+    counts and energies are dropped when a job completes (keep_results off),
+    as a server that hands them on would."""
     import numpy as np
 
     import workloads as W
@@ -160,8 +165,16 @@ def served(n_requests, rate, seed=5):
 
     import torch
     reqs = W.serve_requests(seed=seed, count=n_requests)
-    # request payloads arrive in pinned host buffers (as from a network stack)
-    xs = [torch.from_numpy(W.request_positions(r)).pin_memory() for r in reqs]
+    # request payloads arrive in pinned host memory (as from a network stack):
+    # one pinned buffer, a view per request
+    sizes = [r["n"] * 3 for r in reqs]
+    buf = torch.empty(sum(sizes), dtype=torch.float64, pin_memory=True)
+    xs, off = [], 0
+    for r, sz in zip(reqs, sizes):
+        v = buf[off: off + sz].view(r["n"], 3)
+        v.copy_(torch.from_numpy(W.request_positions(r)))
+        xs.append(v)
+        off += sz
 
     def jobs(rate):
         g = np.random.Generator(np.random.PCG64(seed + 1))
@@ -171,18 +184,46 @@ def served(n_requests, rate, seed=5):
             out.append(Job(r["id"], x, r["H"], r["cutoff"], r["kind"], arrival=t))
         return out
 
-    warm = Server(hbm_budget=8 << 30)
+    warm = Server(hbm_budget=budget, keep_results=False)
     warm.run(jobs(None)[: min(64, n_requests)], realtime=False)
-    closed = Server(hbm_budget=8 << 30).run(jobs(None), realtime=False)
+    closed = Server(hbm_budget=budget, keep_results=False).run(jobs(None), realtime=False)
     cap = closed["jobs_per_s"]
-    opened = Server(hbm_budget=8 << 30).run(jobs(rate), realtime=True)
-    return {"requests": n_requests, "capacity_jobs_per_s": cap, "rate_jobs_per_s": rate,
-            "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"], "mean_ms": opened["mean_ms"],
-            "mean_admission_wait_ms": opened["mean_admission_wait_ms"],
-            "pairs_per_s": opened["pairs_per_s"], "mean_batch": opened["mean_batch"],
-            "closed_loop_p50_ms": closed["p50_ms"], "closed_loop_p99_ms": closed["p99_ms"],
-            "hbm_budget_bytes": 8 << 30, "peak_hbm_bytes": opened["peak_hbm_bytes"],
-            "nl_retries": opened["nl_retries"], "failed": opened["failed"] + closed["failed"]}
+    out = {"requests": n_requests, "capacity_jobs_per_s": cap, "hbm_budget_bytes": budget,
+           "closed_loop": {k: closed[k] for k in ("p50_ms", "p99_ms", "mean_batch", "failed",
+                                                  "rejected", "nl_retries", "peak_hbm_bytes")},
+           "rates": []}
+    for f in fracs:
+        r = Server(hbm_budget=budget, keep_results=False).run(jobs(f * cap), realtime=True)
+        out["rates"].append({"frac_of_capacity": f, "rate_jobs_per_s": f * cap, "p50_ms": r["p50_ms"],
+                             "p99_ms": r["p99_ms"], "mean_ms": r["mean_ms"],
+                             "mean_admission_wait_ms": r["mean_admission_wait_ms"],
+                             "mean_batch": r["mean_batch"], "pairs_per_s": r["pairs_per_s"],
+                             "jobs": r["jobs"], "failed": r["failed"], "rejected": r["rejected"],
+                             "nl_retries": r["nl_retries"], "peak_hbm_bytes": r["peak_hbm_bytes"]})
+        log(f"served at {f:.2f} x capacity: {out['rates'][-1]}")
+    del buf, xs
+    return out
+
+
+def sweep_forms(clm, cl, xt, sigma, eps, reps=5):
+    """Sweep-kernel time of the FP32+guard LJ forces in its three forms:
+    the half-shell sweep (every pair once) with and without the pruning of
+    candidates by the tile's bounding box, and the full-shell gather."""
+    import torch
+    out = {}
+    for key, kw in (("half_pruned_ms", dict(half=True, prune=True)),
+                    ("half_unpruned_ms", dict(half=True, prune=False)),
+                    ("full_shell_ms", dict(half=False))):
+        cl.lj_forces(sigma, eps, **kw)
+        torch.cuda.synchronize()
+        clm.set_timing(True)
+        clm.stats(reset=True)
+        for _ in range(reps):
+            cl.lj_forces(sigma, eps, **kw)
+        st = clm.stats(reset=True)
+        clm.set_timing(False)
+        out[key] = st["sweep_ms"] / max(st["sweeps"], 1)
+    return out
 
 
 def build_roofline(clm, W, n, lcell, steps=5):
@@ -379,6 +420,15 @@ def measured_peaks(clm):
 
 
 def cpu_model():
+    """The CPU model string (lscpu's "Model name", else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            if line.strip().startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
@@ -388,6 +438,14 @@ def cpu_model():
     return None
 
 
+def usable_cpus():
+    """CPUs this process may run on (what nproc prints)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
 def per_core_sample(W):
     """The headline density (10^6 particles per 215.4-box) in a box of half
     the lattice-vector lengths: 125,000 particles, the same angles, cutoff and
@@ -395,6 +453,30 @@ def per_core_sample(W):
     H = 0.5 * W.triclinic_h(W.CFG2_LENGTHS, W.CFG2_ANGLES)
     x = W.rng(2).random((125_000, 3)) @ H.T
     return {"x": x, "H": H, "cutoff": 12.0, "sigma": 3.4, "epsilon": 0.238}
+
+
+def lattice_accuracy(clm, W, nthreads):
+    """FP32+guard LJ energy and forces (half-shell sweep) on the jittered
+    lattice of the headline box against the oracle: energy relative error and
+    the largest per-particle force error relative to the sum of that
+    particle's pair-force magnitudes."""
+    import numpy as np
+    import torch
+
+    import oracle
+    c = W.config2(variant="lattice")
+    s, e = c["sigma"], c["epsilon"]
+    xt = torch.from_numpy(c["x"]).to("cuda:0")
+    cl = clm.CellList(xt, clm.Box(c["H"], c["cutoff"], 2), precision="fp32")
+    out = cl.lj_forces(s, e)
+    F = out["forces"].cpu().numpy()
+    E = out["energy"].item()
+    ref = oracle.compute(c["x"], c["H"], c["cutoff"], lj=(s, e), lj_grad=True, lj_fabs=True,
+                         nthreads=nthreads)
+    err = np.linalg.norm(F + ref["lj_grad"], axis=1) / np.maximum(ref["lj_fabs"], 1e-300)
+    return {"workload": c["name"], "energy_rel_err": abs(E - ref["lj_energy"]) / abs(ref["lj_energy"]),
+            "max_force_err": float(err.max()), "mean_force_err": float(err.mean()),
+            "near_pair_evaluations": cl.info()["near_evaluations"], "pairs": ref["count"]}
 
 
 def cpu_baseline(cfg, nthreads):
@@ -440,6 +522,9 @@ def main():
         r = time_steps(clm, cl, xt, args.steps, args.warmup, sigma, eps, args.step_samples)
         info = cl.info()  # after the timed steps: re-evaluation counts of the last map
         r["info"] = info
+        if prec == "fp32":
+            r["forms"] = sweep_forms(clm, cl, xt, sigma, eps)
+            log(f"fp32 sweep forms: {r['forms']}")
         res[prec] = r
         log(f"{prec}: {r['ms_per_step']:.3f} ms/step (sweep {r['sweep_ms']:.3f} ms, build "
             f"{r['build_ms']:.3f} ms) pairs {r['count']} cand(half) {info['candidate_pairs']}")
@@ -474,7 +559,7 @@ def main():
         "phases_ms": {"build": main_r["build_ms"], "sweep": main_r["sweep_ms"]},
         "roofline": {
             "bound": "alu",
-            "kernel": "sweep_kernel<3,fp32,LJ forces>",
+            "kernel": "half_lj_kernel<3,false> (FP32+guard LJ forces, half shell, pruned)",
             "achieved": achieved,
             "peak": VALU_FP32_NONPACKED_TFLOPS,
             "unit": "TFLOP/s",
@@ -485,7 +570,10 @@ def main():
             "frac_in_cutoff_only": pairs * FLOPS_PER_LJ_PAIR / (main_r["sweep_ms"] * 1e-3) / 1e12
             / VALU_FP32_NONPACKED_TFLOPS,
             "peak_if_packed_fp32": VALU_FP32_PACKED_TFLOPS,
+            "target_frac": 0.5,
+            "target_met": achieved / VALU_FP32_NONPACKED_TFLOPS >= 0.5,
         },
+        "sweep_forms_ms": main_r["forms"],
         "guard": {"band_retests": guard["guard_retests"], "near_pair_evaluations": guard["near_evaluations"],
                   "fraction_of_pairs": (guard["guard_retests"] + guard["near_evaluations"]) / max(2 * pairs, 1)},
     }
@@ -527,7 +615,8 @@ def main():
         line["energy_rel_diff_fp32_fp64"] = abs(main_r["energy"] - r64["energy"]) / abs(r64["energy"])
     if args.serve_requests > 0:
         log(f"served mix: {args.serve_requests} requests ...")
-        line["served"] = served(args.serve_requests, args.serve_rate)
+        fracs = [float(f) for f in args.serve_fracs.split(",") if f]
+        line["served"] = served(args.serve_requests, fracs)
         log(f"served: {line['served']}")
     if args.md_steps > 0:
         log(f"Neon MD: {args.md_steps} steps at 1e4, 1e5 and 1e6 atoms ...")
@@ -546,7 +635,8 @@ def main():
         line["nonperiodic_nl"] = nonperiodic_cases()
         log(f"nonperiodic: {line['nonperiodic_nl']}")
     if not args.no_cpu_baseline:
-        nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        nproc = usable_cpus()
+        nth = args.cpu_threads or nproc
         log(f"cpu baseline: oracle on the full workload with {nth} threads ...")
         r, dt = cpu_baseline(cfg, nth)
         line["cpu_baseline"] = {
@@ -558,8 +648,14 @@ def main():
             "pairs": r["count"],
             "pairs_match_gpu": r["count"] == pairs,
             "energy_rel_err_fp32": abs(main_r["energy"] - r["lj_energy"]) / abs(r["lj_energy"]),
+            "nproc": nproc,
+            "os_cpu_count": os.cpu_count(),
             "cpu_model": cpu_model(),
         }
+        if nth != 16 and nproc >= 16:
+            r16, dt16 = cpu_baseline(cfg, 16)
+            line["cpu_baseline"]["threads_16"] = {"value": r16["count"] / dt16, "unit": "pairs/s",
+                                                  "seconds": dt16}
         log("cpu baseline: oracle on one thread (per-core figure) ...")
         pc = per_core_sample(W)
         r1, dt1 = cpu_baseline(pc, 1)
@@ -567,6 +663,11 @@ def main():
             "value": r1["count"] / dt1, "unit": "pairs/s", "threads": 1,
             "sample": f"125,000 particles at the headline density (box of half the lengths), {dt1:.1f} s",
             "pairs": r1["count"]}
+        # the FP32 accuracy where FP32 evaluates most pairs: the jittered
+        # lattice (on uniform points the energy is a few overlapping pairs,
+        # evaluated in FP64 by the near-pair guard)
+        log("fp32 accuracy on the jittered-lattice variant against the oracle ...")
+        line["cpu_baseline"]["fp32_accuracy_lattice"] = lattice_accuracy(clm, W, nth)
     print(json.dumps(line), flush=True)
 
 

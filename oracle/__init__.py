@@ -48,6 +48,7 @@ class _Result(ctypes.Structure):
         ("rel_hist", _u64p), ("rel_sum", _dp), ("nl_i", _i64p), ("nl_j", _i64p),
         ("nl_d", _dp), ("nl_count", ctypes.c_uint64), ("method_used", ctypes.c_int),
         ("nl_d2", _dp), ("sum_w_inv_d", ctypes.c_double), ("dv_hist", _u64p), ("dv_sum", _dp),
+        ("lj_fabs", _dp),
     ]
 
 
@@ -143,7 +144,7 @@ def pair_d2(xi, xj, H, reach):
 def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, lj=None,
             lj_grad=False, hist=None, rel_hist=None, vel_x=None, vel_y=None, nl=False,
             nl_capacity=None, method=METHOD_AUTO, nthreads=0, frame=None, weights=None,
-            dist_vel_hist=None):
+            dist_vel_hist=None, lj_fabs=False):
     """Run the oracle; returns a dict of the requested outputs.
 
     lj = (sigma, epsilon); hist = (nbins, hi); rel_hist = (nbins, hi) with
@@ -153,6 +154,8 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
     earlier step; single set only).  weights = (w_x, w_y or None): the sum
     of w_i w_j / d (Code 5).  dist_vel_hist = (nbins, hi) with vel_x (and
     vel_y): pairs per distance bin and the per-bin sum of |v_j - v_i| (Code 10).
+    lj_fabs (with lj_grad): per particle, the sum over its pairs of the pair-force
+    magnitude |f_s| d -- the scale against which per-particle force errors are measured.
     """
     x = _f64(x)
     H = _f64(H)
@@ -215,9 +218,13 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
     res = _Result()
     keep = []
     grad = None
+    fabs = None
     if lj is not None and lj_grad:
         grad = np.zeros((nx, dim))
         res.lj_grad = _p(grad)
+        if lj_fabs:
+            fabs = np.zeros(nx)
+            res.lj_fabs = _p(fabs)
     h = None
     if hist is not None:
         h = np.zeros(req.hist_nbins + 1, dtype=np.uint64)
@@ -263,6 +270,8 @@ def compute(x, H, cutoff, y=None, *, count=True, sum_d=False, sum_inv_d=False, l
         out["dEdH"] = np.array(res.dEdH[: dim * dim]).reshape(dim, dim)
         if grad is not None:
             out["lj_grad"] = grad
+        if fabs is not None:
+            out["lj_fabs"] = fabs
     if weights is not None:
         out["sum_w_inv_d"] = res.sum_w_inv_d
     if dist_vel_hist is not None:

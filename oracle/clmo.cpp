@@ -340,12 +340,15 @@ void accumulate(Ctx& C, Partial& P, std::vector<Neumaier>& rel_sum, int tid, int
   }
 }
 
-/* dE/dr_i contribution of partner j (gather form): f_s * D_ij. */
-inline void lj_grad_add(const clmo_request& q, int dim, double d2, const double* D, Neumaier* g) {
+/* dE/dr_i contribution of partner j (gather form): f_s * D_ij; and the
+ * magnitude of that pair force, |f_s| d, into ga. */
+inline void lj_grad_add(const clmo_request& q, int dim, double d2, const double* D, Neumaier* g,
+                        Neumaier* ga) {
   double x = (q.sigma * q.sigma) / d2;
   double x3 = x * x * x;
   double fs = 24.0 * q.epsilon * (2.0 * x3 * x3 - x3) / d2;
   for (int a = 0; a < dim; ++a) g[a].add(fs * D[a]);
+  ga->add(std::fabs(fs) * std::sqrt(d2));
 }
 
 int oracle_grid(const Box& B, int* n) {
@@ -528,17 +531,18 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
       int tid = omp_get_thread_num();
       double D[3];
       int K[3];
-      Neumaier g[3];
+      Neumaier g[3], ga;
       for (int64_t j = 0; j < nyy; ++j) {
         if (!cross && j == i) continue;
         double d2 = min_image(B, &C.xw[i * dim], &C.fx[i * dim], &yw[j * dim], &fy[j * dim],
                               reach, D, K);
         if (!(d2 <= B.rc2)) continue;
-        if (grad) lj_grad_add(*req, dim, d2, D, g);
+        if (grad) lj_grad_add(*req, dim, d2, D, g, &ga);
         if (cross || i < j) accumulate(C, partial[i], relsum_part[i], tid, i, j, d2, D, K);
       }
       if (grad)
         for (int a = 0; a < dim; ++a) grad[i * dim + a] = g[a].value();
+      if (grad && res->lj_fabs) res->lj_fabs[i] = ga.value();
     }
   } else {
     const int ncell = dim == 3 ? n[0] * n[1] * n[2] : n[0] * n[1];
@@ -559,7 +563,7 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
       int tid = omp_get_thread_num();
       int cx = c % n[0], cy = (c / n[0]) % n[1], cz = dim == 3 ? c / (n[0] * n[1]) : 0;
       for (int64_t i : xcells[c]) {
-        Neumaier g[3];
+        Neumaier g[3], ga;
         for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); ++dz)
           for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
@@ -586,12 +590,13 @@ int clmo_compute(int dim, const double* H, double cutoff, const double* x, int64
                 }
                 double d2 = pair_d2(B, &C.xw[i * dim], &yw[j * dim], tp, D);
                 if (!(d2 <= B.rc2)) continue;
-                if (grad) lj_grad_add(*req, dim, d2, D, g);
+                if (grad) lj_grad_add(*req, dim, d2, D, g, &ga);
                 if (cross || i < j) accumulate(C, partial[c], relsum_part[c], tid, i, j, d2, D, Kp);
               }
             }
         if (grad)
           for (int a = 0; a < dim; ++a) grad[i * dim + a] = g[a].value();
+        if (grad && res->lj_fabs) res->lj_fabs[i] = ga.value();
       }
     }
   }

@@ -112,6 +112,8 @@ typedef struct clmo_result {
   double sum_w_inv_d;      /* sum of w_i w_j / d */
   uint64_t* dv_hist;       /* caller-owned dv_nbins+1: pairs per distance bin (last = overflow) */
   double* dv_sum;          /* caller-owned dv_nbins: per distance bin, sum of |v_j - v_i| */
+  double* lj_fabs;         /* caller-owned nx (with lj_grad): per particle, the sum over its
+                              pairs of the pair-force magnitude |f_s| d (scale of force errors) */
 } clmo_result;
 
 /* Box geometry per the definitions above.  widths = perpendicular widths

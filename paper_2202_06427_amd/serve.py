@@ -15,6 +15,15 @@ a neighbour list, or a distance histogram (g(r) counts).  The loop
   * retires a batch when its event has completed, records each job's latency
     (arrival -> results complete on the device) and frees its footprint.
 
+Uploads and cell-list builds of newly admitted jobs go to a second stream
+(default priority) while earlier batches run; a batch's sweep waits for its
+jobs' builds through an event.  A neighbour list whose estimated capacity
+was too small is re-run in the next batch with the exact size (the loop
+never blocks on it).  With keep_results=True a finished job's device
+results stay charged to the budget until release(job); with
+keep_results=False only counts and energies are kept and the device
+buffers return at once.
+
 The scheduler is host code; the executor does the device work (all pair
 work runs in libclmap's kernels).
 """
@@ -35,7 +44,7 @@ KINDS = ("lj", "nl", "gr")
 class Job:
     __slots__ = ("id", "x", "H", "cutoff", "kind", "arrival", "params", "lcell", "box", "cl",
                  "xdev", "out", "footprint", "admitted", "done", "result", "status", "capacity",
-                 "retries", "host")
+                 "retries", "host", "built", "held")
 
     def __init__(self, jid, x, H, cutoff, kind, arrival=0.0, params=None, lcell=2):
         if kind not in KINDS:
@@ -56,6 +65,8 @@ class Job:
         self.capacity = 0
         self.retries = 0
         self.host = None  # (host counts, host energies, index) of its batch
+        self.built = None  # event after the upload and build (side stream)
+        self.held = 0      # bytes still charged to the budget after completion
 
 
 def expected_pairs(n, H, cutoff):
@@ -74,30 +85,38 @@ class GpuExecutor:
         self.precision = precision
         self.lj = lj
         self.gr_bins = gr_bins
+        # uploads and builds of admitted jobs (default priority, like the main stream)
+        self.side = torch.cuda.Stream(device=self.device)
+
+    def result_bytes(self, job):
+        """Device bytes of a job's outputs (kept after completion when the
+        server keeps results)."""
+        n, dim = job.x.shape
+        if job.kind == "lj":
+            return n * dim * 8 + dim * dim * 8 + 64
+        if job.kind == "nl":
+            return max(job.capacity, 1) * (8 + 8) + 64
+        return (self.gr_bins + 1) * 8 + 64
 
     def footprint(self, job):
+        """Workspace + positions + outputs + the job's share of a batch
+        workspace (descriptors and tile list), known before any device work."""
         n, dim = job.x.shape
         box = Box(job.H, job.cutoff, job.lcell)
         p = L.CLM_FP32_GUARD if self.precision == "fp32" else L.CLM_FP64
         nb = ctypes.c_size_t(0)
         L.check(L.lib().clm_celllist_workspace_bytes(box._h, n, 0, p, ctypes.byref(nb)))
-        out = 64
-        if job.kind == "lj":
-            out += n * dim * 8 + dim * dim * 8
-        elif job.kind == "nl":
+        if job.kind == "nl" and job.capacity == 0:
             job.capacity = int(1.25 * expected_pairs(n, job.H, job.cutoff) + 4096)
-            out += job.capacity * (8 + 8)
-        else:
-            out += (self.gr_bins + 1) * 8
+        info = box.info()
+        g = info["grid"] + [1] * (3 - len(info["grid"]))
+        tiles = info["ncells"] + 2 * g[1] * g[2] + 5 * ((n + 63) // 64) + 8
+        batch_share = 4096 + 16 * tiles
         job.box = box
-        return int(nb.value) + n * dim * 8 + out + 4096
+        return int(nb.value) + n * dim * 8 + self.result_bytes(job) + batch_share + 4096
 
-    def start(self, job):
-        xt = job.x if isinstance(job.x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(job.x))
-        # a payload in pinned host memory is copied without blocking the host
-        job.xdev = xt.to(self.device, non_blocking=xt.is_pinned())
-        job.cl = CellList(job.xdev, job.box, precision=self.precision)  # enqueues the build
-        n, dim = job.xdev.shape
+    def _outputs(self, job):
+        n, dim = job.x.shape
         dev = self.device
         o = {}  # energy and count are slices of the batch's buffers (launch)
         if job.kind == "lj":
@@ -109,7 +128,23 @@ class GpuExecutor:
             o["dist"] = torch.empty(cap, dtype=torch.float64, device=dev)
         else:
             o["hist"] = torch.empty(self.gr_bins + 1, dtype=torch.int64, device=dev)
-        job.out = o
+        return o
+
+    def start(self, job):
+        xt = job.x if isinstance(job.x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(job.x))
+        with torch.cuda.stream(self.side):
+            # a payload in pinned host memory is copied without blocking the host
+            job.xdev = xt.to(self.device, non_blocking=xt.is_pinned())
+            job.cl = CellList(job.xdev, job.box, precision=self.precision)  # enqueues the build
+            job.built = torch.cuda.Event()
+            job.built.record(self.side)
+        job.out = self._outputs(job)
+
+    def regrow(self, job, capacity):
+        """New neighbour-list outputs of the exact size (the cell list stays)."""
+        job.capacity = int(capacity)
+        job.out = self._outputs(job)
+        job.host = None
 
     def _params(self, job):
         o = job.out
@@ -133,6 +168,11 @@ class GpuExecutor:
         copied to pinned host memory in stream order, so retiring a batch
         never waits on work launched after it."""
         _context(self.device)
+        main = torch.cuda.current_stream(self.device)
+        for job in jobs:  # the builds ran on the side stream
+            if job.built is not None:
+                main.wait_event(job.built)
+                job.built = None
         n = len(jobs)
         cnt_dev = torch.empty(n, dtype=torch.int64, device=self.device)
         e_dev = torch.empty(n, dtype=torch.float64, device=self.device)
@@ -167,28 +207,35 @@ class GpuExecutor:
             return True
         return ev.query()
 
-    def finish(self, job):
-        """Results of a job whose batch has completed (host values already copied)."""
+    def overflow(self, job):
+        """Pairs of a neighbour-list job beyond its capacity (0 otherwise)."""
+        if job.kind != "nl":
+            return 0
+        cnt_host, _, k = job.host
+        cnt = int(cnt_host[k])
+        return cnt if cnt > job.capacity else 0
+
+    def finish(self, job, keep=True):
+        """Results of a job whose batch has completed (host values already
+        copied); keep=False drops the device outputs (count and energy stay)."""
         o = job.out
         cnt_host, e_host, k = job.host
         cnt = int(cnt_host[k])
-        if job.kind == "nl" and cnt > job.capacity:
-            # capacity estimate exceeded: re-run this job alone with the exact size
-            job.retries += 1
-            pairs, dist = job.cl.neighbor_list(capacity=cnt)
-            o["pairs"], o["dist"] = pairs, dist
-            job.capacity = cnt
         res = {"count": cnt}
         if job.kind == "lj":
             res["energy"] = float(e_host[k])
-            res["forces"] = o["forces"]
-            res["grad_box"] = o["grad_box"]
+            if keep:
+                res["forces"] = o["forces"]
+                res["grad_box"] = o["grad_box"]
         elif job.kind == "nl":
-            res["pairs"] = o["pairs"][:cnt]
-            res["dist"] = o["dist"][:cnt]
+            if keep:
+                res["pairs"] = o["pairs"][:cnt]
+                res["dist"] = o["dist"][:cnt]
         else:
-            res["hist"] = o["hist"]
+            if keep:
+                res["hist"] = o["hist"]
         job.result = res
+        job.out = None
         job.cl = None  # the workspace returns to the allocator (stream-ordered)
         job.xdev = None
 
@@ -197,8 +244,10 @@ class GpuExecutor:
 
 
 class Server:
-    def __init__(self, executor=None, hbm_budget=8 << 30, max_slots=256, max_batch=64, **kw):
+    def __init__(self, executor=None, hbm_budget=8 << 30, max_slots=256, max_batch=64,
+                 keep_results=True, **kw):
         self.ex = executor if executor is not None else GpuExecutor(**kw)
+        self.keep_results = bool(keep_results)
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.max_batch = int(max_batch)
@@ -232,6 +281,13 @@ class Server:
                 self.finished.append(job)
                 continue
             if self.used + job.footprint > self.budget:
+                if not (self.ready or self.inflight) and self.active == 0:
+                    # only results the caller has not released hold the budget
+                    self.pending.popleft()
+                    job.status = "rejected: budget held by results not released"
+                    job.done = now
+                    self.finished.append(job)
+                    continue
                 break  # FIFO: wait until running jobs release memory
             self.pending.popleft()
             job.admitted = now
@@ -275,7 +331,20 @@ class Server:
             if self.ex.done(h, block=block_first and k == 0):
                 for job in jobs:
                     try:
-                        self.ex.finish(job)
+                        need = self.ex.overflow(job)
+                        if need:
+                            # the capacity estimate was too small: the exact
+                            # size goes into the next batch (no blocking here)
+                            grow = 16 * (need - job.capacity)
+                            self.ex.regrow(job, need)
+                            job.retries += 1
+                            job.footprint += grow
+                            self.used += grow
+                            self.peak_used = max(self.peak_used, self.used)
+                            job.status = "admitted"
+                            self.ready.append(job)
+                            continue
+                        self.ex.finish(job, keep=self.keep_results)
                         status = "done"
                     except Exception as e:
                         status = f"failed: {e}"
@@ -287,9 +356,22 @@ class Server:
     def _release(self, job, status):
         job.done = self.clock()
         job.status = status
-        self.used -= job.footprint
+        held = 0
+        if status == "done" and self.keep_results and hasattr(self.ex, "result_bytes"):
+            held = min(job.footprint, self.ex.result_bytes(job))
+        job.held = held
+        self.used -= job.footprint - held
         self.active -= 1
         self.finished.append(job)
+
+    def release(self, job):
+        """Return the budget held by a finished job's device results (kept
+        with keep_results=True) and drop them."""
+        if job.held:
+            self.used -= job.held
+            job.held = 0
+        if job.result is not None:
+            job.result = {k: v for k, v in job.result.items() if not isinstance(v, torch.Tensor)}
 
     # ------------------------------------------------------------ loop
     def run(self, jobs, realtime=True):
@@ -302,7 +384,7 @@ class Server:
         self.t0 = time.perf_counter()
         while self.pending or self.ready or self.inflight:
             self._retire()
-            if self._admit(self.clock()):
+            if self._admit(self.clock()) or self.ready:
                 self._launch()
                 continue
             if self.pending and self.pending[0].arrival <= self.clock():

@@ -56,8 +56,55 @@ def test_config1_neighbor_list_and_inverse_distance_sum(clm, precision):
 @pytest.fixture(scope="module")
 def cfg2():
     c = W.config2()
-    ref = oracle.compute(c["x"], c["H"], c["cutoff"], lj=(c["sigma"], c["epsilon"]))
+    ref = oracle.compute(c["x"], c["H"], c["cutoff"], lj=(c["sigma"], c["epsilon"]), lj_grad=True,
+                         lj_fabs=True)
     return c, ref
+
+
+def _force_err(F, ref):
+    """Per-particle force error relative to the sum of the pair-force
+    magnitudes on the particle (forces = -dE/dr)."""
+    return np.linalg.norm(F + ref["lj_grad"], axis=1) / np.maximum(ref["lj_fabs"], 1e-300)
+
+
+@pytest.mark.parametrize("form", ["fp32-half", "fp32-full", "fp64"])
+def test_config2_all_forces_element_by_element(clm, cfg2, form):
+    """All 10^6 forces of the headline workload against the oracle's, each
+    particle's error measured against the sum of its pair-force magnitudes:
+    FP32+guard <= 1e-5 (both the half-shell sweep and the full-shell
+    gather), plain FP64 <= 1e-11; energies 1e-6 / 1e-12, the box gradient
+    1e-5 / 1e-11 of its largest entry."""
+    c, ref = cfg2
+    s, e = c["sigma"], c["epsilon"]
+    prec = "fp64" if form == "fp64" else "fp32"
+    cl = clm.CellList(T(c["x"]), clm.Box(c["H"], c["cutoff"], 2), precision=prec)
+    out = cl.lj_forces(s, e, half=form != "fp32-full")
+    assert int(out["count"].item()) == ref["count"]
+    tol = 1e-11 if form == "fp64" else 1e-5
+    tolE = 1e-12 if form == "fp64" else 1e-6
+    err = _force_err(out["forces"].cpu().numpy(), ref)
+    print(f"{form}: max per-particle force error {err.max():.3e}, mean {err.mean():.3e}", flush=True)
+    assert err.max() <= tol, err.max()
+    assert abs(out["energy"].item() - ref["lj_energy"]) <= tolE * abs(ref["lj_energy"])
+    gb = out["grad_box"].cpu().numpy()
+    assert np.abs(gb - ref["dEdH"]).max() <= tol * np.abs(ref["dEdH"]).max()
+
+
+def test_config2_lattice_fp32_energy_and_forces(clm):
+    """The jittered-lattice variant (no overlapping pairs; the pairs beyond
+    sigma, most of them, are evaluated in FP32): energy within 1e-6 and
+    every particle's force within 1e-5, half-shell sweep."""
+    c = W.config2(variant="lattice")
+    s, e = c["sigma"], c["epsilon"]
+    ref = oracle.compute(c["x"], c["H"], c["cutoff"], lj=(s, e), lj_grad=True, lj_fabs=True)
+    cl = clm.CellList(T(c["x"]), clm.Box(c["H"], c["cutoff"], 2), precision="fp32")
+    out = cl.lj_forces(s, e)
+    assert int(out["count"].item()) == ref["count"]
+    rel = abs(out["energy"].item() - ref["lj_energy"]) / abs(ref["lj_energy"])
+    err = _force_err(out["forces"].cpu().numpy(), ref)
+    print(f"lattice fp32: energy rel err {rel:.3e}, max force err {err.max():.3e}", flush=True)
+    assert rel <= 1e-6
+    assert err.max() <= 1e-5
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])

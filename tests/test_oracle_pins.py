@@ -801,3 +801,26 @@ def test_neighbors_of_against_numpy_enumeration_and_the_list(name, n, rc, far):
         ref_d = dict(zip(other.tolist(), pairs_d[sel].tolist()))
         for j, dj in zip(js.tolist(), dd.tolist()):
             assert math.isclose(dj, ref_d[j], rel_tol=1e-9, abs_tol=1e-9 * (1 + 1e3 * far))
+
+
+@pytest.mark.parametrize("name,n,rc,far", SAMPLE_CASES)
+def test_per_particle_force_magnitude_sum_against_numpy(name, n, rc, far):
+    """lj_fabs: per particle the sum over its pairs of |f_s| d (the scale of
+    the per-particle force error), against a numpy enumeration, in both the
+    cell-list and the brute-force loop."""
+    H = BOXES[name]
+    dim = H.shape[0]
+    s, e = 3.0, 0.238
+    x = _lattice(H, 8 if dim == 3 else 20, 271 + n)[:n]
+    if far:
+        x = x + np.array([1000, -700, 300][:dim]) @ H.T
+    for method in (oracle.METHOD_CELLS, oracle.METHOD_BRUTE):
+        r = oracle.compute(x, H, rc, lj=(s, e), lj_grad=True, lj_fabs=True, method=method)
+        for i in (0, 5, n // 2, n - 1):
+            d2, K = _numpy_min_images(x, i, H)
+            m = (d2 <= rc * rc) & (np.arange(n) != i)
+            _, fs = _lj_pair(d2[m], s, e)
+            ref = (np.abs(fs) * np.sqrt(d2[m])).sum()
+            assert math.isclose(r["lj_fabs"][i], ref, rel_tol=1e-11)
+        # never below the magnitude of the net force
+        assert np.all(r["lj_fabs"] >= np.linalg.norm(r["lj_grad"], axis=1) * (1 - 1e-12))
