@@ -85,6 +85,8 @@ def parse():
                     help="run only --steps Verlet-list MD steps of N Neon atoms (profiling)")
     ap.add_argument("--calibrate", type=int, default=1,
                     help="0: skip the measured device rates (FMA loops, copy kernel)")
+    ap.add_argument("--sweep-forms", type=int, default=1,
+                    help="0: skip timing the unpruned half-shell and full-shell sweeps")
     ap.add_argument("--step-samples", type=int, default=20,
                     help="individually timed steps for the median / min step time (0: skip)")
     ap.add_argument("--section", choices=["kclosest", "nonperiodic", "weighted"], default=None,
@@ -522,7 +524,7 @@ def main():
         r = time_steps(clm, cl, xt, args.steps, args.warmup, sigma, eps, args.step_samples)
         info = cl.info()  # after the timed steps: re-evaluation counts of the last map
         r["info"] = info
-        if prec == "fp32":
+        if prec == "fp32" and args.sweep_forms:
             r["forms"] = sweep_forms(clm, cl, xt, sigma, eps)
             log(f"fp32 sweep forms: {r['forms']}")
         res[prec] = r
@@ -573,7 +575,7 @@ def main():
             "target_frac": 0.5,
             "target_met": achieved / VALU_FP32_NONPACKED_TFLOPS >= 0.5,
         },
-        "sweep_forms_ms": main_r["forms"],
+        "sweep_forms_ms": main_r.get("forms"),
         "guard": {"band_retests": guard["guard_retests"], "near_pair_evaluations": guard["near_evaluations"],
                   "fraction_of_pairs": (guard["guard_retests"] + guard["near_evaluations"]) / max(2 * pairs, 1)},
     }
