@@ -60,7 +60,9 @@ typedef enum clm_status {
   CLM_E_INVALID_ARG = 1,  /* null pointer, bad size, bad enum value, ... */
   CLM_E_BAD_BOX = 2,      /* dim not 2/3, non-finite H, det H <= 0, cell flatter than 1:64 */
   CLM_E_BAD_CUTOFF = 3,   /* rc <= 0 or non-finite, lcell < 1 */
-  CLM_E_CAPACITY = 4,     /* (reserved: overflow is reported on the device, see clm_map_out) */
+  CLM_E_CAPACITY = 4,     /* a neighbour list with check_capacity has more pairs than its
+                             capacity (count_dev holds the true count), or a request needs
+                             more than a fixed library buffer (clm_map_static) */
   CLM_E_WORKSPACE = 5,    /* workspace missing, too small or misaligned */
   CLM_E_DEVICE = 6,       /* a HIP call failed (message from the runtime) */
   CLM_E_UNSUPPORTED = 7   /* valid request this library does not serve */
@@ -146,7 +148,10 @@ typedef struct clm_map_params {
   const double* weights_x_dev;  /* SUM_W_INV_D: n_x FP64 weights (caller order); the map copies
                                    them into the cell list's sorted records */
   const double* weights_y_dev;  /* SUM_W_INV_D, cross set: n_y weights */
-  void* scratch_dev;            /* LJ_EF / LJ_ADJOINT, FP32_GUARD, single set: caller-owned device
+  void* scratch_dev;            /* NEIGHBOR_LIST with sorted: caller-owned device scratch of at least
+                                   clm_pairs_sort_workspace_bytes(capacity, with_distances) bytes
+                                   (256-byte aligned).
+                                   LJ_EF / LJ_ADJOINT, FP32_GUARD, single set: caller-owned device
                                    scratch of at least clm_map_scratch_bytes bytes (256-byte
                                    aligned) enables the half-shell force sweep, which evaluates
                                    every pair once and keeps both particles' force sums in FP32
@@ -160,6 +165,14 @@ typedef struct clm_map_params {
   int no_prune;                 /* half-shell force sweep: 1 keeps every candidate of the visited
                                    cells (no pruning by the distance to the tile's bounding box;
                                    same results, for comparison) */
+  int sorted;                   /* NEIGHBOR_LIST: 1 puts the written pairs in canonical order on the
+                                   device (ascending i, then ascending j; distances moved along),
+                                   as clm_pairs_sort does; needs scratch_dev */
+  int check_capacity;           /* NEIGHBOR_LIST: 1 synchronizes the stream after the map and
+                                   returns CLM_E_CAPACITY when the list has more pairs than
+                                   capacity (count_dev holds the true count; re-call with a
+                                   larger buffer).  0: the call stays asynchronous and overflow
+                                   shows only in *count_dev. */
   int pad_params;
 } clm_map_params;
 
@@ -177,7 +190,8 @@ typedef struct clm_map_out {
                               counting sweep first gives every work item its output
                               offset), so repeated calls give the same list, also in
                               clm_map_batch; small boxes take slots from a shared
-                              counter (order unspecified). */
+                              counter (order unspecified).  With params->sorted:
+                              ascending i, then j, on every path. */
   double* dist_dev;        /* NEIGHBOR_LIST with with_distances: capacity FP64 */
   uint64_t* count_dev;     /* [1] REQUIRED for every kind: number of pairs in the set.
                               NEIGHBOR_LIST: if *count_dev > capacity only the first
@@ -255,6 +269,21 @@ clm_status clm_map_batch_workspace_bytes(int njobs, clm_celllist* const* cls, si
 clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
                          const clm_map_params* params, const clm_map_out* outs, void* workspace_dev,
                          size_t workspace_bytes);
+
+/* Canonical order of a neighbour list (section 4.1's list of pairs within
+ * the cutoff): the first min(*count_dev, capacity) pairs of pairs_dev
+ * (int32 (i, j), 8-byte aligned, i < n_i, j < n_j) are put in ascending
+ * order of i, then j, in place, with dist_dev (FP64, may be NULL) moved
+ * along.  Asynchronous on the context's stream (the count is read on the
+ * device).  The workspace (256-byte aligned, clm_pairs_sort_workspace_bytes
+ * bytes) holds a second key buffer, a second distance buffer and the digit
+ * table of the radix sort.  Errors: CLM_E_INVALID_ARG (index ranges outside
+ * 1..2^31, capacity outside 0..2^31 - 2^20, misaligned pairs),
+ * CLM_E_WORKSPACE. */
+clm_status clm_pairs_sort_workspace_bytes(int64_t capacity, int with_distances, size_t* bytes);
+clm_status clm_pairs_sort(clm_context* ctx, int64_t n_i, int64_t n_j, int32_t* pairs_dev,
+                          double* dist_dev, const uint64_t* count_dev, int64_t capacity,
+                          void* workspace_dev, size_t workspace_bytes);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): bin and

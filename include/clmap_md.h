@@ -75,6 +75,19 @@ clm_status clm_md_kick_drift(clm_md* md, double* x_dev, double* v_dev, const dou
  * ke_dev when not NULL, and kept for the next rescale). */
 clm_status clm_md_kick(clm_md* md, double* v_dev, const double* f_dev, double* ke_dev);
 
+/* Kinetic energy of velocities v alone: KE = mass/2 sum |v|^2, written to
+ * ke_dev when not NULL and kept for the next rescale, as clm_md_kick computes
+ * it (v is not changed).  The initial kinetic energy of a run (section 4.2
+ * reports the kinetic energy of every step, the first included). */
+clm_status clm_md_kinetic(clm_md* md, const double* v_dev, double* ke_dev);
+
+/* v = sqrt(target_ke / KE) v in place, KE the one kept by the last
+ * clm_md_kick, clm_vlist_lj with an integrator, or clm_md_kinetic: the
+ * velocity rescaling of section 4.2 applied at the end of a run (within a run
+ * clm_md_kick_drift applies it at the start of the next step).  target_ke > 0.
+ * Errors: CLM_E_INVALID_ARG. */
+clm_status clm_md_rescale(clm_md* md, double* v_dev, double target_ke);
+
 clm_status clm_md_destroy(clm_md* md);
 
 /* ---------------------------------------------------------------- Verlet list */

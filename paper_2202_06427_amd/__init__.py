@@ -382,22 +382,36 @@ class CellList:
         m = int(found.value)
         return i[:m], j[:m], d2[:m]
 
-    def neighbor_list(self, capacity=None, distances=True, cutoff=None):
-        """Pairs (i, j) within the cutoff (single set: i < j) and their d.
+    def neighbor_list(self, capacity=None, distances=True, cutoff=None, sorted=False):
+        """Pairs (i, j) within the cutoff (single set: i < j) and their d;
+        with ``sorted`` in ascending (i, j) order (sorted on the device).
 
-        Synchronizes to read the pair count; grows the buffers and re-runs
-        when the capacity was too small."""
+        Synchronizes (the library's capacity check); grows the buffers and
+        re-runs when the list has more pairs than the capacity."""
         cap = int(capacity) if capacity is not None else max(1024, 64 * self.nx)
         while True:
             pairs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.device)
             dist = torch.empty(max(cap, 1), dtype=torch.float64, device=self.device) if distances else None
             _, c = self._scalars()
-            P = L.MapParams(capacity=cap, with_distances=int(distances), cutoff=_rc(cutoff))
-            self._map("neighbor_list", P, L.MapOut(pairs_dev=_ptr(pairs), dist_dev=_ptr(dist), count_dev=_ptr(c)))
+            P = L.MapParams(capacity=cap, with_distances=int(distances), cutoff=_rc(cutoff),
+                            sorted=int(bool(sorted)), check_capacity=1)
+            ws = None
+            if sorted:
+                need = ctypes.c_size_t(0)
+                L.check(L.lib().clm_pairs_sort_workspace_bytes(cap, int(distances), ctypes.byref(need)))
+                ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=self.device)
+                P.scratch_dev = ctypes.c_void_p(ws.data_ptr() + (-ws.data_ptr()) % 256)
+                P.scratch_bytes = int(need.value)
+            try:
+                self._map("neighbor_list", P, L.MapOut(pairs_dev=_ptr(pairs), dist_dev=_ptr(dist),
+                                                       count_dev=_ptr(c)))
+            except L.ClmError as e:
+                if e.status != L.STATUS_CODES["CLM_E_CAPACITY"]:
+                    raise
+                cap = int(c.item())
+                continue
             n = int(c.item())
-            if n <= cap:
-                return pairs[:n], (dist[:n] if distances else None)
-            cap = n
+            return pairs[:n], (dist[:n] if distances else None)
 
 
 # ---------------------------------------------------------------- device rates

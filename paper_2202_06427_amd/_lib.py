@@ -56,7 +56,8 @@ class MapParams(ctypes.Structure):
         ("want_sums", ctypes.c_int), ("capacity", ctypes.c_int64), ("with_distances", ctypes.c_int),
         ("cutoff", ctypes.c_double), ("weights_x_dev", _vp), ("weights_y_dev", _vp),
         ("scratch_dev", _vp), ("scratch_bytes", ctypes.c_size_t),
-        ("no_prune", ctypes.c_int), ("pad_params", ctypes.c_int),
+        ("no_prune", ctypes.c_int), ("sorted", ctypes.c_int), ("check_capacity", ctypes.c_int),
+        ("pad_params", ctypes.c_int),
     ]
 
 
@@ -92,8 +93,10 @@ EXPORTS = [
     "clm_status_string", "clm_context_set_timing", "clm_stats_get", "clm_map_batch_workspace_bytes",
     "clm_map_batch", "clm_box_nonperiodic", "clm_extrema_workspace_bytes", "clm_extrema",
     "clm_map_static_max_bytes", "clm_map_static", "clm_map_scratch_bytes",
+    "clm_pairs_sort_workspace_bytes", "clm_pairs_sort",
     # include/clmap_md.h
-    "clm_md_workspace_bytes", "clm_md_create", "clm_md_kick_drift", "clm_md_kick", "clm_md_destroy",
+    "clm_md_workspace_bytes", "clm_md_create", "clm_md_kick_drift", "clm_md_kick", "clm_md_kinetic",
+    "clm_md_rescale", "clm_md_destroy",
     "clm_vlist_workspace_bytes", "clm_vlist_create", "clm_vlist_update", "clm_vlist_lj",
     "clm_vlist_info_get", "clm_vlist_destroy",
     # include/clmap_kclosest.h
@@ -145,12 +148,16 @@ def lib():
     szp = ctypes.POINTER(ctypes.c_size_t)
     L.clm_map_static_max_bytes.argtypes = [szp]
     L.clm_map_scratch_bytes.argtypes = [_vp, c_int, szp]
+    L.clm_pairs_sort_workspace_bytes.argtypes = [c_i64, c_int, szp]
+    L.clm_pairs_sort.argtypes = [_vp, c_i64, c_i64, _vp, _vp, _vp, c_i64, _vp, ctypes.c_size_t]
     L.clm_map_static.argtypes = [_vp, _vp, _vp, c_i64, _vp, c_i64, c_int, c_int,
                                  ctypes.POINTER(MapParams), ctypes.POINTER(MapOut)]
     L.clm_md_workspace_bytes.argtypes = [c_i64, szp]
     L.clm_md_create.argtypes = [_vp, c_int, c_i64, c_d, c_d, _vp, ctypes.c_size_t, pvp]
     L.clm_md_kick_drift.argtypes = [_vp, _vp, _vp, _vp, c_d]
     L.clm_md_kick.argtypes = [_vp, _vp, _vp, _vp]
+    L.clm_md_kinetic.argtypes = [_vp, _vp, _vp]
+    L.clm_md_rescale.argtypes = [_vp, _vp, c_d]
     L.clm_md_destroy.argtypes = [_vp]
     L.clm_vlist_workspace_bytes.argtypes = [_vp, c_i64, szp]
     L.clm_vlist_create.argtypes = [_vp, c_d, c_i64, _vp, ctypes.c_size_t, pvp]

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libclmap.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["build_kernels.hip", "sweep_kernels.hip", "sweep_half.hip", "md_kernels.hip", "kclosest_kernels.hip",
-           "calib_kernels.hip", "static_map.hip",
+           "calib_kernels.hip", "static_map.hip", "nl_sort.hip",
            "clmap_api.cpp", "md_api.cpp", "kclosest_api.cpp", "calib_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -731,6 +731,11 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
     if (P->capacity > 0 && !O->pairs_dev) return fail(CLM_E_INVALID_ARG, "pairs_dev is NULL");
     if (P->capacity > 0 && P->with_distances && !O->dist_dev)
       return fail(CLM_E_INVALID_ARG, "with_distances needs dist_dev");
+    if (P->sorted && P->capacity > 0 && cl->nx > 0 && (!cl->cross || cl->ny > 0)) {
+      clm_status s = sort_pairs_check(cl->nx, cl->cross ? cl->ny : cl->nx, O->pairs_dev, P->capacity,
+                                      P->with_distances != 0, P->scratch_dev, P->scratch_bytes);
+      if (s != CLM_OK) return s;
+    }
   }
   // membership cutoff of this map (the grid stays the box's)
   double rcm = B.rc;
@@ -877,8 +882,42 @@ clm_status clm_map_scratch_bytes(const clm_celllist* cl, clm_map_kind kind, size
 
 }  // extern "C"
 
+// Neighbour lists after the map: the device sort into canonical order
+// (params->sorted), then the synchronous capacity check (params->check_capacity).
+static clm_status nl_sort_after(clm_celllist* cl, const clm_map_params* P, const clm_map_out* O) {
+  if (!P->sorted || P->capacity == 0 || cl->nx == 0 || (cl->cross && cl->ny == 0)) return CLM_OK;
+  return sort_pairs(cl->ctx->stream, cl->nx, cl->cross ? cl->ny : cl->nx, O->pairs_dev,
+                    P->with_distances ? O->dist_dev : nullptr, (const unsigned long long*)O->count_dev,
+                    P->capacity, P->scratch_dev);
+}
+
+static clm_status nl_capacity_after(clm_celllist* cl, const clm_map_params* P, const clm_map_out* O) {
+  if (!P->check_capacity) return CLM_OK;
+  uint64_t c = 0;
+  hipStream_t st = cl->ctx->stream;
+  CLM_HIP(hipMemcpyAsync(&c, O->count_dev, sizeof c, hipMemcpyDeviceToHost, st));
+  CLM_HIP(hipStreamSynchronize(st));
+  if (c > (uint64_t)P->capacity)
+    return fail(CLM_E_CAPACITY, "the neighbour list has %llu pairs and capacity %lld: only the first "
+                "capacity pairs were written (count_dev holds the total)", (unsigned long long)c,
+                (long long)P->capacity);
+  return CLM_OK;
+}
+
+static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
+                                const clm_map_out* O, bool nl_two_pass_ok);
+
 clm_status map_one(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P, const clm_map_out* O,
                    bool nl_two_pass_ok) {
+  clm_status s = map_one_inner(cl, kind, P, O, nl_two_pass_ok);
+  if (s != CLM_OK || kind != CLM_MAP_NEIGHBOR_LIST) return s;
+  s = nl_sort_after(cl, P, O);
+  if (s != CLM_OK) return s;
+  return nl_capacity_after(cl, P, O);
+}
+
+static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
+                                const clm_map_out* O, bool nl_two_pass_ok) {
   JobDesc jd;
   FinalArgs F;
   int k_launch = 0;
@@ -1088,6 +1127,18 @@ clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
   s = ts.stop();
   if (s != CLM_OK) return s;
   CLM_HIP(launch_finalize_batch(jobs_dev, fin_dev, nb, st));
+  if (kind == CLM_MAP_NEIGHBOR_LIST) {  // small-box jobs were finished by clm_map above
+    for (int k = 0; k < njobs; ++k) {
+      if (cls[k]->box.small) continue;
+      clm_status s = nl_sort_after(cls[k], &P[k], &O[k]);
+      if (s != CLM_OK) return s;
+    }
+    for (int k = 0; k < njobs; ++k) {
+      if (cls[k]->box.small) continue;
+      clm_status s = nl_capacity_after(cls[k], &P[k], &O[k]);
+      if (s != CLM_OK) return s;
+    }
+  }
   return CLM_OK;
 }
 

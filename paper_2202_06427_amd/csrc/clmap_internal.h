@@ -404,6 +404,8 @@ hipError_t launch_md_kick_drift(double* x, double* v, const double* f, int64_t n
                                 double dt, double target_ke, const double* ke, hipStream_t s);
 hipError_t launch_md_kick(double* v, const double* f, int n, int dim, double h, double* part,
                           hipStream_t s);
+hipError_t launch_md_rescale(double* v, int64_t ncomp, double target_ke, const double* ke,
+                             hipStream_t s);
 hipError_t launch_md_finalize(const MdFinal& F, hipStream_t s);
 int vl_drift_blocks(int64_t n);
 hipError_t launch_vl_drift(const double* x, const double* xref, int n, int dim, double lim2,

@@ -176,6 +176,12 @@ inline BuildGeom geom_of(const clm_box& B) {
 // lists, where the counter is not contended).
 clm_status map_one(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P, const clm_map_out* O,
                    bool nl_two_pass_ok);
+// Neighbour lists in canonical order (nl_sort.hip).
+clm_status sort_pairs_check(int64_t n_i, int64_t n_j, const int32_t* pairs, int64_t capacity,
+                            bool dist, const void* ws, size_t ws_bytes);
+size_t sort_pairs_bytes(int64_t capacity, bool dist);
+clm_status sort_pairs(hipStream_t st, int64_t n_i, int64_t n_j, int32_t* pairs, double* dist,
+                      const unsigned long long* count, int64_t capacity, void* ws);
 
 // Fills a caller-provided cell-list handle over workspace `ws` (the body of
 // clm_celllist_create without the host allocation of the handle).

@@ -131,9 +131,8 @@ clm_status clm_md_kick_drift(clm_md* md, double* x, double* v, const double* f, 
   return CLM_OK;
 }
 
-clm_status clm_md_kick(clm_md* md, double* v, const double* f, double* ke) {
-  if (!md) return fail(CLM_E_INVALID_ARG, "md is NULL");
-  if (md->n > 0 && (!v || !f)) return fail(CLM_E_INVALID_ARG, "v or f is NULL");
+// Second half-kick (f != NULL) or kinetic energy alone (f == NULL).
+static clm_status md_kick_or_ke(clm_md* md, double* v, const double* f, double* ke) {
   CLM_HIP(hipSetDevice(md->ctx->device));
   hipStream_t st = md->ctx->stream;
   if (md->n > 0) CLM_HIP(launch_md_kick(v, f, (int)md->n, md->dim, md->h, md->part, st));
@@ -146,6 +145,28 @@ clm_status clm_md_kick(clm_md* md, double* v, const double* f, double* ke) {
   F.ke = ke;
   F.ke_keep = md->ke_keep;
   CLM_HIP(launch_md_finalize(F, st));
+  return CLM_OK;
+}
+
+clm_status clm_md_kick(clm_md* md, double* v, const double* f, double* ke) {
+  if (!md) return fail(CLM_E_INVALID_ARG, "md is NULL");
+  if (md->n > 0 && (!v || !f)) return fail(CLM_E_INVALID_ARG, "v or f is NULL");
+  return md_kick_or_ke(md, v, f, ke);
+}
+
+clm_status clm_md_kinetic(clm_md* md, const double* v, double* ke) {
+  if (!md) return fail(CLM_E_INVALID_ARG, "md is NULL");
+  if (md->n > 0 && !v) return fail(CLM_E_INVALID_ARG, "v is NULL");
+  return md_kick_or_ke(md, const_cast<double*>(v), nullptr, ke);
+}
+
+clm_status clm_md_rescale(clm_md* md, double* v, double target_ke) {
+  if (!md) return fail(CLM_E_INVALID_ARG, "md is NULL");
+  if (md->n > 0 && !v) return fail(CLM_E_INVALID_ARG, "v is NULL");
+  if (!(target_ke > 0.0) || !std::isfinite(target_ke))
+    return fail(CLM_E_INVALID_ARG, "target_ke must be > 0");
+  CLM_HIP(hipSetDevice(md->ctx->device));
+  CLM_HIP(launch_md_rescale(v, md->n * md->dim, target_ke, md->ke_keep, md->ctx->stream));
   return CLM_OK;
 }
 

@@ -89,13 +89,25 @@ __global__ void __launch_bounds__(kMdBlock) md_kick_kernel(double* __restrict__ 
   if (i < n) {
     double q = 0.0;
     for (int a = 0; a < dim; ++a) {
-      const double va = v[(size_t)i * dim + a] + h * f[(size_t)i * dim + a];
-      v[(size_t)i * dim + a] = va;
+      double va = v[(size_t)i * dim + a];
+      if (f) {  // f == NULL: kinetic energy of v only
+        va = va + h * f[(size_t)i * dim + a];
+        v[(size_t)i * dim + a] = va;
+      }
       q = a == 0 ? va * va : q + va * va;
     }
     acc[MP_KE] = q;
   }
   block_partials(acc, 0ull, part, nullptr, blockIdx.x);
+}
+
+// v = sqrt(target_ke / KE) v, KE the integrator's kept kinetic energy.
+__global__ void __launch_bounds__(kMdBlock) md_rescale_kernel(double* __restrict__ v, int64_t ncomp,
+                                                              double target_ke,
+                                                              const double* __restrict__ ke) {
+  const int64_t k = (int64_t)blockIdx.x * kMdBlock + threadIdx.x;
+  if (k >= ncomp) return;
+  v[k] = sqrt(target_ke / *ke) * v[k];
 }
 
 // One block: fixed-order sums of nb partials (each thread sums rows t,
@@ -561,6 +573,13 @@ hipError_t launch_md_kick_drift(double* x, double* v, const double* f, int64_t n
 hipError_t launch_md_kick(double* v, const double* f, int n, int dim, double h, double* part,
                           hipStream_t s) {
   md_kick_kernel<<<blocks_for(n, kMdBlock), kMdBlock, 0, s>>>(v, f, n, dim, h, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_rescale(double* v, int64_t ncomp, double target_ke, const double* ke,
+                             hipStream_t s) {
+  if (ncomp == 0) return hipSuccess;
+  md_rescale_kernel<<<blocks_for(ncomp, kMdBlock), kMdBlock, 0, s>>>(v, ncomp, target_ke, ke);
   return hipGetLastError();
 }
 

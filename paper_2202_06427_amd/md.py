@@ -57,6 +57,17 @@ class Integrator:
         _context(self.device)
         L.check(L.lib().clm_md_kick(self._h, _ptr(v), _ptr(f), _ptr(ke)))
 
+    def kinetic(self, v, ke=None):
+        """Kinetic energy of v into ke (device float64[1]) if given; kept
+        for the next rescale."""
+        _context(self.device)
+        L.check(L.lib().clm_md_kinetic(self._h, _ptr(v), _ptr(ke)))
+
+    def rescale(self, v, target_ke):
+        """v = sqrt(target_ke / KE) v with the last kept kinetic energy."""
+        _context(self.device)
+        L.check(L.lib().clm_md_rescale(self._h, _ptr(v), float(target_ke)))
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and L is not None and L._lib is not None:
@@ -136,7 +147,8 @@ class _RebuildForces:
 
 
 def run(x, v, H, *, cutoff, sigma, epsilon, mass, dt, nsteps, mode="verlet", skin=0.1,
-        rescale_every=10, target_ke=None, lcell=2, precision="fp32", capacity=None, graph=False):
+        rescale_every=10, target_ke=None, lcell=2, precision="fp32", capacity=None, graph=False,
+        trajectory=None):
     """Velocity-Verlet trajectory on the GPU (the step of ``oracle.md_run``).
 
     x, v: (n, dim) float64 device tensors, updated in place.  Returns a dict
@@ -146,9 +158,18 @@ def run(x, v, H, *, cutoff, sigma, epsilon, mass, dt, nsteps, mode="verlet", ski
     of rescale_every the velocities are scaled by sqrt(target_ke / KE); the
     scaling is applied at the start of the next step, and after the last step
     when it falls on one.  graph=True records one rescaling period of steps
-    as a HIP graph (after a first period run eagerly) and replays it."""
+    as a HIP graph (after a first period run eagerly) and replays it.
+    trajectory: an optional (nsteps + 1, n, dim) float64 device tensor that
+    receives a copy of the positions each step's forces and count were taken
+    at (eager steps only: not with graph=True)."""
     n, dim = x.shape
     dev = x.device
+    if trajectory is not None:
+        if graph:
+            raise ValueError("trajectory copies are not recorded into a graph")
+        if tuple(trajectory.shape) != (nsteps + 1, n, dim) or trajectory.dtype != torch.float64 \
+                or trajectory.device != dev:
+            raise ValueError("trajectory must be a float64 (nsteps + 1, n, dim) tensor on x's device")
     if target_ke is None:
         rescale_every = 0
     integ = Integrator(n, dim, mass, dt, dev)
@@ -177,9 +198,13 @@ def run(x, v, H, *, cutoff, sigma, epsilon, mass, dt, nsteps, mode="verlet", ski
         resc = rescale_every and k > 1 and (k - 1) % rescale_every == 0
         integ.kick_drift(x, v, F, target_ke if resc else 0.0)
         forces(e, ke, c, True)
+        if trajectory is not None:
+            trajectory[k].copy_(x)
 
     forces(E[0:1], KE[0:1], C[0:1], False)
-    KE[0] = 0.5 * mass * torch.sum(v * v)
+    if trajectory is not None:
+        trajectory[0].copy_(x)
+    integ.kinetic(v, KE[0:1])
     k = 1
     if graph and rescale_every and nsteps >= 2 * rescale_every:
         while k <= rescale_every:           # first period eagerly: kernels loaded, no rescale at k = 1
@@ -206,7 +231,7 @@ def run(x, v, H, *, cutoff, sigma, epsilon, mass, dt, nsteps, mode="verlet", ski
         one_step(k, E[k:k + 1], KE[k:k + 1], C[k:k + 1])
         k += 1
     if rescale_every and nsteps > 0 and nsteps % rescale_every == 0:
-        v.mul_(torch.sqrt(target_ke / KE[nsteps]))
+        integ.rescale(v, target_ke)
     out = {"energy": E, "ke": KE, "count": C, "forces": F}
     if vl is not None:
         out["list"] = vl

@@ -228,3 +228,28 @@ def test_calibration_arguments():
     ms, work = ctypes.c_double(0.0), ctypes.c_double(0.0)
     assert lib.clm_calibrate(None, 0, None, None, 0, 1, ctypes.byref(ms), ctypes.byref(work)) \
         == L.STATUS_CODES["CLM_E_INVALID_ARG"]
+
+
+def test_pairs_sort_workspace_and_validation():
+    """Neighbour-list sort: workspace sizes (a key buffer, a distance buffer,
+    the digit table) and argument checks before any device call."""
+    lib = L.lib()
+    b = ctypes.c_size_t(0)
+    assert lib.clm_pairs_sort_workspace_bytes(10**6, 1, ctypes.byref(b)) == 0
+    with_d = b.value
+    assert with_d >= 10**6 * 16 + 256 * (10**6 // 2048) * 4
+    assert lib.clm_pairs_sort_workspace_bytes(10**6, 0, ctypes.byref(b)) == 0
+    assert with_d - b.value >= 10**6 * 8
+    assert lib.clm_pairs_sort_workspace_bytes(0, 0, ctypes.byref(b)) == 0
+    bad = L.STATUS_CODES["CLM_E_INVALID_ARG"]
+    assert lib.clm_pairs_sort_workspace_bytes(-1, 0, ctypes.byref(b)) == bad
+    assert lib.clm_pairs_sort_workspace_bytes(1 << 31, 0, ctypes.byref(b)) == bad
+    assert lib.clm_pairs_sort_workspace_bytes(10, 0, None) == bad
+    assert lib.clm_pairs_sort(None, 10, 10, None, None, None, 10, None, 0) == bad
+
+
+def test_md_kinetic_and_rescale_validation():
+    lib = L.lib()
+    bad = L.STATUS_CODES["CLM_E_INVALID_ARG"]
+    assert lib.clm_md_kinetic(None, None, None) == bad
+    assert lib.clm_md_rescale(None, None, 1.0) == bad

@@ -153,16 +153,6 @@ def test_vlist_row_overflow_is_reported(md):
     assert info["overflow"] == 1 and info["max_row"] > 16
 
 
-def _counts_close(got, ref):
-    """A trajectory driven by FP32 forces is another rounding of the same
-    dynamics (positions agree to ~1e-10 nm), so a pair within that distance
-    of the cutoff may be counted on one side only: per-step pair counts agree
-    to 2 pairs on at most a few steps.  (For given positions the pair set is
-    exact: the per-configuration parity tests.)"""
-    diff = np.abs(got.astype(np.int64) - ref.astype(np.int64))
-    assert diff.max() <= 2 and np.count_nonzero(diff) <= 3, diff
-
-
 def _md_case(n=6000, seed=15):
     w = W.neon_fluid(n, seed=seed)
     ndof = 3 * n - 3
@@ -186,7 +176,7 @@ def test_md_trajectory_matches_the_oracle(md, mode, graph):
     E = out["energy"].cpu().numpy()
     assert np.abs(E - ref["energy"]).max() <= 1e-10 * np.abs(ref["energy"]).max()
     KE = out["ke"].cpu().numpy()
-    assert np.abs(KE[1:] - ref["ke"][1:]).max() <= 1e-10 * np.abs(ref["ke"]).max()
+    assert np.abs(KE - ref["ke"]).max() <= 1e-10 * np.abs(ref["ke"]).max()
     assert np.abs(x.cpu().numpy() - ref["x"]).max() < 1e-10
     assert np.abs(v.cpu().numpy() - ref["v"]).max() < 1e-9 * np.abs(ref["v"]).max()
     if mode == "verlet":
@@ -196,17 +186,29 @@ def test_md_trajectory_matches_the_oracle(md, mode, graph):
 
 
 def test_md_rebuild_mode_fp32_guard(md):
-    """The paper's protocol with FP32+guard forces: the same pair counts and
-    a trajectory within the FP32 force tolerance."""
+    """The paper's protocol with FP32+guard forces.  The trajectory is another
+    rounding of the FP64 one (FP32 forces), so a pair within ~1e-10 nm of the
+    cutoff may sit on different sides in the two runs; the pair set of each
+    step is therefore checked exactly against the oracle at the positions the
+    GPU step itself used, and the trajectory against the FP64 oracle run
+    within the FP32 force tolerance."""
     w, target = _md_case(5000, seed=16)
     nsteps = 20
     ref = oracle.md_run(w["x"], w["v"], w["H"], RC, SIG, EPS, w["mass"], w["dt"], nsteps,
                         rescale_every=10, target_ke=target)
     x, v = T(w["x"]), T(w["v"])
+    traj = torch.empty((nsteps + 1,) + tuple(x.shape), dtype=torch.float64, device="cuda:0")
     out = md.run(x, v, w["H"], cutoff=RC, sigma=SIG, epsilon=EPS, mass=w["mass"], dt=w["dt"],
-                 nsteps=nsteps, mode="rebuild", rescale_every=10, target_ke=target, precision="fp32")
+                 nsteps=nsteps, mode="rebuild", rescale_every=10, target_ke=target, precision="fp32",
+                 trajectory=traj)
     torch.cuda.synchronize()
-    _counts_close(out["count"].cpu().numpy(), ref["count"])
+    counts = out["count"].cpu().numpy()
     E = out["energy"].cpu().numpy()
+    tr = traj.cpu().numpy()
+    for k in range(nsteps + 1):
+        own = oracle.compute(tr[k], w["H"], RC, lj=(SIG, EPS))
+        assert counts[k] == own["count"], k
+        assert abs(E[k] - own["lj_energy"]) <= 1e-6 * abs(own["lj_energy"]), k
     assert np.abs(E - ref["energy"]).max() <= 1e-6 * np.abs(ref["energy"]).max()
     assert np.abs(x.cpu().numpy() - ref["x"]).max() < 1e-9
+    assert np.abs(tr[nsteps] - x.cpu().numpy()).max() == 0.0
