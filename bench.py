@@ -4,7 +4,8 @@ Workload (the headline configuration): 1,000,000 uniform-random particles in
 a triclinic periodic box (lengths 215.4, angles 80/95/100 degrees), cutoff
 12, Lennard-Jones energy + forces (sigma 3.4, epsilon 0.238) through the
 adjoint sweep.  One step = one pass of the whole hot path over the resident
-positions: bin (wrap, cell index, prefix scan, tiles, scatter) + the LJ
+positions: build (wrap and cell index with LDS bucket counts, prefix scan,
+bucket pass, per-bucket placement, tiles) + the LJ
 sweep with fused energy/force/box-gradient reduction (FP32+guard: the
 half-shell sweep, every pair once; plain FP64: the full-shell gather) +
 per-particle force gather + finalize.  The FP32+guard form is the headline
@@ -93,6 +94,8 @@ def parse():
                     help="run only this section and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
+    ap.add_argument("--build-only", type=int, default=0, metavar="N",
+                    help="only time cell-list builds of N uniform particles (profiling)")
     return ap.parse_args()
 
 
@@ -229,7 +232,7 @@ def sweep_forms(clm, cl, xt, sigma, eps, reps=5):
 
 
 def build_roofline(clm, W, n, lcell, steps=5):
-    """Build-only timing (bin + scan + tiles + scatter) of n uniform particles
+    """Build-only timing (count + scan + bucket + place + tiles) of n uniform particles
     in the headline triclinic box shape scaled to the same density."""
     import numpy as np
     import torch
@@ -494,6 +497,11 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.build_only:
+        import paper_2202_06427_amd as clm
+        import workloads as W
+        print(json.dumps({"build_only": build_roofline(clm, W, args.build_only, args.lcell)}), flush=True)
         return
     if args.md_only:
         md_only(args.md_only, args.steps)

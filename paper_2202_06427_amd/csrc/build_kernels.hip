@@ -2,14 +2,27 @@
 // particles assigned to cells by their coordinates, with a contiguous copy of
 // every cell's coordinates; section 2.8: cell side = cutoff / lcell).
 //
-// The build is a counting sort in HBM:
-//   bin      one thread per particle: canonical FP64 wrap into the primary
-//            cell, fractional cell index, rank = atomicAdd(count[cell])
-//   scan     exclusive prefix of the counts -> cell offsets
+// The build is a two-level counting sort whose counters all live in LDS:
+//   count    per block of particles: canonical FP64 wrap into the primary
+//            cell, the cell index written out, and an LDS histogram over
+//            buckets of consecutive cells (a few thousand particles each)
+//   scan     exclusive prefix of the (bucket, block) table, bucket-major:
+//            every block's first slot in every bucket
+//   bucket   per block: (index, cell) records to the bucket-ordered array,
+//            slots from LDS counters seeded with the block's offsets
+//   place    one block per bucket: LDS histogram over its cells, their
+//            offsets (written to the cell-offset array), then every record
+//            takes its slot from an LDS counter, its position is gathered,
+//            wrapped again and written as the FP32 cell-local offset, the
+//            FP64 wrapped position, the original index and the wrap integers
 //   tiles    one wave per cell row: greedy work units of <= 64 particles
-//   scatter  one thread per particle: FP32 cell-local offset, FP64 wrapped
-//            position, original index and wrap integers at offset+rank
-// Every kernel is HBM- or latency-bound; nothing here is a dense contraction.
+// Device-wide atomics on random addresses run at a fixed rate of a few tens
+// of G/s on this chip whatever the XCD layout, so none are used; the one
+// random access per particle is the gather of its 24-byte position, and
+// every output of a bucket lands in one contiguous range.  Every kernel is
+// HBM- or latency-bound; nothing here is a dense contraction.
+#include <algorithm>
+
 #include "clmap_internal.h"
 
 namespace clm {
@@ -79,52 +92,174 @@ __device__ __forceinline__ void cell_of(const BuildGeom& g, const double* f, int
   }
 }
 
-__global__ void __launch_bounds__(256) bin_kernel(const double* __restrict__ x, int n, BuildGeom g,
-                                                  uint32_t* __restrict__ count,
-                                                  uint32_t* __restrict__ cell,
-                                                  uint32_t* __restrict__ rank,
-                                                  const uint32_t* __restrict__ gate) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || gate_closed(gate)) return;
-  double r[3] = {0.0, 0.0, 0.0};
-  for (int a = 0; a < g.dim; ++a) r[a] = x[(size_t)i * g.dim + a];
-  double f[3], rw[3];
-  int w[3], c[3];
-  wrap_one(g, r, f, w, rw);
-  cell_of(g, f, c);
-  uint32_t lin = (uint32_t)(c[0] + g.n[0] * (c[1] + g.n[1] * c[2]));
-  cell[i] = lin;
-  rank[i] = atomicAdd(&count[lin], 1u);
+// Pass 1: cell of every particle, bucket histogram of the block in LDS.
+__global__ void __launch_bounds__(kBinThreads) bin_count_kernel(const double* __restrict__ x, int n,
+                                                                BuildGeom g, BinPlan P,
+                                                                uint32_t* __restrict__ key,
+                                                                uint32_t* __restrict__ hist,
+                                                                const uint32_t* __restrict__ gate) {
+  __shared__ uint32_t sh[kMaxBuckets];
+  if (gate_closed(gate)) return;
+  for (int b = threadIdx.x; b < P.nbk; b += kBinThreads) sh[b] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kBinThreads * P.per;
+#pragma unroll 4
+  for (int k = 0; k < P.per; ++k) {
+    const int64_t i = base + (int64_t)k * kBinThreads + threadIdx.x;
+    if (i < n) {
+      double r[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < g.dim; ++a) r[a] = x[(size_t)i * g.dim + a];
+      double f[3], rw[3];
+      int w[3], c[3];
+      wrap_one(g, r, f, w, rw);
+      cell_of(g, f, c);
+      const uint32_t lin = (uint32_t)(c[0] + g.n[0] * (c[1] + g.n[1] * c[2]));
+      key[i] = lin;
+      atomicAdd(&sh[lin / (uint32_t)P.cpb], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < P.nbk; b += kBinThreads) hist[(size_t)b * P.nblk + blockIdx.x] = sh[b];
 }
 
-__global__ void __launch_bounds__(256) scatter_kernel(
-    const double* __restrict__ x, int n, BuildGeom g, const uint32_t* __restrict__ off,
-    const uint32_t* __restrict__ cell, const uint32_t* __restrict__ rank, float4* __restrict__ pos,
+// Pass 2: records (position as given, index, cell) into bucket order; the
+// records of one block and bucket are consecutive.
+__global__ void __launch_bounds__(kBinThreads) bin_bucket_kernel(const double* __restrict__ x, int n,
+                                                                 int dim, BinPlan P,
+                                                                 const uint32_t* __restrict__ key,
+                                                                 const uint32_t* __restrict__ hist,
+                                                                 BinRec* __restrict__ rec,
+                                                                 const uint32_t* __restrict__ gate) {
+  __shared__ uint32_t cur[kMaxBuckets];
+  if (gate_closed(gate)) return;
+  for (int b = threadIdx.x; b < P.nbk; b += kBinThreads) cur[b] = hist[(size_t)b * P.nblk + blockIdx.x];
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kBinThreads * P.per;
+#pragma unroll 4
+  for (int k = 0; k < P.per; ++k) {
+    const int64_t i = base + (int64_t)k * kBinThreads + threadIdx.x;
+    if (i < n) {
+      const uint32_t lin = key[i];
+      BinRec R;
+      R.x = x[(size_t)i * dim];
+      R.y = x[(size_t)i * dim + 1];
+      R.z = dim == 3 ? x[(size_t)i * dim + 2] : 0.0;
+      R.i = (uint32_t)i;
+      R.cell = lin;
+      rec[atomicAdd(&cur[lin / (uint32_t)P.cpb], 1u)] = R;
+    }
+  }
+}
+
+// Exclusive scan over a block of kBinThreads threads; *total receives the
+// block sum.  Every thread of the block must call it (it has barriers).
+__device__ __forceinline__ uint32_t block_excl_scan_bin(uint32_t v, uint32_t* total) {
+  constexpr int kWaves = kBinThreads / kWave;
+  __shared__ uint32_t wsum[kWaves];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += t;
+  }
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) {
+    pre += k < wid ? wsum[k] : 0u;
+    tot += wsum[k];
+  }
+  *total = tot;
+  __syncthreads();  // wsum is reused by the next call
+  return pre + incl - v;
+}
+
+// Pass 3: one block per bucket.  Cell histogram and offsets in LDS (the
+// offsets also go to the cell-offset array), then every record takes its
+// slot from an LDS counter and is wrapped into its four outputs.  A bucket
+// of at most kPlaceCap particles is assembled in LDS and written out with
+// consecutive stores; a larger one (clustered input) is written in place.
+__global__ void __launch_bounds__(kBinThreads) bin_place_kernel(
+    int n, BuildGeom g, BinPlan P, int ncells, const uint32_t* __restrict__ hist,
+    const BinRec* __restrict__ rec, uint32_t* __restrict__ off, float4* __restrict__ pos,
     double4* __restrict__ r64, uint32_t* __restrict__ idx, int4* __restrict__ wrap,
     const uint32_t* __restrict__ gate) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || gate_closed(gate)) return;
-  double r[3] = {0.0, 0.0, 0.0};
-  for (int a = 0; a < g.dim; ++a) r[a] = x[(size_t)i * g.dim + a];
-  double f[3], rw[3];
-  int w[3], c[3];
-  wrap_one(g, r, f, w, rw);
-  cell_of(g, f, c);
-  // cell origin H (c / n) in FP64, then the FP32 offset from it
-  double u[3];
-#pragma unroll
-  for (int b = 0; b < 3; ++b) u[b] = (double)c[b] / (double)g.n[b];
-  float o[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double O = g.H[a * 3 + 0] * u[0] + g.H[a * 3 + 1] * u[1] + g.H[a * 3 + 2] * u[2];
-    o[a] = a < g.dim ? (float)(rw[a] - O) : 0.0f;
+  __shared__ uint32_t cnt[kMaxBucketCells];
+  __shared__ uint32_t cur[kMaxBucketCells];
+  __shared__ float4 s_pos[kPlaceCap];
+  __shared__ double4 s_r64[kPlaceCap];
+  __shared__ int4 s_wrap[kPlaceCap];
+  __shared__ uint32_t s_idx[kPlaceCap];
+  if (gate_closed(gate)) return;
+  const int b = blockIdx.x;
+  const uint32_t lo = hist[(size_t)b * P.nblk];
+  const uint32_t hi = b + 1 < P.nbk ? hist[(size_t)(b + 1) * P.nblk] : (uint32_t)n;
+  const int c0 = b * P.cpb;
+  const int nc = min(P.cpb, ncells - c0);
+  const bool staged = hi - lo <= (uint32_t)kPlaceCap;
+  for (int c = threadIdx.x; c < nc; c += kBinThreads) cnt[c] = 0;
+  __syncthreads();
+  for (uint32_t s = lo + threadIdx.x; s < hi; s += kBinThreads)
+    atomicAdd(&cnt[rec[s].cell - (uint32_t)c0], 1u);
+  __syncthreads();
+  uint32_t carry = lo;
+  for (int base = 0; base < nc; base += kBinThreads) {
+    const int c = base + threadIdx.x;
+    const uint32_t v = c < nc ? cnt[c] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan_bin(v, &tot);
+    if (c < nc) {
+      cur[c] = carry + ex;
+      off[c0 + c] = carry + ex;
+    }
+    carry += tot;
   }
-  uint32_t dst = off[cell[i]] + rank[i];
-  pos[dst] = make_float4(o[0], o[1], o[2], 0.0f);
-  r64[dst] = make_double4(rw[0], rw[1], rw[2], 0.0);
-  idx[dst] = (uint32_t)i;
-  wrap[dst] = make_int4(w[0], w[1], w[2], 0);
+  if (b == P.nbk - 1 && threadIdx.x == 0) off[ncells] = (uint32_t)n;
+  __syncthreads();
+  for (uint32_t s = lo + threadIdx.x; s < hi; s += kBinThreads) {
+    const BinRec R = rec[s];
+    const uint32_t dst = atomicAdd(&cur[R.cell - (uint32_t)c0], 1u);
+    const double r[3] = {R.x, R.y, R.z};
+    double f[3], rw[3];
+    int w[3], c[3];
+    wrap_one(g, r, f, w, rw);
+    cell_of(g, f, c);
+    // cell origin H (c / n) in FP64, then the FP32 offset from it
+    double u[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) u[q] = (double)c[q] / (double)g.n[q];
+    float o[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double O = g.H[a * 3 + 0] * u[0] + g.H[a * 3 + 1] * u[1] + g.H[a * 3 + 2] * u[2];
+      o[a] = a < g.dim ? (float)(rw[a] - O) : 0.0f;
+    }
+    const float4 po = make_float4(o[0], o[1], o[2], 0.0f);
+    const double4 ro = make_double4(rw[0], rw[1], rw[2], 0.0);
+    const int4 wo = make_int4(w[0], w[1], w[2], 0);
+    if (staged) {
+      const uint32_t d = dst - lo;
+      s_pos[d] = po;
+      s_r64[d] = ro;
+      s_wrap[d] = wo;
+      s_idx[d] = R.i;
+    } else {
+      pos[dst] = po;
+      r64[dst] = ro;
+      wrap[dst] = wo;
+      idx[dst] = R.i;
+    }
+  }
+  if (!staged) return;  // uniform over the block
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < hi - lo; d += kBinThreads) {
+    pos[lo + d] = s_pos[d];
+    r64[lo + d] = s_r64[d];
+    wrap[lo + d] = s_wrap[d];
+    idx[lo + d] = s_idx[d];
+  }
 }
 
 // ---------------------------------------------------------------- scan
@@ -452,13 +587,6 @@ hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s, const u
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const double* x, int n, const BuildGeom& g, uint32_t* count, uint32_t* cell,
-                      uint32_t* rank, hipStream_t s, const uint32_t* gate) {
-  if (n == 0) return hipSuccess;
-  bin_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, n, g, count, cell, rank, gate);
-  return hipGetLastError();
-}
-
 size_t scan_scratch_elems(int n) { return (size_t)(n + kScanChunk - 1) / kScanChunk + 1; }
 
 hipError_t launch_scan(const uint32_t* in, int n, uint32_t* sums, uint32_t* out, hipStream_t s,
@@ -471,11 +599,38 @@ hipError_t launch_scan(const uint32_t* in, int n, uint32_t* sums, uint32_t* out,
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const double* x, int n, const BuildGeom& g, const uint32_t* off,
-                          const uint32_t* cell, const uint32_t* rank, float4* pos, double4* r64,
-                          uint32_t* idx, int4* wrap, hipStream_t s, const uint32_t* gate) {
-  if (n == 0) return hipSuccess;
-  scatter_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, n, g, off, cell, rank, pos, r64, idx, wrap, gate);
+BinPlan bin_plan(int64_t ncells, int64_t n) {
+  BinPlan P;
+  // about kPlaceTarget particles per bucket, so that nearly every bucket
+  // fits the LDS assembly of the place pass; at most kMaxBuckets buckets and
+  // kMaxBucketCells cells per bucket (LDS tables)
+  int64_t cpb = n > 0 ? (kPlaceTarget * ncells) / n : ncells;
+  cpb = std::min<int64_t>(cpb, kMaxBucketCells);
+  cpb = std::max<int64_t>(cpb, (ncells + kMaxBuckets - 1) / kMaxBuckets);
+  cpb = std::min<int64_t>(std::max<int64_t>(cpb, 1), std::max<int64_t>(ncells, 1));
+  P.cpb = (int)cpb;
+  P.nbk = (int)((std::max<int64_t>(ncells, 1) + cpb - 1) / cpb);
+  // particles per thread of the count and bucket passes: about one block per CU
+  const int64_t per = (n + (int64_t)kBinThreads * 256 - 1) / ((int64_t)kBinThreads * 256);
+  P.per = (int)std::min<int64_t>(std::max<int64_t>(per, 1), 256);
+  P.nblk = (int)std::max<int64_t>(1, (n + (int64_t)kBinThreads * P.per - 1) / ((int64_t)kBinThreads * P.per));
+  return P;
+}
+
+hipError_t launch_bin(const double* x, int n, const BuildGeom& g, int ncells, const BinPlan& P,
+                      uint32_t* key, uint32_t* hist, uint32_t* scan_scratch, BinRec* rec, uint32_t* off,
+                      float4* pos, double4* r64, uint32_t* idx, int4* wrap, hipStream_t s,
+                      const uint32_t* gate) {
+  bin_count_kernel<<<P.nblk, kBinThreads, 0, s>>>(x, n, g, P, key, hist, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan(hist, P.nbk * P.nblk, scan_scratch, hist, s, gate);
+  if (e != hipSuccess) return e;
+  bin_bucket_kernel<<<P.nblk, kBinThreads, 0, s>>>(x, n, g.dim, P, key, hist, rec, gate);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  bin_place_kernel<<<P.nbk, kBinThreads, 0, s>>>(n, g, P, ncells, hist, rec, off, pos, r64, idx, wrap,
+                                                  gate);
   return hipGetLastError();
 }
 

@@ -230,21 +230,25 @@ static int64_t max_tiles_for(const clm_box& B, int64_t n) {
 static void layout(clm_celllist* cl, char* base, size_t* total) {
   const clm_box& B = cl->box;
   Carve c;
+  int64_t hist_max = 1;
   auto set = [&](SetBufs& S, int64_t n) {
-    size_t o_count = c.take(sizeof(uint32_t) * B.ncells);
+    const BinPlan P = bin_plan(B.ncells, n);
+    const int64_t nh = (int64_t)P.nbk * P.nblk;
+    hist_max = std::max(hist_max, nh);
+    size_t o_hist = c.take(sizeof(uint32_t) * (nh + 1));
     size_t o_off = c.take(sizeof(uint32_t) * (B.ncells + 1));
-    size_t o_cell = c.take(sizeof(uint32_t) * n);
-    size_t o_rank = c.take(sizeof(uint32_t) * n);
+    size_t o_key = c.take(sizeof(uint32_t) * std::max<int64_t>(n, 1));
+    size_t o_rec = c.take(sizeof(BinRec) * std::max<int64_t>(n, 1));
     size_t o_pos = c.take(sizeof(float4) * (n + kPadParticles));
     size_t o_r64 = c.take(sizeof(double4) * (n + kPadParticles));
     size_t o_idx = c.take(sizeof(uint32_t) * (n + kPadParticles));
     size_t o_wrap = c.take(sizeof(int4) * (n + kPadParticles));
     size_t o_vel = c.take(sizeof(float4) * (n + kPadParticles));
     if (base) {
-      S.count = (uint32_t*)(base + o_count);
+      S.hist = (uint32_t*)(base + o_hist);
       S.off = (uint32_t*)(base + o_off);
-      S.cell = (uint32_t*)(base + o_cell);
-      S.rank = (uint32_t*)(base + o_rank);
+      S.key = (uint32_t*)(base + o_key);
+      S.rec = (BinRec*)(base + o_rec);
       S.pos = (float4*)(base + o_pos);
       S.r64 = (double4*)(base + o_r64);
       S.idx = (uint32_t*)(base + o_idx);
@@ -263,7 +267,7 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
       B.small ? std::max<int64_t>(1, (cl->nx + kWave - 1) / kWave) * brute_chunks(nyb) : 1;
   const int64_t parts = std::max<int64_t>(maxt, brute_rows);
   const size_t scan_elems =
-      std::max(scan_scratch_elems((int)std::max<int64_t>(B.ncells, 1)), scan_scratch_elems(nrows));
+      std::max(scan_scratch_elems((int)hist_max), scan_scratch_elems(nrows));
   size_t o_scan = c.take(sizeof(uint32_t) * scan_elems);
   size_t o_rt = c.take(sizeof(uint32_t) * (nrows + 1));
   size_t o_ro = c.take(sizeof(uint32_t) * (nrows + 1));
@@ -580,10 +584,9 @@ static clm_status build_set(clm_celllist* cl, const double* x, int64_t n, SetBuf
   hipStream_t st = cl->ctx->stream;
   const BuildGeom g = geom_of(cl->box);
   const int nc = (int)cl->box.ncells;
-  CLM_HIP(launch_fill_u32(S.count, (size_t)nc, 0u, st, gate));
-  CLM_HIP(launch_bin(x, (int)n, g, S.count, S.cell, S.rank, st, gate));
-  CLM_HIP(launch_scan(S.count, nc, cl->scan_scratch, S.off, st, gate));
-  CLM_HIP(launch_scatter(x, (int)n, g, S.off, S.cell, S.rank, S.pos, S.r64, S.idx, S.wrap, st, gate));
+  const BinPlan P = bin_plan(nc, n);
+  CLM_HIP(launch_bin(x, (int)n, g, nc, P, S.key, S.hist, cl->scan_scratch, S.rec, S.off, S.pos, S.r64,
+                     S.idx, S.wrap, st, gate));
   return CLM_OK;
 }
 

@@ -348,14 +348,31 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
                            const uint32_t* gate = nullptr);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s,
                            const uint32_t* gate = nullptr);
-hipError_t launch_bin(const double* x, int n, const BuildGeom& g, uint32_t* count, uint32_t* cell,
-                      uint32_t* rank, hipStream_t s, const uint32_t* gate = nullptr);
+// Binning plan: cells per bucket, buckets, particles per thread and blocks
+// of the count and bucket passes (host-side, from the sizes only).
+constexpr int kBinThreads = 1024;
+constexpr int kMaxBuckets = 16384;
+constexpr int kMaxBucketCells = 1024;  // with kMaxBuckets: up to 2^24 cells
+constexpr int kPlaceCap = 2048;        // particles of a bucket assembled in LDS
+constexpr int kPlaceTarget = 1280;     // mean particles per bucket aimed at
+static_assert((int64_t)kMaxBuckets * kMaxBucketCells >= (int64_t(1) << 24), "cell cap");
+struct BinPlan {
+  int cpb, nbk, per, nblk;
+};
+struct alignas(32) BinRec {
+  double x, y, z;   // position as given (z = 0 in 2D)
+  uint32_t i, cell;
+};
+BinPlan bin_plan(int64_t ncells, int64_t n);
+// Bin n particles: key (n), hist (nbk * nblk + 1, scanned in place), rec
+// (n) are scratch; off (ncells + 1) and the sorted records are the result.
+hipError_t launch_bin(const double* x, int n, const BuildGeom& g, int ncells, const BinPlan& P,
+                      uint32_t* key, uint32_t* hist, uint32_t* scan_scratch, BinRec* rec, uint32_t* off,
+                      float4* pos, double4* r64, uint32_t* idx, int4* wrap, hipStream_t s,
+                      const uint32_t* gate = nullptr);
 hipError_t launch_scan(const uint32_t* in, int n, uint32_t* sums_scratch, uint32_t* out,
                        hipStream_t s, const uint32_t* gate = nullptr);
 size_t scan_scratch_elems(int n);
-hipError_t launch_scatter(const double* x, int n, const BuildGeom& g, const uint32_t* off,
-                          const uint32_t* cell, const uint32_t* rank, float4* pos, double4* r64,
-                          uint32_t* idx, int4* wrap, hipStream_t s, const uint32_t* gate = nullptr);
 hipError_t launch_tiles(const uint32_t* off, const TileGeom& g, uint32_t* row_tiles,
                         uint32_t* row_off, uint32_t* scan_scratch, Tile* tiles, hipStream_t s,
                         const uint32_t* gate = nullptr);

@@ -113,10 +113,10 @@ struct Carve {
 };
 
 struct SetBufs {
-  uint32_t* count = nullptr;  // ncells
+  uint32_t* hist = nullptr;   // binning: (bucket, block) table, nbk * nblk + 1
   uint32_t* off = nullptr;    // ncells + 1
-  uint32_t* cell = nullptr;   // n
-  uint32_t* rank = nullptr;   // n
+  uint32_t* key = nullptr;    // binning: cell of every particle, n
+  BinRec* rec = nullptr;      // binning: records in bucket order, n
   float4* pos = nullptr;      // n + pad
   double4* r64 = nullptr;
   uint32_t* idx = nullptr;
