@@ -90,7 +90,9 @@ def parse():
                     help="0: skip timing the unpruned half-shell and full-shell sweeps")
     ap.add_argument("--step-samples", type=int, default=20,
                     help="individually timed steps for the median / min step time (0: skip)")
-    ap.add_argument("--section", choices=["kclosest", "nonperiodic", "weighted"], default=None,
+    ap.add_argument("--pruning", type=int, default=1,
+                    help="0: skip the pruning section (sweep forms at lcell 1/2/3, 2D clustered)")
+    ap.add_argument("--section", choices=["kclosest", "nonperiodic", "weighted", "pruning"], default=None,
                     help="run only this section and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
@@ -397,6 +399,38 @@ def weighted_cases(reps=5):
     return out
 
 
+def pruning_cases(reps=5):
+    """Candidate pruning of the half-shell LJ force sweep (FP32+guard): sweep
+    time with and without pruning and of the full-shell gather, on the
+    headline workload at lcell 1, 2 and 3 and on the 2D clustered workload
+    (2*10^6 points, rc 0.01, sigma 1e-4: about the spacing inside a
+    cluster), with the half-shell candidate count of each grid."""
+    import torch
+    import paper_2202_06427_amd as clm
+    import workloads as W
+
+    out = {}
+    cfg = W.config2()
+    x = torch.from_numpy(cfg["x"]).to("cuda:0")
+    for lc in (1, 2, 3):
+        cl = clm.CellList(x, clm.Box(cfg["H"], cfg["cutoff"], lc), precision="fp32")
+        forms = sweep_forms(clm, cl, x, cfg["sigma"], cfg["epsilon"], reps)
+        info = cl.info()
+        out[f"headline_lcell{lc}"] = {**forms, "half_shell_candidates": info["candidate_pairs"],
+                                      "ntiles": info["ntiles"]}
+        del cl
+    del x
+    cfg4 = W.config4()
+    x4 = torch.from_numpy(cfg4["x"]).to("cuda:0")
+    cl4 = clm.CellList(x4, clm.Box(cfg4["H"], cfg4["cutoff"], 2), precision="fp32")
+    forms = sweep_forms(clm, cl4, x4, 1e-4, 1.0, reps)
+    info = cl4.info()
+    c = int(cl4.count().item())
+    out["clustered2d_lcell2"] = {**forms, "half_shell_candidates": info["candidate_pairs"], "pairs": c,
+                                 "near_evaluations": info["near_evaluations"]}
+    return out
+
+
 def md_only(n, steps):
     """Verlet-list MD of n Neon atoms (skin 0.1 nm) for `steps` steps."""
     import torch
@@ -507,7 +541,8 @@ def main():
         md_only(args.md_only, args.steps)
         return
     if args.section:
-        f = {"kclosest": kclosest_cases, "nonperiodic": nonperiodic_cases, "weighted": weighted_cases}
+        f = {"kclosest": kclosest_cases, "nonperiodic": nonperiodic_cases, "weighted": weighted_cases,
+             "pruning": pruning_cases}
         print(json.dumps({"section": args.section, **f[args.section]()}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -636,6 +671,10 @@ def main():
         log("weighted maps ...")
         line["weighted_maps"] = weighted_cases()
         log(f"weighted: {line['weighted_maps']}")
+    if args.pruning:
+        log("pruning: sweep forms at lcell 1/2/3 and on the 2D clustered workload ...")
+        line["pruning"] = pruning_cases()
+        log(f"pruning: {line['pruning']}")
     if args.kclosest:
         log("k closest pairs ...")
         line["kclosest"] = kclosest_cases()

@@ -173,7 +173,11 @@ typedef struct clm_map_params {
                                    capacity (count_dev holds the true count; re-call with a
                                    larger buffer).  0: the call stays asynchronous and overflow
                                    shows only in *count_dev. */
-  int pad_params;
+  int half_shell;               /* LJ_EF / LJ_ADJOINT with a map scratch: 0 runs the half-shell sweep
+                                   when the grid gives at least 4096 (cell row, neighbour row)
+                                   work items and the full-shell gather otherwise (too few items
+                                   cannot fill the device: one wave works through a whole row);
+                                   1 runs the half-shell sweep whenever it applies; -1 never. */
 } clm_map_params;
 
 typedef struct clm_map_out {

@@ -134,6 +134,11 @@ class Box:
             self._h = None
 
 
+def _half_mode(half):
+    """clm_map_params.half_shell for lj_forces / lj_adjoint's half argument."""
+    return 0 if half is None else (1 if half else -1)
+
+
 def _as_coords(x, dim, name):
     if not isinstance(x, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor on a GPU")
@@ -301,34 +306,37 @@ class CellList:
         raw = self._scratch[0]
         return ctypes.c_void_p(raw.data_ptr() + (-raw.data_ptr()) % 256), need
 
-    def lj_forces(self, sigma, epsilon, near_factor=1.0, virial=False, cutoff=None, half=True,
+    def lj_forces(self, sigma, epsilon, near_factor=1.0, virial=False, cutoff=None, half=None,
                   prune=True):
         """Energy, forces (-dE/dr, paper Code 7), dE/dH and optionally the virial.
-        half: FP32 form only -- evaluate every pair once (half-shell sweep with
-        map scratch) instead of from both ends (full-shell gather); prune:
-        that sweep skips candidates farther than the cutoff from the tile's
-        bounding box (same results)."""
+        half (FP32 form only): True evaluates every pair once (the half-shell
+        sweep, with map scratch), False from both ends (the full-shell
+        gather), None lets the library choose (the half-shell sweep when the
+        cell grid gives it enough work items); prune: the half-shell sweep
+        skips candidates farther than the cutoff from the tile's bounding box
+        (same results)."""
         e, c = self._scalars()
         f = torch.empty((self.nx, self.dim), dtype=torch.float64, device=self.device)
         gb = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device)
         w = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device) if virial else None
-        sp, sb = self._half_scratch("lj_ef", half)
+        sp, sb = self._half_scratch("lj_ef", half is not False)
         P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, want_virial=int(virial),
-                        cutoff=_rc(cutoff), scratch_dev=sp, scratch_bytes=sb, no_prune=int(not prune))
+                        cutoff=_rc(cutoff), scratch_dev=sp, scratch_bytes=sb, no_prune=int(not prune),
+                        half_shell=_half_mode(half))
         o = L.MapOut(energy_dev=_ptr(e), forces_dev=_ptr(f), grad_box_dev=_ptr(gb),
                      virial_dev=_ptr(w), count_dev=_ptr(c))
         self._map("lj_ef", P, o)
         return {"energy": e, "forces": f, "grad_box": gb, "virial": w, "count": c}
 
-    def lj_adjoint(self, sigma, epsilon, upstream, near_factor=1.0, cutoff=None, half=True):
+    def lj_adjoint(self, sigma, epsilon, upstream, near_factor=1.0, cutoff=None, half=None):
         """g dE/dr and g dE/dH for an upstream gradient g (device float64[1])."""
         e, c = self._scalars()
         up = upstream.detach().to(device=self.device, dtype=torch.float64).reshape(1).contiguous()
         gx = torch.empty((self.nx, self.dim), dtype=torch.float64, device=self.device)
         gb = torch.empty((self.dim, self.dim), dtype=torch.float64, device=self.device)
-        sp, sb = self._half_scratch("lj_adjoint", half)
+        sp, sb = self._half_scratch("lj_adjoint", half is not False)
         P = L.MapParams(sigma=sigma, epsilon=epsilon, near_factor=near_factor, upstream_dev=_ptr(up),
-                        cutoff=_rc(cutoff), scratch_dev=sp, scratch_bytes=sb)
+                        cutoff=_rc(cutoff), scratch_dev=sp, scratch_bytes=sb, half_shell=_half_mode(half))
         o = L.MapOut(energy_dev=_ptr(e), forces_dev=_ptr(gx), grad_box_dev=_ptr(gb), count_dev=_ptr(c))
         self._map("lj_adjoint", P, o)
         self._keep_up = up

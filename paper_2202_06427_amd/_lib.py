@@ -57,7 +57,7 @@ class MapParams(ctypes.Structure):
         ("cutoff", ctypes.c_double), ("weights_x_dev", _vp), ("weights_y_dev", _vp),
         ("scratch_dev", _vp), ("scratch_bytes", ctypes.c_size_t),
         ("no_prune", ctypes.c_int), ("sorted", ctypes.c_int), ("check_capacity", ctypes.c_int),
-        ("pad_params", ctypes.c_int),
+        ("half_shell", ctypes.c_int),
     ]
 
 

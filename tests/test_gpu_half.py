@@ -171,3 +171,26 @@ def test_half_shell_scratch_errors(clm):
     # where the sweep does not apply (FP64 form) the scratch is 0 bytes
     cl64 = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp64")
     assert cl64._half_scratch("lj_ef", True) == (None, 0)
+
+
+def test_automatic_choice_between_half_and_full_shell(clm):
+    """half=None: the half-shell sweep when the grid gives at least 4096
+    (cell row, neighbour row) work items, the full-shell gather otherwise;
+    the two forms round differently, so the choice shows bit for bit."""
+    sigma, eps = 1.1, 0.3
+    for L_box, n, want_half in ((30.0, 3000, False), (60.0, 20000, True)):
+        H = np.diag([L_box] * 3)
+        x = _lattice(H, n, 14)
+        cl = clm.CellList(T(x), clm.Box(H, 5.0, 2), precision="fp32")
+        rows = 1
+        for g in clm.Box(H, 5.0, 2).info()["grid"][1:]:
+            rows *= g
+        assert (rows * 13 >= 4096) == want_half
+        auto = cl.lj_forces(sigma, eps, virial=True)
+        forced = cl.lj_forces(sigma, eps, virial=True, half=want_half)
+        other = cl.lj_forces(sigma, eps, virial=True, half=not want_half)
+        fa, ff, fo = (r["forces"].cpu().numpy() for r in (auto, forced, other))
+        assert fa.tobytes() == ff.tobytes()
+        assert fa.tobytes() != fo.tobytes()
+        ref = oracle.compute(x, H, 5.0, lj=(sigma, eps), lj_grad=True, nl=True)
+        _check(auto, ref, x, sigma, eps)
