@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--lcell", type=int, default=2)
+    ap.add_argument("--lcell-x", type=int, default=6,
+                    help="cell reach along the row axis of the FP32+guard form's grid (0: lcell); "
+                         "the FP64 form keeps lcell along every axis")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -230,10 +233,14 @@ def sweep_forms(clm, cl, xt, sigma, eps, reps=5):
         st = clm.stats(reset=True)
         clm.set_timing(False)
         out[key] = st["sweep_ms"] / max(st["sweeps"], 1)
+        if key == "half_pruned_ms":
+            info = cl.info()
+            out["half_pairs_tested"] = info["half_pairs_tested"]
+            out["half_pairs_kept"] = info["half_pairs_kept"]
     return out
 
 
-def build_roofline(clm, W, n, lcell, steps=5):
+def build_roofline(clm, W, n, lcell, steps=5, lcell_x=None):
     """Build-only timing (count + scan + bucket + place + tiles) of n uniform particles
     in the headline triclinic box shape scaled to the same density."""
     import numpy as np
@@ -243,7 +250,7 @@ def build_roofline(clm, W, n, lcell, steps=5):
     x = W.uniform_in_box(n, H, 21)
     xt = torch.from_numpy(x).to("cuda:0")
     del x
-    cl = clm.CellList(xt, clm.Box(H, c["cutoff"], lcell), precision="fp32")
+    cl = clm.CellList(xt, clm.Box(H, c["cutoff"], lcell, lcell_x), precision="fp32")
     for _ in range(2):
         cl.build(xt)
     torch.cuda.synchronize()
@@ -402,7 +409,8 @@ def weighted_cases(reps=5):
 def pruning_cases(reps=5):
     """Candidate pruning of the half-shell LJ force sweep (FP32+guard): sweep
     time with and without pruning and of the full-shell gather, on the
-    headline workload at lcell 1, 2 and 3 and on the 2D clustered workload
+    headline workload at lcell 1, 2 and 3, at lcell 2 with row-axis reach
+    4, 6 and 8 (thinner cells along the row), and on the 2D clustered workload
     (2*10^6 points, rc 0.01, sigma 1e-4: about the spacing inside a
     cluster), with the half-shell candidate count of each grid."""
     import torch
@@ -412,12 +420,12 @@ def pruning_cases(reps=5):
     out = {}
     cfg = W.config2()
     x = torch.from_numpy(cfg["x"]).to("cuda:0")
-    for lc in (1, 2, 3):
-        cl = clm.CellList(x, clm.Box(cfg["H"], cfg["cutoff"], lc), precision="fp32")
+    for lc, lx in ((1, None), (2, None), (3, None), (2, 4), (2, 6), (2, 8)):
+        cl = clm.CellList(x, clm.Box(cfg["H"], cfg["cutoff"], lc, lx), precision="fp32")
         forms = sweep_forms(clm, cl, x, cfg["sigma"], cfg["epsilon"], reps)
         info = cl.info()
-        out[f"headline_lcell{lc}"] = {**forms, "half_shell_candidates": info["candidate_pairs"],
-                                      "ntiles": info["ntiles"]}
+        key = f"headline_lcell{lc}" + (f"_x{lx}" if lx else "")
+        out[key] = {**forms, "half_shell_candidates": info["candidate_pairs"], "ntiles": info["ntiles"]}
         del cl
     del x
     cfg4 = W.config4()
@@ -535,7 +543,8 @@ def main():
     if args.build_only:
         import paper_2202_06427_amd as clm
         import workloads as W
-        print(json.dumps({"build_only": build_roofline(clm, W, args.build_only, args.lcell)}), flush=True)
+        print(json.dumps({"build_only": build_roofline(clm, W, args.build_only, args.lcell,
+                                                       lcell_x=args.lcell_x or None)}), flush=True)
         return
     if args.md_only:
         md_only(args.md_only, args.steps)
@@ -557,13 +566,15 @@ def main():
     cfg = W.config2(n=args.n)
     sigma, eps = cfg["sigma"], cfg["epsilon"]
     xt = torch.from_numpy(cfg["x"]).to("cuda:0")
-    box = clm.Box(cfg["H"], cfg["cutoff"], args.lcell)
+    box = clm.Box(cfg["H"], cfg["cutoff"], args.lcell, args.lcell_x or None)
+    box64 = clm.Box(cfg["H"], cfg["cutoff"], args.lcell)
     binfo = box.info()
-    log(f"box grid {binfo['grid']} lcell {binfo['lcell']} band {binfo['guard_band']:.3e}")
+    log(f"box grid {binfo['grid']} lcell {binfo['lcell']} lcell_x {binfo['lcell_x']} "
+        f"band {binfo['guard_band']:.3e}")
 
     res = {}
     for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
-        cl = clm.CellList(xt, box, precision=prec)
+        cl = clm.CellList(xt, box if prec == "fp32" else box64, precision=prec)
         r = time_steps(clm, cl, xt, args.steps, args.warmup, sigma, eps, args.step_samples)
         info = cl.info()  # after the timed steps: re-evaluation counts of the last map
         r["info"] = info
@@ -598,7 +609,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "uniform-1e6-triclinic-215.4-80/95/100-rc12 LJ energy+forces (bin + sweep + reduce)",
-            "n": args.n, "cutoff": cfg["cutoff"], "lcell": binfo["lcell"], "grid": binfo["grid"],
+            "n": args.n, "cutoff": cfg["cutoff"], "lcell": binfo["lcell"], "lcell_x": binfo["lcell_x"],
+            "grid": binfo["grid"], "fp64_grid": box64.info()["grid"],
             "sigma": sigma, "epsilon": eps, "pairs": pairs, "candidate_pairs_half_shell": cand,
         },
         "phases_ms": {"build": main_r["build_ms"], "sweep": main_r["sweep_ms"]},
@@ -619,6 +631,9 @@ def main():
             "target_met": achieved / VALU_FP32_NONPACKED_TFLOPS >= 0.5,
         },
         "sweep_forms_ms": main_r.get("forms"),
+        "half_sweep_pairs": {"tested": guard["half_pairs_tested"], "kept_after_pruning": guard["half_pairs_kept"],
+                             "kept_fraction": guard["half_pairs_kept"] / max(guard["half_pairs_tested"], 1),
+                             "in_cutoff_fraction_of_kept": pairs / max(guard["half_pairs_kept"], 1)},
         "guard": {"band_retests": guard["guard_retests"], "near_pair_evaluations": guard["near_evaluations"],
                   "fraction_of_pairs": (guard["guard_retests"] + guard["near_evaluations"]) / max(2 * pairs, 1)},
     }
@@ -629,7 +644,8 @@ def main():
                               "bytes_per_particle": BUILD_BYTES_PER_PARTICLE, "points": [b1]}
     if args.build_n_large > 0:
         log(f"build-only timing at n={args.build_n_large} ...")
-        line["build_roofline"]["points"].append(build_roofline(clm, W, args.build_n_large, args.lcell))
+        line["build_roofline"]["points"].append(build_roofline(clm, W, args.build_n_large, args.lcell,
+                                                               lcell_x=args.lcell_x or None))
     line["step_ms_median"] = main_r["step_ms_median"]
     line["step_ms_min"] = main_r["step_ms_min"]
     if args.calibrate:

@@ -127,6 +127,9 @@ typedef struct clm_celllist_info {
                               decided in FP64 */
   int64_t near_evaluations;/* last map, FP32_GUARD: other FP64 re-evaluations (LJ pairs
                               closer than near_factor*sigma, histogram values near an edge) */
+  int64_t half_pairs_tested;/* last map, half-shell force sweep: (tile particle, candidate)
+                              pairs before pruning by the tile's bounding box */
+  int64_t half_pairs_kept;  /* the same after pruning: the pairs the sweep evaluates */
 } clm_celllist_info;
 
 typedef struct clm_map_params {

@@ -45,6 +45,7 @@ class CellListInfo(ctypes.Structure):
         ("ntiles", ctypes.c_int64), ("nonempty_cells", ctypes.c_int64),
         ("max_occupancy", ctypes.c_int64), ("candidate_pairs", ctypes.c_int64),
         ("guard_retests", ctypes.c_int64), ("near_evaluations", ctypes.c_int64),
+        ("half_pairs_tested", ctypes.c_int64), ("half_pairs_kept", ctypes.c_int64),
     ]
 
 

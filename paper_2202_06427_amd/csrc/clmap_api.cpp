@@ -282,7 +282,7 @@ static void layout(clm_celllist* cl, char* base, size_t* total) {
   size_t o_vm = c.take(sizeof(unsigned int) * 2);
   size_t o_nlc = c.take(sizeof(unsigned long long) * 2);
   size_t o_cand = c.take(sizeof(unsigned long long) * maxt);
-  size_t o_guard = c.take(sizeof(unsigned long long) * 2);
+  size_t o_guard = c.take(sizeof(unsigned long long) * 4);
   size_t o_fin = c.take(sizeof(double) * kPartialD * kFinalBlocks);
   size_t o_finc = c.take(sizeof(unsigned long long) * kFinalBlocks);
   size_t o_fb = B.small ? c.take(sizeof(double) * 3 * (size_t)brute_chunks(nyb) * (size_t)cl->nx) : 0;
@@ -616,7 +616,7 @@ clm_status celllist_build_gated(clm_celllist* cl, const double* x, const double*
     CLM_HIP(launch_tiles(cl->X.off, tg, cl->row_tiles, cl->row_off, cl->scan_scratch, cl->tiles,
                          cl->ctx->stream, gate));
   }
-  CLM_HIP(launch_fill_u64(cl->guard, 2, 0ull, cl->ctx->stream, gate));
+  CLM_HIP(launch_fill_u64(cl->guard, 4, 0ull, cl->ctx->stream, gate));
   s = tb.stop();
   if (s != CLM_OK) return s;
   cl->built = 1;
@@ -825,7 +825,7 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
       CLM_HIP(launch_gather_weights(P->weights_y_dev, cl->Y.idx, (int)cl->ny, cl->Y.pos, cl->Y.r64, st));
   }
   if (k == K_NL) CLM_HIP(launch_fill_u64(cl->nl_counter, 1, 0ull, st));
-  CLM_HIP(launch_fill_u64(cl->guard, 2, 0ull, st));
+  CLM_HIP(launch_fill_u64(cl->guard, 4, 0ull, st));
 
   FinalArgs F;
   std::memset(&F, 0, sizeof F);
@@ -1016,7 +1016,7 @@ static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_m
       CLM_HIP(launch_sweep(B.dim, cl->prec == CLM_FP32_GUARD, K_COUNT, cl->job_dev, cl->tiles,
                            &cl->row_off[cl->nrows], cl->max_tiles, 0, st, split));
       CLM_HIP(launch_nl_offsets(cl->pcount, &cl->row_off[cl->nrows], cl->max_tiles, split, cl->nl_off, st));
-      CLM_HIP(launch_fill_u64(cl->guard, 2, 0ull, st));  // count the list pass's re-tests only
+      CLM_HIP(launch_fill_u64(cl->guard, 4, 0ull, st));  // count the list pass's re-tests only
     }
     CLM_HIP(launch_sweep(B.dim, cl->prec == CLM_FP32_GUARD, k_launch, cl->job_dev, cl->tiles,
                          &cl->row_off[cl->nrows], cl->max_tiles, hist ? P->nbins : 0, st, split));
@@ -1134,7 +1134,7 @@ clm_status clm_map_batch(int njobs, clm_celllist* const* cls, clm_map_kind kind,
                          (int)std::min<int64_t>(maxt, INT32_MAX), 0, st));
     for (clm_celllist* c : bcl) {
       CLM_HIP(launch_nl_offsets(c->pcount, &c->row_off[c->nrows], c->max_tiles, 1, c->nl_off, st));
-      CLM_HIP(launch_fill_u64(c->guard, 2, 0ull, st));
+      CLM_HIP(launch_fill_u64(c->guard, 4, 0ull, st));
     }
   }
   CLM_HIP(launch_sweep(dim, prec == CLM_FP32_GUARD, k_launch, jobs_dev, tiles_dev, total_dev,
@@ -1186,11 +1186,13 @@ clm_status clm_celllist_info_get(clm_celllist* cl, clm_celllist_info* o) {
   o->nonempty_cells = ne;
   o->max_occupancy = mo;
   {
-    unsigned long long g[2] = {0, 0};
+    unsigned long long g[4] = {0, 0, 0, 0};
     CLM_HIP(hipMemcpyAsync(g, cl->guard, sizeof g, hipMemcpyDeviceToHost, st));
     CLM_HIP(hipStreamSynchronize(st));
     o->guard_retests = (int64_t)g[0];
     o->near_evaluations = (int64_t)g[1];
+    o->half_pairs_tested = (int64_t)g[2];
+    o->half_pairs_kept = (int64_t)g[3];
   }
   if (cl->box.small) {
     o->ntiles = 0;

@@ -135,6 +135,7 @@ struct Half {
   double W[6];
   uint32_t qband, qnear;
   unsigned long long cnt;  // wave-uniform
+  unsigned long long ntested, nkept;  // wave-uniform: (tile particle, candidate) pairs before / after pruning
   // per block
   float xj[3];
   float acc[3];
@@ -496,6 +497,8 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR>& S, const HalfArgs& A, 
           keep = dd <= rcut2;
         }
         const unsigned long long km = __builtin_amdgcn_ballot_w64(keep);
+        S.ntested += (unsigned long long)count * min(je - cb, (uint32_t)kWave);
+        S.nkept += (unsigned long long)count * (unsigned long long)__popcll(km);
         if (keep)
           S.LST[(S.ltail + (uint32_t)lane_rank(km)) & (uint32_t)(kHLCap - 1)] = make_uint2(j, (uint32_t)kc);
         S.ltail += (uint32_t)__popcll(km);
@@ -556,6 +559,8 @@ half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   S.qband = 0;
   S.qnear = 0;
   S.cnt = 0;
+  S.ntested = 0;
+  S.nkept = 0;
   S.qhead = 0;
   S.qtail = 0;
   S.key = 0x7fffffff;
@@ -610,10 +615,14 @@ half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
     }
   }
   const unsigned long long gb = wave_sum_u64(S.qband), gn = wave_sum_u64(S.qnear);
-  if (lane == 0 && (gb | gn)) {
+  if (lane == 0) {
     unsigned long long* g = ldu(&J->guard);
-    atomicAdd(&g[0], gb);
-    atomicAdd(&g[1], gn);
+    if (gb | gn) {
+      atomicAdd(&g[0], gb);
+      atomicAdd(&g[1], gn);
+    }
+    atomicAdd(&g[2], S.ntested);
+    atomicAdd(&g[3], S.nkept);
   }
 }
 

@@ -100,6 +100,10 @@ def test_half_shell_uniform_random_near_pairs(clm, name, prune):
     _check(out, ref, x, sigma, eps)
     info = cl.info()
     assert info["near_evaluations"] > 0
+    # every evaluated pair was tested; pruning drops only pairs beyond the cutoff
+    assert ref["count"] <= info["half_pairs_kept"] <= info["half_pairs_tested"]
+    if not prune:
+        assert info["half_pairs_kept"] == info["half_pairs_tested"]
 
 
 def test_half_shell_heavy_cell_tiles(clm):
