@@ -154,16 +154,16 @@ typedef struct clm_map_params {
   void* scratch_dev;            /* NEIGHBOR_LIST with sorted: caller-owned device scratch of at least
                                    clm_pairs_sort_workspace_bytes(capacity, with_distances) bytes
                                    (256-byte aligned).
-                                   LJ_EF / LJ_ADJOINT, FP32_GUARD, single set: caller-owned device
-                                   scratch of at least clm_map_scratch_bytes bytes (256-byte
-                                   aligned) enables the half-shell force sweep, which evaluates
-                                   every pair once and keeps both particles' force sums in FP32
-                                   planes (one writer per slot) summed per particle in FP64.
-                                   NULL: the full-shell gather, which evaluates every pair
-                                   from both ends.  Both meet the FP32_GUARD tolerances; their
-                                   force values differ in rounding.  A non-NULL scratch that is
-                                   too small or misaligned is CLM_E_WORKSPACE; other kinds and
-                                   forms ignore it. */
+                                   LJ_EF / LJ_ADJOINT, single set, either precision: caller-owned
+                                   device scratch of at least clm_map_scratch_bytes bytes
+                                   (256-byte aligned) enables the half-shell force sweep, which
+                                   evaluates every pair once and keeps both particles' force sums
+                                   in planes (FP32 in the FP32_GUARD form, FP64 in the FP64 form;
+                                   one writer per slot) summed per particle in FP64.  NULL: the
+                                   full-shell gather, which evaluates every pair from both ends.
+                                   Both meet the form's tolerances; their force values differ in
+                                   rounding.  A non-NULL scratch that is too small or misaligned
+                                   is CLM_E_WORKSPACE; other kinds and cross sets ignore it. */
   size_t scratch_bytes;
   int no_prune;                 /* half-shell force sweep: 1 keeps every candidate of the visited
                                    cells (no pruning by the distance to the tile's bounding box;
@@ -255,10 +255,11 @@ clm_status clm_celllist_create(clm_context* ctx, const clm_box* box, int64_t n_x
  * NULL for a single set.  The inputs may be freed after the build. */
 clm_status clm_celllist_build(clm_celllist* cl, const double* x_dev, const double* y_dev);
 /* Bytes of map scratch (clm_map_params.scratch_dev) that make LJ_EF and
- * LJ_ADJOINT use the half-shell force sweep on this cell list (0 where that
- * sweep does not apply: FP64 form, cross sets, boxes with fewer than
- * 2*lcell+1 cells per axis, other kinds).  About 26 x 12 bytes per particle
- * at lcell 2 in 3D (2 (2 l^2 + 2 l + 1) planes of 3 FP32 components). */
+ * LJ_ADJOINT use the half-shell force sweep on this cell list (paper
+ * section 2.8's half shell; 0 where that sweep does not apply: cross sets,
+ * boxes with fewer than 2*lcell+1 cells per axis, other kinds).  About
+ * 26 x 12 bytes per particle at lcell 2 in 3D (2 (2 l^2 + 2 l + 1) planes of
+ * 3 FP32 components), twice that in the FP64 form. */
 clm_status clm_map_scratch_bytes(const clm_celllist* cl, clm_map_kind kind, size_t* bytes);
 /* Map one kind over the pair set and reduce it (async). */
 clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* params,

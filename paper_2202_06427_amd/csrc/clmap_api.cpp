@@ -766,6 +766,16 @@ static clm_status prepare_job(clm_celllist* cl, clm_map_kind kind, const clm_map
       jd.half_lo[sp] = round_down_f((rcm * rcm - bd) / s2);
       jd.half_hi[sp] = round_up_f((rcm * rcm + bd) / s2);
     }
+    {
+      // FP64 form: the sweep's d^2 (sigma units about the tile's centre)
+      // differs from the canonical one by a few roundings of coordinates of
+      // at most a few box lengths; a band of 2^-40 (rc + sum of the box's
+      // lattice-vector lengths)^2 covers that many times over
+      const double ext = rcm + B.sum_len;
+      const double bd = std::ldexp(ext * ext, -40);
+      jd.half_lo64 = std::nextafter((rcm * rcm - bd) / s2, 0.0);
+      jd.half_hi64 = std::nextafter((rcm * rcm + bd) / s2, HUGE_VAL);
+    }
     const double nf = P->near_factor > 0.0 ? P->near_factor : 1.0;
     jd.half_near2 = round_up_f(nf * nf);
     jd.half_noprune = P->no_prune ? 1 : 0;
@@ -859,7 +869,7 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
 static constexpr int kHalfMinItems = 4096;
 
 static bool half_applies(const clm_celllist* cl, int k) {
-  return k == K_LJ_F && cl->prec == CLM_FP32_GUARD && !cl->box.small && !cl->cross && cl->nx > 0;
+  return k == K_LJ_F && !cl->box.small && !cl->cross && cl->nx > 0;
 }
 
 struct HalfLayout {
@@ -874,7 +884,8 @@ static HalfLayout half_layout(const clm_celllist* cl) {
   L.ngather = (int)((cl->nx + 255) / 256);
   L.npad = (size_t)((cl->nx + 63) / 64) * 64;
   Carve c;
-  L.o_part = c.take(sizeof(float) * 2 * (size_t)L.NR * 3 * L.npad);
+  const size_t esz = cl->prec == CLM_FP64 ? sizeof(double) : sizeof(float);
+  L.o_part = c.take(esz * 2 * (size_t)L.NR * 3 * L.npad);
   L.o_parts = c.take(sizeof(double) * kPartialD * (size_t)(L.nitems + L.ngather));
   L.o_pc = c.take(sizeof(unsigned long long) * (size_t)(L.nitems + L.ngather));
   L.total = c.off;
@@ -950,7 +961,7 @@ static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_m
     const HalfLayout HL = half_layout(cl);
     char* base = (char*)P->scratch_dev;
     HalfArgs A;
-    A.part = (float*)(base + HL.o_part);
+    A.part = (void*)(base + HL.o_part);
     A.npad = HL.npad;
     A.partials = (double*)(base + HL.o_parts);
     A.pcount = (unsigned long long*)(base + HL.o_pc);
@@ -965,10 +976,11 @@ static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_m
     Timed ts(cl->untimed ? nullptr : cl->ctx, &cl->ctx->sweep_ev);
     s = ts.start();
     if (s != CLM_OK) return s;
-    CLM_HIP(launch_half_lj(B.dim, k_launch == K_LJ_FV, cl->job_dev, A, st));
+    const bool fp64 = cl->prec == CLM_FP64;
+    CLM_HIP(launch_half_lj(B.dim, k_launch == K_LJ_FV, fp64, cl->job_dev, A, st));
     s = ts.stop();
     if (s != CLM_OK) return s;
-    CLM_HIP(launch_half_gather(B.dim, cl->job_dev, A, (int)cl->nx, st));
+    CLM_HIP(launch_half_gather(B.dim, fp64, cl->job_dev, A, (int)cl->nx, st));
     F.nparts = HL.nitems + HL.ngather;
     F.nparts_dev = nullptr;
     F.split_rows = 0;

@@ -117,6 +117,7 @@ struct JobDesc {
   // thresholds on d^2 / sigma^2 per tile span (1..kMaxSpan cells along x) and
   // the near threshold near_factor^2
   float half_lo[kMaxSpan + 1], half_hi[kMaxSpan + 1];
+  double half_lo64, half_hi64;  // the same for the FP64 form (any span)
   float half_near2;
   int half_noprune;          // 1: keep every candidate (no bounding-box pruning)
 };
@@ -218,7 +219,7 @@ inline int sweep_split_rows(int kind, int dim, int lcell, bool full) {
 // 2 NR planes of 3 components (stride npad floats): plane 2 rho holds the
 // i-side sums of offset rho, plane 2 rho + 1 the j-side sums.
 struct HalfArgs {
-  float* part;
+  void* part;                  // 2 NR force planes of 3 components (float, or double in the FP64 form)
   size_t npad;
   double* partials;            // nitems + gather blocks, kPartialD each
   unsigned long long* pcount;  // nitems + gather blocks
@@ -409,8 +410,10 @@ __host__ __device__ inline int brute_chunks(int64_t ny) {
 }
 hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, double* FB, int* nparts_out,
                         hipStream_t s);
-hipError_t launch_half_lj(int dim, bool virial, const JobDesc* jobs, const HalfArgs& A, hipStream_t s);
-hipError_t launch_half_gather(int dim, const JobDesc* jobs, const HalfArgs& A, int n, hipStream_t s);
+hipError_t launch_half_lj(int dim, bool virial, bool fp64, const JobDesc* jobs, const HalfArgs& A,
+                          hipStream_t s);
+hipError_t launch_half_gather(int dim, bool fp64, const JobDesc* jobs, const HalfArgs& A, int n,
+                              hipStream_t s);
 hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, double* scratch,
                            unsigned long long* scratch_count, hipStream_t s);
 constexpr int kFinalBlocks = 128;  // first-level blocks of the two-level finalize

@@ -88,6 +88,42 @@ __device__ __forceinline__ float shfl_f(float v, int src_byte) {
   return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src_byte, __builtin_bit_cast(int, v)));
 }
 
+// The same lane moves for FP64 values (two 32-bit halves each).
+template <int K>
+__device__ __forceinline__ double row_ror(double v) {
+  if constexpr (K == 0) {
+    return v;
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x120 + K, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x120 + K, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  }
+}
+template <int K>
+__device__ __forceinline__ double row_back(double v) {
+  if constexpr (K == 0) {
+    return v;
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x120 + (16 - K), 0xF, 0xF, true);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x120 + (16 - K), 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  }
+}
+__device__ __forceinline__ double shfl_f(double v, int src_byte) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src_byte, (int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src_byte, (int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float rcp_t(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double rcp_t(double v) { return rcp64(v); }
+
 __device__ __forceinline__ double wave_min_d(double v) {
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) v = fmin(v, __shfl_xor(v, d, 64));
@@ -117,17 +153,17 @@ __device__ __forceinline__ void row_offset(int l, int rho, int* dy, int* dz) {
   *dy = q % (2 * l + 1) - l;
 }
 
-template <int DIM, bool VIR>
+template <int DIM, bool VIR, typename T>
 struct Half {
   const JobDesc* J;
   int lane;
   // uniform
   double rc2, s2, inv_sig;
-  float near2f;            // (near_factor)^2: sigma units
-  float lo, hi;            // membership thresholds on d^2 / sigma^2
+  T near2f;                // (near_factor)^2: sigma units
+  T lo, hi;                // membership thresholds on d^2 / sigma^2
   // per lane (i side, fixed for a tile)
-  double O[3];             // origin of the FP32 coordinates: centre of the tile's bounding box
-  float xi[3];             // relative to O, sigma units
+  double O[3];             // origin of the sweep's coordinates: centre of the tile's bounding box
+  T xi[3];                 // relative to O, sigma units
   double Fi[3];
   // per lane accumulators of the item
   double E64;
@@ -137,12 +173,12 @@ struct Half {
   unsigned long long cnt;  // wave-uniform
   unsigned long long ntested, nkept;  // wave-uniform: (tile particle, candidate) pairs before / after pruning
   // per block
-  float xj[3];
-  float acc[3];
+  T xj[3];
+  T acc[3];
   int key;                 // home row: candidate's sorted index (pairs only j > i), else INT_MAX
-  float e32;
-  float fi32[3];
-  float w32[6];
+  T e32;
+  T fi32[3];
+  T w32[6];
   // LDS
   uint32_t* Q;             // queue of FP64 re-evaluations: i lane | candidate << 6 | band << 31
   double* GA;              // [64][3] FP64 i-side sums of queued pairs
@@ -224,11 +260,10 @@ struct Half {
   // jtag: (candidate held by this lane) << 6.
   template <int K, bool SELF, int JW>
   __device__ __forceinline__ void step(int jtag) {
-    const float dx = row_ror<K>(xj[0]) - xi[0];
-    const float dy = row_ror<K>(xj[1]) - xi[1];
-    const float dz = DIM == 3 ? row_ror<K>(xj[2]) - xi[2] : 0.0f;
-    const float d2 = DIM == 3 ? __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))
-                              : __builtin_fmaf(dy, dy, dx * dx);
+    const T dx = row_ror<K>(xj[0]) - xi[0];
+    const T dy = row_ror<K>(xj[1]) - xi[1];
+    const T dz = DIM == 3 ? row_ror<K>(xj[2]) - xi[2] : T(0);
+    const T d2 = DIM == 3 ? fma_t(dz, dz, fma_t(dy, dy, dx * dx)) : fma_t(dy, dy, dx * dx);
     unsigned long long okm = ~0ull;
     if constexpr (SELF) okm = __builtin_amdgcn_ballot_w64(row_ror_i<K>(key) > (int)(tstart + (uint32_t)lane));
     const unsigned long long mlo = __builtin_amdgcn_ballot_w64(d2 <= lo) & okm;
@@ -236,12 +271,12 @@ struct Half {
     const unsigned long long mnr = __builtin_amdgcn_ballot_w64(d2 < near2f) & okm;
     cnt += (unsigned long long)__popcll(mlo);
     const bool fast = __builtin_amdgcn_inverse_ballot_w64(mlo & ~mnr);
-    const float x = fast ? __builtin_amdgcn_rcpf(d2) : 0.0f;  // sigma^2 / d^2
-    const float x3 = x * x * x;
-    const float u = __builtin_fmaf(x3, x3, -x3);
+    const T x = fast ? rcp_t(d2) : T(0);  // sigma^2 / d^2
+    const T x3 = x * x * x;
+    const T u = fma_t(x3, x3, -x3);
     e32 += u;
-    const float f = __builtin_fmaf(2.0f, u, x3) * x;
-    const float tx = f * dx, ty = f * dy, tz = f * dz;
+    const T f = fma_t(T(2), u, x3) * x;
+    const T tx = f * dx, ty = f * dy, tz = f * dz;
     fi32[0] += tx;
     fi32[1] += ty;
     acc[0] += row_back<K>(tx);
@@ -251,13 +286,13 @@ struct Half {
       acc[2] += row_back<K>(tz);
     }
     if constexpr (VIR) {
-      w32[0] = __builtin_fmaf(tx, dx, w32[0]);
-      w32[1] = __builtin_fmaf(tx, dy, w32[1]);
-      w32[3] = __builtin_fmaf(ty, dy, w32[3]);
+      w32[0] = fma_t(tx, dx, w32[0]);
+      w32[1] = fma_t(tx, dy, w32[1]);
+      w32[3] = fma_t(ty, dy, w32[3]);
       if (DIM == 3) {
-        w32[2] = __builtin_fmaf(tx, dz, w32[2]);
-        w32[4] = __builtin_fmaf(ty, dz, w32[4]);
-        w32[5] = __builtin_fmaf(tz, dz, w32[5]);
+        w32[2] = fma_t(tx, dz, w32[2]);
+        w32[4] = fma_t(ty, dz, w32[4]);
+        w32[5] = fma_t(tz, dz, w32[5]);
       }
     }
     // keep the accumulator updates in this step (an empty asm that reads and
@@ -304,7 +339,7 @@ struct Half {
   // One block of the nb (1..JW) candidates at list positions bbase..;
   // part_j: this item's j-side plane (3 components, stride npad).
   template <bool SELF, int JW>
-  __device__ __forceinline__ void block(uint32_t nb, float* part_j, size_t npad) {
+  __device__ __forceinline__ void block(uint32_t nb, T* part_j, size_t npad) {
     const int m = lane & (JW - 1);
     const bool jv = (uint32_t)m < nb;
     const uint2 c = jv ? LST[(bbase + (uint32_t)m) & (uint32_t)(kHLCap - 1)] : make_uint2(0u, kCenter);
@@ -312,29 +347,29 @@ struct Half {
     {
       const double4 r = jv ? J->r64_x[c.x] : make_double4(0.0, 0.0, 0.0, 0.0);
       const double* t = &tK[c.y * 4];
-      xj[0] = jv ? (float)(((r.x + t[0]) - O[0]) * inv_sig) : -1e18f;
-      xj[1] = jv ? (float)(((r.y + t[1]) - O[1]) * inv_sig) : -1e18f;
-      xj[2] = DIM == 3 ? (jv ? (float)(((r.z + t[2]) - O[2]) * inv_sig) : -1e18f) : 0.0f;
+      xj[0] = jv ? (T)(((r.x + t[0]) - O[0]) * inv_sig) : T(-1e18);
+      xj[1] = jv ? (T)(((r.y + t[1]) - O[1]) * inv_sig) : T(-1e18);
+      xj[2] = DIM == 3 ? (jv ? (T)(((r.z + t[2]) - O[2]) * inv_sig) : T(-1e18)) : T(0);
     }
     if constexpr (SELF) key = (jv && c.y == kCenter) ? (int)c.x : 0x7fffffff;
-    float jold[3] = {0.0f, 0.0f, 0.0f};
+    T jold[3] = {T(0), T(0), T(0)};
     if (jv && lane < JW) {
 #pragma unroll
       for (int a = 0; a < DIM; ++a) jold[a] = part_j[(size_t)a * npad + c.x];
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      acc[a] = 0.0f;
-      fi32[a] = 0.0f;
+      acc[a] = T(0);
+      fi32[a] = T(0);
     }
     if (lane < JW) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) GJ[lane * 3 + a] = 0.0;
     }
-    e32 = 0.0f;
+    e32 = T(0);
     if constexpr (VIR) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) w32[k] = 0.0f;
+      for (int k = 0; k < 6; ++k) w32[k] = T(0);
     }
     __builtin_amdgcn_wave_barrier();
     // phases: the candidates rotate by 16 lanes inside each JW-lane group
@@ -379,7 +414,7 @@ struct Half {
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
         S[a] = (double)acc[a] * inv_sig + GJ[lane * 3 + a];
-        part_j[(size_t)a * npad + c.x] = (float)((double)jold[a] - S[a]);
+        part_j[(size_t)a * npad + c.x] = (T)((double)jold[a] - S[a]);
       }
       if (c.y != kCenter) {  // a periodic image: the box-gradient term S p^T
         const int p[3] = {(int)(c.y % 3u) - 1, (int)((c.y / 3u) % 3u) - 1, (int)(c.y / 9u) - 1};
@@ -392,7 +427,7 @@ struct Half {
   }
 
   template <bool SELF>
-  __device__ __forceinline__ void run_full(float* part_j, size_t npad) {
+  __device__ __forceinline__ void run_full(T* part_j, size_t npad) {
     while (ltail - lhead >= (uint32_t)kWave) {
       bbase = lhead;
       block<SELF, 64>(64u, part_j, npad);
@@ -401,7 +436,7 @@ struct Half {
   }
 
   template <bool SELF>
-  __device__ __forceinline__ void run_tail(float* part_j, size_t npad) {
+  __device__ __forceinline__ void run_tail(T* part_j, size_t npad) {
     const uint32_t r = ltail - lhead;
     if (r == 0u) return;
     bbase = lhead;
@@ -415,9 +450,9 @@ struct Half {
   }
 };
 
-template <int DIM, bool VIR, bool SELF>
-__device__ __forceinline__ void run_tiles(Half<DIM, VIR>& S, const HalfArgs& A, int h, int py, int pz,
-                                          int rbase, float* part_i, float* part_j) {
+template <int DIM, bool VIR, typename T, bool SELF>
+__device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& A, int h, int py, int pz,
+                                          int rbase, T* part_i, T* part_j) {
   const JobDesc* J = S.J;
   const int lane = S.lane;
   const int nx = ldu(&J->n[0]), lx = ldu(&J->lcell_x);
@@ -432,15 +467,20 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR>& S, const HalfArgs& A, 
   for (int ti = t0; ti < t1; ++ti) {
     // the previous tile's plane updates are visible to every lane
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    const Tile T = ldu(&tiles[ti]);
-    const int count = T.count;
-    const int cx0 = T.cx0, cx1 = T.cx1;
+    const Tile tl = ldu(&tiles[ti]);
+    const int count = tl.count;
+    const int cx0 = tl.cx0, cx1 = tl.cx1;
     const bool active = lane < count;
-    S.tstart = T.start;
-    const uint32_t i = T.start + (uint32_t)(active ? lane : count - 1);
+    S.tstart = tl.start;
+    const uint32_t i = tl.start + (uint32_t)(active ? lane : count - 1);
     const int span = cx1 - cx0 + 1;
-    S.lo = ldu(&J->half_lo[span]);
-    S.hi = ldu(&J->half_hi[span]);
+    if constexpr (sizeof(T) == 4) {
+      S.lo = ldu(&J->half_lo[span]);
+      S.hi = ldu(&J->half_hi[span]);
+    } else {
+      S.lo = ldu(&J->half_lo64);
+      S.hi = ldu(&J->half_hi64);
+    }
     double bl[3] = {0.0, 0.0, 0.0}, bh[3] = {0.0, 0.0, 0.0};
     {
       const double4 r = J->r64_x[i];
@@ -455,9 +495,9 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR>& S, const HalfArgs& A, 
         bh[a] = wave_max_d(ri[a]);
         S.O[a] = 0.5 * (bl[a] + bh[a]);
       }
-      S.xi[0] = active ? (float)((ri[0] - S.O[0]) * S.inv_sig) : 1e18f;
-      S.xi[1] = active ? (float)((ri[1] - S.O[1]) * S.inv_sig) : 1e18f;
-      S.xi[2] = DIM == 3 ? (active ? (float)((ri[2] - S.O[2]) * S.inv_sig) : 1e18f) : 0.0f;
+      S.xi[0] = active ? (T)((ri[0] - S.O[0]) * S.inv_sig) : T(1e18);
+      S.xi[1] = active ? (T)((ri[1] - S.O[1]) * S.inv_sig) : T(1e18);
+      S.xi[2] = DIM == 3 ? (active ? (T)((ri[2] - S.O[2]) * S.inv_sig) : T(1e18)) : T(0);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -478,7 +518,7 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR>& S, const HalfArgs& A, 
       const int c0 = a0 - px * nx, c1 = a1 - px * nx;  // wrapped cell indices
       uint32_t jb = ldu(&off[rbase + c0]);
       const uint32_t je = ldu(&off[rbase + c1 + 1]);
-      if (SELF && px == 0) jb = T.start;  // pairs j > i: from the tile's first particle on
+      if (SELF && px == 0) jb = tl.start;  // pairs j > i: from the tile's first particle on
       const int kc = kcode(px, py, pz);
       const double t[3] = {ldu(&J->tK[kc * 4 + 0]), ldu(&J->tK[kc * 4 + 1]), ldu(&J->tK[kc * 4 + 2])};
       for (uint32_t cb = jb; cb < je; cb += kWave) {
@@ -512,20 +552,16 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR>& S, const HalfArgs& A, 
     for (int a = 0; a < DIM; ++a) S.Fi[a] += S.GA[lane * 3 + a];
     if (active) {
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) part_i[(size_t)a * npad + i] = (float)S.Fi[a];
+      for (int a = 0; a < DIM; ++a) part_i[(size_t)a * npad + i] = (T)S.Fi[a];
     }
   }
 }
 
 }  // namespace
 
-template <int DIM, bool VIR>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
-half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
-  __shared__ uint32_t sQ[kHQCap];
-  __shared__ uint2 sL[kHLCap];
-  __shared__ double sGA[kWave * 3];
-  __shared__ double sGJ[kWave * 3];
+template <int DIM, bool VIR, typename T>
+__device__ __forceinline__ void half_lj_body(const JobDesc* __restrict__ jobs, const HalfArgs& A,
+                                             uint32_t* sQ, uint2* sL, double* sGA, double* sGJ) {
   const int lane = (int)__lane_id();
   const int nitems = A.nitems;
   int b = blockIdx.x;
@@ -540,7 +576,7 @@ half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   const int h = item / NR, rho = item - (item / NR) * NR;
   const JobDesc* J = &jobs[0];
 
-  Half<DIM, VIR> S;
+  Half<DIM, VIR, T> S;
   S.J = J;
   S.lane = lane;
   S.Q = sQ;
@@ -550,7 +586,7 @@ half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   S.rc2 = ldu(&J->rc2);
   S.s2 = ldu(&J->s2);
   S.inv_sig = 1.0 / sqrt(S.s2);
-  S.near2f = ldu(&J->half_near2);
+  S.near2f = (T)ldu(&J->half_near2);
   S.E64 = 0.0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) S.B[k] = 0.0;
@@ -577,19 +613,19 @@ half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   const uint32_t* off = ldu(&J->off_x);
   const int rbase = (uy + ny * uz) * nx;
   const size_t npad = A.npad;
-  float* part_i = A.part + (size_t)(2 * rho) * 3 * npad;
-  float* part_j = A.part + (size_t)(2 * rho + 1) * 3 * npad;
+  T* part_i = (T*)A.part + (size_t)(2 * rho) * 3 * npad;
+  T* part_j = (T*)A.part + (size_t)(2 * rho + 1) * 3 * npad;
   {  // this item owns the j-side plane over row r: clear it
     const uint32_t r0 = ldu(&off[rbase]), r1 = ldu(&off[rbase + nx]);
     for (uint32_t j = r0 + (uint32_t)lane; j < r1; j += kWave) {
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) part_j[(size_t)a * npad + j] = 0.0f;
+      for (int a = 0; a < DIM; ++a) part_j[(size_t)a * npad + j] = T(0);
     }
   }
   if (rho == 0)
-    run_tiles<DIM, VIR, true>(S, A, h, py, pz, rbase, part_i, part_j);
+    run_tiles<DIM, VIR, T, true>(S, A, h, py, pz, rbase, part_i, part_j);
   else
-    run_tiles<DIM, VIR, false>(S, A, h, py, pz, rbase, part_i, part_j);
+    run_tiles<DIM, VIR, T, false>(S, A, h, py, pz, rbase, part_i, part_j);
 
   // ---- item partials
   const unsigned long long cnt = S.cnt;
@@ -626,10 +662,33 @@ half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   }
 }
 
+// FP32 + FP64-guard form: 128 registers (four waves per SIMD).
+template <int DIM, bool VIR>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
+  __shared__ uint32_t sQ[kHQCap];
+  __shared__ uint2 sL[kHLCap];
+  __shared__ double sGA[kWave * 3];
+  __shared__ double sGJ[kWave * 3];
+  half_lj_body<DIM, VIR, float>(jobs, A, sQ, sL, sGA, sGJ);
+}
+
+// Plain FP64 form: the same sweep with FP64 coordinates, sums and force
+// planes; twice the registers.
+template <int DIM, bool VIR>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+half_lj64_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
+  __shared__ uint32_t sQ[kHQCap];
+  __shared__ uint2 sL[kHLCap];
+  __shared__ double sGA[kWave * 3];
+  __shared__ double sGJ[kWave * 3];
+  half_lj_body<DIM, VIR, double>(jobs, A, sQ, sL, sGA, sGJ);
+}
+
 // Sum of the 2 NR planes of each particle (fixed order), forces in original
 // order, and the wrap term of the box gradient, sum over particles of
 // G_p w_p^T (block partials after the item partials).
-template <int DIM>
+template <int DIM, typename T>
 __global__ void __launch_bounds__(256) half_gather_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A,
                                                           int n) {
   const JobDesc& J = jobs[0];
@@ -641,7 +700,7 @@ __global__ void __launch_bounds__(256) half_gather_kernel(const JobDesc* __restr
   if (p < n) {
     const size_t npad = A.npad;
     for (int q = 0; q < 2 * A.NR; ++q) {
-      const float* pl = A.part + (size_t)q * 3 * npad;
+      const T* pl = (const T*)A.part + (size_t)q * 3 * npad;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) G[a] += (double)pl[(size_t)a * npad + p];
     }
@@ -675,25 +734,35 @@ __global__ void __launch_bounds__(256) half_gather_kernel(const JobDesc* __restr
   if (tid == 0) A.pcount[slot] = 0ull;
 }
 
-hipError_t launch_half_lj(int dim, bool virial, const JobDesc* jobs, const HalfArgs& A, hipStream_t s) {
+hipError_t launch_half_lj(int dim, bool virial, bool fp64, const JobDesc* jobs, const HalfArgs& A,
+                          hipStream_t s) {
   if (A.nitems > 0) {
-    if (dim == 3)
-      virial ? half_lj_kernel<3, true><<<A.nitems, 64, 0, s>>>(jobs, A)
-             : half_lj_kernel<3, false><<<A.nitems, 64, 0, s>>>(jobs, A);
-    else
-      virial ? half_lj_kernel<2, true><<<A.nitems, 64, 0, s>>>(jobs, A)
-             : half_lj_kernel<2, false><<<A.nitems, 64, 0, s>>>(jobs, A);
+    const unsigned g = (unsigned)A.nitems;
+    if (fp64) {
+      if (dim == 3)
+        virial ? half_lj64_kernel<3, true><<<g, 64, 0, s>>>(jobs, A) : half_lj64_kernel<3, false><<<g, 64, 0, s>>>(jobs, A);
+      else
+        virial ? half_lj64_kernel<2, true><<<g, 64, 0, s>>>(jobs, A) : half_lj64_kernel<2, false><<<g, 64, 0, s>>>(jobs, A);
+    } else {
+      if (dim == 3)
+        virial ? half_lj_kernel<3, true><<<g, 64, 0, s>>>(jobs, A) : half_lj_kernel<3, false><<<g, 64, 0, s>>>(jobs, A);
+      else
+        virial ? half_lj_kernel<2, true><<<g, 64, 0, s>>>(jobs, A) : half_lj_kernel<2, false><<<g, 64, 0, s>>>(jobs, A);
+    }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_half_gather(int dim, const JobDesc* jobs, const HalfArgs& A, int n, hipStream_t s) {
+hipError_t launch_half_gather(int dim, bool fp64, const JobDesc* jobs, const HalfArgs& A, int n,
+                              hipStream_t s) {
   const int nb = (n + 255) / 256;
   if (nb > 0) {
-    if (dim == 3)
-      half_gather_kernel<3><<<nb, 256, 0, s>>>(jobs, A, n);
+    if (fp64)
+      dim == 3 ? half_gather_kernel<3, double><<<nb, 256, 0, s>>>(jobs, A, n)
+               : half_gather_kernel<2, double><<<nb, 256, 0, s>>>(jobs, A, n);
     else
-      half_gather_kernel<2><<<nb, 256, 0, s>>>(jobs, A, n);
+      dim == 3 ? half_gather_kernel<3, float><<<nb, 256, 0, s>>>(jobs, A, n)
+               : half_gather_kernel<2, float><<<nb, 256, 0, s>>>(jobs, A, n);
   }
   return hipGetLastError();
 }

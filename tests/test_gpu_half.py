@@ -1,12 +1,13 @@
-"""GPU parity of the half-shell Lennard-Jones force sweep (FP32 + FP64 guard;
-every pair evaluated once, both particles' force sums kept in FP32 planes
-with one writer per slot, summed per particle in FP64) against the oracle and
-against the full-shell gather, through the C-ABI.
+"""GPU parity of the half-shell Lennard-Jones force sweep (every pair
+evaluated once, both particles' force sums kept in planes with one writer per
+slot, summed per particle in FP64) in its two forms -- FP32 + FP64 guard
+(FP32 planes) and plain FP64 (FP64 planes) -- against the oracle and against
+the full-shell gather, through the C-ABI.
 
-Tolerances as for every FP32+guard map: energy 1e-6 relative, per-particle
-force error 1e-5 relative to the sum of the pair-force magnitudes on that
-particle, box gradient and virial 1e-5 of their largest entry; pair counts
-exact."""
+Tolerances as for every map of the form: FP32+guard energy 1e-6 relative,
+per-particle force error 1e-5 relative to the sum of the pair-force
+magnitudes on that particle, box gradient and virial 1e-5 of their largest
+entry; FP64 1e-12, 1e-11 and 1e-11; pair counts exact."""
 import numpy as np
 import pytest
 import torch
@@ -48,17 +49,21 @@ def _force_scale(ref, n, sigma, eps):
     return s
 
 
-def _check(out, ref, x, sigma, eps, virial=True):
+TOL = {"fp32": (1e-6, 1e-5), "fp64": (1e-12, 1e-11)}
+
+
+def _check(out, ref, x, sigma, eps, virial=True, precision="fp32"):
     n = len(x)
+    tolE, tolF = TOL[precision]
     assert int(out["count"].item()) == ref["count"]
-    assert abs(out["energy"].item() - ref["lj_energy"]) <= 1e-6 * abs(ref["lj_energy"])
+    assert abs(out["energy"].item() - ref["lj_energy"]) <= tolE * abs(ref["lj_energy"])
     scale = _force_scale(ref, n, sigma, eps)
     err = np.linalg.norm(out["forces"].cpu().numpy() + ref["lj_grad"], axis=1) / np.maximum(scale, 1e-300)
-    assert err.max() <= 1e-5, err.max()
+    assert err.max() <= tolF, err.max()
     gb = out["grad_box"].cpu().numpy()
-    assert np.abs(gb - ref["dEdH"]).max() <= 1e-5 * np.abs(ref["dEdH"]).max()
+    assert np.abs(gb - ref["dEdH"]).max() <= tolF * np.abs(ref["dEdH"]).max()
     if virial:
-        assert np.abs(out["virial"].cpu().numpy() - ref["virial"]).max() <= 1e-5 * np.abs(ref["virial"]).max()
+        assert np.abs(out["virial"].cpu().numpy() - ref["virial"]).max() <= tolF * np.abs(ref["virial"]).max()
 
 
 BOXES = {
@@ -70,34 +75,38 @@ BOXES = {
 }
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("name", list(BOXES))
 @pytest.mark.parametrize("lcell,lcell_x", [(1, None), (2, None), (3, None), (2, 3)])
 @pytest.mark.parametrize("prune", [True, False])
-def test_half_shell_lattice_against_oracle(clm, name, lcell, lcell_x, prune):
+def test_half_shell_lattice_against_oracle(clm, name, lcell, lcell_x, prune, precision):
     H, rc = BOXES[name]
     dim = H.shape[0]
     x = _lattice(H, 6000 if dim == 3 else 5000, 11) + H @ np.array([3, -2, 5][:dim])
     sigma, eps = 1.1, 0.3
     ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
-    cl = clm.CellList(T(x), clm.Box(H, rc, lcell, lcell_x), precision="fp32")
+    cl = clm.CellList(T(x), clm.Box(H, rc, lcell, lcell_x), precision=precision)
     assert cl._half_scratch("lj_ef", True)[1] > 0, "the half-shell sweep applies here"
-    print(f"case {name} lcell={lcell} lcell_x={lcell_x} prune={prune}", flush=True)
-    _check(cl.lj_forces(sigma, eps, virial=True, half=True, prune=prune), ref, x, sigma, eps)
-    _check(cl.lj_forces(sigma, eps, virial=False, half=True, prune=prune), ref, x, sigma, eps, virial=False)
+    print(f"case {name} lcell={lcell} lcell_x={lcell_x} prune={prune} {precision}", flush=True)
+    _check(cl.lj_forces(sigma, eps, virial=True, half=True, prune=prune), ref, x, sigma, eps,
+           precision=precision)
+    _check(cl.lj_forces(sigma, eps, virial=False, half=True, prune=prune), ref, x, sigma, eps, virial=False,
+           precision=precision)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("name", ["tric3", "cube3", "tric2"])
 @pytest.mark.parametrize("prune", [True, False])
-def test_half_shell_uniform_random_near_pairs(clm, name, prune):
-    """Uniform random points: pairs far inside sigma (FP64 near-pair path,
-    forces into both particles' planes) dominate E."""
+def test_half_shell_uniform_random_near_pairs(clm, name, prune, precision):
+    """Uniform random points: pairs far inside sigma (the canonical FP64
+    near-pair path, forces into both particles' planes) dominate E."""
     H, rc = BOXES[name]
     x = W.uniform_in_box(6000, H, 21)
     sigma, eps = 3.4 if H.shape[0] == 3 else 1.0, 0.238
     ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
-    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp32")
+    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision=precision)
     out = cl.lj_forces(sigma, eps, virial=True, half=True, prune=prune)
-    _check(out, ref, x, sigma, eps)
+    _check(out, ref, x, sigma, eps, precision=precision)
     info = cl.info()
     assert info["near_evaluations"] > 0
     # every evaluated pair was tested; pruning drops only pairs beyond the cutoff
@@ -106,7 +115,8 @@ def test_half_shell_uniform_random_near_pairs(clm, name, prune):
         assert info["half_pairs_kept"] == info["half_pairs_tested"]
 
 
-def test_half_shell_heavy_cell_tiles(clm):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_half_shell_heavy_cell_tiles(clm, precision):
     """900 particles in one cell (tiles that split a cell, so the home row's
     first block starts inside a cell) among uniform ones."""
     H = np.diag([40.0, 40.0, 40.0])
@@ -114,32 +124,35 @@ def test_half_shell_heavy_cell_tiles(clm):
     x = np.concatenate([20.0 + 0.8 * g.random((900, 3)), W.uniform_in_box(3000, H, 4)])
     sigma, eps = 0.2, 0.01
     ref = oracle.compute(x, H, 3.0, lj=(sigma, eps), lj_grad=True, nl=True)
-    cl = clm.CellList(T(x), clm.Box(H, 3.0, 2), precision="fp32")
-    _check(cl.lj_forces(sigma, eps, virial=True, half=True), ref, x, sigma, eps)
+    cl = clm.CellList(T(x), clm.Box(H, 3.0, 2), precision=precision)
+    _check(cl.lj_forces(sigma, eps, virial=True, half=True), ref, x, sigma, eps, precision=precision)
 
 
-def test_half_shell_map_cutoff_and_adjoint(clm):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_half_shell_map_cutoff_and_adjoint(clm, precision):
     H, rc = BOXES["tric3"]
     x = _lattice(H, 6000, 12)
     sigma, eps = 1.1, 0.3
-    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp32")
+    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision=precision)
     rm = 0.7 * rc
     ref = oracle.compute(x, H, rm, lj=(sigma, eps), lj_grad=True, nl=True)
-    _check(cl.lj_forces(sigma, eps, virial=True, cutoff=rm, half=True), ref, x, sigma, eps)
+    _check(cl.lj_forces(sigma, eps, virial=True, cutoff=rm, half=True), ref, x, sigma, eps, precision=precision)
     g = torch.tensor([2.5], dtype=torch.float64, device="cuda:0")
     ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
     gx, gb, e = cl.lj_adjoint(sigma, eps, g, half=True)
     scale = _force_scale(ref, len(x), sigma, eps)
     err = np.linalg.norm(gx.cpu().numpy() - 2.5 * ref["lj_grad"], axis=1) / np.maximum(2.5 * scale, 1e-300)
-    assert err.max() <= 1e-5
-    assert np.abs(gb.cpu().numpy() - 2.5 * ref["dEdH"]).max() <= 1e-5 * 2.5 * np.abs(ref["dEdH"]).max()
+    tolF = TOL[precision][1]
+    assert err.max() <= tolF
+    assert np.abs(gb.cpu().numpy() - 2.5 * ref["dEdH"]).max() <= tolF * 2.5 * np.abs(ref["dEdH"]).max()
 
 
-def test_half_shell_equals_full_shell_and_repeats_bitwise(clm):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_half_shell_equals_full_shell_and_repeats_bitwise(clm, precision):
     H, rc = BOXES["skew3"]
     x = W.uniform_in_box(8000, H, 31)
     sigma, eps = 2.0, 0.2
-    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp32")
+    cl = clm.CellList(T(x), clm.Box(H, rc, 2), precision=precision)
     a = cl.lj_forces(sigma, eps, virial=True, half=True)
     b = cl.lj_forces(sigma, eps, virial=True, half=True)
     for k in ("energy", "forces", "grad_box", "virial", "count"):
@@ -147,8 +160,8 @@ def test_half_shell_equals_full_shell_and_repeats_bitwise(clm):
     f = cl.lj_forces(sigma, eps, virial=True, half=False)
     assert int(f["count"].item()) == int(a["count"].item())
     ref = oracle.compute(x, H, rc, lj=(sigma, eps), lj_grad=True, nl=True)
-    _check(a, ref, x, sigma, eps)
-    _check(f, ref, x, sigma, eps)
+    _check(a, ref, x, sigma, eps, precision=precision)
+    _check(f, ref, x, sigma, eps, precision=precision)
 
 
 def test_half_shell_scratch_errors(clm):
@@ -172,9 +185,12 @@ def test_half_shell_scratch_errors(clm):
     assert st == L.STATUS_CODES["CLM_E_WORKSPACE"]
     torch.cuda.synchronize()
     assert int(c.item()) == -1
-    # where the sweep does not apply (FP64 form) the scratch is 0 bytes
+    # the FP64 form keeps FP64 planes: twice the plane bytes; where the
+    # sweep does not apply (a cross set) the scratch is 0 bytes
     cl64 = clm.CellList(T(x), clm.Box(H, rc, 2), precision="fp64")
-    assert cl64._half_scratch("lj_ef", True) == (None, 0)
+    assert cl64._half_scratch("lj_ef", True)[1] > need
+    clx = clm.CellList(T(x), clm.Box(H, rc, 2), y=T(x[:100]), precision="fp32")
+    assert clx._half_scratch("lj_ef", True) == (None, 0)
 
 
 def test_automatic_choice_between_half_and_full_shell(clm):
