@@ -440,12 +440,17 @@ struct Half {
     const uint32_t r = ltail - lhead;
     if (r == 0u) return;
     bbase = lhead;
-    if (r > 32u)
+    if (r > 48u) {
       block<SELF, 64>(r, part_j, npad);
-    else if (r > 16u)
+    } else if (r > 32u) {  // 32 + 16 steps instead of 64
+      block<SELF, 32>(32u, part_j, npad);
+      bbase = lhead + 32u;
+      block<SELF, 16>(r - 32u, part_j, npad);
+    } else if (r > 16u) {
       block<SELF, 32>(r, part_j, npad);
-    else
+    } else {
       block<SELF, 16>(r, part_j, npad);
+    }
     lhead = ltail;
   }
 };
