@@ -874,7 +874,7 @@ static bool half_applies(const clm_celllist* cl, int k) {
 
 struct HalfLayout {
   int NR, nitems, ngather;
-  size_t npad, o_part, o_parts, o_pc, total;
+  size_t npad, o_part, o_parts, o_pc, o_boxes, total;
 };
 
 static HalfLayout half_layout(const clm_celllist* cl) {
@@ -888,6 +888,7 @@ static HalfLayout half_layout(const clm_celllist* cl) {
   L.o_part = c.take(esz * 2 * (size_t)L.NR * 3 * L.npad);
   L.o_parts = c.take(sizeof(double) * kPartialD * (size_t)(L.nitems + L.ngather));
   L.o_pc = c.take(sizeof(unsigned long long) * (size_t)(L.nitems + L.ngather));
+  L.o_boxes = c.take(sizeof(double) * 6 * (size_t)std::max<int64_t>(cl->max_tiles, 1));
   L.total = c.off;
   return L;
 }
@@ -967,6 +968,7 @@ static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_m
     A.pcount = (unsigned long long*)(base + HL.o_pc);
     A.row_off = cl->row_off;
     A.tiles = cl->tiles;
+    A.boxes = (double*)(base + HL.o_boxes);
     A.max_tiles = cl->max_tiles;
     A.nitems = HL.nitems;
     A.NR = HL.NR;
@@ -977,6 +979,7 @@ static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_m
     s = ts.start();
     if (s != CLM_OK) return s;
     const bool fp64 = cl->prec == CLM_FP64;
+    CLM_HIP(launch_half_boxes(cl->job_dev, A, st));
     CLM_HIP(launch_half_lj(B.dim, k_launch == K_LJ_FV, fp64, cl->job_dev, A, st));
     s = ts.stop();
     if (s != CLM_OK) return s;

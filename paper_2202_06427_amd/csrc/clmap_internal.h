@@ -225,7 +225,8 @@ struct HalfArgs {
   unsigned long long* pcount;  // nitems + gather blocks
   const uint32_t* row_off;     // tiles of row h: [row_off[h], row_off[h + 1])
   const Tile* tiles;
-  int max_tiles;               // entries of tiles
+  double* boxes;               // per tile: bounding box of its wrapped positions (lo xyz, hi xyz)
+  int max_tiles;               // entries of tiles (and boxes)
   int nitems, NR;
 };
 // Half-shell row offsets including the home row: 2 l^2 + 2 l + 1 in 3D, l + 1 in 2D.
@@ -412,6 +413,7 @@ hipError_t launch_brute(const JobDesc* jobs, const BruteArgs& A, double* FB, int
                         hipStream_t s);
 hipError_t launch_half_lj(int dim, bool virial, bool fp64, const JobDesc* jobs, const HalfArgs& A,
                           hipStream_t s);
+hipError_t launch_half_boxes(const JobDesc* jobs, const HalfArgs& A, hipStream_t s);
 hipError_t launch_half_gather(int dim, bool fp64, const JobDesc* jobs, const HalfArgs& A, int n,
                               hipStream_t s);
 hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, double* scratch,

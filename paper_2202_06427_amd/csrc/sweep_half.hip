@@ -490,14 +490,15 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& 
     {
       const double4 r = J->r64_x[i];
       const double ri[3] = {r.x, r.y, r.z};
-      // the tile's bounding box (inactive lanes repeat the last particle);
-      // its centre is the origin of the FP32 coordinates
+      // the tile's bounding box (half_boxes_kernel); its centre is the
+      // origin of the sweep's coordinates
 #pragma unroll
       for (int a = 0; a < 3; ++a) S.O[a] = 0.0;
+      const double* bx = A.boxes + (size_t)ti * 6;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        bl[a] = wave_min_d(ri[a]);
-        bh[a] = wave_max_d(ri[a]);
+        bl[a] = ldu(&bx[a]);
+        bh[a] = ldu(&bx[3 + a]);
         S.O[a] = 0.5 * (bl[a] + bh[a]);
       }
       S.xi[0] = active ? (T)((ri[0] - S.O[0]) * S.inv_sig) : T(1e18);
@@ -688,6 +689,36 @@ half_lj64_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   __shared__ double sGA[kWave * 3];
   __shared__ double sGJ[kWave * 3];
   half_lj_body<DIM, VIR, double>(jobs, A, sQ, sL, sGA, sGJ);
+}
+
+// Bounding box of every tile's wrapped positions (one wave per tile; the
+// sweep reads it once per (tile, neighbour row) instead of reducing it).
+__global__ void __launch_bounds__(256) half_boxes_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
+  const JobDesc* J = &jobs[0];
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int t = (int)(blockIdx.x * 4 + threadIdx.x / kWave);
+  const int ntiles = min((int)ldu(&A.row_off[A.nitems / A.NR]), A.max_tiles);
+  if (t >= ntiles) return;
+  const Tile tl = A.tiles[t];
+  const int count = tl.count;
+  const uint32_t i = tl.start + (uint32_t)(lane < count ? lane : count - 1);
+  const double4 r = J->r64_x[i];
+  const double ri[3] = {r.x, r.y, r.z};
+  double* bx = A.boxes + (size_t)t * 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double lo = wave_min_d(ri[a]), hi = wave_max_d(ri[a]);
+    if (lane == 0) {
+      bx[a] = lo;
+      bx[3 + a] = hi;
+    }
+  }
+}
+
+hipError_t launch_half_boxes(const JobDesc* jobs, const HalfArgs& A, hipStream_t s) {
+  const unsigned nb = (unsigned)((A.max_tiles + 3) / 4);
+  if (nb > 0) half_boxes_kernel<<<nb, 256, 0, s>>>(jobs, A);
+  return hipGetLastError();
 }
 
 // Sum of the 2 NR planes of each particle (fixed order), forces in original
