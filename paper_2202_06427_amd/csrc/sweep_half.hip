@@ -375,7 +375,9 @@ struct Half {
     // phases: the candidates rotate by 16 lanes inside each JW-lane group
     int jtag = (lane & (JW - 1)) << 6;
     const int src = ((lane & ~(JW - 1)) | ((lane + 16) & (JW - 1))) << 2;
-#pragma unroll
+    // not unrolled: one copy of the 16 steps per block shape keeps the
+    // kernel's code small for the instruction cache
+#pragma unroll 1
     for (int g = 0; g < JW / 16; ++g) {
       phase<SELF, JW>(jtag);
       if constexpr (JW > 16) {
