@@ -893,6 +893,57 @@ static HalfLayout half_layout(const clm_celllist* cl) {
   return L;
 }
 
+// Launch order of the half-shell row offsets, by the distance between the
+// cross-sections (perpendicular to the rows) of the home row's cell and the
+// neighbour row's: the closest rows hold the most candidates within the
+// cutoff of a tile, so their items start first.  The home row (about half of
+// an adjacent row's work) comes after the adjacent rows.
+static void half_rho_order(const clm_box& B, int NR, uint8_t* order) {
+  const int dim = B.dim, l = B.lcell;
+  std::vector<double> key(NR, 0.0);
+  // the lattice vectors a1 (along the rows), a2 / ny, a3 / nz
+  double a1[3], u[3], v[3];
+  for (int r = 0; r < 3; ++r) {
+    a1[r] = B.H[r * 3 + 0];
+    u[r] = dim > 1 ? B.H[r * 3 + 1] / B.n[1] : 0.0;
+    v[r] = dim > 2 ? B.H[r * 3 + 2] / B.n[2] : 0.0;
+  }
+  const double a1n = std::sqrt(a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]);
+  auto perp = [&](const double* p, double* q) {  // component perpendicular to a1
+    const double t = (p[0] * a1[0] + p[1] * a1[1] + p[2] * a1[2]) / (a1n * a1n);
+    for (int r = 0; r < 3; ++r) q[r] = p[r] - t * a1[r];
+  };
+  double pu[3], pv[3];
+  perp(u, pu);
+  perp(v, pv);
+  auto norm = [](const double* p) { return std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]); };
+  for (int rho = 1; rho < NR; ++rho) {
+    int dy, dz;
+    if (rho <= l) { dy = rho; dz = 0; }
+    else { const int q = rho - l - 1; dz = 1 + q / (2 * l + 1); dy = q % (2 * l + 1) - l; }
+    // distance from 0 to {(dy + s) pu + (dz + t) pv : |s|, |t| <= 1}: the
+    // smallest over a grid of the parallelogram's points (close enough for
+    // an ordering)
+    double best = 1e300;
+    for (int i = 0; i <= 32; ++i)
+      for (int j = 0; j <= (dim > 2 ? 32 : 0); ++j) {
+        const double s = dy - 1.0 + i / 16.0, t = dim > 2 ? dz - 1.0 + j / 16.0 : 0.0;
+        double p[3];
+        for (int r = 0; r < 3; ++r) p[r] = s * pu[r] + t * pv[r];
+        best = std::min(best, norm(p));
+      }
+    key[rho] = best;
+  }
+  std::vector<int> ix(NR);
+  for (int r = 0; r < NR; ++r) ix[r] = r;
+  // home row: after every row at distance 0
+  std::stable_sort(ix.begin(), ix.end(), [&](int a, int b) {
+    const double ka = a == 0 ? 1e-300 : key[a], kb = b == 0 ? 1e-300 : key[b];
+    return ka < kb;
+  });
+  for (int r = 0; r < NR; ++r) order[r] = (uint8_t)ix[r];
+}
+
 clm_status clm_map_scratch_bytes(const clm_celllist* cl, clm_map_kind kind, size_t* bytes) {
   if (!cl || !bytes) return fail(CLM_E_INVALID_ARG, "NULL argument");
   const int k = internal_kind(kind);
@@ -972,6 +1023,7 @@ static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_m
     A.max_tiles = cl->max_tiles;
     A.nitems = HL.nitems;
     A.NR = HL.NR;
+    half_rho_order(B, HL.NR, A.rho_order);
     jd.partials = A.partials;  // the finalize reads the item and gather partials
     jd.pcount = A.pcount;
     CLM_HIP(launch_set_job(jd, cl->job_dev, st));

@@ -218,6 +218,11 @@ inline int sweep_split_rows(int kind, int dim, int lcell, bool full) {
 // half-shell row offset) item; FP32 force planes indexed by sorted slot,
 // 2 NR planes of 3 components (stride npad floats): plane 2 rho holds the
 // i-side sums of offset rho, plane 2 rho + 1 the j-side sums.
+// Half-shell row offsets including the home row: 2 l^2 + 2 l + 1 in 3D, l + 1 in 2D.
+__host__ __device__ inline constexpr int half_rows(int dim, int l) { return dim == 3 ? 2 * l * l + 2 * l + 1 : l + 1; }
+constexpr int kMaxHalfRows = 152;  // >= half_rows(3, 8), the largest lcell
+static_assert(half_rows(3, 8) <= kMaxHalfRows, "row-offset order table too small");
+
 struct HalfArgs {
   void* part;                  // 2 NR force planes of 3 components (float, or double in the FP64 form)
   size_t npad;
@@ -228,9 +233,10 @@ struct HalfArgs {
   double* boxes;               // per tile: bounding box of its wrapped positions (lo xyz, hi xyz)
   int max_tiles;               // entries of tiles (and boxes)
   int nitems, NR;
+  // launch order of the row offsets: rho_order[k] is the k-th (most
+  // candidates first); items of one rank are launched before the next's
+  uint8_t rho_order[kMaxHalfRows];
 };
-// Half-shell row offsets including the home row: 2 l^2 + 2 l + 1 in 3D, l + 1 in 2D.
-__host__ __device__ inline int half_rows(int dim, int l) { return dim == 3 ? 2 * l * l + 2 * l + 1 : l + 1; }
 
 struct FinalArgs {
   int nparts;                      // used when nparts_dev is NULL

@@ -52,7 +52,7 @@ namespace clm {
 
 namespace {
 
-constexpr int kHQCap = 512;   // FP64 re-evaluation queue (power of two, >= 63 + 4 * 64)
+constexpr int kHQCap = 320;   // FP64 re-evaluation queue (>= 63 + 4 * 64 entries)
 constexpr int kHLCap = 128;   // packed candidate list (power of two, >= 63 + 64)
 constexpr uint32_t kCenter = 13u;  // image code of K = (0, 0, 0)
 
@@ -184,7 +184,7 @@ struct Half {
   double* GA;              // [64][3] FP64 i-side sums of queued pairs
   double* GJ;              // [64][3] FP64 sums of f D (i -> j) of queued pairs, by candidate
   uint2* LST;              // packed candidates (sorted index, image code)
-  uint32_t qhead, qtail;
+  uint32_t qtail;          // queued entries: Q[0 .. qtail)
   uint32_t lhead, ltail;
   uint32_t tstart;
   uint32_t bbase;          // list position of the block's first candidate
@@ -236,13 +236,13 @@ struct Half {
   }
 
   __device__ __forceinline__ void drain(bool all) {
-    uint32_t h = (uint32_t)uniform((int)qhead);
+    uint32_t h = 0;
     const uint32_t tl = (uint32_t)uniform((int)qtail);
     while (tl - h >= (uint32_t)kWave || (all && tl != h)) {
       const uint32_t nb = min(tl - h, (uint32_t)kWave);
       bool band_in = false;
       if ((uint32_t)lane < nb) {
-        const uint32_t e = Q[(h + (uint32_t)lane) & (uint32_t)(kHQCap - 1)];
+        const uint32_t e = Q[h + (uint32_t)lane];
         bool in = false;
         process(e, &in);
         const bool band = (e >> 31) != 0u;  // above lo in FP32: FP64 decides and counts
@@ -253,7 +253,16 @@ struct Half {
       cnt += (unsigned long long)__popcll(__builtin_amdgcn_ballot_w64(band_in));
       h = (uint32_t)uniform((int)(h + nb));
     }
-    qhead = h;
+    // what is left (fewer than 64 entries) moves to the front
+    const uint32_t left = tl - h;
+    if (h != 0u && left != 0u) {
+      uint32_t e = 0u;
+      if ((uint32_t)lane < left) e = Q[h + (uint32_t)lane];
+      __builtin_amdgcn_wave_barrier();
+      if ((uint32_t)lane < left) Q[lane] = e;
+      __builtin_amdgcn_wave_barrier();
+    }
+    qtail = left;
   }
 
   // ---------------------------------------------------------------- one step
@@ -309,16 +318,12 @@ struct Half {
       // entry: i lane | candidate << 6 | band << 31 (jtag rotates with the
       // candidates; the DPP read happens with every lane active: a source
       // lane outside exec would read as 0)
-      const uint32_t jt = (uint32_t)row_ror_i<K>(jtag);
-      const uint32_t t0 = (uint32_t)uniform((int)qtail);
-      if (__builtin_amdgcn_inverse_ballot_w64(spec)) {
-        const uint32_t slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(spec >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)spec, t0));
-        const uint32_t me = __builtin_amdgcn_inverse_ballot_w64(band) ? ((uint32_t)lane | 0x80000000u)
-                                                                      : (uint32_t)lane;
-        Q[slot & (uint32_t)(kHQCap - 1)] = jt | me;
-      }
-      qtail = (uint32_t)uniform((int)(t0 + (uint32_t)__popcll(spec)));
+      uint32_t ent = (uint32_t)row_ror_i<K>(jtag) | (uint32_t)lane;
+      if (band) ent = __builtin_amdgcn_inverse_ballot_w64(band) ? (ent | 0x80000000u) : ent;  // rare
+      const uint32_t t0 = qtail;
+      // byte offset of the lane's slot in the ring
+      if (__builtin_amdgcn_inverse_ballot_w64(spec)) Q[(uint32_t)lane_rank(spec) + t0] = ent;
+      qtail = t0 + (uint32_t)__popcll(spec);
     }
   }
 
@@ -327,13 +332,13 @@ struct Half {
   template <bool SELF, int JW>
   __device__ __forceinline__ void phase(int jtag) {
     step<0, SELF, JW>(jtag); step<1, SELF, JW>(jtag); step<2, SELF, JW>(jtag); step<3, SELF, JW>(jtag);
-    if (qtail - qhead >= (uint32_t)kWave) drain(false);
+    if (qtail >= (uint32_t)kWave) drain(false);
     step<4, SELF, JW>(jtag); step<5, SELF, JW>(jtag); step<6, SELF, JW>(jtag); step<7, SELF, JW>(jtag);
-    if (qtail - qhead >= (uint32_t)kWave) drain(false);
+    if (qtail >= (uint32_t)kWave) drain(false);
     step<8, SELF, JW>(jtag); step<9, SELF, JW>(jtag); step<10, SELF, JW>(jtag); step<11, SELF, JW>(jtag);
-    if (qtail - qhead >= (uint32_t)kWave) drain(false);
+    if (qtail >= (uint32_t)kWave) drain(false);
     step<12, SELF, JW>(jtag); step<13, SELF, JW>(jtag); step<14, SELF, JW>(jtag); step<15, SELF, JW>(jtag);
-    if (qtail - qhead >= (uint32_t)kWave) drain(false);
+    if (qtail >= (uint32_t)kWave) drain(false);
   }
 
   // One block of the nb (1..JW) candidates at list positions bbase..;
@@ -571,17 +576,24 @@ template <int DIM, bool VIR, typename T>
 __device__ __forceinline__ void half_lj_body(const JobDesc* __restrict__ jobs, const HalfArgs& A,
                                              uint32_t* sQ, uint2* sL, double* sGA, double* sGJ) {
   const int lane = (int)__lane_id();
-  const int nitems = A.nitems;
-  int b = blockIdx.x;
-  if (b >= nitems) return;
-  if (nitems >= 8) {  // each XCD takes a contiguous range of items (neighbouring rows share L2)
-    const int per = nitems / 8, rem = nitems % 8;
-    const int xcd = b % 8, k = b / 8;
-    b = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k;
-  }
-  const int item = uniform(b);
   const int NR = A.NR;
-  const int h = item / NR, rho = item - (item / NR) * NR;
+  const int nrows = A.nitems / NR;
+  // Launch order: each XCD (block index mod 8) takes a contiguous range of
+  // rows (neighbouring rows share its L2) and runs its items rank by rank of
+  // the row-offset order, the offsets with the most candidates first, so
+  // that the cheapest items end the launch.
+  int r0 = 0, nr = nrows, k = (int)blockIdx.x;
+  if (nrows >= 8) {
+    const int x = k & 7;
+    r0 = (x * nrows) >> 3;
+    nr = (((x + 1) * nrows) >> 3) - r0;
+    k >>= 3;
+  }
+  if (k >= nr * NR) return;
+  const int rank = k / nr;
+  const int h = uniform(r0 + (k - rank * nr));
+  const int rho = uniform((int)A.rho_order[rank]);
+  const int item = h * NR + rho;
   const JobDesc* J = &jobs[0];
 
   Half<DIM, VIR, T> S;
@@ -605,7 +617,6 @@ __device__ __forceinline__ void half_lj_body(const JobDesc* __restrict__ jobs, c
   S.cnt = 0;
   S.ntested = 0;
   S.nkept = 0;
-  S.qhead = 0;
   S.qtail = 0;
   S.key = 0x7fffffff;
 
@@ -775,7 +786,9 @@ __global__ void __launch_bounds__(256) half_gather_kernel(const JobDesc* __restr
 hipError_t launch_half_lj(int dim, bool virial, bool fp64, const JobDesc* jobs, const HalfArgs& A,
                           hipStream_t s) {
   if (A.nitems > 0) {
-    const unsigned g = (unsigned)A.nitems;
+    // blocks beyond an XCD's rows return at once (half_lj_body)
+    const int nrows = A.nitems / A.NR;
+    const unsigned g = nrows >= 8 ? (unsigned)(8 * ((nrows + 7) / 8) * A.NR) : (unsigned)A.nitems;
     if (fp64) {
       if (dim == 3)
         virial ? half_lj64_kernel<3, true><<<g, 64, 0, s>>>(jobs, A) : half_lj64_kernel<3, false><<<g, 64, 0, s>>>(jobs, A);
