@@ -885,10 +885,10 @@ static HalfLayout half_layout(const clm_celllist* cl) {
   L.npad = (size_t)((cl->nx + 63) / 64) * 64;
   Carve c;
   const size_t esz = cl->prec == CLM_FP64 ? sizeof(double) : sizeof(float);
-  L.o_part = c.take(esz * 2 * (size_t)L.NR * 3 * L.npad);
+  L.o_part = c.take(esz * 3 * (size_t)L.NR * 3 * L.npad);
   L.o_parts = c.take(sizeof(double) * kPartialD * (size_t)(L.nitems + L.ngather));
   L.o_pc = c.take(sizeof(unsigned long long) * (size_t)(L.nitems + L.ngather));
-  L.o_boxes = c.take(sizeof(double) * 6 * (size_t)std::max<int64_t>(cl->max_tiles, 1));
+  L.o_boxes = c.take(sizeof(double) * 12 * (size_t)std::max<int64_t>(cl->max_tiles, 1));
   L.total = c.off;
   return L;
 }

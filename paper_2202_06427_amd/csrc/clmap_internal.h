@@ -224,13 +224,14 @@ constexpr int kMaxHalfRows = 152;  // >= half_rows(3, 8), the largest lcell
 static_assert(half_rows(3, 8) <= kMaxHalfRows, "row-offset order table too small");
 
 struct HalfArgs {
-  void* part;                  // 2 NR force planes of 3 components (float, or double in the FP64 form)
+  void* part;                  // 3 NR force planes of 3 components (float, or double in the FP64 form)
   size_t npad;
   double* partials;            // nitems + gather blocks, kPartialD each
   unsigned long long* pcount;  // nitems + gather blocks
   const uint32_t* row_off;     // tiles of row h: [row_off[h], row_off[h + 1])
   const Tile* tiles;
-  double* boxes;               // per tile: bounding box of its wrapped positions (lo xyz, hi xyz)
+  double* boxes;               // per tile: bounding boxes of its two 32-particle halves' wrapped
+                               // positions (lo xyz, hi xyz of half A, then of half B)
   int max_tiles;               // entries of tiles (and boxes)
   int nitems, NR;
   // launch order of the row offsets: rho_order[k] is the k-th (most

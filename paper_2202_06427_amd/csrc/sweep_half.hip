@@ -10,36 +10,39 @@
 // (dz, dy) > (0, 0).  One wavefront runs one item: for each tile of row h
 // (<= 64 consecutive sorted particles, one per lane) it scans the tile's
 // reach in row r = h + offset(rho) (one to three pieces of consecutive
-// cells, with their periodic images) and keeps the particles whose distance
-// to the tile's bounding box is within the cutoff (the paper's section 2.8
-// pruning of candidates by their position, applied to the whole tile).  The
-// kept candidates are packed, in order, into blocks of 64 (the last one of
-// 16, 32 or 64).
+// cells, with their periodic images).  The tile's two halves (lanes 0..31:
+// its first 32 particles; lanes 32..63: the others) keep separate candidate
+// lists: a candidate enters a half's list when its distance to that half's
+// bounding box is within the cutoff (the paper's section 2.8 pruning of
+// candidates by their position, applied to 32 particles at a time).
 //
-// A block is a 64 x JW set of pairs visited in JW steps: the JW candidates
-// sit in the lanes (JW < 64: 64 / JW copies), and in step (phase g, k) lane
-// l pairs its i with the candidate that a DPP row rotation by k brings from
-// its 16-lane row (the candidates rotate by 16 lanes inside each JW-lane
-// group between phases).  The rotation is folded into the subtractions
-// (v_sub_f32 with a DPP source) and the candidate-side force term goes back
-// through the inverse rotation folded into an add: a step is 26 VALU
-// instructions (one of them a quarter-rate reciprocal) for 64 pairs.
-// Coordinates are in units of sigma, so x = sigma^2 / d^2 is one reciprocal.
+// A block pairs up to 32 candidates of each list with its half in 32 steps
+// (JW = 32; when neither list has more than 16 left, 16 steps with the 16
+// candidates in both rows of the half).  In step (phase g, k) lane l pairs
+// its i with the candidate that a DPP row rotation by k brings from its
+// 16-lane row; between the two phases the candidates move by 16 lanes inside
+// their half.  The rotation is folded into the subtractions (v_sub_f32 with
+// a DPP source) and the candidate-side force term goes back through the
+// inverse rotation folded into an add: a step is 26 VALU instructions (one
+// of them a quarter-rate reciprocal) for 64 pairs.  Coordinates are in units
+// of sigma, so x = sigma^2 / d^2 is one reciprocal.
 //
 // Force sums: per lane, the i-side FP32 sum of a block is folded into FP64;
 // the candidate-side FP32 sum of a block (the copies added) is added (FP64
 // arithmetic, one FP32 rounding) into a FP32 plane slot owned by this item
-// alone:
-//     plane 2 rho     : i-side sums of item (row(i), rho)
-//     plane 2 rho + 1 : j-side sums of item (row(j) - offset(rho), rho)
-// Both are indexed by sorted index, so every slot has exactly one writer; a
-// gather kernel sums the 2 NR planes of each particle in FP64 in a fixed
+// and half alone:
+//     plane 3 rho     : i-side sums of item (row(i), rho)
+//     plane 3 rho + 1 : j-side sums of half A of item (row(j) - offset(rho), rho)
+//     plane 3 rho + 2 : the same for half B
+// All are indexed by sorted index, so every slot has exactly one writer; a
+// gather kernel sums the 3 NR planes of each particle in FP64 in a fixed
 // order.
 //
-// FP32 coordinates: relative to the centre O of the tile's bounding box,
-// x_i = fl32((r'_i - O) / sigma) and x_j = fl32((r'_j + t - O) / sigma),
-// computed in FP64.  |x_i,a| <= C_a, half the tile's extent (at most span
-// cells along x, one cell across), and |x_j,a| <= C_a + |D_a|, so
+// FP32 coordinates: relative to the centre O of the bounding box of the
+// lane's half of the tile, x_i = fl32((r'_i - O) / sigma) and
+// x_j = fl32((r'_j + t - O) / sigma), computed in FP64.  |x_i,a| <= C_a,
+// half that box's extent (at most the tile's: span cells along x, one cell
+// across), and |x_j,a| <= C_a + |D_a|, so
 // |D32_a - D_a| <= u (2 C_a + 2 |D_a|) + FP64 roundings (in sigma units):
 // the steep pairs (|D| near sigma) keep small errors when the tile is
 // compact.  The membership band comes from that bound per tile span (host
@@ -124,17 +127,6 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 __device__ __forceinline__ float rcp_t(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double rcp_t(double v) { return rcp64(v); }
 
-__device__ __forceinline__ double wave_min_d(double v) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v = fmin(v, __shfl_xor(v, d, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_max_d(double v) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
-  return v;
-}
-
 // (dy, dz) of half-shell row offset rho: 0 -> home row; then (0, 1..l);
 // then dz = 1..l with dy = -l..l.  2D: dz = 0, dy = 0..l.
 __device__ __forceinline__ void row_offset(int l, int rho, int* dy, int* dz) {
@@ -161,9 +153,11 @@ struct Half {
   double rc2, s2, inv_sig;
   T near2f;                // (near_factor)^2: sigma units
   T lo, hi;                // membership thresholds on d^2 / sigma^2
+  // the tile's two halves (lanes 0..31 and 32..63): origins of the sweep's
+  // coordinates, the centres of their bounding boxes (uniform)
+  double OA[3], OB[3];
   // per lane (i side, fixed for a tile)
-  double O[3];             // origin of the sweep's coordinates: centre of the tile's bounding box
-  T xi[3];                 // relative to O, sigma units
+  T xi[3];                 // relative to the origin of the lane's half, sigma units
   double Fi[3];
   // per lane accumulators of the item
   double E64;
@@ -183,18 +177,18 @@ struct Half {
   uint32_t* Q;             // queue of FP64 re-evaluations: i lane | candidate << 6 | band << 31
   double* GA;              // [64][3] FP64 i-side sums of queued pairs
   double* GJ;              // [64][3] FP64 sums of f D (i -> j) of queued pairs, by candidate
-  uint2* LST;              // packed candidates (sorted index, image code)
+  uint2* LST;              // packed candidates (sorted index, image code): list A, then list B
+  uint2* BC;               // [64] the current block's candidates by slot
   uint32_t qtail;          // queued entries: Q[0 .. qtail)
-  uint32_t lhead, ltail;
+  uint32_t lhA, ltA, lhB, ltB;  // ring positions of lists A and B
   uint32_t tstart;
-  uint32_t bbase;          // list position of the block's first candidate
 
   // ---------------------------------------------------------------- FP64 queue
-  // Canonical FP64 evaluation of one queued pair (i lane il, candidate jm of
-  // the current block).
+  // Canonical FP64 evaluation of one queued pair (i lane il, candidate slot
+  // jm of the current block).
   __device__ __forceinline__ void process(uint32_t e, bool* in_out) {
     const int il = (int)(e & 63u), jm = (int)((e >> 6) & 63u);
-    const uint2 c = LST[(bbase + (uint32_t)jm) & (uint32_t)(kHLCap - 1)];
+    const uint2 c = BC[jm];
     const double4 rI = J->r64_x[tstart + (uint32_t)il];
     const double4 rJ = J->r64_x[c.x];
     const double* tk = &J->tK[c.y * 4];
@@ -341,35 +335,44 @@ struct Half {
     if (qtail >= (uint32_t)kWave) drain(false);
   }
 
-  // One block of the nb (1..JW) candidates at list positions bbase..;
-  // part_j: this item's j-side plane (3 components, stride npad).
+  // One block: nA (0..JW) candidates of list A from ring position bA for the
+  // lanes 0..31 (the tile's first 32 particles) and nB of list B from bB for
+  // the lanes 32..63 (the others).  JW = 32: a candidate per lane, rotating
+  // by 16 lanes inside its half between the two phases; JW = 16: the 16
+  // candidates of a half sit in both of its rows (two copies).  A candidate's
+  // slot is its lane (JW = 32) or its lane in the half's first row (JW = 16).
+  // pjA / pjB: this item's j-side planes of the two halves.
   template <bool SELF, int JW>
-  __device__ __forceinline__ void block(uint32_t nb, T* part_j, size_t npad) {
+  __device__ __forceinline__ void block(uint32_t nA, uint32_t bA, uint32_t nB, uint32_t bB, T* pjA, T* pjB,
+                                        size_t npad) {
+    const bool hb = lane >= 32;  // lane in half B
     const int m = lane & (JW - 1);
-    const bool jv = (uint32_t)m < nb;
-    const uint2 c = jv ? LST[(bbase + (uint32_t)m) & (uint32_t)(kHLCap - 1)] : make_uint2(0u, kCenter);
+    const bool jv = (uint32_t)m < (hb ? nB : nA);
+    const bool canon = JW == 32 || (lane & 16) == 0;  // the lane that owns the candidate's sums
+    const int slot = JW == 32 ? lane : ((lane & 15) | (lane & 32));
+    const uint32_t pos = ((hb ? bB : bA) + (uint32_t)m) & (uint32_t)(kHLCap - 1);
+    const uint2 c = jv ? LST[(hb ? kHLCap : 0) + pos] : make_uint2(0u, kCenter);
+    T* pj = hb ? pjB : pjA;
     const double* tK = J->tK;
     {
       const double4 r = jv ? J->r64_x[c.x] : make_double4(0.0, 0.0, 0.0, 0.0);
       const double* t = &tK[c.y * 4];
-      xj[0] = jv ? (T)(((r.x + t[0]) - O[0]) * inv_sig) : T(-1e18);
-      xj[1] = jv ? (T)(((r.y + t[1]) - O[1]) * inv_sig) : T(-1e18);
-      xj[2] = DIM == 3 ? (jv ? (T)(((r.z + t[2]) - O[2]) * inv_sig) : T(-1e18)) : T(0);
+      xj[0] = jv ? (T)(((r.x + t[0]) - (hb ? OB[0] : OA[0])) * inv_sig) : T(-1e18);
+      xj[1] = jv ? (T)(((r.y + t[1]) - (hb ? OB[1] : OA[1])) * inv_sig) : T(-1e18);
+      xj[2] = DIM == 3 ? (jv ? (T)(((r.z + t[2]) - (hb ? OB[2] : OA[2])) * inv_sig) : T(-1e18)) : T(0);
     }
     if constexpr (SELF) key = (jv && c.y == kCenter) ? (int)c.x : 0x7fffffff;
     T jold[3] = {T(0), T(0), T(0)};
-    if (jv && lane < JW) {
+    if (jv && canon) {
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) jold[a] = part_j[(size_t)a * npad + c.x];
+      for (int a = 0; a < DIM; ++a) jold[a] = pj[(size_t)a * npad + c.x];
     }
+    if (canon) BC[slot] = c;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       acc[a] = T(0);
       fi32[a] = T(0);
-    }
-    if (lane < JW) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) GJ[lane * 3 + a] = 0.0;
+      GJ[lane * 3 + a] = 0.0;
     }
     e32 = T(0);
     if constexpr (VIR) {
@@ -377,31 +380,22 @@ struct Half {
       for (int k = 0; k < 6; ++k) w32[k] = T(0);
     }
     __builtin_amdgcn_wave_barrier();
-    // phases: the candidates rotate by 16 lanes inside each JW-lane group
-    int jtag = (lane & (JW - 1)) << 6;
-    const int src = ((lane & ~(JW - 1)) | ((lane + 16) & (JW - 1))) << 2;
-    // not unrolled: one copy of the 16 steps per block shape keeps the
-    // kernel's code small for the instruction cache
-#pragma unroll 1
-    for (int g = 0; g < JW / 16; ++g) {
+    int jtag = slot << 6;
+    if constexpr (JW == 32) {
+      const int src = ((lane & 32) | ((lane + 16) & 31)) << 2;  // 16 lanes on inside the half
       phase<SELF, JW>(jtag);
-      if constexpr (JW > 16) {
-        if (g + 1 < JW / 16) {
 #pragma unroll
-          for (int a = 0; a < DIM; ++a) xj[a] = shfl_f(xj[a], src);
-          if constexpr (SELF) key = __builtin_amdgcn_ds_bpermute(src, key);
-        }
+      for (int a = 0; a < DIM; ++a) xj[a] = shfl_f(xj[a], src);
+      if constexpr (SELF) key = __builtin_amdgcn_ds_bpermute(src, key);
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) acc[a] = shfl_f(acc[a], src);  // back in place after the last
-        jtag = __builtin_amdgcn_ds_bpermute(src, jtag);
-      }
-    }
-    // the 64 / JW copies of each candidate's sums
-    if constexpr (JW <= 32) {
+      for (int a = 0; a < DIM; ++a) acc[a] = shfl_f(acc[a], src);
+      jtag = __builtin_amdgcn_ds_bpermute(src, jtag);
+      phase<SELF, JW>(jtag);
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) acc[a] += shfl_f(acc[a], (lane ^ 32) << 2);
-    }
-    if constexpr (JW <= 16) {
+      for (int a = 0; a < DIM; ++a) acc[a] = shfl_f(acc[a], src);  // back in place
+    } else {
+      phase<SELF, JW>(jtag);
+      // the two copies of each candidate's sums
 #pragma unroll
       for (int a = 0; a < DIM; ++a) acc[a] += shfl_f(acc[a], (lane ^ 16) << 2);
     }
@@ -416,12 +410,12 @@ struct Half {
 #pragma unroll
       for (int k = 0; k < 6; ++k) W[k] += (double)w32[k];
     }
-    if (jv && lane < JW) {
+    if (jv && canon) {
       double S[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        S[a] = (double)acc[a] * inv_sig + GJ[lane * 3 + a];
-        part_j[(size_t)a * npad + c.x] = (T)((double)jold[a] - S[a]);
+        S[a] = (double)acc[a] * inv_sig + GJ[slot * 3 + a];
+        pj[(size_t)a * npad + c.x] = (T)((double)jold[a] - S[a]);
       }
       if (c.y != kCenter) {  // a periodic image: the box-gradient term S p^T
         const int p[3] = {(int)(c.y % 3u) - 1, (int)((c.y / 3u) % 3u) - 1, (int)(c.y / 9u) - 1};
@@ -433,38 +427,45 @@ struct Half {
     }
   }
 
+  // Blocks while both lists hold 32 candidates or one holds 64: afterwards
+  // each holds fewer than 64, so the next scan (at most 64 more per list)
+  // stays within the ring.
   template <bool SELF>
-  __device__ __forceinline__ void run_full(T* part_j, size_t npad) {
-    while (ltail - lhead >= (uint32_t)kWave) {
-      bbase = lhead;
-      block<SELF, 64>(64u, part_j, npad);
-      lhead += (uint32_t)kWave;
+  __device__ __forceinline__ void run_full(T* pjA, T* pjB, size_t npad) {
+    for (;;) {
+      const uint32_t a = ltA - lhA, b = ltB - lhB;
+      if (!((a >= 32u && b >= 32u) || a >= 64u || b >= 64u)) break;
+      const uint32_t nA = min(a, 32u), nB = min(b, 32u);
+      block<SELF, 32>(nA, lhA, nB, lhB, pjA, pjB, npad);
+      lhA += nA;
+      lhB += nB;
     }
   }
 
+  // The rest of both lists at the end of a tile: blocks of 32, the last one
+  // of 16 when neither list has more than 16 left.
   template <bool SELF>
-  __device__ __forceinline__ void run_tail(T* part_j, size_t npad) {
-    const uint32_t r = ltail - lhead;
-    if (r == 0u) return;
-    bbase = lhead;
-    if (r > 48u) {
-      block<SELF, 64>(r, part_j, npad);
-    } else if (r > 32u) {  // 32 + 16 steps instead of 64
-      block<SELF, 32>(32u, part_j, npad);
-      bbase = lhead + 32u;
-      block<SELF, 16>(r - 32u, part_j, npad);
-    } else if (r > 16u) {
-      block<SELF, 32>(r, part_j, npad);
-    } else {
-      block<SELF, 16>(r, part_j, npad);
+  __device__ __forceinline__ void run_tail(T* pjA, T* pjB, size_t npad) {
+    for (;;) {
+      const uint32_t a = ltA - lhA, b = ltB - lhB;
+      if (a == 0u && b == 0u) break;
+      if (a > 16u || b > 16u) {
+        const uint32_t nA = min(a, 32u), nB = min(b, 32u);
+        block<SELF, 32>(nA, lhA, nB, lhB, pjA, pjB, npad);
+        lhA += nA;
+        lhB += nB;
+      } else {
+        block<SELF, 16>(a, lhA, b, lhB, pjA, pjB, npad);
+        lhA += a;
+        lhB += b;
+      }
     }
-    lhead = ltail;
   }
 };
 
 template <int DIM, bool VIR, typename T, bool SELF>
 __device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& A, int h, int py, int pz,
-                                          int rbase, T* part_i, T* part_j) {
+                                          int rbase, T* part_i, T* pjA, T* pjB) {
   const JobDesc* J = S.J;
   const int lane = S.lane;
   const int nx = ldu(&J->n[0]), lx = ldu(&J->lcell_x);
@@ -475,7 +476,8 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& 
   const Tile* tiles = A.tiles;
   // pruning threshold: above the cutoff by far more than the FP64 rounding
   // of the bounding-box distance
-  const double rcut2 = ldu(&J->half_noprune) ? __builtin_inf() : S.rc2 * (1.0 + 1e-9);
+  const bool noprune = ldu(&J->half_noprune) != 0;
+  const double rcut2 = noprune ? __builtin_inf() : S.rc2 * (1.0 + 1e-9);
   for (int ti = t0; ti < t1; ++ti) {
     // the previous tile's plane updates are visible to every lane
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -493,24 +495,34 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& 
       S.lo = ldu(&J->half_lo64);
       S.hi = ldu(&J->half_hi64);
     }
-    double bl[3] = {0.0, 0.0, 0.0}, bh[3] = {0.0, 0.0, 0.0};
+    // the bounding boxes of the tile's halves (half_boxes_kernel; an empty
+    // half B has lo = +inf, hi = -inf); their centres are the origins of the
+    // sweep's coordinates
+    const int countA = min(count, 32), countB = count - countA;
+    double blA[3] = {0.0, 0.0, 0.0}, bhA[3] = {0.0, 0.0, 0.0};
+    double blB[3] = {0.0, 0.0, 0.0}, bhB[3] = {0.0, 0.0, 0.0};
     {
       const double4 r = J->r64_x[i];
       const double ri[3] = {r.x, r.y, r.z};
-      // the tile's bounding box (half_boxes_kernel); its centre is the
-      // origin of the sweep's coordinates
+      const double* bx = A.boxes + (size_t)ti * 12;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) S.O[a] = 0.0;
-      const double* bx = A.boxes + (size_t)ti * 6;
+      for (int a = 0; a < 3; ++a) {
+        S.OA[a] = 0.0;
+        S.OB[a] = 0.0;
+      }
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        bl[a] = ldu(&bx[a]);
-        bh[a] = ldu(&bx[3 + a]);
-        S.O[a] = 0.5 * (bl[a] + bh[a]);
+        blA[a] = ldu(&bx[a]);
+        bhA[a] = ldu(&bx[3 + a]);
+        blB[a] = ldu(&bx[6 + a]);
+        bhB[a] = ldu(&bx[9 + a]);
+        S.OA[a] = 0.5 * (blA[a] + bhA[a]);
+        S.OB[a] = countB > 0 ? 0.5 * (blB[a] + bhB[a]) : S.OA[a];
       }
-      S.xi[0] = active ? (T)((ri[0] - S.O[0]) * S.inv_sig) : T(1e18);
-      S.xi[1] = active ? (T)((ri[1] - S.O[1]) * S.inv_sig) : T(1e18);
-      S.xi[2] = DIM == 3 ? (active ? (T)((ri[2] - S.O[2]) * S.inv_sig) : T(1e18)) : T(0);
+      const bool hb = lane >= 32;
+      S.xi[0] = active ? (T)((ri[0] - (hb ? S.OB[0] : S.OA[0])) * S.inv_sig) : T(1e18);
+      S.xi[1] = active ? (T)((ri[1] - (hb ? S.OB[1] : S.OA[1])) * S.inv_sig) : T(1e18);
+      S.xi[2] = DIM == 3 ? (active ? (T)((ri[2] - (hb ? S.OB[2] : S.OA[2])) * S.inv_sig) : T(1e18)) : T(0);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -518,8 +530,10 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& 
       S.GA[lane * 3 + a] = 0.0;
     }
     __builtin_amdgcn_wave_barrier();
-    S.lhead = 0;
-    S.ltail = 0;
+    S.lhA = 0;
+    S.ltA = 0;
+    S.lhB = 0;
+    S.ltB = 0;
     // pieces of the visited cell range [xlo, xhi] of row r: px = -1, 0, +1
     const int xlo = SELF ? cx0 : cx0 - lx, xhi = cx1 + lx;
     for (int px = -1; px <= 1; ++px) {
@@ -535,32 +549,41 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& 
       const int kc = kcode(px, py, pz);
       const double t[3] = {ldu(&J->tK[kc * 4 + 0]), ldu(&J->tK[kc * 4 + 1]), ldu(&J->tK[kc * 4 + 2])};
       for (uint32_t cb = jb; cb < je; cb += kWave) {
-        // keep the candidates within the cutoff of the tile's bounding box
+        // keep, in the list of each half, the candidates within the cutoff
+        // of that half's bounding box
         const uint32_t j = cb + (uint32_t)lane;
-        bool keep = false;
+        bool keepA = false, keepB = false;
         if (j < je) {
           const double4 r = J->r64_x[j];
           const double q[3] = {r.x + t[0], r.y + t[1], r.z + t[2]};
-          double dd = 0.0;
+          double ddA = 0.0, ddB = 0.0;
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
-            const double e = fmax(0.0, fmax(bl[a] - q[a], q[a] - bh[a]));
-            dd += e * e;
+            const double eA = fmax(0.0, fmax(blA[a] - q[a], q[a] - bhA[a]));
+            const double eB = fmax(0.0, fmax(blB[a] - q[a], q[a] - bhB[a]));
+            ddA += eA * eA;
+            ddB += eB * eB;
           }
-          keep = dd <= rcut2;
+          keepA = ddA <= rcut2;
+          // home row: half B pairs only with j after its first particle
+          keepB = ddB <= rcut2 && !(SELF && px == 0 && !noprune && j <= tl.start + 32u);
         }
-        const unsigned long long km = __builtin_amdgcn_ballot_w64(keep);
+        const unsigned long long kmA = __builtin_amdgcn_ballot_w64(keepA);
+        const unsigned long long kmB = __builtin_amdgcn_ballot_w64(keepB);
         S.ntested += (unsigned long long)count * min(je - cb, (uint32_t)kWave);
-        S.nkept += (unsigned long long)count * (unsigned long long)__popcll(km);
-        if (keep)
-          S.LST[(S.ltail + (uint32_t)lane_rank(km)) & (uint32_t)(kHLCap - 1)] = make_uint2(j, (uint32_t)kc);
-        S.ltail += (uint32_t)__popcll(km);
+        S.nkept += (unsigned long long)countA * (unsigned long long)__popcll(kmA) +
+                   (unsigned long long)countB * (unsigned long long)__popcll(kmB);
+        const uint2 ent = make_uint2(j, (uint32_t)kc);
+        if (keepA) S.LST[(S.ltA + (uint32_t)lane_rank(kmA)) & (uint32_t)(kHLCap - 1)] = ent;
+        if (keepB) S.LST[kHLCap + ((S.ltB + (uint32_t)lane_rank(kmB)) & (uint32_t)(kHLCap - 1))] = ent;
+        S.ltA += (uint32_t)__popcll(kmA);
+        S.ltB += (uint32_t)__popcll(kmB);
         __builtin_amdgcn_wave_barrier();
-        S.template run_full<SELF>(part_j, npad);
+        S.template run_full<SELF>(pjA, pjB, npad);
       }
     }
-    S.template run_tail<SELF>(part_j, npad);
-    // the tile's i-side sums (plane 2 rho, one writer per particle)
+    S.template run_tail<SELF>(pjA, pjB, npad);
+    // the tile's i-side sums (plane 3 rho, one writer per particle)
 #pragma unroll
     for (int a = 0; a < DIM; ++a) S.Fi[a] += S.GA[lane * 3 + a];
     if (active) {
@@ -574,7 +597,7 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& 
 
 template <int DIM, bool VIR, typename T>
 __device__ __forceinline__ void half_lj_body(const JobDesc* __restrict__ jobs, const HalfArgs& A,
-                                             uint32_t* sQ, uint2* sL, double* sGA, double* sGJ) {
+                                             uint32_t* sQ, uint2* sL, uint2* sBC, double* sGA, double* sGJ) {
   const int lane = (int)__lane_id();
   const int NR = A.NR;
   const int nrows = A.nitems / NR;
@@ -601,6 +624,7 @@ __device__ __forceinline__ void half_lj_body(const JobDesc* __restrict__ jobs, c
   S.lane = lane;
   S.Q = sQ;
   S.LST = sL;
+  S.BC = sBC;
   S.GA = sGA;
   S.GJ = sGJ;
   S.rc2 = ldu(&J->rc2);
@@ -632,19 +656,23 @@ __device__ __forceinline__ void half_lj_body(const JobDesc* __restrict__ jobs, c
   const uint32_t* off = ldu(&J->off_x);
   const int rbase = (uy + ny * uz) * nx;
   const size_t npad = A.npad;
-  T* part_i = (T*)A.part + (size_t)(2 * rho) * 3 * npad;
-  T* part_j = (T*)A.part + (size_t)(2 * rho + 1) * 3 * npad;
-  {  // this item owns the j-side plane over row r: clear it
+  T* part_i = (T*)A.part + (size_t)(3 * rho) * 3 * npad;
+  T* pjA = (T*)A.part + (size_t)(3 * rho + 1) * 3 * npad;
+  T* pjB = (T*)A.part + (size_t)(3 * rho + 2) * 3 * npad;
+  {  // this item owns the two j-side planes over row r: clear them
     const uint32_t r0 = ldu(&off[rbase]), r1 = ldu(&off[rbase + nx]);
     for (uint32_t j = r0 + (uint32_t)lane; j < r1; j += kWave) {
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) part_j[(size_t)a * npad + j] = T(0);
+      for (int a = 0; a < DIM; ++a) {
+        pjA[(size_t)a * npad + j] = T(0);
+        pjB[(size_t)a * npad + j] = T(0);
+      }
     }
   }
   if (rho == 0)
-    run_tiles<DIM, VIR, T, true>(S, A, h, py, pz, rbase, part_i, part_j);
+    run_tiles<DIM, VIR, T, true>(S, A, h, py, pz, rbase, part_i, pjA, pjB);
   else
-    run_tiles<DIM, VIR, T, false>(S, A, h, py, pz, rbase, part_i, part_j);
+    run_tiles<DIM, VIR, T, false>(S, A, h, py, pz, rbase, part_i, pjA, pjB);
 
   // ---- item partials
   const unsigned long long cnt = S.cnt;
@@ -686,10 +714,11 @@ template <int DIM, bool VIR>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   __shared__ uint32_t sQ[kHQCap];
-  __shared__ uint2 sL[kHLCap];
+  __shared__ uint2 sL[2 * kHLCap];
+  __shared__ uint2 sBC[kWave];
   __shared__ double sGA[kWave * 3];
   __shared__ double sGJ[kWave * 3];
-  half_lj_body<DIM, VIR, float>(jobs, A, sQ, sL, sGA, sGJ);
+  half_lj_body<DIM, VIR, float>(jobs, A, sQ, sL, sBC, sGA, sGJ);
 }
 
 // Plain FP64 form: the same sweep with FP64 coordinates, sums and force
@@ -698,10 +727,11 @@ template <int DIM, bool VIR>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 half_lj64_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   __shared__ uint32_t sQ[kHQCap];
-  __shared__ uint2 sL[kHLCap];
+  __shared__ uint2 sL[2 * kHLCap];
+  __shared__ uint2 sBC[kWave];
   __shared__ double sGA[kWave * 3];
   __shared__ double sGJ[kWave * 3];
-  half_lj_body<DIM, VIR, double>(jobs, A, sQ, sL, sGA, sGJ);
+  half_lj_body<DIM, VIR, double>(jobs, A, sQ, sL, sBC, sGA, sGJ);
 }
 
 // Bounding box of every tile's wrapped positions (one wave per tile; the
@@ -714,16 +744,23 @@ __global__ void __launch_bounds__(256) half_boxes_kernel(const JobDesc* __restri
   if (t >= ntiles) return;
   const Tile tl = A.tiles[t];
   const int count = tl.count;
-  const uint32_t i = tl.start + (uint32_t)(lane < count ? lane : count - 1);
+  const bool act = lane < count;
+  const uint32_t i = tl.start + (uint32_t)(act ? lane : count - 1);
   const double4 r = J->r64_x[i];
   const double ri[3] = {r.x, r.y, r.z};
-  double* bx = A.boxes + (size_t)t * 6;
+  double* bx = A.boxes + (size_t)t * 12;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double lo = wave_min_d(ri[a]), hi = wave_max_d(ri[a]);
-    if (lane == 0) {
-      bx[a] = lo;
-      bx[3 + a] = hi;
+    // per 32-lane half; a half without particles gets lo = +inf, hi = -inf
+    double lo = act ? ri[a] : __builtin_inf(), hi = act ? ri[a] : -__builtin_inf();
+#pragma unroll
+    for (int d = 16; d > 0; d >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, d, 64));
+      hi = fmax(hi, __shfl_xor(hi, d, 64));
+    }
+    if ((lane & 31) == 0) {
+      bx[(lane >> 5) * 6 + a] = lo;
+      bx[(lane >> 5) * 6 + 3 + a] = hi;
     }
   }
 }
@@ -734,7 +771,7 @@ hipError_t launch_half_boxes(const JobDesc* jobs, const HalfArgs& A, hipStream_t
   return hipGetLastError();
 }
 
-// Sum of the 2 NR planes of each particle (fixed order), forces in original
+// Sum of the 3 NR planes of each particle (fixed order), forces in original
 // order, and the wrap term of the box gradient, sum over particles of
 // G_p w_p^T (block partials after the item partials).
 template <int DIM, typename T>
@@ -748,7 +785,7 @@ __global__ void __launch_bounds__(256) half_gather_kernel(const JobDesc* __restr
   double Bl[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (p < n) {
     const size_t npad = A.npad;
-    for (int q = 0; q < 2 * A.NR; ++q) {
+    for (int q = 0; q < 3 * A.NR; ++q) {
       const T* pl = (const T*)A.part + (size_t)q * 3 * npad;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) G[a] += (double)pl[(size_t)a * npad + p];
