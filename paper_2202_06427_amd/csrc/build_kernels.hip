@@ -238,14 +238,14 @@ __global__ void __launch_bounds__(kBinThreads) bin_place_kernel(
     }
     const float4 po = make_float4(o[0], o[1], o[2], 0.0f);
     const double4 ro = make_double4(rw[0], rw[1], rw[2], 0.0);
-    const int4 wo = make_int4(w[0], w[1], w[2], 0);
     if (staged) {
       const uint32_t d = dst - lo;
       s_pos[d] = po;
       s_r64[d] = ro;
-      s_wrap[d] = wo;
+      s_wrap[d] = make_int4(w[0], w[1], w[2], (int)(R.cell - (uint32_t)c0));  // .w: the cell in the bucket
       s_idx[d] = R.i;
     } else {
+      const int4 wo = make_int4(w[0], w[1], w[2], 0);
       pos[dst] = po;
       r64[dst] = ro;
       wrap[dst] = wo;
@@ -254,11 +254,28 @@ __global__ void __launch_bounds__(kBinThreads) bin_place_kernel(
   }
   if (!staged) return;  // uniform over the block
   __syncthreads();
+  // Within a cell of at most kSortCell particles the order is by wrapped
+  // Cartesian x, then by original index: a rebuild from the same positions
+  // gives the same order, and a split of a row's run of particles (the
+  // sweep's tile halves) splits it along x.  (Larger cells keep the order
+  // in which the placements above were made.)
   for (uint32_t d = threadIdx.x; d < hi - lo; d += kBinThreads) {
-    pos[lo + d] = s_pos[d];
-    r64[lo + d] = s_r64[d];
-    wrap[lo + d] = s_wrap[d];
-    idx[lo + d] = s_idx[d];
+    const int4 wv = s_wrap[d];
+    const uint32_t e = cur[wv.w] - lo, k = cnt[wv.w], st = e - k;
+    uint32_t p = d;
+    if (k <= (uint32_t)kSortCell) {
+      const double xd = s_r64[d].x;
+      const uint32_t id = s_idx[d];
+      p = st;
+      for (uint32_t q = st; q < e; ++q) {
+        const double xq = s_r64[q].x;
+        p += (xq < xd || (xq == xd && s_idx[q] < id)) ? 1u : 0u;
+      }
+    }
+    pos[lo + p] = s_pos[d];
+    r64[lo + p] = s_r64[d];
+    wrap[lo + p] = make_int4(wv.x, wv.y, wv.z, 0);
+    idx[lo + p] = s_idx[d];
   }
 }
 

@@ -364,6 +364,7 @@ constexpr int kMaxBuckets = 16384;
 constexpr int kMaxBucketCells = 1024;  // with kMaxBuckets: up to 2^24 cells
 constexpr int kPlaceCap = 2048;        // particles of a bucket assembled in LDS
 constexpr int kPlaceTarget = 1280;     // mean particles per bucket aimed at
+constexpr int kSortCell = 64;          // placement: cells up to this size are ordered by x within the cell
 static_assert((int64_t)kMaxBuckets * kMaxBucketCells >= (int64_t(1) << 24), "cell cap");
 struct BinPlan {
   int cpb, nbk, per, nblk;

@@ -5,7 +5,8 @@ are written at offsets from a counting pass (same pairs in the same order).  Che
 the rows of a tile are spread over several waves (few tiles: small sets,
 cross sets) and where they are not (10^5 particles), in both precisions.
 Per-bin FP64 sums of the speed histograms are merged with device atomics and
-are not covered (their counts are)."""
+are not covered (their counts are).  A rebuild from the same positions gives
+the same cell list, so maps over two builds match too."""
 import numpy as np
 import pytest
 import torch
@@ -69,6 +70,28 @@ def test_repeated_maps_are_bitwise_identical(clm, n, precision):
     a = _maps(cl, v)
     b = _maps(cl, v)
     _same(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_rebuilt_cell_list_gives_bitwise_identical_maps(clm, precision):
+    """A rebuild from the same positions places every particle at the same
+    sorted index (within a cell the order is by x, then by index, not by
+    the order of the placing threads), so maps over two builds match bit
+    for bit: the half-shell force sweep, the tile sweeps and the
+    neighbour-list order."""
+    n = 100_000
+    side = (n / 0.1) ** (1.0 / 3.0)
+    H = W.triclinic_h((side, 0.97 * side, 1.03 * side), (85.0, 95.0, 100.0))
+    x = W.uniform_in_box(n, H, 704)
+    v = T(W.rng(705).normal(size=(n, 3)))
+    box = clm.Box(H, 8.0, 2)
+    cl = clm.CellList(T(x), box, precision=precision)
+    a = _maps(cl, v)
+    cl.build(T(x))
+    b = _maps(cl, v)
+    _same(a, b)
+    c = _maps(clm.CellList(T(x), box, precision=precision), v)
+    _same(a, c)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
