@@ -378,10 +378,11 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const uint32_t
 }
 
 // ---------------------------------------------------------------- tiles
-// One wave per cell row (cy, cz): greedy tiles of consecutive sorted
-// particles, whole cells only, <= 64 particles and <= smax cells; a cell with
-// more than 64 particles is split into chunks of 64.  The lanes load the
-// row's cell offsets (64 cells per load); the greedy walk then runs on
+// One wave per cell row (cy, cz): tiles of 64 consecutive sorted particles
+// of the row (the last one of the rest), cut where a tile would span more
+// than smax cells; a tile may begin or end inside a cell (the particles of a
+// cell are ordered by x, so it splits the cell along x).  The lanes load
+// the row's cell offsets (64 cells per load); the walk then runs on
 // wave-uniform values read from the lanes, so a row costs one load round
 // trip per 64 cells instead of one per cell.
 constexpr int kTileRowsPerBlock = 256 / kWave;
@@ -395,11 +396,11 @@ __device__ uint32_t walk_row(const uint32_t* __restrict__ off, const TileGeom& g
   bool open = false;  // a tile of cells c0..last (tcount particles from a0) is open
   int c0 = 0, last = 0;
   uint32_t a0 = 0, tcount = 0;
-  auto emit = [&](uint32_t start, uint32_t count, int first, int lastc) {
+  auto emit = [&]() {
     if (EMIT && lane == 0 && t0 + nt < g.max_tiles)
-      tiles[t0 + nt] = Tile{start, (uint32_t)row, (uint16_t)count, (uint16_t)first, (uint16_t)lastc,
-                            (uint16_t)g.job};
+      tiles[t0 + nt] = Tile{a0, (uint32_t)row, (uint16_t)tcount, (uint16_t)c0, (uint16_t)last, (uint16_t)g.job};
     ++nt;
+    open = false;
   };
   for (int cs = 0; cs < nx; cs += kWave) {
     uint32_t av = 0u, bv = 0u;
@@ -412,35 +413,25 @@ __device__ uint32_t walk_row(const uint32_t* __restrict__ off, const TileGeom& g
       const int cx = cs + L;
       const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)av, L);
       const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)bv, L) - a;
-      if (open) {
-        // the open tile ends at smax cells, or before a cell that does not fit
-        if (cx - c0 >= g.smax || (cnt != 0u && tcount + cnt > (uint32_t)kTileMax)) {
-          emit(a0, tcount, c0, last);
-          open = false;
-        } else {
-          if (cnt != 0u) {
-            tcount += cnt;
-            last = cx;
-          }
-          continue;
-        }
-      }
       if (cnt == 0u) continue;
-      if (cnt > (uint32_t)kTileMax) {  // a heavy cell: chunks of 64
-        for (uint32_t s = a; s < a + cnt; s += kTileMax) {
-          const uint32_t c = a + cnt - s < (uint32_t)kTileMax ? a + cnt - s : (uint32_t)kTileMax;
-          emit(s, c, cx, cx);
+      if (open && cx - c0 >= g.smax) emit();  // the open tile would span too many cells
+      uint32_t s = a;  // next particle of the cell to place
+      while (s < a + cnt) {
+        if (!open) {
+          open = true;
+          c0 = cx;
+          a0 = s;
+          tcount = 0;
         }
-        continue;
+        const uint32_t take = min(a + cnt - s, (uint32_t)kTileMax - tcount);
+        tcount += take;
+        last = cx;
+        s += take;
+        if (tcount == (uint32_t)kTileMax) emit();
       }
-      open = true;
-      c0 = cx;
-      last = cx;
-      a0 = a;
-      tcount = cnt;
     }
   }
-  if (open) emit(a0, tcount, c0, last);
+  if (open) emit();
   return nt;
 }
 
