@@ -281,7 +281,8 @@ __global__ void __launch_bounds__(kBinThreads) bin_place_kernel(
 
 // ---------------------------------------------------------------- scan
 // Exclusive prefix of n uint32 counts into out[0..n] (out[n] = total).
-// Three phases: per-block sums, one-block scan of the sums, per-block apply.
+// Two passes: per-chunk sums, then per-chunk apply (each block adds up the
+// sums of the chunks before it); a single chunk takes one pass.
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 4;
 constexpr int kScanChunk = kScanThreads * kScanPer;
@@ -337,28 +338,21 @@ __global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(const uint32_t*
   }
 }
 
-// One block: exclusive scan of nb block sums in place (chunks of 1024).
-__global__ void __launch_bounds__(kScanThreads) scan_top_kernel(uint32_t* __restrict__ sums, int nb,
-                                                                const uint32_t* __restrict__ gate) {
-  if (gate_closed(gate)) return;
-  uint32_t carry = 0;
-  for (int base = 0; base < nb; base += kScanThreads) {
-    int i = base + threadIdx.x;
-    uint32_t v = i < nb ? sums[i] : 0u;
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(v, &tot);
-    if (i < nb) sums[i] = carry + ex;
-    carry += tot;
-    __syncthreads();
-  }
-}
-
+// Per chunk: its exclusive prefix, offset by the sum of the chunk sums
+// before it (each block adds those up itself: at most a few thousand).
+template <bool ONE>
 __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const uint32_t* __restrict__ in,
                                                                   int n,
                                                                   const uint32_t* __restrict__ sums,
                                                                   uint32_t* __restrict__ out,
                                                                   const uint32_t* __restrict__ gate) {
   if (gate_closed(gate)) return;
+  uint32_t pre = 0;
+  if constexpr (!ONE) {
+    uint32_t part = 0;
+    for (int k = (int)threadIdx.x; k < (int)blockIdx.x; k += kScanThreads) part += sums[k];
+    block_excl_scan(part, &pre);
+  }
   const size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * kScanPer;
   uint32_t v[kScanPer];
   uint32_t s = 0;
@@ -368,13 +362,13 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const uint32_t
     s += v[k];
   }
   uint32_t tot;
-  uint32_t ex = block_excl_scan(s, &tot) + sums[blockIdx.x];
+  uint32_t ex = block_excl_scan(s, &tot) + pre;
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
     if (base + k < (size_t)n) out[base + k] = ex;
     ex += v[k];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = sums[blockIdx.x] + tot;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = pre + tot;
 }
 
 // ---------------------------------------------------------------- tiles
@@ -600,10 +594,12 @@ size_t scan_scratch_elems(int n) { return (size_t)(n + kScanChunk - 1) / kScanCh
 hipError_t launch_scan(const uint32_t* in, int n, uint32_t* sums, uint32_t* out, hipStream_t s,
                        const uint32_t* gate) {
   int nb = (n + kScanChunk - 1) / kScanChunk;
-  if (nb < 1) nb = 1;
+  if (nb <= 1) {  // one chunk: one block
+    scan_apply_kernel<true><<<1, kScanThreads, 0, s>>>(in, n, sums, out, gate);
+    return hipGetLastError();
+  }
   scan_sums_kernel<<<nb, kScanThreads, 0, s>>>(in, n, sums, gate);
-  scan_top_kernel<<<1, kScanThreads, 0, s>>>(sums, nb, gate);
-  scan_apply_kernel<<<nb, kScanThreads, 0, s>>>(in, n, sums, out, gate);
+  scan_apply_kernel<false><<<nb, kScanThreads, 0, s>>>(in, n, sums, out, gate);
   return hipGetLastError();
 }
 
