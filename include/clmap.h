@@ -121,8 +121,11 @@ typedef struct clm_celllist_info {
   int64_t ntiles;          /* work units of <= 64 particles */
   int64_t nonempty_cells;  /* cells holding particles of x */
   int64_t max_occupancy;   /* most particles in one cell (x or y) */
-  int64_t candidate_pairs; /* pairs the sweep tests (half shell; full shell for
-                              LJ_EF/LJ_ADJOINT and cross sets counts both) */
+  int64_t candidate_pairs; /* pairs of the cell method on this grid: the particles
+                              of each cell times those of its half-shell stencil
+                              (lcell_x cells on along the row, the full reach of
+                              the rows with (dz, dy) > (0, 0)), plus the pairs
+                              within the cell; cross sets: the full stencil */
   int64_t guard_retests;   /* last map, FP32_GUARD: candidates within the band of rc^2
                               decided in FP64 */
   int64_t near_evaluations;/* last map, FP32_GUARD: other FP64 re-evaluations (LJ pairs

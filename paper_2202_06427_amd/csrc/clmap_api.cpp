@@ -1272,18 +1272,14 @@ clm_status clm_celllist_info_get(clm_celllist* cl, clm_celllist_info* o) {
   if ((int64_t)nt > cl->max_tiles)
     return fail(CLM_E_DEVICE, "internal: %u tiles exceed the bound %d", nt, cl->max_tiles);
   o->ntiles = nt;
-  // candidates: the sweep's half shell (full shell for cross sets)
+  // candidates: the grid's half-shell cell pairs (full stencil for cross sets)
   JobDesc jd = base_job(cl);
   CLM_HIP(launch_set_job(jd, cl->job_dev, st));
-  CLM_HIP(launch_candidates(cl->job_dev, cl->tiles, (int)nt, 0, cl->cand, st));
-  unsigned long long* hc = new (std::nothrow) unsigned long long[nt + 1];
-  if (!hc) return fail(CLM_E_INVALID_ARG, "out of host memory");
-  if (nt) CLM_HIP(hipMemcpyAsync(hc, cl->cand, sizeof(unsigned long long) * nt, hipMemcpyDeviceToHost, st));
+  CLM_HIP(launch_candidates(cl->job_dev, (int)cl->box.ncells, 0, cl->cand, st));
+  unsigned long long tot = 0;
+  CLM_HIP(hipMemcpyAsync(&tot, cl->cand, sizeof tot, hipMemcpyDeviceToHost, st));
   CLM_HIP(hipStreamSynchronize(st));
-  int64_t tot = 0;
-  for (uint32_t t = 0; t < nt; ++t) tot += (int64_t)hc[t];
-  delete[] hc;
-  o->candidate_pairs = tot;
+  o->candidate_pairs = (int64_t)tot;
   return CLM_OK;
 }
 

@@ -451,8 +451,8 @@ hipError_t launch_kc_keys(const KcKeys& A, hipStream_t s);
 hipError_t launch_kc_sort(KcRecord* rec, int n, hipStream_t s);
 hipError_t launch_kc_output(const KcRecord* rec, int k, int found, int32_t* io, int32_t* jo, double* d2o,
                             hipStream_t s);
-hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
-                             unsigned long long* out, hipStream_t s);
+hipError_t launch_candidates(const JobDesc* jobs, int ncells, int full, unsigned long long* out,
+                             hipStream_t s);
 
 // ---------------------------------------------------------------- calibration
 // Microbenchmarks of the device's attainable FMA rate and copy bandwidth.

@@ -1247,46 +1247,55 @@ __global__ void relspeed_band_kernel(const unsigned int* __restrict__ vmax_bits,
   }
 }
 
-// Candidate pairs per tile (pairs the sweep tests with a valid lane), for
-// reporting only.
-__global__ void __launch_bounds__(256) candidates_kernel(const JobDesc* __restrict__ jobs,
-                                                         const Tile* __restrict__ tiles, int ntiles,
-                                                         int full, unsigned long long* out) {
+// Candidate pairs of the cell method on this grid (the roofline's unit):
+// for every cell c, its particles times those of each cell of its stencil
+// (the half shell: the lx cells after c in its row and the whole reach of
+// the rows with (dz, dy) > (0, 0), plus the pairs within c; cross sets: the
+// x particles of c times the y particles of the full stencil).  One thread
+// per cell; block sums added to out[0] (integers: any order is exact).
+__global__ void __launch_bounds__(256) candidates_kernel(const JobDesc* __restrict__ jobs, int full,
+                                                         unsigned long long* out) {
   const JobDesc& J = jobs[0];
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntiles) return;
-  const Tile T = tiles[t];
-  const int l = J.lcell, lx = J.lcell_x, nx = J.n[0], ny = J.n[1], nz = J.n[2];
-  const int dim = J.dim;
-  const int cy = (int)(T.row % (uint32_t)ny), cz = dim == 3 ? (int)(T.row / (uint32_t)ny) : 0;
-  const bool fs = full || J.cross;
-  const uint32_t* off = J.cross ? J.off_y : J.off_x;
+  const int nx = J.n[0], ny = J.n[1], nz = J.dim == 3 ? J.n[2] : 1;
+  const int ncell = nx * ny * nz;
+  const int cid = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c = 0;
-  for (int dz = dim == 3 ? -l : 0; dz <= (dim == 3 ? l : 0); ++dz)
-    for (int dy = -l; dy <= l; ++dy) {
-      if (!fs && (dz < 0 || (dz == 0 && dy < 0))) continue;
-      const bool home = !fs && dz == 0 && dy == 0;
-      const int uy = (cy + dy + ny) % ny, uz = dim == 3 ? (cz + dz + nz) % nz : 0;
-      const int rowbase = (uy + ny * uz) * nx;
-      const int xlo = home ? (int)T.cx0 : (int)T.cx0 - lx, xhi = (int)T.cx1 + lx;
-      for (int ux = xlo; ux <= xhi; ++ux) {
-        const bool wrapped = ux < 0 || ux >= nx;
-        const int cc = rowbase + ((ux % nx) + nx) % nx;
-        const uint32_t jb = off[cc], je = off[cc + 1];
-        for (int k = 0; k < T.count; ++k) {
-          const uint32_t i = T.start + (uint32_t)k;
-          if (home && !wrapped) {
-            uint32_t lo = jb > i + 1 ? jb : i + 1;
-            c += je > lo ? je - lo : 0;
-          } else if (fs && !J.cross && dz == 0 && dy == 0 && !wrapped && i >= jb && i < je) {
-            c += je - jb - 1;
-          } else {
-            c += je - jb;
+  if (cid < ncell) {
+    const int l = J.lcell, lx = J.lcell_x, dim = J.dim;
+    const bool fs = full || J.cross;
+    const uint32_t* offx = J.off_x;
+    const uint32_t* offy = J.cross ? J.off_y : J.off_x;
+    const int cx = cid % nx, cy = (cid / nx) % ny, cz = cid / (nx * ny);
+    const unsigned long long ni = offx[cid + 1] - offx[cid];
+    if (ni != 0ull) {
+      unsigned long long nj = 0;  // candidates of one particle of c in other cells
+      for (int dz = dim == 3 ? -l : 0; dz <= (dim == 3 ? l : 0); ++dz)
+        for (int dy = -l; dy <= l; ++dy) {
+          if (!fs && (dz < 0 || (dz == 0 && dy < 0))) continue;
+          const bool home = dz == 0 && dy == 0;
+          const int uy = (cy + dy + ny) % ny, uz = dim == 3 ? (cz + dz + nz) % nz : 0;
+          const int rowbase = (uy + ny * uz) * nx;
+          const int xlo = (home && !fs) ? cx + 1 : cx - lx;
+          for (int ux = xlo; ux <= cx + lx; ++ux) {
+            if (home && ux == cx) continue;  // the cell itself: below
+            const int cc = rowbase + ((ux % nx) + nx) % nx;
+            nj += offy[cc + 1] - offy[cc];
           }
         }
-      }
+      c = ni * nj;
+      if (J.cross) c += ni * (unsigned long long)(offy[cid + 1] - offy[cid]);
+      else c += fs ? ni * (ni - 1ull) : ni * (ni - 1ull) / 2ull;
     }
-  out[t] = c;
+  }
+  __shared__ unsigned long long red[256 / kWave];
+  for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int k = 0; k < 256 / kWave; ++k) t += red[k];
+    if (t) atomicAdd(out, t);
+  }
 }
 
 // ---------------------------------------------------------------- job tables
@@ -1487,10 +1496,11 @@ hipError_t launch_finalize(const JobDesc* jobs, const FinalArgs& F, double* scra
   return hipGetLastError();
 }
 
-hipError_t launch_candidates(const JobDesc* jobs, const Tile* tiles, int ntiles, int full,
-                             unsigned long long* out, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  candidates_kernel<<<(ntiles + 255) / 256, 256, 0, s>>>(jobs, tiles, ntiles, full, out);
+hipError_t launch_candidates(const JobDesc* jobs, int ncells, int full, unsigned long long* out,
+                             hipStream_t s) {
+  hipError_t e = launch_fill_u64(out, 1, 0ull, s);
+  if (e != hipSuccess) return e;
+  if (ncells > 0) candidates_kernel<<<(ncells + 255) / 256, 256, 0, s>>>(jobs, full, out);
   return hipGetLastError();
 }
 

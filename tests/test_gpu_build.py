@@ -90,3 +90,47 @@ def test_cell_membership_is_the_canonical_wrap(clm):
     x = W.uniform_in_box(8000, H, 47) + H @ np.array([5.0, -3.0, 2.0])
     for rc in (1.0, 3.0):
         _check_pairs(clm, x, H, rc, lcell=1)
+
+
+def _stencil_pairs(x, H, grid, lx, l):
+    """Candidate pairs of the cell method on a grid, by counting: the
+    particles of each cell times those of each cell of its half-shell stencil
+    (lx cells on along x; the rows with (dz, dy) > (0, 0) over the whole x
+    reach), plus the pairs within a cell."""
+    dim = H.shape[0]
+    s = x @ np.linalg.inv(H).T
+    s -= np.floor(s)
+    n = np.array(grid)
+    cell = np.minimum((s * n).astype(np.int64), n - 1)
+    shape = tuple(n[::-1])
+    cnt = np.zeros(shape, np.int64)
+    np.add.at(cnt, tuple(cell[:, a] for a in reversed(range(dim))), 1)
+    tot = int((cnt * (cnt - 1) // 2).sum())
+    for dz in (range(0, l + 1) if dim == 3 else [0]):
+        for dy in range(-l, l + 1):
+            if dz == 0 and dy < 0:
+                continue
+            for dx in range(-lx, lx + 1):
+                if dz == 0 and dy == 0 and dx <= 0:
+                    continue
+                sh = (-dz, -dy, -dx)[3 - dim:]
+                tot += int((cnt * np.roll(cnt, shift=sh, axis=tuple(range(dim)))).sum())
+    return tot
+
+
+@pytest.mark.parametrize("case", ["tric3", "tric3_x6", "square2"])
+def test_candidate_pairs_are_the_grids_half_shell(clm, case):
+    """The candidate count reported with the cell list (the roofline unit)
+    is the half-shell cell-pair count of the grid, whatever the tiles."""
+    if case == "square2":
+        H = np.diag([60.0, 60.0])
+        x = W.uniform_in_box(20_000, H, 48)
+        box = clm.Box(H, 2.0, 2)
+    else:
+        H = W.triclinic_h((50.0, 48.0, 52.0), (80.0, 95.0, 100.0))
+        x = W.uniform_in_box(12_000, H, 49)
+        box = clm.Box(H, 6.0, 2, 6 if case == "tric3_x6" else None)
+    bi = box.info()
+    cl = clm.CellList(T(x), box, precision="fp32")
+    info = cl.info()
+    assert info["candidate_pairs"] == _stencil_pairs(x, H, bi["grid"], bi["lcell_x"], bi["lcell"])
