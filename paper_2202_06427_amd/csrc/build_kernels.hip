@@ -382,8 +382,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const uint32_t
 constexpr int kTileRowsPerBlock = 256 / kWave;
 
 template <bool EMIT>
-__device__ uint32_t walk_row(const uint32_t* __restrict__ off, const TileGeom& g, int row,
-                             Tile* __restrict__ tiles, uint32_t t0, int lane) {
+__device__ uint32_t walk_row_seq(const uint32_t* __restrict__ off, const TileGeom& g, int row,
+                                 Tile* __restrict__ tiles, uint32_t t0, int lane) {
   const int nx = g.n[0];
   const uint32_t* o = off + (size_t)row * nx;
   uint32_t nt = 0;
@@ -426,6 +426,53 @@ __device__ uint32_t walk_row(const uint32_t* __restrict__ off, const TileGeom& g
     }
   }
   if (open) emit();
+  return nt;
+}
+
+// Cell (x index) of sorted particle a of a row whose cell offsets are
+// o[0..nx]: the last cell c with o[c] <= a.
+__device__ __forceinline__ int cell_of_particle(const uint32_t* __restrict__ o, int nx, uint32_t a) {
+  int lo = 0, hi = nx - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (o[mid] <= a) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The tiles of a row.  When no run of 64 consecutive particles of the row
+// spans more than smax cells, they are the row's 64-particle chunks: one
+// lane per tile finds its first and last cells by binary search (the walk
+// above gives the same tiles, one cell at a time); otherwise the walk.
+template <bool EMIT>
+__device__ uint32_t walk_row(const uint32_t* __restrict__ off, const TileGeom& g, int row,
+                             Tile* __restrict__ tiles, uint32_t t0, int lane) {
+  const int nx = g.n[0];
+  const uint32_t* o = off + (size_t)row * nx;
+  const uint32_t rs = o[0], re = o[nx];
+  const uint32_t nt = (re - rs + (uint32_t)kTileMax - 1) / (uint32_t)kTileMax;
+  bool wide = false;  // a chunk spans more than smax cells
+  for (uint32_t tb = 0; tb < nt; tb += kWave) {
+    const uint32_t t = tb + (uint32_t)lane;
+    if (t < nt) {
+      const uint32_t a0 = rs + t * (uint32_t)kTileMax;
+      const uint32_t a1 = min(a0 + (uint32_t)kTileMax, re) - 1u;
+      wide |= cell_of_particle(o, nx, a1) - cell_of_particle(o, nx, a0) >= g.smax;
+    }
+  }
+  if (__builtin_amdgcn_ballot_w64(wide) != 0ull) return walk_row_seq<EMIT>(off, g, row, tiles, t0, lane);
+  if (EMIT) {
+    for (uint32_t tb = 0; tb < nt; tb += kWave) {
+      const uint32_t t = tb + (uint32_t)lane;
+      if (t < nt && t0 + t < g.max_tiles) {
+        const uint32_t a0 = rs + t * (uint32_t)kTileMax;
+        const uint32_t a1 = min(a0 + (uint32_t)kTileMax, re) - 1u;
+        tiles[t0 + t] = Tile{a0, (uint32_t)row, (uint16_t)(a1 - a0 + 1u), (uint16_t)cell_of_particle(o, nx, a0),
+                             (uint16_t)cell_of_particle(o, nx, a1), (uint16_t)g.job};
+      }
+    }
+  }
   return nt;
 }
 
