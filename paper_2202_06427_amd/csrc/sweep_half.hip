@@ -56,7 +56,7 @@ namespace clm {
 namespace {
 
 constexpr int kHQCap = 320;   // FP64 re-evaluation queue (>= 63 + 4 * 64 entries)
-constexpr int kHLCap = 128;   // packed candidate list (power of two, >= 63 + 64)
+constexpr int kHLCap = 128;   // each half's packed candidate ring (power of two, >= 63 + 64)
 constexpr uint32_t kCenter = 13u;  // image code of K = (0, 0, 0)
 
 template <int K>
@@ -734,8 +734,9 @@ half_lj64_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   half_lj_body<DIM, VIR, double>(jobs, A, sQ, sL, sBC, sGA, sGJ);
 }
 
-// Bounding box of every tile's wrapped positions (one wave per tile; the
-// sweep reads it once per (tile, neighbour row) instead of reducing it).
+// Bounding boxes of the wrapped positions of each tile's two halves (its
+// first 32 particles, then the others; one wave per tile): the sweep reads
+// them once per (tile, neighbour row) instead of reducing them.
 __global__ void __launch_bounds__(256) half_boxes_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   const JobDesc* J = &jobs[0];
   const int lane = (int)(threadIdx.x & (kWave - 1));
