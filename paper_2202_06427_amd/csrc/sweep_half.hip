@@ -179,6 +179,8 @@ struct Half {
   double* GJ;              // [64][3] FP64 sums of f D (i -> j) of queued pairs, by candidate
   uint2* LST;              // packed candidates (sorted index, image code): list A, then list B
   uint2* BC;               // [64] the current block's candidates by slot
+  double* RI;              // [64][3] FP64 positions of the tile's particles, by lane
+  double* RJ;              // [64][3] FP64 positions of the block's candidates, by slot
   uint32_t qtail;          // queued entries: Q[0 .. qtail)
   uint32_t lhA, ltA, lhB, ltB;  // ring positions of lists A and B
   uint32_t tstart;
@@ -189,15 +191,15 @@ struct Half {
   __device__ __forceinline__ void process(uint32_t e, bool* in_out) {
     const int il = (int)(e & 63u), jm = (int)((e >> 6) & 63u);
     const uint2 c = BC[jm];
-    const double4 rI = J->r64_x[tstart + (uint32_t)il];
-    const double4 rJ = J->r64_x[c.x];
+    const double* rI = &RI[il * 3];
+    const double* rJ = &RJ[jm * 3];
     const double* tk = &J->tK[c.y * 4];
     double D[3];
-    D[0] = (rJ.x - rI.x) + tk[0];
-    D[1] = (rJ.y - rI.y) + tk[1];
+    D[0] = (rJ[0] - rI[0]) + tk[0];
+    D[1] = (rJ[1] - rI[1]) + tk[1];
     double d2 = D[0] * D[0] + D[1] * D[1];
     if (DIM == 3) {
-      D[2] = (rJ.z - rI.z) + tk[2];
+      D[2] = (rJ[2] - rI[2]) + tk[2];
       d2 = d2 + D[2] * D[2];
     } else {
       D[2] = 0.0;
@@ -360,6 +362,11 @@ struct Half {
       xj[0] = jv ? (T)(((r.x + t[0]) - (hb ? OB[0] : OA[0])) * inv_sig) : T(-1e18);
       xj[1] = jv ? (T)(((r.y + t[1]) - (hb ? OB[1] : OA[1])) * inv_sig) : T(-1e18);
       xj[2] = DIM == 3 ? (jv ? (T)(((r.z + t[2]) - (hb ? OB[2] : OA[2])) * inv_sig) : T(-1e18)) : T(0);
+      if (canon) {  // the candidate's FP64 position for queued pairs
+        RJ[slot * 3 + 0] = r.x;
+        RJ[slot * 3 + 1] = r.y;
+        RJ[slot * 3 + 2] = r.z;
+      }
     }
     if constexpr (SELF) key = (jv && c.y == kCenter) ? (int)c.x : 0x7fffffff;
     T jold[3] = {T(0), T(0), T(0)};
@@ -504,6 +511,8 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& 
     {
       const double4 r = J->r64_x[i];
       const double ri[3] = {r.x, r.y, r.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) S.RI[lane * 3 + a] = ri[a];  // for queued pairs
       const double* bx = A.boxes + (size_t)ti * 12;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -597,7 +606,8 @@ __device__ __forceinline__ void run_tiles(Half<DIM, VIR, T>& S, const HalfArgs& 
 
 template <int DIM, bool VIR, typename T>
 __device__ __forceinline__ void half_lj_body(const JobDesc* __restrict__ jobs, const HalfArgs& A,
-                                             uint32_t* sQ, uint2* sL, uint2* sBC, double* sGA, double* sGJ) {
+                                             uint32_t* sQ, uint2* sL, uint2* sBC, double* sGA, double* sGJ,
+                                             double* sR) {
   const int lane = (int)__lane_id();
   const int NR = A.NR;
   const int nrows = A.nitems / NR;
@@ -627,6 +637,8 @@ __device__ __forceinline__ void half_lj_body(const JobDesc* __restrict__ jobs, c
   S.BC = sBC;
   S.GA = sGA;
   S.GJ = sGJ;
+  S.RI = sR;
+  S.RJ = sR + kWave * 3;
   S.rc2 = ldu(&J->rc2);
   S.s2 = ldu(&J->s2);
   S.inv_sig = 1.0 / sqrt(S.s2);
@@ -718,7 +730,8 @@ half_lj_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   __shared__ uint2 sBC[kWave];
   __shared__ double sGA[kWave * 3];
   __shared__ double sGJ[kWave * 3];
-  half_lj_body<DIM, VIR, float>(jobs, A, sQ, sL, sBC, sGA, sGJ);
+  __shared__ double sR[kWave * 6];
+  half_lj_body<DIM, VIR, float>(jobs, A, sQ, sL, sBC, sGA, sGJ, sR);
 }
 
 // Plain FP64 form: the same sweep with FP64 coordinates, sums and force
@@ -731,7 +744,8 @@ half_lj64_kernel(const JobDesc* __restrict__ jobs, const HalfArgs A) {
   __shared__ uint2 sBC[kWave];
   __shared__ double sGA[kWave * 3];
   __shared__ double sGJ[kWave * 3];
-  half_lj_body<DIM, VIR, double>(jobs, A, sQ, sL, sBC, sGA, sGJ);
+  __shared__ double sR[kWave * 6];
+  half_lj_body<DIM, VIR, double>(jobs, A, sQ, sL, sBC, sGA, sGJ, sR);
 }
 
 // Bounding boxes of the wrapped positions of each tile's two halves (its
