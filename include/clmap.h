@@ -181,9 +181,11 @@ typedef struct clm_map_params {
                                    shows only in *count_dev. */
   int half_shell;               /* LJ_EF / LJ_ADJOINT with a map scratch: 0 runs the half-shell sweep
                                    when the grid gives at least 4096 (cell row, neighbour row)
-                                   work items and the full-shell gather otherwise (too few items
-                                   cannot fill the device: one wave works through a whole row);
-                                   1 runs the half-shell sweep whenever it applies; -1 never. */
+                                   work items, or when a cell row holds no more 64-particle tiles
+                                   (on average) than a gather tile visits rows, (2l+1)^(dim-1);
+                                   otherwise the full-shell gather (one half-shell wave works
+                                   through a whole row: long rows with few items leave the device
+                                   idle); 1 runs the half-shell sweep whenever it applies; -1 never. */
 } clm_map_params;
 
 typedef struct clm_map_out {

@@ -862,11 +862,26 @@ clm_status clm_map(clm_celllist* cl, clm_map_kind kind, const clm_map_params* P,
 }
 
 // ---------------------------------------------------------------- half-shell LJ scratch
-// Below this many (cell row, neighbour row) items the half-shell sweep
-// cannot fill the device (one wave works through a whole cell row; on a
-// 2D clustered set of 2*10^6 points with 600 items it took 86 ms against
-// 9.3 ms for the full-shell gather), so the automatic choice takes the gather.
+// The automatic choice between the half-shell sweep and the full-shell
+// gather.  With at least kHalfMinItems (cell row, neighbour row) items the
+// half shell fills the device.  With fewer, both sweeps are bound by their
+// longest wave: an item works through the tiles of a row against one
+// neighbour row, a gather tile through the (2l+1)^(dim-1) rows of its
+// stencil, so the half shell is taken while a row holds no more tiles than
+// that (its waves are then no longer, and it evaluates half the pairs).
+// Long rows with few items take the gather (a 2D clustered set of 2*10^6
+// points, 600 items of 156 tiles a row: 93 against 9 ms; 10^6 particles at
+// lcell 1: 4.5 against 3.9 ms), short ones the half shell (10^4 Neon atoms,
+// 637 items of 3 tiles a row: 0.12 against 0.58 ms).
 static constexpr int kHalfMinItems = 4096;
+
+static bool half_auto(const clm_celllist* cl, int nitems) {
+  if (nitems >= kHalfMinItems) return true;
+  const int l = cl->box.lcell;
+  const int reach = cl->box.dim == 3 ? (2 * l + 1) * (2 * l + 1) : 2 * l + 1;
+  const double tiles_per_row = (double)cl->nx / ((double)kTileMax * std::max(cl->nrows, 1));
+  return tiles_per_row <= (double)reach;
+}
 
 static bool half_applies(const clm_celllist* cl, int k) {
   return k == K_LJ_F && !cl->box.small && !cl->cross && cl->nx > 0;
@@ -1008,7 +1023,7 @@ static clm_status map_one_inner(clm_celllist* cl, clm_map_kind kind, const clm_m
   if (s != CLM_OK) return s;
   const clm_box& B = cl->box;
   hipStream_t st = cl->ctx->stream;
-  if (half_ok && (P->half_shell > 0 || half_layout(cl).nitems >= kHalfMinItems)) {
+  if (half_ok && (P->half_shell > 0 || half_auto(cl, half_layout(cl).nitems))) {
     // half-shell LJ sweep: every pair once, force planes in the map scratch
     const HalfLayout HL = half_layout(cl);
     char* base = (char*)P->scratch_dev;

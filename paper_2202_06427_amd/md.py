@@ -141,7 +141,11 @@ class _RebuildForces:
 
     def step(self, x, sigma, eps, F, E, C):
         self.cl.build(x)
-        P = L.MapParams(sigma=sigma, epsilon=eps, near_factor=1.0)
+        # the map scratch lets the library take the half-shell sweep where it
+        # is faster (its automatic choice)
+        sp, sb = self.cl._half_scratch("lj_ef", True)
+        P = L.MapParams(sigma=sigma, epsilon=eps, near_factor=1.0, scratch_dev=sp, scratch_bytes=sb,
+                        half_shell=0)
         o = L.MapOut(energy_dev=_ptr(E), forces_dev=_ptr(F), count_dev=_ptr(C))
         self.cl._map("lj_ef", P, o)
 

@@ -195,17 +195,26 @@ def test_half_shell_scratch_errors(clm):
 
 def test_automatic_choice_between_half_and_full_shell(clm):
     """half=None: the half-shell sweep when the grid gives at least 4096
-    (cell row, neighbour row) work items, the full-shell gather otherwise;
-    the two forms round differently, so the choice shows bit for bit."""
+    (cell row, neighbour row) work items, or when a cell row holds no more
+    64-particle tiles on average than a gather tile visits rows
+    ((2l+1)^2 in 3D); the full-shell gather otherwise (long rows, few
+    items).  The two forms round differently, so the choice shows bit for
+    bit."""
     sigma, eps = 1.1, 0.3
-    for L_box, n, want_half in ((30.0, 3000, False), (60.0, 20000, True)):
+    cases = ((30.0, 3000, 2, True),    # 1872 items, 0.3 tiles a row
+             (60.0, 20000, 2, True),   # 7488 items
+             (30.0, 30000, 1, False))  # 180 items, 13 tiles a row > 9
+    for L_box, n, lcell, want_half in cases:
         H = np.diag([L_box] * 3)
         x = _lattice(H, n, 14)
-        cl = clm.CellList(T(x), clm.Box(H, 5.0, 2), precision="fp32")
+        box = clm.Box(H, 5.0, lcell)
         rows = 1
-        for g in clm.Box(H, 5.0, 2).info()["grid"][1:]:
+        for g in box.info()["grid"][1:]:
             rows *= g
-        assert (rows * 13 >= 4096) == want_half
+        nr = 2 * lcell * lcell + 2 * lcell + 1
+        reach = (2 * lcell + 1) ** 2
+        assert (rows * nr >= 4096 or n / (64 * rows) <= reach) == want_half
+        cl = clm.CellList(T(x), box, precision="fp32")
         auto = cl.lj_forces(sigma, eps, virial=True)
         forced = cl.lj_forces(sigma, eps, virial=True, half=want_half)
         other = cl.lj_forces(sigma, eps, virial=True, half=not want_half)
